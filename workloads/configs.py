@@ -1,0 +1,131 @@
+"""Layer shapes and HE parameter sets of the five benchmark workloads.
+
+Shapes follow the paper's evaluation networks (App. D: the MNIST MLP's first
+layer 784->128, CIFAR-shaped 3x3 convolutions) and the batch sizes used for the
+per-layer cost table (Table V, batch 64).  All convolutions are stride 1 with
+"same" padding 1, which is the configuration the packed encodings of App. A
+cover (a valid correlation over a zero-padded input).
+"""
+from dataclasses import dataclass, field
+from typing import List, Tuple
+
+
+@dataclass(frozen=True)
+class LayerSpec:
+    """One linear layer.  kind is "fc" or "conv".
+
+    FC layers are stored as conv layers with h = w = k = 1 and pad = 0: the
+    matrix encoding of App. A is the 1x1 case of the convolution encoding.
+    Weight layout is PyTorch's: fc (c_out, c_in), conv (c_out, c_in, k, k).
+    Activations are (batch, c_in, h, w); fc activations are (batch, c_in).
+    """
+    kind: str
+    batch: int
+    c_in: int
+    c_out: int
+    h: int = 1
+    w: int = 1
+    k: int = 1
+    pad: int = 0
+    # value distributions, consumed by workloads.gen
+    x_dist: Tuple = ("normal", 1.0)
+    w_dist: Tuple = ("normal", 0.1)
+    dy_dist: Tuple = ("normal", 1.0)
+    # HE parameter set for this layer
+    log2_n: int = 13
+    num_limbs: int = 3
+    prime_bits: int = 60
+
+    @property
+    def h_out(self):
+        return self.h + 2 * self.pad - self.k + 1
+
+    @property
+    def w_out(self):
+        return self.w + 2 * self.pad - self.k + 1
+
+    def x_shape(self):
+        if self.kind == "fc":
+            return (self.batch, self.c_in)
+        return (self.batch, self.c_in, self.h, self.w)
+
+    def w_shape(self):
+        if self.kind == "fc":
+            return (self.c_out, self.c_in)
+        return (self.c_out, self.c_in, self.k, self.k)
+
+    def y_shape(self):
+        if self.kind == "fc":
+            return (self.batch, self.c_out)
+        return (self.batch, self.c_out, self.h_out, self.w_out)
+
+
+def fc(batch, c_in, c_out, **kw):
+    return LayerSpec("fc", batch, c_in, c_out, **kw)
+
+
+def conv(batch, c_in, c_out, hw, k=3, pad=1, **kw):
+    return LayerSpec("conv", batch, c_in, c_out, hw, hw, k, pad, **kw)
+
+
+def he_std(fan_in):
+    return (2.0 / fan_in) ** 0.5
+
+
+@dataclass
+class Config:
+    index: int
+    name: str
+    layers: List[LayerSpec]
+    ops: Tuple[str, ...]
+    first_layer_shares: bool = False  # <X>_0 = 0 for the network's input layer
+    seed: int = 0
+    notes: str = ""
+    extra: dict = field(default_factory=dict)
+
+
+def _conv_he(batch, cin, cout, hw, log2_n, limbs):
+    return conv(batch, cin, cout, hw, x_dist=("normal", 1.0), w_dist=("normal", he_std(cin * 9)),
+                dy_dist=("normal", 1.0), log2_n=log2_n, num_limbs=limbs, prime_bits=60)
+
+
+CONFIGS = {
+    1: Config(1, "fc64x10_b8_fwd_n4096",
+              [fc(8, 64, 10, x_dist=("normal", 1.0), w_dist=("normal", 0.1), log2_n=12, num_limbs=2,
+                  prime_bits=50)],
+              ops=("fwd",), first_layer_shares=True, seed=0),
+    2: Config(2, "fc784x128_b64_fwdbwd_n8192",
+              [fc(64, 784, 128, x_dist=("uniform", 0.0, 1.0), w_dist=("normal", 0.05),
+                  dy_dist=("normal", 1.0), log2_n=13, num_limbs=3, prime_bits=60)],
+              ops=("fwd", "dx", "dw"), seed=1),
+    3: Config(3, "conv3x64_k3_32x32_b64_fwdbwd_n8192",
+              [_conv_he(64, 3, 64, 32, 13, 3)],
+              ops=("fwd", "dx", "dw"), seed=2),
+    4: Config(4, "cnn4_b128_step_mixedN",
+              [_conv_he(128, 3, 32, 32, 14, 4),
+               _conv_he(128, 32, 64, 16, 13, 3),
+               _conv_he(128, 64, 128, 8, 13, 3),
+               fc(128, 2048, 10, x_dist=("normal", 1.0), w_dist=("normal", he_std(2048)),
+                  dy_dist=("normal", 1.0), log2_n=14, num_limbs=4, prime_bits=60)],
+              ops=("fwd", "dx", "dw"), seed=3),
+    5: Config(5, "resnet8conv_b64_n16384",
+              [_conv_he(64, 64, 64, 32, 14, 4)] * 3 + [_conv_he(64, 128, 128, 16, 14, 4)] * 3
+              + [_conv_he(64, 256, 256, 8, 14, 4)] * 2,
+              ops=("fwd", "dx", "dw"), seed=4),
+}
+
+
+def config_layers(index):
+    return CONFIGS[index].layers
+
+
+def small_cases():
+    """Small layers spanning several tiles and ragged tails, for full
+    ciphertext-level comparison (the oracle finishes them in seconds)."""
+    return [
+        fc(8, 64, 10, log2_n=12, num_limbs=2, prime_bits=50),
+        fc(5, 37, 7, log2_n=11, num_limbs=2, prime_bits=50),
+        conv(3, 2, 3, 5, k=3, pad=1, log2_n=11, num_limbs=2, prime_bits=50),
+        conv(2, 3, 4, 7, k=3, pad=1, log2_n=11, num_limbs=3, prime_bits=60),
+        conv(2, 2, 2, 6, k=2, pad=0, log2_n=10, num_limbs=2, prime_bits=60),
+    ]
