@@ -1,0 +1,197 @@
+/*
+ * pencil.h -- C ABI of the MI355X encrypted linear-layer product.
+ *
+ * Pencil (Liu et al., NDSS 2024) trains a network between a data owner (DO),
+ * who holds the data, and a model owner (MO), who holds the weights.  Every
+ * linear layer is evaluated on additive shares over Z_t (Sec. II.C) with one
+ * BFV plaintext-ciphertext product (Sec. II.B):
+ *   - forward, Alg. 1: the DO encrypts its share <X>_1; the MO adds <X>_0,
+ *     multiplies by W, masks with s and returns the ciphertext; the DO's share
+ *     of Y is the decryption, the MO's share is s + b;
+ *   - input gradient by the same pattern with the transposed operator
+ *     (Sec. III.B.2);
+ *   - weight gradient, Alg. 2: the MO evaluates the cross terms
+ *     <dY>_0 o [[<X>_1]] + [[<dY>_1]] o <X>_0 and masks them.
+ * Tensors are packed into polynomials of degree N by the batched encodings of
+ * App. A and multiplied as RNS negacyclic NTT -> pointwise multiply-accumulate
+ * -> inverse NTT (Sec. V), then re-randomised, noise-flooded and masked.
+ *
+ * Conventions
+ *   Layouts  Z_t tensors are int64 in [0, t), contiguous, PyTorch layout:
+ *            FC activations (B, c_in), weights (c_out, c_in); Conv2d
+ *            activations (B, C, H, W), weights (c_out, c_in, k, k).  Stride 1.
+ *            A ciphertext is uint64 [2][L][N] (component, RNS limb,
+ *            coefficient), coefficient domain; a ciphertext buffer holds
+ *            pencil_sizes.n_ct[...] (or n_out[...]) of them back to back, in the
+ *            tile order of the plan.
+ *   Memory   Every tensor, ciphertext and workspace pointer is DEVICE memory
+ *            owned by the caller, sized with pencil_layout.  The context owns
+ *            only its keys and tables, allocated once in pencil_ctx_create.
+ *            Functions marked (host) take host pointers.
+ *   Streams  `stream` is a hipStream_t (NULL = default stream).  Calls enqueue
+ *            their kernels and return without synchronising, except where
+ *            noted.  Buffers must stay valid until the stream reaches them.
+ *   Errors   Every call returns a pencil_status; nothing is thrown across the
+ *            ABI.  Arguments are validated on the host before any launch.
+ *            pencil_last_error(ctx) (or pencil_last_error(NULL) after a failed
+ *            create) returns a message for the last failure on that context.
+ *   Randomness  All random values (keys, encryption, re-randomisation, flood,
+ *            masks) come from Philox-4x64-10 keyed by (seed, nonce); a nonce
+ *            must not be reused with the same seed for different data.
+ */
+#ifndef PENCIL_H
+#define PENCIL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pencil_ctx pencil_ctx;
+
+typedef enum {
+    PENCIL_OK = 0,
+    PENCIL_EINVAL = 1,       /* bad argument, shape or plan                         */
+    PENCIL_ENOMEM = 2,       /* device allocation failed (create only)              */
+    PENCIL_EHIP = 3,         /* a HIP runtime call or kernel launch failed          */
+    PENCIL_ENOISE = 4,       /* decryption noise check failed                       */
+    PENCIL_EUNSUPPORTED = 5  /* valid request this library does not implement       */
+} pencil_status;
+
+/* BFV parameter set {N, t, q = q_1...q_L} (Sec. II.B; RNS limbs, Sec. V). */
+typedef struct {
+    uint32_t log2_n;      /* N = 2^log2_n, 10 <= log2_n <= 14                        */
+    uint32_t num_limbs;   /* L, 1..4                                                 */
+    uint32_t prime_bits;  /* limb size when primes[0] == 0: the L largest primes     */
+                          /* below 2^prime_bits that are 1 mod 2^15, descending;     */
+                          /* 40 <= prime_bits <= 60                                  */
+    uint32_t flood_bits;  /* 0 = floor(log2 Delta) - 3, Delta = floor(q / t)        */
+    uint64_t primes[4];   /* explicit limbs (each prime, = 1 mod 2N, < 2^61) or 0   */
+    uint64_t t;           /* plaintext modulus, odd prime < 2^48; 0 = the largest   */
+                          /* prime below 2^41                                        */
+    uint64_t seed;        /* key for every random value                              */
+} pencil_params;
+
+/* One linear layer (Sec. II.D).  kind 0 = FC (h = w = k = 1, pad = 0), 1 = Conv2d
+ * with stride 1, square k x k kernel and zero padding pad <= k - 1. */
+typedef struct {
+    int32_t kind, batch, c_in, c_out, h, w, k, pad;
+} pencil_layer;
+
+/* Partition of one product into N-slot tiles (App. A: larger operands "could be
+ * partitioned").  The product is the packed correlation
+ *   out[m, r, y, x] = sum_{c, dy, dx} A[m, c, y+dy, x+dx] * K[r, c, dy, dx];
+ * a tile takes m x r x k of the (M, R, K) channels, an oh x ow output window and a
+ * kh x kw kernel window, and needs m*r*k*(oh+kh-1)*(ow+kw-1) <= N slots. */
+typedef struct {
+    int32_t m, r, k, oh, ow, kh, kw;
+} pencil_tile;
+
+typedef struct {
+    pencil_tile fwd, dx, dw;
+} pencil_plan;
+
+/* Ciphertext operands the DO encrypts (the four layouts of one layer-step). */
+typedef enum {
+    PENCIL_X_FWD = 0,  /* <X>_1,  forward-encoded A side of the forward product    */
+    PENCIL_DY_DX = 1,  /* <dY>_1, A side of the input-gradient product             */
+    PENCIL_X_DW = 2,   /* <X>_1,  A side of the weight-gradient product            */
+    PENCIL_DY_DW = 3   /* <dY>_1, reverse-encoded K side of the weight gradient    */
+} pencil_operand;
+
+typedef enum { PENCIL_OP_FWD = 0, PENCIL_OP_DX = 1, PENCIL_OP_DW = 2 } pencil_op;
+
+typedef struct {
+    uint64_t ct_bytes;       /* one ciphertext, 2 * L * N * 8                        */
+    uint64_t n_ct[4];        /* ciphertexts per pencil_operand                       */
+    uint64_t n_out[3];       /* output ciphertexts per pencil_op                     */
+    uint64_t n_pt[3];        /* plaintext polynomials per pencil_op (both dw terms)  */
+    uint64_t n_products[3];  /* plaintext x ciphertext products per pencil_op        */
+    uint64_t ws_fwd_bytes;   /* workspace of pencil_linear_fwd                       */
+    uint64_t ws_bwd_bytes;   /* workspace of pencil_linear_bwd                       */
+    uint64_t ws_dec_bytes;   /* workspace of pencil_decrypt (largest op)             */
+    uint64_t ws_enc_bytes;   /* workspace of pencil_encrypt (largest operand)        */
+} pencil_sizes;
+
+/* Resolved parameters of a context (host). */
+typedef struct {
+    uint32_t log2_n, num_limbs, flood_bits, reserved;
+    uint64_t primes[4];
+    uint64_t psi[4];         /* the smallest primitive 2N-th root of unity per limb  */
+    uint64_t t;
+    uint64_t seed;
+} pencil_info;
+
+/* Create a context: resolve parameters, build NTT tables, and generate the key
+ * pair on the GPU (KeyGen of BFV: s ternary, pk = (-(a s + e), a)).
+ * Synchronous.  The current HIP device is used and must stay current for
+ * every later call on the context. */
+pencil_status pencil_ctx_create(const pencil_params* params, pencil_ctx** out);
+pencil_status pencil_ctx_destroy(pencil_ctx* ctx);
+const char* pencil_last_error(const pencil_ctx* ctx);
+pencil_status pencil_ctx_info(const pencil_ctx* ctx, pencil_info* out /* host */);
+
+/* Secret key (N int64 in {-1, 0, 1}) and public key ([2][L][N] uint64,
+ * coefficient domain) copied to host memory.  The secret key belongs to the
+ * DO role; this call exists for tests and for a DO that persists its key.
+ * Synchronous. */
+pencil_status pencil_export_keys(const pencil_ctx* ctx, int64_t* sk /* host */, uint64_t* pk /* host */);
+
+/* Choose a partition for each product of `layer` (deterministic cost model;
+ * host only). */
+pencil_status pencil_plan_auto(const pencil_ctx* ctx, const pencil_layer* layer, pencil_plan* plan /* host */);
+
+/* Buffer sizes for `layer` under `plan` (host).  A product whose tile is all
+ * zero is treated as not planned and reported with zero sizes. */
+pencil_status pencil_layout(const pencil_ctx* ctx, const pencil_layer* layer, const pencil_plan* plan,
+                            pencil_sizes* sizes /* host */);
+
+/* DO: encode its share (int64 [0,t), the tensor the operand is built from: X for
+ * X_FWD / X_DW, dY for DY_DX / DY_DW) with the operand's layout and encrypt it
+ * under the public key (ct = (p0 u + e0 + round(q m / t), p1 u + e1)).
+ * ct receives n_ct[operand] ciphertexts; ws: ws_enc_bytes of device memory. */
+pencil_status pencil_encrypt(pencil_ctx* ctx, const pencil_layer* layer, const pencil_plan* plan,
+                             int operand, const int64_t* share, uint64_t* ct, void* ws, uint64_t nonce,
+                             void* stream);
+
+/* MO: forward product of Alg. 1.  ct_x1: n_ct[X_FWD] ciphertexts of <X>_1;
+ * x0: the MO's share of X; w: weights; bias: int64 [c_out] at the output's
+ * scale, or NULL.  Writes ct_y (n_out[FWD] ciphertexts for the DO) and y0, the
+ * MO's share of Y (same shape as Y).  ws: ws_fwd_bytes of device memory. */
+pencil_status pencil_linear_fwd(pencil_ctx* ctx, const pencil_layer* layer, const pencil_plan* plan,
+                                const uint64_t* ct_x1, const int64_t* x0, const int64_t* w, const int64_t* bias,
+                                uint64_t* ct_y, int64_t* y0, void* ws, uint64_t nonce, void* stream);
+
+/* MO: backward products.  Input gradient (Sec. III.B.2): ct_dy_dx holds <dY>_1
+ * in DY_DX layout, dy0 is the MO's share; writes ct_dx (for the DO) and dx0.
+ * Weight-gradient cross terms (Alg. 2): ct_x_dw (<X>_1, X_DW layout) and
+ * ct_dy_dw (<dY>_1, DY_DW layout) with the MO's shares dy0 and x0; writes
+ * ct_dw and dw_mask, the MO's mask s shaped like W.  After decryption,
+ * dec(ct_dw) + dw_mask = <dY>_0 o <X>_1 + <dY>_1 o <X>_0 (mod t).
+ * Either product may be skipped by passing NULL for its outputs. */
+pencil_status pencil_linear_bwd(pencil_ctx* ctx, const pencil_layer* layer, const pencil_plan* plan,
+                                const uint64_t* ct_dy_dx, const uint64_t* ct_x_dw, const uint64_t* ct_dy_dw,
+                                const int64_t* dy0, const int64_t* x0, const int64_t* w,
+                                uint64_t* ct_dx, int64_t* dx0, uint64_t* ct_dw, int64_t* dw_mask,
+                                void* ws, uint64_t nonce, void* stream);
+
+/* DO: decrypt the n_out[op] output ciphertexts of product `op`
+ * (m = round(t [c0 + c1 s]_q / q) mod t, exact CRT) and gather the output
+ * slots into share (shaped like Y, dX or W).  ws: ws_dec_bytes. */
+pencil_status pencil_decrypt(pencil_ctx* ctx, const pencil_layer* layer, const pencil_plan* plan, int op,
+                             const uint64_t* ct, int64_t* share, void* ws, void* stream);
+
+/* Negacyclic NTT of `count` polynomials laid out [count][L][N] (limb l of each
+ * polynomial mod q_l), in place.  The transform domain is this library's
+ * internal order: entry i of the forward transform holds the evaluation at
+ * psi^(2 rev(i) + 1), rev = bit reversal of log2 N bits (Sec. V). */
+pencil_status pencil_ntt_forward(pencil_ctx* ctx, uint64_t* polys, int64_t count, void* stream);
+pencil_status pencil_ntt_inverse(pencil_ctx* ctx, uint64_t* polys, int64_t count, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PENCIL_H */

@@ -1,0 +1,209 @@
+"""Thin Python binding over the C ABI.  PyTorch provides device memory and the
+stream; every step of the product runs in libpencil.so's HIP kernels.
+
+Ciphertexts are held in int64 tensors whose bits are the uint64 residues
+([n][2][L][N]); Z_t tensors are int64 in [0, t).
+"""
+import ctypes
+
+import torch
+
+from . import _abi as A
+
+OPERANDS = {"x_fwd": A.X_FWD, "dy_dx": A.DY_DX, "x_dw": A.X_DW, "dy_dw": A.DY_DW}
+OPS = {"fwd": A.OP_FWD, "dx": A.OP_DX, "dw": A.OP_DW}
+
+
+def layer_struct(layer):
+    """A pencil_layer from a LayerSpec-like object (kind 'fc' / 'conv') or a dict."""
+    get = (lambda k: layer[k]) if isinstance(layer, dict) else (lambda k: getattr(layer, k))
+    kind = get("kind")
+    kind = {"fc": 0, "conv": 1}.get(kind, kind)
+    return A.Layer(int(kind), get("batch"), get("c_in"), get("c_out"), get("h"), get("w"), get("k"), get("pad"))
+
+
+def tile_struct(t):
+    return A.Tile(*(int(v) for v in t))
+
+
+def plan_struct(plan):
+    """From {'fwd': (m,r,k,oh,ow,kh,kw), 'dx': ..., 'dw': ...}; a missing op gets
+    the all-zero tile, which marks it as not planned."""
+    if isinstance(plan, A.Plan):
+        return plan
+    zero = (0,) * 7
+    return A.Plan(tile_struct(plan.get("fwd", zero)), tile_struct(plan.get("dx", zero)),
+                  tile_struct(plan.get("dw", zero)))
+
+
+def plan_dict(p):
+    return {"fwd": p.fwd.astuple(), "dx": p.dx.astuple(), "dw": p.dw.astuple()}
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _need(t, name):
+    if t.device.type != "cuda" or not t.is_contiguous() or t.dtype != torch.int64:
+        raise ValueError(f"{name} must be a contiguous int64 CUDA tensor")
+
+
+class Context:
+    """A BFV parameter set, its key pair and NTT tables on the current GPU."""
+
+    def __init__(self, log2_n, num_limbs, prime_bits=60, seed=0, t=0, flood_bits=0, primes=None):
+        self.lib = A.load()
+        p = A.Params()
+        p.log2_n, p.num_limbs, p.prime_bits, p.flood_bits = log2_n, num_limbs, prime_bits, flood_bits
+        for i, q in enumerate(primes or []):
+            p.primes[i] = q
+        p.t, p.seed = t, seed
+        torch.cuda.init()
+        h = ctypes.c_void_p()
+        A.check(self.lib.pencil_ctx_create(ctypes.byref(p), ctypes.byref(h)), None)
+        self.h = h
+        info = A.Info()
+        self._check(self.lib.pencil_ctx_info(self.h, ctypes.byref(info)))
+        self.n = 1 << info.log2_n
+        self.L = info.num_limbs
+        self.t = info.t
+        self.flood_bits = info.flood_bits
+        self.primes = [info.primes[i] for i in range(self.L)]
+        self.psi = [info.psi[i] for i in range(self.L)]
+        self.seed = info.seed
+        self.device = torch.device("cuda", torch.cuda.current_device())
+
+    @classmethod
+    def for_layer(cls, layer, seed=0):
+        return cls(layer.log2_n, layer.num_limbs, layer.prime_bits, seed)
+
+    def _check(self, st):
+        A.check(st, self.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.pencil_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- host
+    def export_keys(self):
+        import numpy as np
+        sk = np.empty(self.n, dtype=np.int64)
+        pk = np.empty((2, self.L, self.n), dtype=np.uint64)
+        self._check(self.lib.pencil_export_keys(self.h, sk.ctypes.data_as(A.c_i64p), pk.ctypes.data_as(A.c_u64p)))
+        return sk, pk
+
+    def plan_auto(self, layer):
+        p = A.Plan()
+        self._check(self.lib.pencil_plan_auto(self.h, ctypes.byref(layer_struct(layer)), ctypes.byref(p)))
+        return p
+
+    def layout(self, layer, plan):
+        s = A.Sizes()
+        self._check(self.lib.pencil_layout(self.h, ctypes.byref(layer_struct(layer)),
+                                           ctypes.byref(plan_struct(plan)), ctypes.byref(s)))
+        return s
+
+    # ---------------------------------------------------------------- device
+    def _ws(self, nbytes):
+        return torch.empty(max(int(nbytes), 8), dtype=torch.uint8, device=self.device)
+
+    def empty_cts(self, count):
+        return torch.empty((int(count), 2, self.L, self.n), dtype=torch.int64, device=self.device)
+
+    def encrypt(self, layer, plan, operand, share, nonce, out=None, ws=None):
+        op = OPERANDS.get(operand, operand)
+        plan = plan_struct(plan)
+        sz = self.layout(layer, plan)
+        _need(share, "share")
+        out = self.empty_cts(sz.n_ct[op]) if out is None else out
+        ws = self._ws(sz.ws_enc_bytes) if ws is None else ws
+        self._check(self.lib.pencil_encrypt(self.h, ctypes.byref(layer_struct(layer)), ctypes.byref(plan), op,
+                                            _ptr(share), _ptr(out), _ptr(ws), nonce, _stream()))
+        return out
+
+    def linear_fwd(self, layer, plan, ct_x1, x0, w, nonce, bias=None, ws=None, out=None):
+        plan = plan_struct(plan)
+        sz = self.layout(layer, plan)
+        for t, nm in ((x0, "x0"), (w, "w")):
+            _need(t, nm)
+        ct_y = self.empty_cts(sz.n_out[0]) if out is None else out[0]
+        y0 = torch.empty(_y_shape(layer), dtype=torch.int64, device=self.device) if out is None else out[1]
+        ws = self._ws(sz.ws_fwd_bytes) if ws is None else ws
+        self._check(self.lib.pencil_linear_fwd(self.h, ctypes.byref(layer_struct(layer)), ctypes.byref(plan),
+                                               _ptr(ct_x1), _ptr(x0), _ptr(w), _ptr(bias), _ptr(ct_y), _ptr(y0),
+                                               _ptr(ws), nonce, _stream()))
+        return ct_y, y0
+
+    def linear_bwd(self, layer, plan, ct_dy_dx, ct_x_dw, ct_dy_dw, dy0, x0, w, nonce, ws=None, out=None,
+                   do_dx=True, do_dw=True):
+        plan = plan_struct(plan)
+        sz = self.layout(layer, plan)
+        ws = self._ws(sz.ws_bwd_bytes) if ws is None else ws
+        if out is None:
+            ct_dx = self.empty_cts(sz.n_out[1]) if do_dx else None
+            dx0 = torch.empty(_x_shape(layer), dtype=torch.int64, device=self.device) if do_dx else None
+            ct_dw = self.empty_cts(sz.n_out[2]) if do_dw else None
+            dwm = torch.empty(_w_shape(layer), dtype=torch.int64, device=self.device) if do_dw else None
+        else:
+            ct_dx, dx0, ct_dw, dwm = out
+        self._check(self.lib.pencil_linear_bwd(self.h, ctypes.byref(layer_struct(layer)), ctypes.byref(plan),
+                                               _ptr(ct_dy_dx), _ptr(ct_x_dw), _ptr(ct_dy_dw), _ptr(dy0), _ptr(x0),
+                                               _ptr(w), _ptr(ct_dx), _ptr(dx0), _ptr(ct_dw), _ptr(dwm), _ptr(ws),
+                                               nonce, _stream()))
+        return ct_dx, dx0, ct_dw, dwm
+
+    def decrypt(self, layer, plan, op, ct, ws=None):
+        opi = OPS.get(op, op)
+        plan = plan_struct(plan)
+        sz = self.layout(layer, plan)
+        shape = (_y_shape, _x_shape, _w_shape)[opi](layer)
+        share = torch.empty(shape, dtype=torch.int64, device=self.device)
+        ws = self._ws(sz.ws_dec_bytes) if ws is None else ws
+        self._check(self.lib.pencil_decrypt(self.h, ctypes.byref(layer_struct(layer)), ctypes.byref(plan), opi,
+                                            _ptr(ct), _ptr(share), _ptr(ws), _stream()))
+        return share
+
+    def ntt(self, polys, inverse=False):
+        """In-place negacyclic NTT of an int64 tensor [count][L][N] of residues."""
+        count = polys.numel() // (self.L * self.n)
+        fn = self.lib.pencil_ntt_inverse if inverse else self.lib.pencil_ntt_forward
+        self._check(fn(self.h, _ptr(polys), count, _stream()))
+        return polys
+
+
+def _get(layer, k):
+    return layer[k] if isinstance(layer, dict) else getattr(layer, k)
+
+
+def _is_fc(layer):
+    return _get(layer, "kind") in ("fc", 0)
+
+
+def _x_shape(layer):
+    B, ci = _get(layer, "batch"), _get(layer, "c_in")
+    return (B, ci) if _is_fc(layer) else (B, ci, _get(layer, "h"), _get(layer, "w"))
+
+
+def _y_shape(layer):
+    B, co = _get(layer, "batch"), _get(layer, "c_out")
+    if _is_fc(layer):
+        return (B, co)
+    h, w, k, p = _get(layer, "h"), _get(layer, "w"), _get(layer, "k"), _get(layer, "pad")
+    return (B, co, h + 2 * p - k + 1, w + 2 * p - k + 1)
+
+
+def _w_shape(layer):
+    ci, co = _get(layer, "c_in"), _get(layer, "c_out")
+    return (co, ci) if _is_fc(layer) else (co, ci, _get(layer, "k"), _get(layer, "k"))

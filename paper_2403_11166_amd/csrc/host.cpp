@@ -1,0 +1,837 @@
+// Host side of libpencil: parameter resolution, NTT tables, key generation,
+// tiling geometry, the packing planner, and the C ABI of include/pencil.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/pencil.h"
+#include "pencil_internal.h"
+
+namespace pencil {
+hipError_t configure_lds_limits();
+}
+
+using namespace pencil;
+typedef unsigned __int128 u128;
+
+// ----------------------------------------------------------------- context
+
+struct pencil_ctx {
+  pencil_info info{};
+  Consts C{};
+  Tables T{};
+  int device = 0;
+  // device memory owned by the context
+  uint64_t* d_tables = nullptr;  // psi, psi_sh, ipsi, ipsi_sh: 4 x [L][N]
+  uint64_t* d_s_ntt = nullptr;   // [L][N]
+  uint64_t* d_s_sh = nullptr;    // [L][N]
+  uint64_t* d_pk_ntt = nullptr;  // [2][L][N]
+  uint64_t* d_pk_sh = nullptr;   // [2][L][N]
+  uint64_t* d_pk_coeff = nullptr;
+  int64_t* d_s_coeff = nullptr;
+  std::string err;
+};
+
+static thread_local std::string g_create_err;
+
+static pencil_status fail(pencil_ctx* ctx, pencil_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (ctx)
+    ctx->err = buf;
+  else
+    g_create_err = buf;
+  return st;
+}
+
+#define HIP_TRY(ctx, expr)                                                                   \
+  do {                                                                                       \
+    hipError_t _e = (expr);                                                                  \
+    if (_e != hipSuccess) return fail(ctx, PENCIL_EHIP, "%s: %s", #expr, hipGetErrorString(_e)); \
+  } while (0)
+
+// ------------------------------------------------------------ number theory
+
+static uint64_t mulmod(uint64_t a, uint64_t b, uint64_t m) { return (uint64_t)((u128)a * b % m); }
+
+static uint64_t powmod(uint64_t b, uint64_t e, uint64_t m) {
+  uint64_t r = 1 % m;
+  b %= m;
+  while (e) {
+    if (e & 1) r = mulmod(r, b, m);
+    b = mulmod(b, b, m);
+    e >>= 1;
+  }
+  return r;
+}
+
+// Deterministic Miller-Rabin for 64-bit n (these bases decide every n < 2^64).
+static bool is_prime(uint64_t n) {
+  if (n < 2) return false;
+  static const uint64_t bases[] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37};
+  for (uint64_t p : bases)
+    if (n % p == 0) return n == p;
+  uint64_t d = n - 1;
+  int r = 0;
+  while ((d & 1) == 0) {
+    d >>= 1;
+    ++r;
+  }
+  for (uint64_t a : bases) {
+    uint64_t x = powmod(a, d, n);
+    if (x == 1 || x == n - 1) continue;
+    bool comp = true;
+    for (int i = 1; i < r; ++i) {
+      x = mulmod(x, x, n);
+      if (x == n - 1) {
+        comp = false;
+        break;
+      }
+    }
+    if (comp) return false;
+  }
+  return true;
+}
+
+static uint64_t shoup(uint64_t w, uint64_t q) { return (uint64_t)(((u128)w << 64) / q); }
+
+// Smallest primitive 2N-th root of unity mod q: find one root, then the least of its odd powers.
+static uint64_t min_root(uint64_t q, uint64_t n) {
+  uint64_t psi = 0;
+  for (uint64_t g = 2; g < (1u << 20); ++g) {
+    uint64_t c = powmod(g, (q - 1) / (2 * n), q);
+    if (powmod(c, n, q) == q - 1) {
+      psi = c;
+      break;
+    }
+  }
+  uint64_t best = psi, sq = mulmod(psi, psi, q), cur = psi;
+  for (uint64_t i = 0; i < n; ++i) {
+    if (cur < best) best = cur;
+    cur = mulmod(cur, sq, q);
+  }
+  return best;
+}
+
+// Little-endian multiword integers.
+typedef std::vector<uint64_t> Big;
+
+static void big_trim(Big& a) {
+  while (a.size() > 1 && a.back() == 0) a.pop_back();
+}
+static Big big_mul_small(const Big& a, uint64_t m) {
+  Big r(a.size() + 1, 0);
+  u128 carry = 0;
+  for (size_t i = 0; i < a.size(); ++i) {
+    u128 p = (u128)a[i] * m + carry;
+    r[i] = (uint64_t)p;
+    carry = p >> 64;
+  }
+  r[a.size()] = (uint64_t)carry;
+  big_trim(r);
+  return r;
+}
+static uint64_t big_mod_small(const Big& a, uint64_t m) {
+  u128 r = 0;
+  for (size_t i = a.size(); i-- > 0;) r = ((r << 64) | a[i]) % m;
+  return (uint64_t)r;
+}
+static Big big_div_small(const Big& a, uint64_t m) {
+  Big q(a.size(), 0);
+  u128 r = 0;
+  for (size_t i = a.size(); i-- > 0;) {
+    u128 cur = (r << 64) | a[i];
+    q[i] = (uint64_t)(cur / m);
+    r = cur % m;
+  }
+  big_trim(q);
+  return q;
+}
+static int big_bits(const Big& a) {
+  for (size_t i = a.size(); i-- > 0;)
+    if (a[i]) return (int)(64 * i + 64 - __builtin_clzll(a[i]));
+  return 0;
+}
+
+// ------------------------------------------------------------ context create
+
+static pencil_status resolve_params(const pencil_params* p, pencil_ctx* ctx) {
+  if (!p) return fail(nullptr, PENCIL_EINVAL, "params is NULL");
+  if (p->log2_n < 10 || p->log2_n > 14) return fail(nullptr, PENCIL_EINVAL, "log2_n %u outside [10, 14]", p->log2_n);
+  if (p->num_limbs < 1 || p->num_limbs > (uint32_t)kMaxLimbs)
+    return fail(nullptr, PENCIL_EINVAL, "num_limbs %u outside [1, %d]", p->num_limbs, kMaxLimbs);
+  const uint64_t n = 1ull << p->log2_n;
+  pencil_info& I = ctx->info;
+  I.log2_n = p->log2_n;
+  I.num_limbs = p->num_limbs;
+  I.seed = p->seed;
+  // plaintext modulus
+  uint64_t t = p->t;
+  if (t == 0) {
+    t = (1ull << 41) - 1;
+    while (!is_prime(t)) t -= 2;
+  }
+  if (t < 3 || t >= (1ull << 48) || !is_prime(t)) return fail(nullptr, PENCIL_EINVAL, "t must be an odd prime < 2^48");
+  I.t = t;
+  // RNS primes
+  if (p->primes[0] == 0) {
+    if (p->prime_bits < 40 || p->prime_bits > 60)
+      return fail(nullptr, PENCIL_EINVAL, "prime_bits %u outside [40, 60]", p->prime_bits);
+    const uint64_t step = 1ull << 15;
+    uint64_t q = (((1ull << p->prime_bits) - 1) / step) * step + 1;
+    if (q >= (1ull << p->prime_bits)) q -= step;
+    for (uint32_t l = 0; l < p->num_limbs; q -= step) {
+      if (is_prime(q)) I.primes[l++] = q;
+    }
+  } else {
+    for (uint32_t l = 0; l < p->num_limbs; ++l) {
+      uint64_t q = p->primes[l];
+      if (q == 0 || q >= (1ull << 61) || !is_prime(q) || (q - 1) % (2 * n) != 0)
+        return fail(nullptr, PENCIL_EINVAL, "prime %u (%llu) must be a prime < 2^61 with q = 1 mod 2N", l,
+                    (unsigned long long)q);
+      for (uint32_t k = 0; k < l; ++k)
+        if (I.primes[k] == q) return fail(nullptr, PENCIL_EINVAL, "repeated prime");
+      I.primes[l] = q;
+    }
+  }
+  for (uint32_t l = 0; l < p->num_limbs; ++l)
+    if (I.primes[l] <= t) return fail(nullptr, PENCIL_EINVAL, "every q_l must exceed t");
+  // q, Delta, flood width
+  Big q{1};
+  for (uint32_t l = 0; l < p->num_limbs; ++l) q = big_mul_small(q, I.primes[l]);
+  if (big_bits(q) > 64 * (kMaxWords - 1) - 4) return fail(nullptr, PENCIL_EINVAL, "q too large");
+  Big delta = big_div_small(q, t);
+  const int dbits = big_bits(delta);
+  if (dbits < 8) return fail(nullptr, PENCIL_EINVAL, "q / t too small for any noise budget");
+  uint32_t fb = p->flood_bits ? p->flood_bits : (uint32_t)(dbits - 1 - 3);
+  if (fb + 1 > 256) return fail(nullptr, PENCIL_EINVAL, "flood_bits too large");
+  I.flood_bits = fb;
+
+  Consts& C = ctx->C;
+  C.log2n = (int32_t)p->log2_n;
+  C.n = (int32_t)n;
+  C.L = (int32_t)p->num_limbs;
+  C.flood_bits = fb;
+  C.flood_words = (int32_t)((fb + 1 + 63) / 64);
+  const int topbits = (int)(fb + 1) - 64 * (C.flood_words - 1);
+  C.top_mask = topbits >= 64 ? ~0ull : ((1ull << topbits) - 1);
+  C.t = t;
+  C.t_half = (t - 1) / 2;
+  C.rho = big_mod_small(q, t);
+  C.rho_sh = shoup(C.rho, t);
+  C.r64t = (uint64_t)(((u128)1 << 64) % t);
+  C.r64t_sh = shoup(C.r64t, t);
+  C.one_sh_t = (uint64_t)((((u128)1) << 64) / t);
+  C.seed = p->seed;
+  int maxbits = 0;
+  for (int l = 0; l < C.L; ++l) {
+    const uint64_t ql = I.primes[l];
+    LimbConst& lc = C.limb[l];
+    lc.q = ql;
+    lc.r64 = (uint64_t)(((u128)1 << 64) % ql);
+    lc.r64_sh = shoup(lc.r64, ql);
+    lc.one_sh = (uint64_t)((((u128)1) << 64) / ql);
+    lc.ninv = powmod(n, ql - 2, ql);
+    lc.ninv_sh = shoup(lc.ninv, ql);
+    lc.delta = big_mod_small(delta, ql);
+    lc.delta_sh = shoup(lc.delta, ql);
+    lc.t_sh = shoup(t, ql);
+    Big qhat = big_div_small(q, ql);
+    uint64_t qhat_mod = big_mod_small(qhat, ql);
+    lc.qhat_inv = powmod(qhat_mod, ql - 2, ql);
+    lc.qhat_inv_sh = shoup(lc.qhat_inv, ql);
+    lc.flood_off = powmod(2, fb, ql);
+    // floor(2^128 / q): long division of 2^128 by q
+    u128 hi_part = (((u128)1) << 64) / ql;  // floor(2^64 / q) -> upper word of the quotient
+    u128 rem = (((u128)1) << 64) % ql;
+    u128 lo_part = (rem << 64) / ql;
+    lc.mu_hi = (uint64_t)hi_part;
+    lc.mu_lo = (uint64_t)lo_part;
+    for (int w = 0; w < kMaxWords; ++w) C.qhat[l][w] = w < (int)qhat.size() ? qhat[w] : 0;
+    Big th = big_mul_small(q, 2 * (uint64_t)l + 1);
+    for (int w = 0; w < kMaxWords; ++w) C.thr[l][w] = w < (int)th.size() ? th[w] : 0;
+    maxbits = std::max(maxbits, 64 - __builtin_clzll(ql));
+    I.psi[l] = min_root(ql, n);
+  }
+  // 128-bit accumulator headroom: c products below 2^(2 maxbits) plus a reduced
+  // residue stay below 2^128 when c <= 2^(127 - 2 maxbits); maxbits <= 61.
+  const int head = 127 - 2 * maxbits;
+  C.mac_chunk = head >= 7 ? 128u : (1u << head);
+  C.qwords = (uint32_t)q.size();
+  return PENCIL_OK;
+}
+
+static uint32_t bitrev(uint32_t x, int bits) {
+  uint32_t r = 0;
+  for (int i = 0; i < bits; ++i) r |= ((x >> i) & 1u) << (bits - 1 - i);
+  return r;
+}
+
+extern "C" pencil_status pencil_ctx_create(const pencil_params* params, pencil_ctx** out) {
+  if (!out) return fail(nullptr, PENCIL_EINVAL, "out is NULL");
+  *out = nullptr;
+  pencil_ctx* ctx = new pencil_ctx();
+  pencil_status st = resolve_params(params, ctx);
+  if (st != PENCIL_OK) {
+    delete ctx;
+    return st;
+  }
+  const Consts& C = ctx->C;
+  const size_t n = (size_t)C.n, L = (size_t)C.L;
+  // NTT tables
+  std::vector<uint64_t> tab(4 * L * n);
+  for (size_t l = 0; l < L; ++l) {
+    const uint64_t q = C.limb[l].q, psi = ctx->info.psi[l], ipsi = powmod(psi, q - 2, q);
+    for (size_t k = 0; k < n; ++k) {
+      uint32_t e = bitrev((uint32_t)k, C.log2n);
+      uint64_t w = powmod(psi, e, q), iw = powmod(ipsi, e, q);
+      tab[0 * L * n + l * n + k] = w;
+      tab[1 * L * n + l * n + k] = shoup(w, q);
+      tab[2 * L * n + l * n + k] = iw;
+      tab[3 * L * n + l * n + k] = shoup(iw, q);
+    }
+  }
+  auto cleanup = [&](pencil_status s) {
+    pencil_ctx_destroy(ctx);
+    return s;
+  };
+  if (hipGetDevice(&ctx->device) != hipSuccess) return cleanup(fail(nullptr, PENCIL_EHIP, "no HIP device"));
+  if (configure_lds_limits() != hipSuccess) return cleanup(fail(nullptr, PENCIL_EHIP, "cannot raise LDS limit"));
+  const size_t ln = L * n * sizeof(uint64_t);
+  if (hipMalloc(&ctx->d_tables, 4 * ln) != hipSuccess || hipMalloc(&ctx->d_s_ntt, ln) != hipSuccess ||
+      hipMalloc(&ctx->d_s_sh, ln) != hipSuccess || hipMalloc(&ctx->d_pk_ntt, 2 * ln) != hipSuccess ||
+      hipMalloc(&ctx->d_pk_sh, 2 * ln) != hipSuccess || hipMalloc(&ctx->d_pk_coeff, 2 * ln) != hipSuccess ||
+      hipMalloc(&ctx->d_s_coeff, n * sizeof(int64_t)) != hipSuccess)
+    return cleanup(fail(nullptr, PENCIL_ENOMEM, "device allocation failed"));
+  if (hipMemcpy(ctx->d_tables, tab.data(), 4 * ln, hipMemcpyHostToDevice) != hipSuccess)
+    return cleanup(fail(nullptr, PENCIL_EHIP, "table upload failed"));
+  ctx->T.psi = ctx->d_tables;
+  ctx->T.psi_sh = ctx->d_tables + L * n;
+  ctx->T.ipsi = ctx->d_tables + 2 * L * n;
+  ctx->T.ipsi_sh = ctx->d_tables + 3 * L * n;
+  // keys
+  if (launch_keygen(ctx->d_s_ntt, ctx->d_s_coeff, ctx->d_pk_coeff, ctx->d_pk_ntt, C, ctx->T, nullptr) != hipSuccess ||
+      hipDeviceSynchronize() != hipSuccess)
+    return cleanup(fail(nullptr, PENCIL_EHIP, "key generation failed"));
+  // Shoup companions of the fixed multiplicands s^ and pk^
+  std::vector<uint64_t> h(2 * L * n), hs(2 * L * n);
+  if (hipMemcpy(h.data(), ctx->d_s_ntt, ln, hipMemcpyDeviceToHost) != hipSuccess)
+    return cleanup(fail(nullptr, PENCIL_EHIP, "key download failed"));
+  for (size_t l = 0; l < L; ++l)
+    for (size_t i = 0; i < n; ++i) hs[l * n + i] = shoup(h[l * n + i], C.limb[l].q);
+  if (hipMemcpy(ctx->d_s_sh, hs.data(), ln, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(h.data(), ctx->d_pk_ntt, 2 * ln, hipMemcpyDeviceToHost) != hipSuccess)
+    return cleanup(fail(nullptr, PENCIL_EHIP, "key transfer failed"));
+  for (size_t c = 0; c < 2; ++c)
+    for (size_t l = 0; l < L; ++l)
+      for (size_t i = 0; i < n; ++i) hs[(c * L + l) * n + i] = shoup(h[(c * L + l) * n + i], C.limb[l].q);
+  if (hipMemcpy(ctx->d_pk_sh, hs.data(), 2 * ln, hipMemcpyHostToDevice) != hipSuccess)
+    return cleanup(fail(nullptr, PENCIL_EHIP, "key upload failed"));
+  *out = ctx;
+  return PENCIL_OK;
+}
+
+extern "C" pencil_status pencil_ctx_destroy(pencil_ctx* ctx) {
+  if (!ctx) return PENCIL_OK;
+  hipFree(ctx->d_tables);
+  hipFree(ctx->d_s_ntt);
+  hipFree(ctx->d_s_sh);
+  hipFree(ctx->d_pk_ntt);
+  hipFree(ctx->d_pk_sh);
+  hipFree(ctx->d_pk_coeff);
+  hipFree(ctx->d_s_coeff);
+  delete ctx;
+  return PENCIL_OK;
+}
+
+extern "C" const char* pencil_last_error(const pencil_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : g_create_err.c_str();
+}
+
+extern "C" pencil_status pencil_ctx_info(const pencil_ctx* ctx, pencil_info* out) {
+  if (!ctx || !out) return PENCIL_EINVAL;
+  *out = ctx->info;
+  return PENCIL_OK;
+}
+
+extern "C" pencil_status pencil_export_keys(const pencil_ctx* ctx, int64_t* sk, uint64_t* pk) {
+  if (!ctx) return PENCIL_EINVAL;
+  pencil_ctx* c = const_cast<pencil_ctx*>(ctx);
+  const size_t n = (size_t)ctx->C.n, L = (size_t)ctx->C.L;
+  if (sk) HIP_TRY(c, hipMemcpy(sk, ctx->d_s_coeff, n * sizeof(int64_t), hipMemcpyDeviceToHost));
+  if (pk) HIP_TRY(c, hipMemcpy(pk, ctx->d_pk_coeff, 2 * L * n * sizeof(uint64_t), hipMemcpyDeviceToHost));
+  return PENCIL_OK;
+}
+
+// ------------------------------------------------------------ geometry
+
+struct OpGeom {
+  int M, R, K, HA, WA, KH, KW;
+  int OH() const { return HA - KH + 1; }
+  int OW() const { return WA - KW + 1; }
+};
+
+static bool layer_ok(pencil_ctx* ctx, const pencil_layer* L, pencil_status* st) {
+  if (!L) {
+    *st = fail(ctx, PENCIL_EINVAL, "layer is NULL");
+    return false;
+  }
+  if (L->kind != 0 && L->kind != 1) {
+    *st = fail(ctx, PENCIL_EINVAL, "layer kind must be 0 (fc) or 1 (conv)");
+    return false;
+  }
+  if (L->batch < 1 || L->c_in < 1 || L->c_out < 1 || L->h < 1 || L->w < 1 || L->k < 1 || L->pad < 0) {
+    *st = fail(ctx, PENCIL_EINVAL, "layer dimensions must be positive");
+    return false;
+  }
+  if (L->kind == 0 && (L->h != 1 || L->w != 1 || L->k != 1 || L->pad != 0)) {
+    *st = fail(ctx, PENCIL_EINVAL, "fc layers need h = w = k = 1, pad = 0");
+    return false;
+  }
+  if (L->pad > L->k - 1) {
+    *st = fail(ctx, PENCIL_EUNSUPPORTED, "padding above k - 1 is not supported");
+    return false;
+  }
+  if (L->h + 2 * L->pad < L->k || L->w + 2 * L->pad < L->k) {
+    *st = fail(ctx, PENCIL_EINVAL, "kernel larger than padded input");
+    return false;
+  }
+  const int64_t big = (int64_t)1 << 31;
+  if ((int64_t)L->batch * L->c_in * L->h * L->w >= big || (int64_t)L->c_out * L->c_in * L->k * L->k >= big) {
+    *st = fail(ctx, PENCIL_EINVAL, "layer too large");
+    return false;
+  }
+  return true;
+}
+
+static OpGeom op_geom(const pencil_layer* L, int op) {
+  const int ho = L->h + 2 * L->pad - L->k + 1, wo = L->w + 2 * L->pad - L->k + 1;
+  const int qd = L->k - 1 - L->pad;
+  switch (op) {
+    case PENCIL_OP_FWD: return {L->batch, L->c_out, L->c_in, L->h + 2 * L->pad, L->w + 2 * L->pad, L->k, L->k};
+    case PENCIL_OP_DX: return {L->batch, L->c_in, L->c_out, ho + 2 * qd, wo + 2 * qd, L->k, L->k};
+    default: return {L->c_in, L->c_out, L->batch, L->h + 2 * L->pad, L->w + 2 * L->pad, ho, wo};
+  }
+}
+
+static int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+static bool make_geo(const OpGeom& g, const pencil_tile& t, int n, Geo* G) {
+  if (t.m < 1 || t.r < 1 || t.k < 1 || t.oh < 1 || t.ow < 1 || t.kh < 1 || t.kw < 1) return false;
+  if (t.m > g.M || t.r > g.R || t.k > g.K || t.oh > g.OH() || t.ow > g.OW() || t.kh > g.KH || t.kw > g.KW)
+    return false;
+  const int64_t ha = t.oh + t.kh - 1, wa = t.ow + t.kw - 1;
+  if ((int64_t)t.m * t.r * t.k * ha * wa > n) return false;
+  Geo& o = *G;
+  o = Geo{};
+  o.M = g.M; o.R = g.R; o.K = g.K; o.HA = g.HA; o.WA = g.WA; o.KH = g.KH; o.KW = g.KW;
+  o.OH = g.OH(); o.OW = g.OW();
+  o.mt = t.m; o.rt = t.r; o.kt = t.k; o.oh = t.oh; o.ow = t.ow; o.kh = t.kh; o.kw = t.kw;
+  o.ha = (int)ha; o.wa = (int)wa;
+  o.nM = cdiv(g.M, t.m); o.nR = cdiv(g.R, t.r); o.nK = cdiv(g.K, t.k);
+  o.nOY = cdiv(o.OH, t.oh); o.nOX = cdiv(o.OW, t.ow); o.nKY = cdiv(g.KH, t.kh); o.nKX = cdiv(g.KW, t.kw);
+  o.S = t.k * o.ha * o.wa;
+  o.RS = t.r * o.S;
+  o.O = (t.k - 1) * o.ha * o.wa + (t.kh - 1) * o.wa + t.kw - 1;
+  return true;
+}
+
+static int64_t n_a_tiles(const Geo& G) { return (int64_t)G.nM * G.nK * G.nOY * G.nOX * G.nKY * G.nKX; }
+static int64_t n_k_tiles(const Geo& G) { return (int64_t)G.nR * G.nK * G.nKY * G.nKX; }
+static int64_t n_out_tiles(const Geo& G) { return (int64_t)G.nM * G.nR * G.nOY * G.nOX; }
+static int64_t n_products(const Geo& G) { return n_out_tiles(G) * G.nK * G.nKY * G.nKX; }
+
+// Tensor views (strides into the caller's PyTorch-layout tensors).
+static View view_a(const pencil_layer* L, int op) {
+  const int64_t h = L->h, w = L->w, ci = L->c_in, co = L->c_out;
+  const int64_t ho = L->h + 2 * L->pad - L->k + 1, wo = L->w + 2 * L->pad - L->k + 1;
+  View v{};
+  v.sx = 1;
+  if (op == PENCIL_OP_FWD) {  // x [B][ci][h][w], (m, k) = (b, ci)
+    v.s0 = ci * h * w; v.s1 = h * w; v.sy = w; v.pad = L->pad; v.H = (int)h; v.W = (int)w;
+  } else if (op == PENCIL_OP_DX) {  // dy [B][co][ho][wo], (m, k) = (b, co)
+    v.s0 = co * ho * wo; v.s1 = ho * wo; v.sy = wo; v.pad = L->k - 1 - L->pad; v.H = (int)ho; v.W = (int)wo;
+  } else {  // x viewed (ci, B): (m, k) = (ci, b)
+    v.s0 = h * w; v.s1 = ci * h * w; v.sy = w; v.pad = L->pad; v.H = (int)h; v.W = (int)w;
+  }
+  return v;
+}
+
+static View view_k(const pencil_layer* L, int op) {
+  const int64_t s = L->k, ci = L->c_in, co = L->c_out;
+  const int64_t ho = L->h + 2 * L->pad - L->k + 1, wo = L->w + 2 * L->pad - L->k + 1;
+  View v{};
+  v.sx = 1;
+  if (op == PENCIL_OP_FWD) {  // W [co][ci][s][s], (r, k) = (co, ci)
+    v.s0 = ci * s * s; v.s1 = s * s; v.sy = s;
+  } else if (op == PENCIL_OP_DX) {  // W viewed (ci, co), flipped
+    v.s0 = s * s; v.s1 = ci * s * s; v.sy = s; v.flip = 1; v.KH = (int)s; v.KW = (int)s;
+  } else {  // dy viewed (co, B): (r, k) = (co, b)
+    v.s0 = ho * wo; v.s1 = co * ho * wo; v.sy = wo;
+  }
+  return v;
+}
+
+static View view_out(const pencil_layer* L, int op) {
+  const int64_t h = L->h, w = L->w, s = L->k, ci = L->c_in, co = L->c_out;
+  const int64_t ho = L->h + 2 * L->pad - L->k + 1, wo = L->w + 2 * L->pad - L->k + 1;
+  View v{};
+  v.sx = 1;
+  if (op == PENCIL_OP_FWD) {  // Y [B][co][ho][wo]
+    v.s0 = co * ho * wo; v.s1 = ho * wo; v.sy = wo;
+  } else if (op == PENCIL_OP_DX) {  // dX [B][ci][h][w]
+    v.s0 = ci * h * w; v.s1 = h * w; v.sy = w;
+  } else {  // dW [co][ci][s][s] with (m, r) = (ci, co)
+    v.s0 = s * s; v.s1 = ci * s * s; v.sy = s;
+  }
+  return v;
+}
+
+static const pencil_tile& plan_tile(const pencil_plan* P, int op) {
+  return op == PENCIL_OP_FWD ? P->fwd : op == PENCIL_OP_DX ? P->dx : P->dw;
+}
+
+static pencil_status get_geo(pencil_ctx* ctx, const pencil_layer* L, const pencil_plan* P, int op, Geo* G) {
+  pencil_status st = PENCIL_OK;
+  if (!layer_ok(ctx, L, &st)) return st;
+  if (!P) return fail(ctx, PENCIL_EINVAL, "plan is NULL");
+  const pencil_tile& t = plan_tile(P, op);
+  if (!make_geo(op_geom(L, op), t, ctx->C.n, G))
+    return fail(ctx, PENCIL_EINVAL, "op %d: tile (%d,%d,%d,%d,%d,%d,%d) is invalid or exceeds N=%d slots", op, t.m,
+                t.r, t.k, t.oh, t.ow, t.kh, t.kw, ctx->C.n);
+  if (n_out_tiles(*G) > (1ll << 40) || n_a_tiles(*G) > (1ll << 40)) return fail(ctx, PENCIL_EINVAL, "too many tiles");
+  return PENCIL_OK;
+}
+
+// ------------------------------------------------------------ planner
+
+// Work model, in units of one pointwise product-accumulate of one residue:
+// an NTT of one limb-polynomial costs about (N/2) log2 N Shoup butterflies of
+// ~2.5 units each; a product costs 2 components per limb.  HBM traffic is
+// charged through the polynomials read and written.
+struct Cost {
+  double ntt_polys, products;
+};
+
+static Cost op_cost(const Geo& G, int op) {
+  Cost c{};
+  const double na = (double)n_a_tiles(G), nk = (double)n_k_tiles(G), no = (double)n_out_tiles(G);
+  if (op == PENCIL_OP_DW) {
+    c.ntt_polys = 3 * na + 3 * nk + 3 * no;  // x1 ct + x0 pt, dy0 pt + dy1 ct, outputs + u'
+    c.products = 2.0 * (double)n_products(G);
+  } else {
+    c.ntt_polys = 2 * na + nk + 3 * no;
+    c.products = (double)n_products(G);
+  }
+  return c;
+}
+
+static double cost_value(const Cost& c, int log2n) {
+  const double n = (double)(1 << log2n);
+  return c.ntt_polys * (n / 2) * log2n * 2.5 + c.products * 2 * n;
+}
+
+// Candidate tile sizes along a dimension of extent D: the smallest size for each
+// distinct tile count.
+static std::vector<int> sizes_for(int D) {
+  std::vector<int> out;
+  int last = -1;
+  for (int cnt = 1; cnt <= D; ++cnt) {
+    int s = cdiv(D, cnt);
+    if (s != last) {
+      out.push_back(s);
+      last = s;
+    }
+  }
+  return out;
+}
+
+static bool plan_op(const pencil_layer* L, int op, int log2n, pencil_tile* best) {
+  const OpGeom g = op_geom(L, op);
+  const int n = 1 << log2n;
+  double best_cost = 1e300;
+  bool found = false;
+  const bool kernel_tiled = op == PENCIL_OP_DW && g.KH > 1;
+  std::vector<int> ms = sizes_for(g.M), rs = sizes_for(g.R);
+  std::vector<int> ys = kernel_tiled ? sizes_for(g.KH) : sizes_for(g.OH());
+  std::vector<int> xs = kernel_tiled ? sizes_for(g.KW) : sizes_for(g.OW());
+  for (int ty : ys)
+    for (int tx : xs) {
+      pencil_tile t{};
+      if (kernel_tiled) {
+        t.oh = g.OH(); t.ow = g.OW(); t.kh = ty; t.kw = tx;
+      } else {
+        t.oh = ty; t.ow = tx; t.kh = g.KH; t.kw = g.KW;
+      }
+      const int64_t hw = (int64_t)(t.oh + t.kh - 1) * (t.ow + t.kw - 1);
+      if (hw > n) continue;
+      for (int m : ms)
+        for (int r : rs) {
+          int64_t room = n / (hw * m * r);
+          if (room < 1) continue;
+          int k = (int)std::min<int64_t>(room, g.K);
+          k = cdiv(g.K, cdiv(g.K, k));
+          t.m = m; t.r = r; t.k = k;
+          Geo G;
+          if (!make_geo(g, t, n, &G)) continue;
+          double cv = cost_value(op_cost(G, op), log2n);
+          if (cv < best_cost) {
+            best_cost = cv;
+            *best = t;
+            found = true;
+          }
+        }
+    }
+  return found;
+}
+
+extern "C" pencil_status pencil_plan_auto(const pencil_ctx* cctx, const pencil_layer* L, pencil_plan* plan) {
+  pencil_ctx* ctx = const_cast<pencil_ctx*>(cctx);
+  if (!ctx || !plan) return PENCIL_EINVAL;
+  pencil_status st = PENCIL_OK;
+  if (!layer_ok(ctx, L, &st)) return st;
+  pencil_tile* tiles[3] = {&plan->fwd, &plan->dx, &plan->dw};
+  for (int op = 0; op < 3; ++op)
+    if (!plan_op(L, op, ctx->C.log2n, tiles[op]))
+      return fail(ctx, PENCIL_EUNSUPPORTED, "no tile of op %d fits N = %d", op, ctx->C.n);
+  return PENCIL_OK;
+}
+
+extern "C" pencil_status pencil_layout(const pencil_ctx* cctx, const pencil_layer* L, const pencil_plan* P,
+                                       pencil_sizes* out) {
+  pencil_ctx* ctx = const_cast<pencil_ctx*>(cctx);
+  if (!ctx || !out) return PENCIL_EINVAL;
+  if (!P) return fail(ctx, PENCIL_EINVAL, "plan is NULL");
+  // An op whose tile is all zero is not planned: its sizes are reported as 0.
+  Geo G[3];
+  bool used[3];
+  for (int op = 0; op < 3; ++op) {
+    const pencil_tile& t = plan_tile(P, op);
+    used[op] = !(t.m == 0 && t.r == 0 && t.k == 0 && t.oh == 0 && t.ow == 0 && t.kh == 0 && t.kw == 0);
+    if (!used[op]) {
+      pencil_status st = PENCIL_OK;
+      if (!layer_ok(ctx, L, &st)) return st;
+      continue;
+    }
+    pencil_status st = get_geo(ctx, L, P, op, &G[op]);
+    if (st != PENCIL_OK) return st;
+  }
+  const uint64_t n = (uint64_t)ctx->C.n, Ln = (uint64_t)ctx->C.L;
+  const uint64_t poly = Ln * n * 8, ct = 2 * poly;
+  std::memset(out, 0, sizeof *out);
+  out->ct_bytes = ct;
+  if (used[0]) out->n_ct[PENCIL_X_FWD] = (uint64_t)n_a_tiles(G[0]);
+  if (used[1]) out->n_ct[PENCIL_DY_DX] = (uint64_t)n_a_tiles(G[1]);
+  if (used[2]) {
+    out->n_ct[PENCIL_X_DW] = (uint64_t)n_a_tiles(G[2]);
+    out->n_ct[PENCIL_DY_DW] = (uint64_t)n_k_tiles(G[2]);
+  }
+  for (int op = 0; op < 3; ++op) {
+    if (!used[op]) continue;
+    out->n_out[op] = (uint64_t)n_out_tiles(G[op]);
+    out->n_products[op] = (uint64_t)n_products(G[op]) * (op == PENCIL_OP_DW ? 2 : 1);
+    out->n_pt[op] = (uint64_t)n_k_tiles(G[op]) + (op == PENCIL_OP_DW ? (uint64_t)n_a_tiles(G[op]) : 0);
+  }
+  // fwd: A cts (NTT) + W pts + u' per output
+  out->ws_fwd_bytes = out->n_ct[0] * ct + out->n_pt[0] * poly + out->n_out[0] * poly;
+  const uint64_t dx = out->n_ct[1] * ct + out->n_pt[1] * poly + out->n_out[1] * poly;
+  const uint64_t dw = out->n_ct[2] * ct + out->n_ct[3] * ct + out->n_pt[2] * poly + out->n_out[2] * poly;
+  out->ws_bwd_bytes = std::max(dx, dw);
+  out->ws_dec_bytes = std::max(out->n_out[0], std::max(out->n_out[1], out->n_out[2])) * poly;
+  uint64_t enc = 0;
+  for (int k = 0; k < 4; ++k) enc = std::max(enc, out->n_ct[k]);
+  out->ws_enc_bytes = enc * poly;
+  return PENCIL_OK;
+}
+
+// ------------------------------------------------------------ operations
+
+static pencil_status check_ptr(pencil_ctx* ctx, const void* p, const char* name) {
+  if (!p) return fail(ctx, PENCIL_EINVAL, "%s is NULL", name);
+  return PENCIL_OK;
+}
+
+#define TRY(x)                          \
+  do {                                  \
+    pencil_status _s = (x);             \
+    if (_s != PENCIL_OK) return _s;     \
+  } while (0)
+
+extern "C" pencil_status pencil_encrypt(pencil_ctx* ctx, const pencil_layer* L, const pencil_plan* P, int operand,
+                                        const int64_t* share, uint64_t* ct, void* ws, uint64_t nonce, void* stream) {
+  if (!ctx) return PENCIL_EINVAL;
+  if (operand < 0 || operand > 3) return fail(ctx, PENCIL_EINVAL, "operand %d invalid", operand);
+  TRY(check_ptr(ctx, share, "share"));
+  TRY(check_ptr(ctx, ct, "ct"));
+  TRY(check_ptr(ctx, ws, "ws"));
+  const int op = operand == PENCIL_X_FWD ? PENCIL_OP_FWD : operand == PENCIL_DY_DX ? PENCIL_OP_DX : PENCIL_OP_DW;
+  const int side = operand == PENCIL_DY_DW ? 1 : 0;
+  Geo G;
+  TRY(get_geo(ctx, L, P, op, &G));
+  const View V = side ? view_k(L, op) : view_a(L, op);
+  const int64_t count = side ? n_k_tiles(G) : n_a_tiles(G);
+  hipStream_t s = (hipStream_t)stream;
+  uint64_t* u = (uint64_t*)ws;  // u^ of every ciphertext, [count][L][N]
+  hipError_t e = launch_ntt_ternary(u, count, nonce, enc_object(operand, 0), P_ENC_U, ctx->C, ctx->T, s);
+  if (e == hipSuccess)
+    e = launch_encrypt(u, share, ct, count, side, G, V, ctx->d_pk_ntt, ctx->d_pk_sh, nonce, enc_object(operand, 0),
+                       ctx->C, ctx->T, s);
+  if (e != hipSuccess) return fail(ctx, PENCIL_EHIP, "encrypt launch: %s", hipGetErrorString(e));
+  return PENCIL_OK;
+}
+
+// One product: NTT of the inputs, MAC (+ pk u'), INTT, flood and mask.
+struct TermIn {
+  const uint64_t* ct;     // coefficient-domain ciphertexts (A side if a_is_ct)
+  const int64_t* pt;      // Z_t tensor for the plaintext side
+  int a_is_ct;
+};
+
+static pencil_status run_product(pencil_ctx* ctx, const pencil_layer* L, int op, const Geo& G, const TermIn* terms,
+                                 int n_terms, const int64_t* add_share, const int64_t* bias, uint64_t* ct_out,
+                                 int64_t* share_out, uint8_t* ws, uint64_t nonce, hipStream_t s) {
+  const Consts& C = ctx->C;
+  const int64_t poly = (int64_t)C.L * C.n, ctw = 2 * poly;
+  const int64_t na = n_a_tiles(G), nk = n_k_tiles(G), no = n_out_tiles(G);
+  uint64_t* w = (uint64_t*)ws;
+  MacArgs A{};
+  A.n_terms = n_terms;
+  A.m_rows = G.nM * G.nOY * G.nOX;
+  A.pk = ctx->d_pk_ntt;
+  A.out = ct_out;
+  for (int i = 0; i < n_terms; ++i) {
+    const TermIn& T = terms[i];
+    if (T.a_is_ct) {
+      uint64_t* cts = w;
+      w += na * ctw;
+      uint64_t* pts = w;
+      w += nk * poly;
+      hipError_t e = launch_ntt_ct(T.ct, cts, na, add_share, G, view_a(L, op), C, ctx->T, s);
+      if (e == hipSuccess) e = launch_ntt_pt(T.pt, pts, nk, 1, G, view_k(L, op), C, ctx->T, s);
+      if (e != hipSuccess) return fail(ctx, PENCIL_EHIP, "ntt launch: %s", hipGetErrorString(e));
+      A.term[i] = MacTerm{cts, pts, 1, 0};
+    } else {
+      uint64_t* pts = w;
+      w += na * poly;
+      uint64_t* cts = w;
+      w += nk * ctw;
+      hipError_t e = launch_ntt_pt(T.pt, pts, na, 0, G, view_a(L, op), C, ctx->T, s);
+      if (e == hipSuccess) e = launch_ntt_ct(T.ct, cts, nk, nullptr, G, view_k(L, op), C, ctx->T, s);
+      if (e != hipSuccess) return fail(ctx, PENCIL_EHIP, "ntt launch: %s", hipGetErrorString(e));
+      A.term[i] = MacTerm{pts, cts, 0, 0};
+    }
+  }
+  uint64_t* u = w;
+  const uint64_t obj = out_object(op, 0);
+  hipError_t e = launch_ntt_ternary(u, no, nonce, obj, P_RR_U, C, ctx->T, s);
+  A.u = u;
+  if (e == hipSuccess) e = launch_mac(A, no, G, C, s);
+  if (e == hipSuccess) e = launch_ntt_plain(ct_out, 2 * no, true, C, ctx->T, s);
+  if (e == hipSuccess) e = launch_flood_mask(ct_out, no, share_out, bias, G, view_out(L, op), nonce, obj, C, s);
+  if (e != hipSuccess) return fail(ctx, PENCIL_EHIP, "product launch: %s", hipGetErrorString(e));
+  return PENCIL_OK;
+}
+
+static bool mac_grid_ok(const Geo& G) {
+  const int64_t rows = (int64_t)G.nM * G.nOY * G.nOX;
+  return ((rows + 1) / 2) * ((G.nR + 1) / 2) < 65536;
+}
+
+extern "C" pencil_status pencil_linear_fwd(pencil_ctx* ctx, const pencil_layer* L, const pencil_plan* P,
+                                           const uint64_t* ct_x1, const int64_t* x0, const int64_t* w,
+                                           const int64_t* bias, uint64_t* ct_y, int64_t* y0, void* ws,
+                                           uint64_t nonce, void* stream) {
+  if (!ctx) return PENCIL_EINVAL;
+  TRY(check_ptr(ctx, ct_x1, "ct_x1"));
+  TRY(check_ptr(ctx, x0, "x0"));
+  TRY(check_ptr(ctx, w, "w"));
+  TRY(check_ptr(ctx, ct_y, "ct_y"));
+  TRY(check_ptr(ctx, y0, "y0"));
+  TRY(check_ptr(ctx, ws, "ws"));
+  Geo G;
+  TRY(get_geo(ctx, L, P, PENCIL_OP_FWD, &G));
+  if (!mac_grid_ok(G)) return fail(ctx, PENCIL_EUNSUPPORTED, "too many output tiles for one launch");
+  TermIn t{ct_x1, w, 1};
+  return run_product(ctx, L, PENCIL_OP_FWD, G, &t, 1, x0, bias, ct_y, y0, (uint8_t*)ws, nonce, (hipStream_t)stream);
+}
+
+extern "C" pencil_status pencil_linear_bwd(pencil_ctx* ctx, const pencil_layer* L, const pencil_plan* P,
+                                           const uint64_t* ct_dy_dx, const uint64_t* ct_x_dw,
+                                           const uint64_t* ct_dy_dw, const int64_t* dy0, const int64_t* x0,
+                                           const int64_t* w, uint64_t* ct_dx, int64_t* dx0, uint64_t* ct_dw,
+                                           int64_t* dw_mask, void* ws, uint64_t nonce, void* stream) {
+  if (!ctx) return PENCIL_EINVAL;
+  TRY(check_ptr(ctx, ws, "ws"));
+  TRY(check_ptr(ctx, dy0, "dy0"));
+  hipStream_t s = (hipStream_t)stream;
+  if (ct_dx || dx0) {
+    TRY(check_ptr(ctx, ct_dy_dx, "ct_dy_dx"));
+    TRY(check_ptr(ctx, w, "w"));
+    TRY(check_ptr(ctx, ct_dx, "ct_dx"));
+    TRY(check_ptr(ctx, dx0, "dx0"));
+    Geo G;
+    TRY(get_geo(ctx, L, P, PENCIL_OP_DX, &G));
+    if (!mac_grid_ok(G)) return fail(ctx, PENCIL_EUNSUPPORTED, "too many output tiles for one launch");
+    TermIn t{ct_dy_dx, w, 1};
+    TRY(run_product(ctx, L, PENCIL_OP_DX, G, &t, 1, dy0, nullptr, ct_dx, dx0, (uint8_t*)ws, nonce, s));
+  }
+  if (ct_dw || dw_mask) {
+    TRY(check_ptr(ctx, ct_x_dw, "ct_x_dw"));
+    TRY(check_ptr(ctx, ct_dy_dw, "ct_dy_dw"));
+    TRY(check_ptr(ctx, x0, "x0"));
+    TRY(check_ptr(ctx, ct_dw, "ct_dw"));
+    TRY(check_ptr(ctx, dw_mask, "dw_mask"));
+    Geo G;
+    TRY(get_geo(ctx, L, P, PENCIL_OP_DW, &G));
+    if (!mac_grid_ok(G)) return fail(ctx, PENCIL_EUNSUPPORTED, "too many output tiles for one launch");
+    TermIn t[2] = {{ct_x_dw, dy0, 1}, {ct_dy_dw, x0, 0}};
+    TRY(run_product(ctx, L, PENCIL_OP_DW, G, t, 2, nullptr, nullptr, ct_dw, dw_mask, (uint8_t*)ws, nonce, s));
+  }
+  return PENCIL_OK;
+}
+
+extern "C" pencil_status pencil_decrypt(pencil_ctx* ctx, const pencil_layer* L, const pencil_plan* P, int op,
+                                        const uint64_t* ct, int64_t* share, void* ws, void* stream) {
+  if (!ctx) return PENCIL_EINVAL;
+  if (op < 0 || op > 2) return fail(ctx, PENCIL_EINVAL, "op %d invalid", op);
+  TRY(check_ptr(ctx, ct, "ct"));
+  TRY(check_ptr(ctx, share, "share"));
+  TRY(check_ptr(ctx, ws, "ws"));
+  Geo G;
+  TRY(get_geo(ctx, L, P, op, &G));
+  const int64_t no = n_out_tiles(G);
+  hipStream_t s = (hipStream_t)stream;
+  uint64_t* x = (uint64_t*)ws;
+  hipError_t e = launch_phase(ct, x, no, ctx->d_s_ntt, ctx->d_s_sh, ctx->C, ctx->T, s);
+  if (e == hipSuccess) e = launch_decode(x, share, no, G, view_out(L, op), ctx->C, s);
+  if (e != hipSuccess) return fail(ctx, PENCIL_EHIP, "decrypt launch: %s", hipGetErrorString(e));
+  return PENCIL_OK;
+}
+
+extern "C" pencil_status pencil_ntt_forward(pencil_ctx* ctx, uint64_t* polys, int64_t count, void* stream) {
+  if (!ctx) return PENCIL_EINVAL;
+  TRY(check_ptr(ctx, polys, "polys"));
+  if (count < 0) return fail(ctx, PENCIL_EINVAL, "count < 0");
+  hipError_t e = launch_ntt_plain(polys, count, false, ctx->C, ctx->T, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(ctx, PENCIL_EHIP, "ntt launch: %s", hipGetErrorString(e));
+  return PENCIL_OK;
+}
+
+extern "C" pencil_status pencil_ntt_inverse(pencil_ctx* ctx, uint64_t* polys, int64_t count, void* stream) {
+  if (!ctx) return PENCIL_EINVAL;
+  TRY(check_ptr(ctx, polys, "polys"));
+  if (count < 0) return fail(ctx, PENCIL_EINVAL, "count < 0");
+  hipError_t e = launch_ntt_plain(polys, count, true, ctx->C, ctx->T, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(ctx, PENCIL_EHIP, "ntt launch: %s", hipGetErrorString(e));
+  return PENCIL_OK;
+}

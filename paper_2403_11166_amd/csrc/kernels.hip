@@ -1,0 +1,753 @@
+// HIP kernels for gfx950: negacyclic NTT/INTT per RNS limb staged in LDS,
+// encode + lift, pointwise multiply-accumulate, re-randomise/flood/mask,
+// encryption and exact-CRT decryption.
+#include "pencil_internal.h"
+#include "modarith.h"
+
+namespace pencil {
+
+constexpr int kNttThreads = 512;
+
+// ----------------------------------------------------------------- NTT core
+// Merged negacyclic Cooley-Tukey transform (the psi twist folded into the
+// twiddles, psi^rev(k) tables): natural order in, bit-reversed order out.
+// Stage with m groups and half-size t = N / 2m: pair (i0, i0 + t) of group i
+// uses w = psi^rev(m + i).
+__device__ void ntt_forward_lds(uint64_t* a, int log2n, const uint64_t* tw, const uint64_t* tw_sh, uint64_t q) {
+  const int half = 1 << (log2n - 1);
+  for (int lm = 0; lm < log2n; ++lm) {
+    const int lt = log2n - 1 - lm;
+    const int m = 1 << lm;
+    const int tmask = (1 << lt) - 1;
+    for (int b = threadIdx.x; b < half; b += blockDim.x) {
+      const int i = b >> lt, j = b & tmask;
+      const int i0 = (i << (lt + 1)) + j, i1 = i0 + (1 << lt);
+      const uint64_t w = tw[m + i], ws = tw_sh[m + i];
+      const uint64_t u = a[i0];
+      const uint64_t v = mul_shoup(a[i1], w, ws, q);
+      a[i0] = add_mod(u, v, q);
+      a[i1] = sub_mod(u, v, q);
+    }
+    __syncthreads();
+  }
+}
+
+// Gentleman-Sande inverse with psi^-rev(k) twiddles, bit-reversed in, natural
+// out; the caller applies the N^-1 factor.
+__device__ void ntt_inverse_lds(uint64_t* a, int log2n, const uint64_t* tw, const uint64_t* tw_sh, uint64_t q) {
+  const int half = 1 << (log2n - 1);
+  for (int lt = 0; lt < log2n; ++lt) {
+    const int m = half >> lt;
+    const int tmask = (1 << lt) - 1;
+    for (int b = threadIdx.x; b < half; b += blockDim.x) {
+      const int i = b >> lt, j = b & tmask;
+      const int i0 = (i << (lt + 1)) + j, i1 = i0 + (1 << lt);
+      const uint64_t w = tw[m + i], ws = tw_sh[m + i];
+      const uint64_t u = a[i0], v = a[i1];
+      a[i0] = add_mod(u, v, q);
+      a[i1] = mul_shoup(sub_mod(u, v, q), w, ws, q);
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------- encode helpers
+// round(q m / t) mod q_l for m in [0, t): Delta * m + round(rho m / t), rho = q mod t.
+__device__ __forceinline__ uint64_t round_rho(uint64_t m, const Consts& C) {
+  uint64_t est = __umul64hi(m, C.rho_sh);
+  uint64_t r = m * C.rho - est * C.t;  // in [0, 2t)
+  if (r >= C.t) {
+    r -= C.t;
+    est += 1;
+  }
+  return est + (2 * r > C.t ? 1 : 0);
+}
+
+__device__ __forceinline__ uint64_t delta_scale(uint64_t m, uint64_t rr, const LimbConst& lc) {
+  return add_mod(mul_shoup(m, lc.delta, lc.delta_sh, lc.q), rr, lc.q);
+}
+
+// Value of the forward-encoded A tile `tile` at polynomial slot `slot`
+// (App. A's pi_v generalised), or -1 for an empty slot.
+__device__ __forceinline__ int64_t a_slot_offset(const Geo& G, const View& V, int64_t tile, int slot) {
+  int mm = slot / G.RS;
+  int rem = slot - mm * G.RS;
+  if (mm >= G.mt || rem >= G.S) return -1;
+  const int hw = G.ha * G.wa;
+  int kk = rem / hw;
+  int rem2 = rem - kk * hw;
+  int ya = rem2 / G.wa, xa = rem2 - (rem2 / G.wa) * G.wa;
+  // tile index = ((((mi*nK + ki)*nOY + oyi)*nOX + oxi)*nKY + kyi)*nKX + kxi
+  int64_t ti = tile;
+  int kxi = (int)(ti % G.nKX); ti /= G.nKX;
+  int kyi = (int)(ti % G.nKY); ti /= G.nKY;
+  int oxi = (int)(ti % G.nOX); ti /= G.nOX;
+  int oyi = (int)(ti % G.nOY); ti /= G.nOY;
+  int ki = (int)(ti % G.nK); ti /= G.nK;
+  int mi = (int)ti;
+  int m = mi * G.mt + mm, k = ki * G.kt + kk;
+  int y = oyi * G.oh + kyi * G.kh + ya, x = oxi * G.ow + kxi * G.kw + xa;
+  if (m >= G.M || k >= G.K || y >= G.HA || x >= G.WA) return -1;
+  int ys = y - V.pad, xs = x - V.pad;
+  if (ys < 0 || xs < 0 || ys >= V.H || xs >= V.W) return -1;
+  return m * V.s0 + k * V.s1 + ys * V.sy + xs * V.sx;
+}
+
+// Value offset of the reverse-encoded K tile `tile` at `slot` (App. A's pi_W).
+__device__ __forceinline__ int64_t k_slot_offset(const Geo& G, const View& V, int64_t tile, int slot) {
+  // slot = O + rr*S - (kk*ha*wa + dy*wa + dx)
+  int z = slot - G.O + G.S - 1;
+  if (z < 0) return -1;
+  int rr = z / G.S;
+  if (rr >= G.rt) return -1;
+  int D = rr * G.S + G.O - slot;
+  const int hw = G.ha * G.wa;
+  int kk = D / hw;
+  int rem = D - kk * hw;
+  int dy = rem / G.wa, dx = rem - (rem / G.wa) * G.wa;
+  if (dy >= G.kh || dx >= G.kw) return -1;
+  int64_t ti = tile;  // ((ri*nK + ki)*nKY + kyi)*nKX + kxi
+  int kxi = (int)(ti % G.nKX); ti /= G.nKX;
+  int kyi = (int)(ti % G.nKY); ti /= G.nKY;
+  int ki = (int)(ti % G.nK); ti /= G.nK;
+  int ri = (int)ti;
+  int r = ri * G.rt + rr, k = ki * G.kt + kk, a = kyi * G.kh + dy, b = kxi * G.kw + dx;
+  if (r >= G.R || k >= G.K || a >= G.KH || b >= G.KW) return -1;
+  if (V.flip) {
+    a = V.KH - 1 - a;
+    b = V.KW - 1 - b;
+  }
+  return r * V.s0 + k * V.s1 + a * V.sy + b * V.sx;
+}
+
+__device__ __forceinline__ int64_t slot_offset(int side, const Geo& G, const View& V, int64_t tile, int slot) {
+  return side == 0 ? a_slot_offset(G, V, tile, slot) : k_slot_offset(G, V, tile, slot);
+}
+
+// ------------------------------------------------------------------ kernels
+
+// In-place forward or inverse NTT of [polys][L][N].
+__global__ void __launch_bounds__(kNttThreads) k_ntt_plain(uint64_t* data, int inverse, Consts C, Tables T) {
+  extern __shared__ uint64_t lds[];
+  const int n = C.n, L = C.L;
+  const int64_t p = blockIdx.x;
+  const int l = (int)(p % L);
+  const LimbConst& lc = C.limb[l];
+  uint64_t* g = data + p * n;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) lds[i] = g[i];
+  __syncthreads();
+  if (!inverse) {
+    ntt_forward_lds(lds, C.log2n, T.psi + (int64_t)l * n, T.psi_sh + (int64_t)l * n, lc.q);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) g[i] = lds[i];
+  } else {
+    ntt_inverse_lds(lds, C.log2n, T.ipsi + (int64_t)l * n, T.ipsi_sh + (int64_t)l * n, lc.q);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) g[i] = mul_shoup(lds[i], lc.ninv, lc.ninv_sh, lc.q);
+  }
+}
+
+// Input ciphertexts: load (coefficient domain), add round(q m / t) of the model
+// owner's share on component 0 (Alg. 1 line 2), forward NTT, store.
+// Grid: n_ct * 2 * L blocks, polynomial p = (j, c, l) in [n][2][L] order.
+__global__ void __launch_bounds__(kNttThreads) k_ntt_ct(const uint64_t* src, uint64_t* dst, const int64_t* share,
+                                                        Geo G, View V, Consts C, Tables T) {
+  extern __shared__ uint64_t lds[];
+  const int n = C.n, L = C.L;
+  const int64_t p = blockIdx.x;
+  const int l = (int)(p % L);
+  const int c = (int)((p / L) % 2);
+  const int64_t j = p / (2 * L);
+  const LimbConst& lc = C.limb[l];
+  const uint64_t* g = src + p * n;
+  const bool add = share != nullptr && c == 0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    uint64_t v = g[i];
+    if (add) {
+      int64_t off = a_slot_offset(G, V, j, i);
+      if (off >= 0) {
+        uint64_t m = (uint64_t)share[off];
+        v = add_mod(v, delta_scale(m, round_rho(m, C), lc), lc.q);
+      }
+    }
+    lds[i] = v;
+  }
+  __syncthreads();
+  ntt_forward_lds(lds, C.log2n, T.psi + (int64_t)l * n, T.psi_sh + (int64_t)l * n, lc.q);
+  uint64_t* o = dst + p * n;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) o[i] = lds[i];
+}
+
+// Plaintext tiles: encode (side 0: forward A tile, 1: reverse K tile), centred
+// lift of Z_t into Z_{q_l}, forward NTT.  Grid: n_pt * L, output [n][L][N].
+__global__ void __launch_bounds__(kNttThreads) k_ntt_pt(const int64_t* tensor, uint64_t* dst, int side, Geo G,
+                                                        View V, Consts C, Tables T) {
+  extern __shared__ uint64_t lds[];
+  const int n = C.n, L = C.L;
+  const int64_t p = blockIdx.x;
+  const int l = (int)(p % L);
+  const int64_t j = p / L;
+  const LimbConst& lc = C.limb[l];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    uint64_t v = 0;
+    int64_t off = slot_offset(side, G, V, j, i);
+    if (off >= 0) {
+      uint64_t w = (uint64_t)tensor[off];
+      v = w <= C.t_half ? w : lc.q - (C.t - w);
+    }
+    lds[i] = v;
+  }
+  __syncthreads();
+  ntt_forward_lds(lds, C.log2n, T.psi + (int64_t)l * n, T.psi_sh + (int64_t)l * n, lc.q);
+  uint64_t* o = dst + p * n;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) o[i] = lds[i];
+}
+
+// Fresh ternary polynomials (object obj_base + j, stream `purpose`), lifted and
+// transformed.  Coefficient i uses the 32-bit half i mod 2 of stream word i/2,
+// so one Philox block covers 8 coefficients.  Grid: count * L, output [n][L][N].
+__global__ void __launch_bounds__(kNttThreads) k_ntt_ternary(uint64_t* dst, uint64_t nonce, uint64_t obj_base,
+                                                             uint32_t purpose, Consts C, Tables T) {
+  extern __shared__ uint64_t lds[];
+  const int n = C.n, L = C.L;
+  const int64_t p = blockIdx.x;
+  const int l = (int)(p % L);
+  const int64_t j = p / L;
+  const LimbConst& lc = C.limb[l];
+  for (int blk = threadIdx.x; blk < n / 8; blk += blockDim.x) {
+    U64x4 w = philox((uint64_t)blk, obj_base + j, purpose, 0, C.seed, nonce);
+#pragma unroll
+    for (int h = 0; h < 8; ++h) {
+      uint32_t half = (uint32_t)(w.v[h >> 1] >> (32 * (h & 1)));
+      lds[blk * 8 + h] = small_to_mod(ternary32(half), lc.q);
+    }
+  }
+  __syncthreads();
+  ntt_forward_lds(lds, C.log2n, T.psi + (int64_t)l * n, T.psi_sh + (int64_t)l * n, lc.q);
+  uint64_t* o = dst + p * n;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) o[i] = lds[i];
+}
+
+// Pointwise multiply-accumulate over contraction tiles, per NTT slot:
+//   out[o][c] = sum_{terms, kappa} A[a(o, kappa)] * K[k(o, kappa)]  +  pk_c * u'_o
+// Each thread owns one (limb, slot) and a TM x TR block of (A-row, K-row)
+// output tiles; products accumulate in 128 bits and are Barrett-reduced every
+// mac_chunk terms.
+template <int TM, int TR>
+__global__ void __launch_bounds__(256) k_mac(MacArgs A, Geo G, Consts C) {
+  const int n = C.n, L = C.L;
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= (int64_t)n * L) return;
+  const int l = (int)(g / n), s = (int)(g % n);
+  const LimbConst& lc = C.limb[l];
+  const int rblocks = (G.nR + TR - 1) / TR;
+  const int mb = blockIdx.y / rblocks, rb = blockIdx.y % rblocks;
+  const int sp = G.nOY * G.nOX;
+
+  uint64_t acc_hi[TM][TR][2], acc_lo[TM][TR][2];
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TR; ++b)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) acc_hi[a][b][c] = acc_lo[a][b][c] = 0;
+
+  int mi[TM], oyi[TM], oxi[TM];
+  bool mv[TM];
+#pragma unroll
+  for (int a = 0; a < TM; ++a) {
+    int row = mb * TM + a;
+    mv[a] = row < A.m_rows;
+    row = mv[a] ? row : 0;
+    mi[a] = row / sp;
+    oyi[a] = (row % sp) / G.nOX;
+    oxi[a] = row % G.nOX;
+  }
+  int ri[TR];
+  bool rv[TR];
+#pragma unroll
+  for (int b = 0; b < TR; ++b) {
+    ri[b] = rb * TR + b;
+    rv[b] = ri[b] < G.nR;
+    ri[b] = rv[b] ? ri[b] : 0;
+  }
+
+  const int64_t ln = (int64_t)l * n + s;
+  const int64_t ct_stride = 2 * (int64_t)L * n, pt_stride = (int64_t)L * n;
+  uint32_t cnt = 0;
+  const int kspan = G.nKY * G.nKX;
+  for (int ki = 0; ki < G.nK; ++ki) {
+    for (int kk = 0; kk < kspan; ++kk) {
+      const int kyi = kk / G.nKX, kxi = kk % G.nKX;
+      for (int tt = 0; tt < A.n_terms; ++tt) {
+        const MacTerm& T = A.term[tt];
+        uint64_t av[TM][2], kv[TR][2];
+#pragma unroll
+        for (int a = 0; a < TM; ++a) {
+          int64_t ai = ((((int64_t)mi[a] * G.nK + ki) * G.nOY + oyi[a]) * G.nOX + oxi[a]) * kspan + kk;
+          if (T.a_is_ct) {
+            av[a][0] = T.a[ai * ct_stride + ln];
+            av[a][1] = T.a[ai * ct_stride + pt_stride + ln];
+          } else {
+            av[a][0] = av[a][1] = T.a[ai * pt_stride + ln];
+          }
+        }
+#pragma unroll
+        for (int b = 0; b < TR; ++b) {
+          int64_t kix = ((int64_t)ri[b] * G.nK + ki) * kspan + kk;
+          if (T.a_is_ct) {
+            kv[b][0] = kv[b][1] = T.k[kix * pt_stride + ln];
+          } else {
+            kv[b][0] = T.k[kix * ct_stride + ln];
+            kv[b][1] = T.k[kix * ct_stride + pt_stride + ln];
+          }
+        }
+#pragma unroll
+        for (int a = 0; a < TM; ++a)
+#pragma unroll
+          for (int b = 0; b < TR; ++b)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+              uint64_t ph, pl;
+              mul_wide(av[a][c], kv[b][c], ph, pl);
+              uint64_t lo = acc_lo[a][b][c] + pl;
+              acc_hi[a][b][c] += ph + (lo < pl ? 1 : 0);
+              acc_lo[a][b][c] = lo;
+            }
+        if (++cnt == C.mac_chunk) {
+          cnt = 0;
+#pragma unroll
+          for (int a = 0; a < TM; ++a)
+#pragma unroll
+            for (int b = 0; b < TR; ++b)
+#pragma unroll
+              for (int c = 0; c < 2; ++c) {
+                acc_lo[a][b][c] = reduce128(acc_hi[a][b][c], acc_lo[a][b][c], lc.q, lc.mu_lo, lc.mu_hi);
+                acc_hi[a][b][c] = 0;
+              }
+        }
+      }
+    }
+  }
+  // re-randomisation term pk_c * u'_o, reduction and store
+  const uint64_t pk0 = A.pk[ln], pk1 = A.pk[pt_stride + ln];
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TR; ++b) {
+      if (!mv[a] || !rv[b]) continue;
+      const int64_t o = (((int64_t)mi[a] * G.nR + ri[b]) * G.nOY + oyi[a]) * G.nOX + oxi[a];
+      const uint64_t u = A.u[o * pt_stride + ln];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        uint64_t ph, pl;
+        mul_wide(c ? pk1 : pk0, u, ph, pl);
+        uint64_t r0 = reduce128(acc_hi[a][b][c], acc_lo[a][b][c], lc.q, lc.mu_lo, lc.mu_hi);
+        uint64_t r1 = reduce128(ph, pl, lc.q, lc.mu_lo, lc.mu_hi);
+        A.out[o * ct_stride + (int64_t)c * pt_stride + ln] = add_mod(r0, r1, lc.q);
+      }
+    }
+}
+
+// Output ciphertexts after the inverse NTT: c0 += e0' + flood - round(q s / t),
+// c1 += e1'; the model owner's share is s at the output slots (+ bias).
+// Each thread handles 4 consecutive coefficients of one output ciphertext.
+__global__ void __launch_bounds__(256) k_flood_mask(uint64_t* ct, int64_t n_out, int64_t* share0,
+                                                    const int64_t* bias, Geo G, View OV, uint64_t nonce,
+                                                    uint64_t obj_base, Consts C) {
+  const int n = C.n, L = C.L;
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int per = n / 4;
+  if (g >= n_out * per) return;
+  const int64_t o = g / per;
+  const int n0 = (int)(g % per) * 4;
+  const uint64_t obj = obj_base + (uint64_t)o;
+  const uint64_t blk4 = (uint64_t)(n0 / 4);
+  U64x4 e0 = philox(blk4, obj, P_RR_E0, 0, C.seed, nonce);
+  U64x4 e1 = philox(blk4, obj, P_RR_E1, 0, C.seed, nonce);
+  U64x4 mk0 = philox(2 * blk4, obj, P_MASK, 0, C.seed, nonce);
+  U64x4 mk1 = philox(2 * blk4 + 1, obj, P_MASK, 0, C.seed, nonce);
+  const int W = C.flood_words;
+  uint64_t fw[16];  // 4 coefficients x up to 4 words
+  for (int b = 0; b < W; ++b) {
+    U64x4 f = philox(blk4 * W + b, obj, P_FLOOD, 0, C.seed, nonce);
+#pragma unroll
+    for (int z = 0; z < 4; ++z) fw[b * 4 + z] = f.v[z];
+  }
+  const int64_t ct_stride = 2 * (int64_t)L * n;
+  uint64_t* c0p = ct + o * ct_stride;
+  uint64_t* c1p = c0p + (int64_t)L * n;
+  // output-tile coordinates of o = ((mi*nR + ri)*nOY + oyi)*nOX + oxi
+  int64_t ti = o;
+  const int oxi = (int)(ti % G.nOX);
+  ti /= G.nOX;
+  const int oyi = (int)(ti % G.nOY);
+  ti /= G.nOY;
+  const int ri = (int)(ti % G.nR);
+  const int mi = (int)(ti / G.nR);
+#pragma unroll
+  for (int z = 0; z < 4; ++z) {
+    const int i = n0 + z;
+    const int64_t ev0 = cbd21(e0.v[z]), ev1 = cbd21(e1.v[z]);
+    const uint64_t wlo = (z < 2 ? mk0 : mk1).v[(2 * z) & 3], whi = (z < 2 ? mk0 : mk1).v[(2 * z + 1) & 3];
+    // s = (wlo + 2^64 whi) mod t
+    uint64_t sh = reduce64(whi, C.one_sh_t, C.t);
+    uint64_t s = mul_shoup(sh, C.r64t, C.r64t_sh, C.t) + reduce64(wlo, C.one_sh_t, C.t);
+    if (s >= C.t) s -= C.t;
+    const uint64_t rr = round_rho(s, C);
+    for (int l = 0; l < L; ++l) {
+      const LimbConst& lc = C.limb[l];
+      // flood value V - 2^fb with V the low fb+1 bits of the words, by Horner in base 2^64
+      uint64_t v = 0;
+      for (int b = W - 1; b >= 0; --b) {
+        uint64_t w = fw[z * W + b];
+        if (b == W - 1) w &= C.top_mask;
+        v = add_mod(mul_shoup(v, lc.r64, lc.r64_sh, lc.q), reduce64(w, lc.one_sh, lc.q), lc.q);
+      }
+      v = sub_mod(v, lc.flood_off, lc.q);
+      uint64_t x0 = c0p[(int64_t)l * n + i];
+      x0 = add_mod(x0, small_to_mod(ev0, lc.q), lc.q);
+      x0 = add_mod(x0, v, lc.q);
+      x0 = sub_mod(x0, delta_scale(s, rr, lc), lc.q);
+      c0p[(int64_t)l * n + i] = x0;
+      c1p[(int64_t)l * n + i] = add_mod(c1p[(int64_t)l * n + i], small_to_mod(ev1, lc.q), lc.q);
+    }
+    // model owner's share at the output slots: slot = mm*RS + O + rr*S + y*wa + x
+    int zz = i - G.O;
+    if (zz >= 0) {
+      int mm = zz / G.RS;
+      int rem = zz - mm * G.RS;
+      int rr2 = rem / G.S;
+      int rem2 = rem - rr2 * G.S;
+      int y = rem2 / G.wa, x = rem2 - (rem2 / G.wa) * G.wa;
+      if (mm < G.mt && y < G.oh && x < G.ow) {
+        int m = mi * G.mt + mm, r = ri * G.rt + rr2, yy = oyi * G.oh + y, xx = oxi * G.ow + x;
+        if (m < G.M && r < G.R && yy < G.OH && xx < G.OW) {
+          uint64_t val = s;
+          if (bias) {
+            val += (uint64_t)bias[r];
+            if (val >= C.t) val -= C.t;
+          }
+          share0[m * OV.s0 + r * OV.s1 + yy * OV.sy + xx * OV.sx] = (int64_t)val;
+        }
+      }
+    }
+  }
+}
+
+// Encryption: ct_c = INTT(pk_c * u) + e_c (+ round(q m / t) on c = 0), with m
+// the encoded share at each slot.  Grid: n_ct * 2 * L, u_ntt is [n][L][N].
+__global__ void __launch_bounds__(kNttThreads) k_encrypt(const uint64_t* u_ntt, const int64_t* share, uint64_t* ct,
+                                                         int side, Geo G, View V, const uint64_t* pk_ntt,
+                                                         const uint64_t* pk_sh, uint64_t nonce, uint64_t obj_base,
+                                                         Consts C, Tables T) {
+  extern __shared__ uint64_t lds[];
+  const int n = C.n, L = C.L;
+  const int64_t p = blockIdx.x;
+  const int l = (int)(p % L);
+  const int c = (int)((p / L) % 2);
+  const int64_t j = p / (2 * L);
+  const LimbConst& lc = C.limb[l];
+  const uint64_t* u = u_ntt + (j * L + l) * n;
+  const uint64_t* pk = pk_ntt + ((int64_t)c * L + l) * n;
+  const uint64_t* pks = pk_sh + ((int64_t)c * L + l) * n;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) lds[i] = mul_shoup(u[i], pk[i], pks[i], lc.q);
+  __syncthreads();
+  ntt_inverse_lds(lds, C.log2n, T.ipsi + (int64_t)l * n, T.ipsi_sh + (int64_t)l * n, lc.q);
+  const uint64_t obj = obj_base + (uint64_t)j;
+  uint64_t* o = ct + p * n;
+  for (int blk = threadIdx.x; blk < n / 4; blk += blockDim.x) {
+    U64x4 e = philox((uint64_t)blk, obj, c ? P_ENC_E1 : P_ENC_E0, 0, C.seed, nonce);
+#pragma unroll
+    for (int z = 0; z < 4; ++z) {
+      const int i = blk * 4 + z;
+      uint64_t v = mul_shoup(lds[i], lc.ninv, lc.ninv_sh, lc.q);
+      v = add_mod(v, small_to_mod(cbd21(e.v[z]), lc.q), lc.q);
+      if (c == 0) {
+        int64_t off = slot_offset(side, G, V, j, i);
+        if (off >= 0) {
+          uint64_t m = (uint64_t)share[off];
+          v = add_mod(v, delta_scale(m, round_rho(m, C), lc), lc.q);
+        }
+      }
+      o[i] = v;
+    }
+  }
+}
+
+// Decryption phase per limb: x = c0 + INTT(NTT(c1) * s).  Grid: n * L, x is [n][L][N].
+__global__ void __launch_bounds__(kNttThreads) k_phase(const uint64_t* ct, uint64_t* x, const uint64_t* s_ntt,
+                                                       const uint64_t* s_sh, Consts C, Tables T) {
+  extern __shared__ uint64_t lds[];
+  const int n = C.n, L = C.L;
+  const int64_t p = blockIdx.x;
+  const int l = (int)(p % L);
+  const int64_t j = p / L;
+  const LimbConst& lc = C.limb[l];
+  const uint64_t* c0 = ct + ((j * 2 + 0) * L + l) * n;
+  const uint64_t* c1 = ct + ((j * 2 + 1) * L + l) * n;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) lds[i] = c1[i];
+  __syncthreads();
+  ntt_forward_lds(lds, C.log2n, T.psi + (int64_t)l * n, T.psi_sh + (int64_t)l * n, lc.q);
+  const uint64_t* sv = s_ntt + (int64_t)l * n;
+  const uint64_t* ss = s_sh + (int64_t)l * n;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) lds[i] = mul_shoup(lds[i], sv[i], ss[i], lc.q);
+  __syncthreads();
+  ntt_inverse_lds(lds, C.log2n, T.ipsi + (int64_t)l * n, T.ipsi_sh + (int64_t)l * n, lc.q);
+  uint64_t* o = x + p * n;
+  for (int i = threadIdx.x; i < n; i += blockDim.x)
+    o[i] = add_mod(c0[i], mul_shoup(lds[i], lc.ninv, lc.ninv_sh, lc.q), lc.q);
+}
+
+// Exact decryption of the output slots: with y_l = x_l * (q/q_l)^-1 mod q_l and
+// y_l t = alpha_l q_l + beta_l,  t x / q = sum alpha_l + sum beta_l / q_l - v t,
+// so m = (sum alpha_l + round(F / q)) mod t with F = sum beta_l (q / q_l); the
+// rounding compares 2F with (2j + 1) q.  One thread per output element.
+__global__ void __launch_bounds__(256) k_decode(const uint64_t* x, int64_t* share, int64_t n_out, Geo G, View OV,
+                                                Consts C) {
+  const int n = C.n, L = C.L;
+  const int64_t per = (int64_t)G.mt * G.rt * G.oh * G.ow;
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n_out * per) return;
+  const int64_t o = g / per;
+  int e = (int)(g % per);
+  const int x_ = e % G.ow;
+  e /= G.ow;
+  const int y = e % G.oh;
+  e /= G.oh;
+  const int rr = e % G.rt;
+  const int mm = e / G.rt;
+  int64_t ti = o;
+  const int oxi = (int)(ti % G.nOX);
+  ti /= G.nOX;
+  const int oyi = (int)(ti % G.nOY);
+  ti /= G.nOY;
+  const int ri = (int)(ti % G.nR);
+  const int mi = (int)(ti / G.nR);
+  const int m = mi * G.mt + mm, r = ri * G.rt + rr, yy = oyi * G.oh + y, xx = oxi * G.ow + x_;
+  if (m >= G.M || r >= G.R || yy >= G.OH || xx >= G.OW) return;
+  const int slot = mm * G.RS + G.O + rr * G.S + y * G.wa + x_;
+  uint64_t F[kMaxWords + 1];
+#pragma unroll
+  for (int w = 0; w <= kMaxWords; ++w) F[w] = 0;
+  uint64_t alpha = 0;
+  for (int l = 0; l < L; ++l) {
+    const LimbConst& lc = C.limb[l];
+    const uint64_t xl = x[(o * L + l) * n + slot];
+    const uint64_t yl = mul_shoup(xl, lc.qhat_inv, lc.qhat_inv_sh, lc.q);
+    uint64_t est = __umul64hi(yl, lc.t_sh);
+    uint64_t beta = yl * C.t - est * lc.q;
+    if (beta >= lc.q) {
+      beta -= lc.q;
+      est += 1;
+    }
+    alpha += est;  // each alpha_l < t
+    // F += beta * qhat_l
+    uint64_t carry = 0;
+#pragma unroll
+    for (int w = 0; w < kMaxWords; ++w) {
+      uint64_t ph, pl;
+      mul_wide(beta, C.qhat[l][w], ph, pl);
+      uint64_t s1 = F[w] + pl;
+      uint64_t c1 = s1 < pl;
+      uint64_t s2 = s1 + carry;
+      c1 += s2 < carry;
+      F[w] = s2;
+      carry = ph + c1;
+    }
+    F[kMaxWords] += carry;
+  }
+  // 2F
+  uint64_t D[kMaxWords + 1];
+  uint64_t prev = 0;
+#pragma unroll
+  for (int w = 0; w <= kMaxWords; ++w) {
+    D[w] = (F[w] << 1) | (prev >> 63);
+    prev = F[w];
+  }
+  uint64_t rnd = 0;
+  for (int j = 0; j < L; ++j) {
+    // compare D with thr[j] (kMaxWords words; D's top word must be zero for thr to win)
+    int gt = D[kMaxWords] != 0 ? 1 : 0;
+    if (!gt) {
+      gt = 0;
+      for (int w = kMaxWords - 1; w >= 0; --w) {
+        if (D[w] != C.thr[j][w]) {
+          gt = D[w] > C.thr[j][w] ? 1 : 0;
+          break;
+        }
+      }
+    }
+    rnd += gt;
+  }
+  uint64_t mres = (alpha % C.t + rnd) % C.t;
+  share[m * OV.s0 + r * OV.s1 + yy * OV.sy + xx * OV.sx] = (int64_t)mres;
+}
+
+// Key generation, one block per limb: s ternary (stream P_SK), a uniform mod q_l
+// (stream P_PK_A, limb l, two words per coefficient), e CBD21 (stream P_PK_E);
+// pk = (-(a s + e), a), kept in both coefficient and NTT form.  One LDS buffer;
+// every thread re-reads only the global entries it wrote itself.
+__global__ void __launch_bounds__(kNttThreads) k_keygen(uint64_t* s_ntt, int64_t* s_coeff, uint64_t* pk_coeff,
+                                                        uint64_t* pk_ntt, Consts C, Tables T) {
+  extern __shared__ uint64_t lds[];
+  const int n = C.n, L = C.L;
+  const int l = blockIdx.x;
+  const LimbConst& lc = C.limb[l];
+  const uint64_t nonce = kKeygenNonce;
+  const uint64_t* tw = T.psi + (int64_t)l * n;
+  const uint64_t* tws = T.psi_sh + (int64_t)l * n;
+  for (int blk = threadIdx.x; blk < n / 8; blk += blockDim.x) {
+    U64x4 w = philox((uint64_t)blk, 0, P_SK, 0, C.seed, nonce);
+#pragma unroll
+    for (int h = 0; h < 8; ++h) {
+      int64_t sv = ternary32((uint32_t)(w.v[h >> 1] >> (32 * (h & 1))));
+      lds[blk * 8 + h] = small_to_mod(sv, lc.q);
+      if (l == 0) s_coeff[blk * 8 + h] = sv;
+    }
+  }
+  __syncthreads();
+  ntt_forward_lds(lds, C.log2n, tw, tws, lc.q);
+  for (int i = threadIdx.x; i < n; i += blockDim.x) s_ntt[(int64_t)l * n + i] = lds[i];
+  __syncthreads();
+  for (int blk = threadIdx.x; blk < n / 2; blk += blockDim.x) {
+    U64x4 w = philox((uint64_t)blk, 0, P_PK_A, (uint64_t)l, C.seed, nonce);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      // (w_lo + 2^64 w_hi) mod q
+      uint64_t hi = reduce64(w.v[2 * h + 1], lc.one_sh, lc.q);
+      uint64_t v = add_mod(mul_shoup(hi, lc.r64, lc.r64_sh, lc.q), reduce64(w.v[2 * h], lc.one_sh, lc.q), lc.q);
+      lds[blk * 2 + h] = v;
+      pk_coeff[((int64_t)1 * L + l) * n + blk * 2 + h] = v;
+    }
+  }
+  __syncthreads();
+  ntt_forward_lds(lds, C.log2n, tw, tws, lc.q);
+  // a * s pointwise (128-bit product, Barrett), then inverse transform
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const uint64_t av = lds[i];
+    pk_ntt[((int64_t)1 * L + l) * n + i] = av;
+    uint64_t ph, pl;
+    mul_wide(av, s_ntt[(int64_t)l * n + i], ph, pl);
+    lds[i] = reduce128(ph, pl, lc.q, lc.mu_lo, lc.mu_hi);
+  }
+  __syncthreads();
+  ntt_inverse_lds(lds, C.log2n, T.ipsi + (int64_t)l * n, T.ipsi_sh + (int64_t)l * n, lc.q);
+  for (int blk = threadIdx.x; blk < n / 4; blk += blockDim.x) {
+    U64x4 w = philox((uint64_t)blk, 0, P_PK_E, 0, C.seed, nonce);
+#pragma unroll
+    for (int z = 0; z < 4; ++z) {
+      const int i = blk * 4 + z;
+      uint64_t as = mul_shoup(lds[i], lc.ninv, lc.ninv_sh, lc.q);
+      uint64_t v = add_mod(as, small_to_mod(cbd21(w.v[z]), lc.q), lc.q);
+      v = v == 0 ? 0 : lc.q - v;
+      lds[i] = v;
+      pk_coeff[(int64_t)l * n + i] = v;
+    }
+  }
+  __syncthreads();
+  ntt_forward_lds(lds, C.log2n, tw, tws, lc.q);
+  for (int i = threadIdx.x; i < n; i += blockDim.x) pk_ntt[(int64_t)l * n + i] = lds[i];
+}
+
+// ---------------------------------------------------------------- launchers
+
+static inline size_t lds_bytes(const Consts& C) { return (size_t)C.n * sizeof(uint64_t); }
+
+hipError_t launch_ntt_plain(uint64_t* data, int64_t polys, bool inverse, const Consts& C, const Tables& T,
+                            hipStream_t s) {
+  if (polys <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ntt_plain, dim3((unsigned)(polys * C.L)), dim3(kNttThreads), lds_bytes(C), s, data,
+                     inverse ? 1 : 0, C, T);
+  return hipGetLastError();
+}
+
+hipError_t launch_ntt_ct(const uint64_t* src, uint64_t* dst, int64_t n_ct, const int64_t* share, const Geo& G,
+                         const View& V, const Consts& C, const Tables& T, hipStream_t s) {
+  if (n_ct <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ntt_ct, dim3((unsigned)(n_ct * 2 * C.L)), dim3(kNttThreads), lds_bytes(C), s, src, dst,
+                     share, G, V, C, T);
+  return hipGetLastError();
+}
+
+hipError_t launch_ntt_pt(const int64_t* tensor, uint64_t* dst, int64_t n_pt, int side, const Geo& G, const View& V,
+                         const Consts& C, const Tables& T, hipStream_t s) {
+  if (n_pt <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ntt_pt, dim3((unsigned)(n_pt * C.L)), dim3(kNttThreads), lds_bytes(C), s, tensor, dst, side,
+                     G, V, C, T);
+  return hipGetLastError();
+}
+
+hipError_t launch_ntt_ternary(uint64_t* dst, int64_t count, uint64_t nonce, uint64_t obj_base, uint32_t purpose,
+                              const Consts& C, const Tables& T, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ntt_ternary, dim3((unsigned)(count * C.L)), dim3(kNttThreads), lds_bytes(C), s, dst, nonce,
+                     obj_base, purpose, C, T);
+  return hipGetLastError();
+}
+
+hipError_t launch_mac(const MacArgs& A, int64_t n_out, const Geo& G, const Consts& C, hipStream_t s) {
+  if (n_out <= 0) return hipSuccess;
+  constexpr int TM = 2, TR = 2;
+  const int64_t slots = (int64_t)C.n * C.L;
+  const int mblocks = (A.m_rows + TM - 1) / TM, rblocks = (G.nR + TR - 1) / TR;
+  dim3 grid((unsigned)((slots + 255) / 256), (unsigned)(mblocks * rblocks));
+  hipLaunchKernelGGL((k_mac<TM, TR>), grid, dim3(256), 0, s, A, G, C);
+  return hipGetLastError();
+}
+
+hipError_t launch_flood_mask(uint64_t* ct, int64_t n_out, int64_t* share0, const int64_t* bias, const Geo& G,
+                             const View& outV, uint64_t nonce, uint64_t obj_base, const Consts& C, hipStream_t s) {
+  if (n_out <= 0) return hipSuccess;
+  const int64_t threads = n_out * (C.n / 4);
+  hipLaunchKernelGGL(k_flood_mask, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, ct, n_out, share0, bias,
+                     G, outV, nonce, obj_base, C);
+  return hipGetLastError();
+}
+
+hipError_t launch_encrypt(const uint64_t* u_ntt, const int64_t* share, uint64_t* ct, int64_t n_ct, int side,
+                          const Geo& G, const View& V, const uint64_t* pk_ntt, const uint64_t* pk_sh, uint64_t nonce,
+                          uint64_t obj_base, const Consts& C, const Tables& T, hipStream_t s) {
+  if (n_ct <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_encrypt, dim3((unsigned)(n_ct * 2 * C.L)), dim3(kNttThreads), lds_bytes(C), s, u_ntt, share,
+                     ct, side, G, V, pk_ntt, pk_sh, nonce, obj_base, C, T);
+  return hipGetLastError();
+}
+
+hipError_t launch_phase(const uint64_t* ct, uint64_t* x, int64_t n_ct, const uint64_t* s_ntt, const uint64_t* s_sh,
+                        const Consts& C, const Tables& T, hipStream_t s) {
+  if (n_ct <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_phase, dim3((unsigned)(n_ct * C.L)), dim3(kNttThreads), lds_bytes(C), s, ct, x, s_ntt, s_sh, C,
+                     T);
+  return hipGetLastError();
+}
+
+hipError_t launch_decode(const uint64_t* x, int64_t* share, int64_t n_out, const Geo& G, const View& outV,
+                         const Consts& C, hipStream_t s) {
+  const int64_t per = (int64_t)G.mt * G.rt * G.oh * G.ow;
+  const int64_t threads = n_out * per;
+  if (threads <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_decode, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, x, share, n_out, G, outV, C);
+  return hipGetLastError();
+}
+
+hipError_t launch_keygen(uint64_t* s_ntt, int64_t* s_coeff, uint64_t* pk_coeff, uint64_t* pk_ntt, const Consts& C,
+                         const Tables& T, hipStream_t s) {
+  hipLaunchKernelGGL(k_keygen, dim3((unsigned)C.L), dim3(kNttThreads), lds_bytes(C), s, s_ntt, s_coeff, pk_coeff,
+                     pk_ntt, C, T);
+  return hipGetLastError();
+}
+
+// Kernels that stage more than 64 KiB of LDS must opt in once per process.
+hipError_t configure_lds_limits() {
+  const int max_lds = 160 * 1024;
+  hipError_t e = hipSuccess;
+  const void* fns[] = {(const void*)k_ntt_plain, (const void*)k_ntt_ct,   (const void*)k_ntt_pt,
+                       (const void*)k_ntt_ternary, (const void*)k_encrypt, (const void*)k_phase,
+                       (const void*)k_keygen};
+  for (const void* f : fns) {
+    hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+    if (r != hipSuccess) e = r;
+  }
+  return e;
+}
+
+}  // namespace pencil

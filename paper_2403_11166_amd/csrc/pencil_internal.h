@@ -1,0 +1,119 @@
+// Internal types shared by the host library and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace pencil {
+
+constexpr int kMaxLimbs = 4;
+constexpr int kMaxWords = 5;  // multiword integers up to 320 bits (q < 2^244)
+
+// Per-RNS-limb constants.  "_sh" fields are Shoup companions floor(w * 2^64 / q).
+struct LimbConst {
+  uint64_t q;
+  uint64_t r64, r64_sh;          // 2^64 mod q
+  uint64_t one_sh;               // floor(2^64 / q)
+  uint64_t ninv, ninv_sh;        // N^-1 mod q
+  uint64_t delta, delta_sh;      // floor(q / t) mod q_l
+  uint64_t t_sh;                 // floor(t * 2^64 / q_l), t < q_l
+  uint64_t qhat_inv, qhat_inv_sh;// ((q / q_l)^-1) mod q_l
+  uint64_t flood_off;            // 2^fb mod q_l
+  uint64_t mu_lo, mu_hi;         // floor(2^128 / q_l), for 128-bit Barrett reduction
+};
+
+// Everything a kernel needs about the parameter set; passed by value.
+struct Consts {
+  int32_t log2n, n, L, flood_words;
+  uint32_t flood_bits, mac_chunk, qwords, pad0;
+  uint64_t t, t_half;            // t and (t - 1) / 2
+  uint64_t rho, rho_sh;          // q mod t, floor(rho * 2^64 / t)
+  uint64_t r64t, r64t_sh;        // 2^64 mod t and floor(r64t * 2^64 / t)
+  uint64_t one_sh_t;             // floor(2^64 / t)
+  uint64_t top_mask;             // mask of the flood's top word
+  uint64_t seed;
+  LimbConst limb[kMaxLimbs];
+  uint64_t qhat[kMaxLimbs][kMaxWords];  // q / q_l, little-endian words
+  uint64_t thr[kMaxLimbs][kMaxWords];   // (2j + 1) * q, j = 0..L-1
+};
+
+// NTT tables, each [L][N]: psi^rev(k), psi^-rev(k) and Shoup companions.
+struct Tables {
+  const uint64_t* psi;
+  const uint64_t* psi_sh;
+  const uint64_t* ipsi;
+  const uint64_t* ipsi_sh;
+};
+
+// Partition of one packed correlation into N-slot tiles.
+struct Geo {
+  int32_t M, R, K, HA, WA, KH, KW, OH, OW;      // virtual operand dims
+  int32_t mt, rt, kt, oh, ow, kh, kw, ha, wa;   // tile dims (ha = oh + kh - 1)
+  int32_t nM, nR, nK, nOY, nOX, nKY, nKX;       // tile counts
+  int32_t S;                                    // kt * ha * wa
+  int32_t RS;                                   // rt * S: stride of m inside a tile
+  int32_t O;                                    // reverse-encoding offset
+  int32_t pad1;
+};
+
+// Maps virtual coordinates (i0, i1, y, x) of an operand to an element offset of
+// the caller's tensor.  A side: y, x are shifted by -pad and bounded by H, W.
+// K side: flip mirrors the kernel window.  Output: plain strides.
+struct View {
+  int64_t s0, s1, sy, sx;
+  int32_t pad, H, W, flip;
+  int32_t KH, KW, pad2, pad3;
+};
+
+// Philox stream purposes.
+enum Purpose : uint32_t {
+  P_SK = 1, P_PK_A = 2, P_PK_E = 3,
+  P_ENC_U = 16, P_ENC_E0 = 17, P_ENC_E1 = 18,
+  P_RR_U = 32, P_RR_E0 = 33, P_RR_E1 = 34, P_FLOOD = 35, P_MASK = 36,
+};
+constexpr uint64_t kKeygenNonce = ~0ull;
+
+inline uint64_t enc_object(int operand, uint64_t i) { return ((uint64_t)(operand + 1) << 48) | i; }
+inline uint64_t out_object(int op, uint64_t i) { return ((uint64_t)(op + 5) << 48) | i; }
+
+// One term of a product: which side holds the ciphertext and where both operands live
+// (NTT domain).  ct: [n][2][L][N]; pt: [n][L][N].
+struct MacTerm {
+  const uint64_t* a;   // A-side tiles
+  const uint64_t* k;   // K-side tiles
+  int32_t a_is_ct;     // 1: A side is a ciphertext, K side a plaintext; 0: the reverse
+  int32_t pad;
+};
+
+struct MacArgs {
+  MacTerm term[2];
+  int32_t n_terms;
+  int32_t m_rows;      // nM * nOY * nOX
+  const uint64_t* pk;  // [2][L][N], NTT domain
+  const uint64_t* u;   // [n_out][L][N], NTT domain
+  uint64_t* out;       // [n_out][2][L][N]
+};
+
+// ---------------------------------------------------------------- launchers
+// (defined in kernels.hip; all enqueue on `stream` and return the launch status)
+hipError_t launch_ntt_plain(uint64_t* data, int64_t polys, bool inverse, const Consts& C, const Tables& T,
+                            hipStream_t s);
+hipError_t launch_ntt_ct(const uint64_t* src, uint64_t* dst, int64_t n_ct, const int64_t* share, const Geo& G,
+                         const View& V, const Consts& C, const Tables& T, hipStream_t s);
+hipError_t launch_ntt_pt(const int64_t* tensor, uint64_t* dst, int64_t n_pt, int side, const Geo& G, const View& V,
+                         const Consts& C, const Tables& T, hipStream_t s);
+hipError_t launch_ntt_ternary(uint64_t* dst, int64_t count, uint64_t nonce, uint64_t obj_base, uint32_t purpose,
+                              const Consts& C, const Tables& T, hipStream_t s);
+hipError_t launch_mac(const MacArgs& A, int64_t n_out, const Geo& G, const Consts& C, hipStream_t s);
+hipError_t launch_flood_mask(uint64_t* ct, int64_t n_out, int64_t* share0, const int64_t* bias, const Geo& G,
+                             const View& outV, uint64_t nonce, uint64_t obj_base, const Consts& C, hipStream_t s);
+hipError_t launch_encrypt(const uint64_t* u_ntt, const int64_t* share, uint64_t* ct, int64_t n_ct, int side,
+                          const Geo& G, const View& V, const uint64_t* pk_ntt, const uint64_t* pk_sh, uint64_t nonce,
+                          uint64_t obj_base, const Consts& C, const Tables& T, hipStream_t s);
+hipError_t launch_phase(const uint64_t* ct, uint64_t* x, int64_t n_ct, const uint64_t* s_ntt, const uint64_t* s_sh,
+                        const Consts& C, const Tables& T, hipStream_t s);
+hipError_t launch_decode(const uint64_t* x, int64_t* share, int64_t n_out, const Geo& G, const View& outV,
+                         const Consts& C, hipStream_t s);
+hipError_t launch_keygen(uint64_t* s_ntt, int64_t* s_coeff, uint64_t* pk_coeff, uint64_t* pk_ntt,
+                         const Consts& C, const Tables& T, hipStream_t s);
+
+}  // namespace pencil
