@@ -143,6 +143,10 @@ pencil_status pencil_export_keys(const pencil_ctx* ctx, int64_t* sk /* host */, 
  * host only). */
 pencil_status pencil_plan_auto(const pencil_ctx* ctx, const pencil_layer* layer, pencil_plan* plan /* host */);
 
+/* The same choice without a context, for a degree N = 2^log2_n (host only,
+ * no GPU needed). */
+pencil_status pencil_plan_auto_n(uint32_t log2_n, const pencil_layer* layer, pencil_plan* plan /* host */);
+
 /* Buffer sizes for `layer` under `plan` (host).  A product whose tile is all
  * zero is treated as not planned and reported with zero sizes. */
 pencil_status pencil_layout(const pencil_ctx* ctx, const pencil_layer* layer, const pencil_plan* plan,
@@ -189,6 +193,19 @@ pencil_status pencil_decrypt(pencil_ctx* ctx, const pencil_layer* layer, const p
  * psi^(2 rev(i) + 1), rev = bit reversal of log2 N bits (Sec. V). */
 pencil_status pencil_ntt_forward(pencil_ctx* ctx, uint64_t* polys, int64_t count, void* stream);
 pencil_status pencil_ntt_inverse(pencil_ctx* ctx, uint64_t* polys, int64_t count, void* stream);
+
+/* Kernel timing: while enabled, every kernel this context launches is bracketed
+ * by HIP events recorded on its launch stream.  enable() clears the totals.
+ * read() waits for the recorded events and fills up to `max` entries (host
+ * memory): kernel name, launches and summed milliseconds. */
+typedef struct {
+    char name[24];
+    uint64_t launches;
+    double total_ms;
+} pencil_kernel_stat;
+
+pencil_status pencil_profile_enable(pencil_ctx* ctx, int enable);
+pencil_status pencil_profile_read(pencil_ctx* ctx, pencil_kernel_stat* out /* host */, int max, int* count);
 
 #ifdef __cplusplus
 }

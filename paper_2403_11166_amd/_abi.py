@@ -52,6 +52,10 @@ class Info(ctypes.Structure):
                 ("t", ctypes.c_uint64), ("seed", ctypes.c_uint64)]
 
 
+class KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 24), ("launches", ctypes.c_uint64), ("total_ms", ctypes.c_double)]
+
+
 # name -> (restype, argtypes)
 SIGNATURES = {
     "pencil_ctx_create": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_void_p)]),
@@ -71,6 +75,10 @@ SIGNATURES = {
                           + [ctypes.c_void_p] * 11 + [ctypes.c_uint64, ctypes.c_void_p]),
     "pencil_decrypt": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Layer), ctypes.POINTER(Plan), ctypes.c_int,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "pencil_plan_auto_n": (ctypes.c_int, [ctypes.c_uint32, ctypes.POINTER(Layer), ctypes.POINTER(Plan)]),
+    "pencil_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "pencil_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(KernelStat), ctypes.c_int,
+                                           ctypes.POINTER(ctypes.c_int)]),
     "pencil_ntt_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
     "pencil_ntt_inverse": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
 }

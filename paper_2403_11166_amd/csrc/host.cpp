@@ -37,7 +37,50 @@ struct pencil_ctx {
   uint64_t* d_pk_coeff = nullptr;
   int64_t* d_s_coeff = nullptr;
   std::string err;
+  // kernel timing with HIP events on the launch stream (pencil_profile_*)
+  bool prof_on = false;
+  std::vector<hipEvent_t> ev_pool;
+  struct Rec {
+    int kid;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> pending;
+  double prof_ms[16] = {};
+  uint64_t prof_launches[16] = {};
 };
+
+enum KernelId {
+  KID_NTT_CT, KID_NTT_PT, KID_NTT_TERNARY, KID_MAC, KID_INTT_OUT, KID_FLOOD, KID_ENCRYPT, KID_PHASE, KID_DECODE,
+  KID_NTT_PLAIN, KID_COUNT
+};
+static const char* kKernelNames[KID_COUNT] = {"ntt_ct", "ntt_pt", "ntt_ternary", "mac", "intt_out",
+                                              "flood_mask", "encrypt", "phase", "decode", "ntt_plain"};
+
+static hipEvent_t pool_event(pencil_ctx* ctx) {
+  if (!ctx->ev_pool.empty()) {
+    hipEvent_t e = ctx->ev_pool.back();
+    ctx->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Run `launch` and, when profiling is on, bracket it with events on stream s.
+template <class F>
+static hipError_t timed(pencil_ctx* ctx, int kid, hipStream_t s, F&& launch) {
+  if (!ctx->prof_on) return launch();
+  hipEvent_t a = pool_event(ctx), b = pool_event(ctx);
+  if (!a || !b) return hipErrorOutOfMemory;
+  hipError_t e = hipEventRecord(a, s);
+  if (e != hipSuccess) return e;
+  e = launch();
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(b, s);
+  ctx->pending.push_back({kid, a, b});
+  return e;
+}
 
 static thread_local std::string g_create_err;
 
@@ -350,6 +393,11 @@ extern "C" pencil_status pencil_ctx_destroy(pencil_ctx* ctx) {
   hipFree(ctx->d_pk_sh);
   hipFree(ctx->d_pk_coeff);
   hipFree(ctx->d_s_coeff);
+  for (auto& r : ctx->pending) {
+    hipEventDestroy(r.a);
+    hipEventDestroy(r.b);
+  }
+  for (hipEvent_t e : ctx->ev_pool) hipEventDestroy(e);
   delete ctx;
   return PENCIL_OK;
 }
@@ -682,10 +730,12 @@ extern "C" pencil_status pencil_encrypt(pencil_ctx* ctx, const pencil_layer* L, 
   const int64_t count = side ? n_k_tiles(G) : n_a_tiles(G);
   hipStream_t s = (hipStream_t)stream;
   uint64_t* u = (uint64_t*)ws;  // u^ of every ciphertext, [count][L][N]
-  hipError_t e = launch_ntt_ternary(u, count, nonce, enc_object(operand, 0), P_ENC_U, ctx->C, ctx->T, s);
+  hipError_t e = timed(ctx, KID_NTT_TERNARY, s, [&] { return launch_ntt_ternary(u, count, nonce, enc_object(operand, 0), P_ENC_U, ctx->C, ctx->T, s); });
   if (e == hipSuccess)
-    e = launch_encrypt(u, share, ct, count, side, G, V, ctx->d_pk_ntt, ctx->d_pk_sh, nonce, enc_object(operand, 0),
-                       ctx->C, ctx->T, s);
+    e = timed(ctx, KID_ENCRYPT, s, [&] {
+      return launch_encrypt(u, share, ct, count, side, G, V, ctx->d_pk_ntt, ctx->d_pk_sh, nonce,
+                            enc_object(operand, 0), ctx->C, ctx->T, s);
+    });
   if (e != hipSuccess) return fail(ctx, PENCIL_EHIP, "encrypt launch: %s", hipGetErrorString(e));
   return PENCIL_OK;
 }
@@ -716,8 +766,9 @@ static pencil_status run_product(pencil_ctx* ctx, const pencil_layer* L, int op,
       w += na * ctw;
       uint64_t* pts = w;
       w += nk * poly;
-      hipError_t e = launch_ntt_ct(T.ct, cts, na, add_share, G, view_a(L, op), C, ctx->T, s);
-      if (e == hipSuccess) e = launch_ntt_pt(T.pt, pts, nk, 1, G, view_k(L, op), C, ctx->T, s);
+      hipError_t e = timed(ctx, KID_NTT_CT, s, [&] { return launch_ntt_ct(T.ct, cts, na, add_share, G, view_a(L, op), C, ctx->T, s); });
+      if (e == hipSuccess)
+        e = timed(ctx, KID_NTT_PT, s, [&] { return launch_ntt_pt(T.pt, pts, nk, 1, G, view_k(L, op), C, ctx->T, s); });
       if (e != hipSuccess) return fail(ctx, PENCIL_EHIP, "ntt launch: %s", hipGetErrorString(e));
       A.term[i] = MacTerm{cts, pts, 1, 0};
     } else {
@@ -725,19 +776,23 @@ static pencil_status run_product(pencil_ctx* ctx, const pencil_layer* L, int op,
       w += na * poly;
       uint64_t* cts = w;
       w += nk * ctw;
-      hipError_t e = launch_ntt_pt(T.pt, pts, na, 0, G, view_a(L, op), C, ctx->T, s);
-      if (e == hipSuccess) e = launch_ntt_ct(T.ct, cts, nk, nullptr, G, view_k(L, op), C, ctx->T, s);
+      hipError_t e = timed(ctx, KID_NTT_PT, s, [&] { return launch_ntt_pt(T.pt, pts, na, 0, G, view_a(L, op), C, ctx->T, s); });
+      if (e == hipSuccess)
+        e = timed(ctx, KID_NTT_CT, s, [&] { return launch_ntt_ct(T.ct, cts, nk, nullptr, G, view_k(L, op), C, ctx->T, s); });
       if (e != hipSuccess) return fail(ctx, PENCIL_EHIP, "ntt launch: %s", hipGetErrorString(e));
       A.term[i] = MacTerm{pts, cts, 0, 0};
     }
   }
   uint64_t* u = w;
   const uint64_t obj = out_object(op, 0);
-  hipError_t e = launch_ntt_ternary(u, no, nonce, obj, P_RR_U, C, ctx->T, s);
+  hipError_t e = timed(ctx, KID_NTT_TERNARY, s, [&] { return launch_ntt_ternary(u, no, nonce, obj, P_RR_U, C, ctx->T, s); });
   A.u = u;
-  if (e == hipSuccess) e = launch_mac(A, no, G, C, s);
-  if (e == hipSuccess) e = launch_ntt_plain(ct_out, 2 * no, true, C, ctx->T, s);
-  if (e == hipSuccess) e = launch_flood_mask(ct_out, no, share_out, bias, G, view_out(L, op), nonce, obj, C, s);
+  if (e == hipSuccess) e = timed(ctx, KID_MAC, s, [&] { return launch_mac(A, no, G, C, s); });
+  if (e == hipSuccess) e = timed(ctx, KID_INTT_OUT, s, [&] { return launch_ntt_plain(ct_out, 2 * no, true, C, ctx->T, s); });
+  if (e == hipSuccess)
+    e = timed(ctx, KID_FLOOD, s, [&] {
+      return launch_flood_mask(ct_out, no, share_out, bias, G, view_out(L, op), nonce, obj, C, s);
+    });
   if (e != hipSuccess) return fail(ctx, PENCIL_EHIP, "product launch: %s", hipGetErrorString(e));
   return PENCIL_OK;
 }
@@ -812,8 +867,8 @@ extern "C" pencil_status pencil_decrypt(pencil_ctx* ctx, const pencil_layer* L, 
   const int64_t no = n_out_tiles(G);
   hipStream_t s = (hipStream_t)stream;
   uint64_t* x = (uint64_t*)ws;
-  hipError_t e = launch_phase(ct, x, no, ctx->d_s_ntt, ctx->d_s_sh, ctx->C, ctx->T, s);
-  if (e == hipSuccess) e = launch_decode(x, share, no, G, view_out(L, op), ctx->C, s);
+  hipError_t e = timed(ctx, KID_PHASE, s, [&] { return launch_phase(ct, x, no, ctx->d_s_ntt, ctx->d_s_sh, ctx->C, ctx->T, s); });
+  if (e == hipSuccess) e = timed(ctx, KID_DECODE, s, [&] { return launch_decode(x, share, no, G, view_out(L, op), ctx->C, s); });
   if (e != hipSuccess) return fail(ctx, PENCIL_EHIP, "decrypt launch: %s", hipGetErrorString(e));
   return PENCIL_OK;
 }
@@ -822,7 +877,8 @@ extern "C" pencil_status pencil_ntt_forward(pencil_ctx* ctx, uint64_t* polys, in
   if (!ctx) return PENCIL_EINVAL;
   TRY(check_ptr(ctx, polys, "polys"));
   if (count < 0) return fail(ctx, PENCIL_EINVAL, "count < 0");
-  hipError_t e = launch_ntt_plain(polys, count, false, ctx->C, ctx->T, (hipStream_t)stream);
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = timed(ctx, KID_NTT_PLAIN, s, [&] { return launch_ntt_plain(polys, count, false, ctx->C, ctx->T, s); });
   if (e != hipSuccess) return fail(ctx, PENCIL_EHIP, "ntt launch: %s", hipGetErrorString(e));
   return PENCIL_OK;
 }
@@ -831,7 +887,61 @@ extern "C" pencil_status pencil_ntt_inverse(pencil_ctx* ctx, uint64_t* polys, in
   if (!ctx) return PENCIL_EINVAL;
   TRY(check_ptr(ctx, polys, "polys"));
   if (count < 0) return fail(ctx, PENCIL_EINVAL, "count < 0");
-  hipError_t e = launch_ntt_plain(polys, count, true, ctx->C, ctx->T, (hipStream_t)stream);
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = timed(ctx, KID_NTT_PLAIN, s, [&] { return launch_ntt_plain(polys, count, true, ctx->C, ctx->T, s); });
   if (e != hipSuccess) return fail(ctx, PENCIL_EHIP, "ntt launch: %s", hipGetErrorString(e));
+  return PENCIL_OK;
+}
+
+// ------------------------------------------------------------ profiling
+
+extern "C" pencil_status pencil_profile_enable(pencil_ctx* ctx, int enable) {
+  if (!ctx) return PENCIL_EINVAL;
+  for (auto& r : ctx->pending) {
+    hipEventSynchronize(r.b);
+    ctx->ev_pool.push_back(r.a);
+    ctx->ev_pool.push_back(r.b);
+  }
+  ctx->pending.clear();
+  for (int k = 0; k < KID_COUNT; ++k) {
+    ctx->prof_ms[k] = 0;
+    ctx->prof_launches[k] = 0;
+  }
+  ctx->prof_on = enable != 0;
+  return PENCIL_OK;
+}
+
+extern "C" pencil_status pencil_profile_read(pencil_ctx* ctx, pencil_kernel_stat* out, int max, int* count) {
+  if (!ctx || !count) return PENCIL_EINVAL;
+  for (auto& r : ctx->pending) {
+    HIP_TRY(ctx, hipEventSynchronize(r.b));
+    float ms = 0;
+    HIP_TRY(ctx, hipEventElapsedTime(&ms, r.a, r.b));
+    ctx->prof_ms[r.kid] += ms;
+    ctx->prof_launches[r.kid] += 1;
+    ctx->ev_pool.push_back(r.a);
+    ctx->ev_pool.push_back(r.b);
+  }
+  ctx->pending.clear();
+  int n = 0;
+  for (int k = 0; k < KID_COUNT && n < max; ++k) {
+    if (!out) break;
+    std::memset(&out[n], 0, sizeof out[n]);
+    std::snprintf(out[n].name, sizeof out[n].name, "%s", kKernelNames[k]);
+    out[n].launches = ctx->prof_launches[k];
+    out[n].total_ms = ctx->prof_ms[k];
+    ++n;
+  }
+  *count = n;
+  return PENCIL_OK;
+}
+
+extern "C" pencil_status pencil_plan_auto_n(uint32_t log2_n, const pencil_layer* L, pencil_plan* plan) {
+  if (!plan || log2_n < 10 || log2_n > 14) return fail(nullptr, PENCIL_EINVAL, "bad plan request");
+  pencil_status st = PENCIL_OK;
+  if (!layer_ok(nullptr, L, &st)) return st;
+  pencil_tile* tiles[3] = {&plan->fwd, &plan->dx, &plan->dw};
+  for (int op = 0; op < 3; ++op)
+    if (!plan_op(L, op, (int)log2_n, tiles[op])) return fail(nullptr, PENCIL_EUNSUPPORTED, "no tile fits");
   return PENCIL_OK;
 }
