@@ -29,7 +29,7 @@ struct pencil_ctx {
   Tables T{};
   int device = 0;
   // device memory owned by the context
-  uint64_t* d_tables = nullptr;  // psi, psi_sh, ipsi, ipsi_sh: 4 x [L][N]
+  TW* d_tables = nullptr;        // forward then inverse twiddles, each [L][N]
   uint64_t* d_s_ntt = nullptr;   // [L][N]
   uint64_t* d_s_sh = nullptr;    // [L][N]
   uint64_t* d_pk_ntt = nullptr;  // [2][L][N]
@@ -331,17 +331,15 @@ extern "C" pencil_status pencil_ctx_create(const pencil_params* params, pencil_c
   }
   const Consts& C = ctx->C;
   const size_t n = (size_t)C.n, L = (size_t)C.L;
-  // NTT tables
-  std::vector<uint64_t> tab(4 * L * n);
+  // NTT tables: [L][N] pairs (w, floor(w 2^64 / q)) of psi^rev(k), then of psi^-rev(k)
+  std::vector<TW> tab(2 * L * n);
   for (size_t l = 0; l < L; ++l) {
     const uint64_t q = C.limb[l].q, psi = ctx->info.psi[l], ipsi = powmod(psi, q - 2, q);
     for (size_t k = 0; k < n; ++k) {
       uint32_t e = bitrev((uint32_t)k, C.log2n);
       uint64_t w = powmod(psi, e, q), iw = powmod(ipsi, e, q);
-      tab[0 * L * n + l * n + k] = w;
-      tab[1 * L * n + l * n + k] = shoup(w, q);
-      tab[2 * L * n + l * n + k] = iw;
-      tab[3 * L * n + l * n + k] = shoup(iw, q);
+      tab[l * n + k] = TW{w, shoup(w, q)};
+      tab[L * n + l * n + k] = TW{iw, shoup(iw, q)};
     }
   }
   auto cleanup = [&](pencil_status s) {
@@ -351,17 +349,15 @@ extern "C" pencil_status pencil_ctx_create(const pencil_params* params, pencil_c
   if (hipGetDevice(&ctx->device) != hipSuccess) return cleanup(fail(nullptr, PENCIL_EHIP, "no HIP device"));
   if (configure_lds_limits() != hipSuccess) return cleanup(fail(nullptr, PENCIL_EHIP, "cannot raise LDS limit"));
   const size_t ln = L * n * sizeof(uint64_t);
-  if (hipMalloc(&ctx->d_tables, 4 * ln) != hipSuccess || hipMalloc(&ctx->d_s_ntt, ln) != hipSuccess ||
+  if (hipMalloc(&ctx->d_tables, 2 * L * n * sizeof(TW)) != hipSuccess || hipMalloc(&ctx->d_s_ntt, ln) != hipSuccess ||
       hipMalloc(&ctx->d_s_sh, ln) != hipSuccess || hipMalloc(&ctx->d_pk_ntt, 2 * ln) != hipSuccess ||
       hipMalloc(&ctx->d_pk_sh, 2 * ln) != hipSuccess || hipMalloc(&ctx->d_pk_coeff, 2 * ln) != hipSuccess ||
       hipMalloc(&ctx->d_s_coeff, n * sizeof(int64_t)) != hipSuccess)
     return cleanup(fail(nullptr, PENCIL_ENOMEM, "device allocation failed"));
-  if (hipMemcpy(ctx->d_tables, tab.data(), 4 * ln, hipMemcpyHostToDevice) != hipSuccess)
+  if (hipMemcpy(ctx->d_tables, tab.data(), 2 * L * n * sizeof(TW), hipMemcpyHostToDevice) != hipSuccess)
     return cleanup(fail(nullptr, PENCIL_EHIP, "table upload failed"));
-  ctx->T.psi = ctx->d_tables;
-  ctx->T.psi_sh = ctx->d_tables + L * n;
-  ctx->T.ipsi = ctx->d_tables + 2 * L * n;
-  ctx->T.ipsi_sh = ctx->d_tables + 3 * L * n;
+  ctx->T.fw = ctx->d_tables;
+  ctx->T.iw = ctx->d_tables + L * n;
   // keys
   if (launch_keygen(ctx->d_s_ntt, ctx->d_s_coeff, ctx->d_pk_coeff, ctx->d_pk_ntt, C, ctx->T, nullptr) != hipSuccess ||
       hipDeviceSynchronize() != hipSuccess)

@@ -6,47 +6,174 @@
 
 namespace pencil {
 
-constexpr int kNttThreads = 512;
-
 // ----------------------------------------------------------------- NTT core
-// Merged negacyclic Cooley-Tukey transform (the psi twist folded into the
-// twiddles, psi^rev(k) tables): natural order in, bit-reversed order out.
-// Stage with m groups and half-size t = N / 2m: pair (i0, i0 + t) of group i
-// uses w = psi^rev(m + i).
-__device__ void ntt_forward_lds(uint64_t* a, int log2n, const uint64_t* tw, const uint64_t* tw_sh, uint64_t q) {
-  const int half = 1 << (log2n - 1);
-  for (int lm = 0; lm < log2n; ++lm) {
-    const int lt = log2n - 1 - lm;
-    const int m = 1 << lm;
-    const int tmask = (1 << lt) - 1;
-    for (int b = threadIdx.x; b < half; b += blockDim.x) {
-      const int i = b >> lt, j = b & tmask;
-      const int i0 = (i << (lt + 1)) + j, i1 = i0 + (1 << lt);
-      const uint64_t w = tw[m + i], ws = tw_sh[m + i];
-      const uint64_t u = a[i0];
-      const uint64_t v = mul_shoup(a[i1], w, ws, q);
-      a[i0] = add_mod(u, v, q);
-      a[i1] = sub_mod(u, v, q);
+// One workgroup transforms one limb-polynomial held in LDS.  N/E threads each
+// keep E residues in registers (E = 16, or 32 at N = 16384) and run several
+// butterfly stages per LDS round trip; the log2 N stages are split into
+// ceil(log2 N / log2 E) passes of near-equal size.  LDS rows are padded by one
+// word every 32 so that strided passes spread over the banks.
+__device__ __forceinline__ int lpad(int i) { return i + (i >> 5); }
+
+template <int LOGN>
+struct NttShape {
+  static constexpr int LOGE = LOGN >= 14 ? 5 : 4;
+  static constexpr int E = 1 << LOGE;
+  static constexpr int T = (1 << LOGN) / E;  // threads per block
+  static constexpr int NP = (LOGN + LOGE - 1) / LOGE;
+  // stages in pass i: the first LOGN % NP passes take one more
+  static constexpr int size(int i) { return LOGN / NP + (i < LOGN % NP ? 1 : 0); }
+  static constexpr int start(int i) { return i == 0 ? 0 : start(i - 1) + size(i - 1); }
+};
+
+// Harvey's lazy Cooley-Tukey butterfly: x, y in [0, 4q) -> [0, 4q), q < 2^62.
+__device__ __forceinline__ void ct_bfly(uint64_t& x, uint64_t& y, const TW w, uint64_t q, uint64_t q2) {
+  const uint64_t a = x >= q2 ? x - q2 : x;
+  const uint64_t t = mul_shoup_lazy(y, w.w, w.ws, q);
+  x = a + t;
+  y = a - t + q2;
+}
+
+// Lazy Gentleman-Sande butterfly: u, v in [0, 2q) -> [0, 2q).
+__device__ __forceinline__ void gs_bfly(uint64_t& u, uint64_t& v, const TW w, uint64_t q, uint64_t q2) {
+  uint64_t s = u + v;
+  s = s >= q2 ? s - q2 : s;
+  const uint64_t d = u - v + q2;
+  v = mul_shoup_lazy(d, w.w, w.ws, q);
+  u = s;
+}
+
+// Forward (merged negacyclic Cooley-Tukey, psi^rev twiddles; natural order in,
+// bit-reversed out) stages S0 .. S0+S-1.  At stage l (t = N >> (l+1)) the pair
+// (i0, i0 + t) of group i = i0 >> (log2 N - l) uses tw[2^l + i].  A thread takes
+// E / 2^S groups of 2^S residues {base + k * 2^LT}, LT = log2 N - S0 - S.
+template <int LOGN, int S0, int S, bool LAST>
+__device__ __forceinline__ void fwd_pass(uint64_t* a, const TW* tw, uint64_t q, uint64_t q2) {
+  using Sh = NttShape<LOGN>;
+  constexpr int T = Sh::T, G = Sh::E >> S, K = 1 << S, LT = LOGN - S0 - S;
+  const int tid = threadIdx.x;
+  uint64_t v[Sh::E];
+#pragma unroll
+  for (int r = 0; r < G; ++r) {
+    const int g = r * T + tid;
+    const int base = ((g >> LT) << (LOGN - S0)) + (g & ((1 << LT) - 1));
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[r * K + k] = a[lpad(base + (k << LT))];
+  }
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int h = 1 << (S - 1 - s);
+#pragma unroll
+    for (int r = 0; r < G; ++r) {
+      const int blk = (r * T + tid) >> LT;
+#pragma unroll
+      for (int j = 0; j < (1 << s); ++j) {
+        const TW w = tw[(1 << (S0 + s)) + (blk << s) + j];
+#pragma unroll
+        for (int k = j << (S - s); k < ((j + 1) << (S - s)); ++k) {
+          if (k & h) continue;
+          ct_bfly(v[r * K + k], v[r * K + k + h], w, q, q2);
+        }
+      }
     }
+  }
+#pragma unroll
+  for (int r = 0; r < G; ++r) {
+    const int g = r * T + tid;
+    const int base = ((g >> LT) << (LOGN - S0)) + (g & ((1 << LT) - 1));
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      uint64_t x = v[r * K + k];
+      if (LAST) {
+        x = x >= q2 ? x - q2 : x;
+        x = x >= q ? x - q : x;
+      }
+      a[lpad(base + (k << LT))] = x;
+    }
+  }
+}
+
+// Inverse (Gentleman-Sande, psi^-rev twiddles; bit-reversed in, natural out)
+// stages with t = 2^L0 .. 2^(L0+S-1): pair (i0, i0 + t), i = i0 >> (l + 1),
+// twiddle itw[(N >> (l + 1)) + i].  Groups are {base + k * 2^L0}.
+template <int LOGN, int L0, int S>
+__device__ __forceinline__ void inv_pass(uint64_t* a, const TW* tw, uint64_t q, uint64_t q2) {
+  using Sh = NttShape<LOGN>;
+  constexpr int T = Sh::T, G = Sh::E >> S, K = 1 << S;
+  const int tid = threadIdx.x;
+  uint64_t v[Sh::E];
+#pragma unroll
+  for (int r = 0; r < G; ++r) {
+    const int g = r * T + tid;
+    const int base = ((g >> L0) << (L0 + S)) + (g & ((1 << L0) - 1));
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[r * K + k] = a[lpad(base + (k << L0))];
+  }
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int h = 1 << s;
+    const int m = (1 << LOGN) >> (L0 + s + 1);
+#pragma unroll
+    for (int r = 0; r < G; ++r) {
+      const int blk = (r * T + tid) >> L0;
+#pragma unroll
+      for (int j = 0; j < (K >> (s + 1)); ++j) {
+        const TW w = tw[m + (blk << (S - s - 1)) + j];
+#pragma unroll
+        for (int k = j << (s + 1); k < ((j + 1) << (s + 1)); ++k) {
+          if (k & h) continue;
+          gs_bfly(v[r * K + k], v[r * K + k + h], w, q, q2);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < G; ++r) {
+    const int g = r * T + tid;
+    const int base = ((g >> L0) << (L0 + S)) + (g & ((1 << L0) - 1));
+#pragma unroll
+    for (int k = 0; k < K; ++k) a[lpad(base + (k << L0))] = v[r * K + k];
+  }
+}
+
+// Forward transform of the LDS polynomial (inputs in [0, q), outputs in [0, q)).
+// Callers synchronise before (inputs written) and after (outputs read).
+template <int LOGN>
+__device__ __forceinline__ void ntt_fwd(uint64_t* a, const TW* tw, uint64_t q) {
+  using Sh = NttShape<LOGN>;
+  const uint64_t q2 = 2 * q;
+  fwd_pass<LOGN, Sh::start(0), Sh::size(0), Sh::NP == 1>(a, tw, q, q2);
+  __syncthreads();
+  if constexpr (Sh::NP > 1) {
+    fwd_pass<LOGN, Sh::start(1), Sh::size(1), Sh::NP == 2>(a, tw, q, q2);
+    __syncthreads();
+  }
+  if constexpr (Sh::NP > 2) {
+    fwd_pass<LOGN, Sh::start(2), Sh::size(2), Sh::NP == 3>(a, tw, q, q2);
+    __syncthreads();
+  }
+  if constexpr (Sh::NP > 3) {
+    fwd_pass<LOGN, Sh::start(3), Sh::size(3), true>(a, tw, q, q2);
     __syncthreads();
   }
 }
 
-// Gentleman-Sande inverse with psi^-rev(k) twiddles, bit-reversed in, natural
-// out; the caller applies the N^-1 factor.
-__device__ void ntt_inverse_lds(uint64_t* a, int log2n, const uint64_t* tw, const uint64_t* tw_sh, uint64_t q) {
-  const int half = 1 << (log2n - 1);
-  for (int lt = 0; lt < log2n; ++lt) {
-    const int m = half >> lt;
-    const int tmask = (1 << lt) - 1;
-    for (int b = threadIdx.x; b < half; b += blockDim.x) {
-      const int i = b >> lt, j = b & tmask;
-      const int i0 = (i << (lt + 1)) + j, i1 = i0 + (1 << lt);
-      const uint64_t w = tw[m + i], ws = tw_sh[m + i];
-      const uint64_t u = a[i0], v = a[i1];
-      a[i0] = add_mod(u, v, q);
-      a[i1] = mul_shoup(sub_mod(u, v, q), w, ws, q);
-    }
+// Inverse transform without the N^-1 factor (inputs in [0, 2q), outputs in [0, 2q)).
+template <int LOGN>
+__device__ __forceinline__ void ntt_inv(uint64_t* a, const TW* tw, uint64_t q) {
+  using Sh = NttShape<LOGN>;
+  const uint64_t q2 = 2 * q;
+  inv_pass<LOGN, Sh::start(0), Sh::size(0)>(a, tw, q, q2);
+  __syncthreads();
+  if constexpr (Sh::NP > 1) {
+    inv_pass<LOGN, Sh::start(1), Sh::size(1)>(a, tw, q, q2);
+    __syncthreads();
+  }
+  if constexpr (Sh::NP > 2) {
+    inv_pass<LOGN, Sh::start(2), Sh::size(2)>(a, tw, q, q2);
+    __syncthreads();
+  }
+  if constexpr (Sh::NP > 3) {
+    inv_pass<LOGN, Sh::start(3), Sh::size(3)>(a, tw, q, q2);
     __syncthreads();
   }
 }
@@ -127,31 +254,35 @@ __device__ __forceinline__ int64_t slot_offset(int side, const Geo& G, const Vie
 // ------------------------------------------------------------------ kernels
 
 // In-place forward or inverse NTT of [polys][L][N].
-__global__ void __launch_bounds__(kNttThreads) k_ntt_plain(uint64_t* data, int inverse, Consts C, Tables T) {
+template <int LOGN>
+__global__ void __launch_bounds__(512, (LOGN >= 14 ? 2 : 4)) k_ntt_plain(uint64_t* data, int inverse, Consts C, Tables T) {
   extern __shared__ uint64_t lds[];
-  const int n = C.n, L = C.L;
+  constexpr int n = 1 << LOGN;
+  const int L = C.L;
   const int64_t p = blockIdx.x;
   const int l = (int)(p % L);
   const LimbConst& lc = C.limb[l];
   uint64_t* g = data + p * n;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) lds[i] = g[i];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) lds[lpad(i)] = g[i];
   __syncthreads();
   if (!inverse) {
-    ntt_forward_lds(lds, C.log2n, T.psi + (int64_t)l * n, T.psi_sh + (int64_t)l * n, lc.q);
-    for (int i = threadIdx.x; i < n; i += blockDim.x) g[i] = lds[i];
+    ntt_fwd<LOGN>(lds, T.fw + (int64_t)l * n, lc.q);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) g[i] = lds[lpad(i)];
   } else {
-    ntt_inverse_lds(lds, C.log2n, T.ipsi + (int64_t)l * n, T.ipsi_sh + (int64_t)l * n, lc.q);
-    for (int i = threadIdx.x; i < n; i += blockDim.x) g[i] = mul_shoup(lds[i], lc.ninv, lc.ninv_sh, lc.q);
+    ntt_inv<LOGN>(lds, T.iw + (int64_t)l * n, lc.q);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) g[i] = mul_shoup(lds[lpad(i)], lc.ninv, lc.ninv_sh, lc.q);
   }
 }
 
 // Input ciphertexts: load (coefficient domain), add round(q m / t) of the model
 // owner's share on component 0 (Alg. 1 line 2), forward NTT, store.
 // Grid: n_ct * 2 * L blocks, polynomial p = (j, c, l) in [n][2][L] order.
-__global__ void __launch_bounds__(kNttThreads) k_ntt_ct(const uint64_t* src, uint64_t* dst, const int64_t* share,
-                                                        Geo G, View V, Consts C, Tables T) {
+template <int LOGN>
+__global__ void __launch_bounds__(512, (LOGN >= 14 ? 2 : 4)) k_ntt_ct(const uint64_t* src, uint64_t* dst, const int64_t* share, Geo G,
+                                                 View V, Consts C, Tables T) {
   extern __shared__ uint64_t lds[];
-  const int n = C.n, L = C.L;
+  constexpr int n = 1 << LOGN;
+  const int L = C.L;
   const int64_t p = blockIdx.x;
   const int l = (int)(p % L);
   const int c = (int)((p / L) % 2);
@@ -168,20 +299,22 @@ __global__ void __launch_bounds__(kNttThreads) k_ntt_ct(const uint64_t* src, uin
         v = add_mod(v, delta_scale(m, round_rho(m, C), lc), lc.q);
       }
     }
-    lds[i] = v;
+    lds[lpad(i)] = v;
   }
   __syncthreads();
-  ntt_forward_lds(lds, C.log2n, T.psi + (int64_t)l * n, T.psi_sh + (int64_t)l * n, lc.q);
+  ntt_fwd<LOGN>(lds, T.fw + (int64_t)l * n, lc.q);
   uint64_t* o = dst + p * n;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) o[i] = lds[i];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) o[i] = lds[lpad(i)];
 }
 
 // Plaintext tiles: encode (side 0: forward A tile, 1: reverse K tile), centred
 // lift of Z_t into Z_{q_l}, forward NTT.  Grid: n_pt * L, output [n][L][N].
-__global__ void __launch_bounds__(kNttThreads) k_ntt_pt(const int64_t* tensor, uint64_t* dst, int side, Geo G,
-                                                        View V, Consts C, Tables T) {
+template <int LOGN>
+__global__ void __launch_bounds__(512, (LOGN >= 14 ? 2 : 4)) k_ntt_pt(const int64_t* tensor, uint64_t* dst, int side, Geo G, View V,
+                                                 Consts C, Tables T) {
   extern __shared__ uint64_t lds[];
-  const int n = C.n, L = C.L;
+  constexpr int n = 1 << LOGN;
+  const int L = C.L;
   const int64_t p = blockIdx.x;
   const int l = (int)(p % L);
   const int64_t j = p / L;
@@ -193,21 +326,23 @@ __global__ void __launch_bounds__(kNttThreads) k_ntt_pt(const int64_t* tensor, u
       uint64_t w = (uint64_t)tensor[off];
       v = w <= C.t_half ? w : lc.q - (C.t - w);
     }
-    lds[i] = v;
+    lds[lpad(i)] = v;
   }
   __syncthreads();
-  ntt_forward_lds(lds, C.log2n, T.psi + (int64_t)l * n, T.psi_sh + (int64_t)l * n, lc.q);
+  ntt_fwd<LOGN>(lds, T.fw + (int64_t)l * n, lc.q);
   uint64_t* o = dst + p * n;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) o[i] = lds[i];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) o[i] = lds[lpad(i)];
 }
 
 // Fresh ternary polynomials (object obj_base + j, stream `purpose`), lifted and
 // transformed.  Coefficient i uses the 32-bit half i mod 2 of stream word i/2,
 // so one Philox block covers 8 coefficients.  Grid: count * L, output [n][L][N].
-__global__ void __launch_bounds__(kNttThreads) k_ntt_ternary(uint64_t* dst, uint64_t nonce, uint64_t obj_base,
-                                                             uint32_t purpose, Consts C, Tables T) {
+template <int LOGN>
+__global__ void __launch_bounds__(512, (LOGN >= 14 ? 2 : 4)) k_ntt_ternary(uint64_t* dst, uint64_t nonce, uint64_t obj_base,
+                                                      uint32_t purpose, Consts C, Tables T) {
   extern __shared__ uint64_t lds[];
-  const int n = C.n, L = C.L;
+  constexpr int n = 1 << LOGN;
+  const int L = C.L;
   const int64_t p = blockIdx.x;
   const int l = (int)(p % L);
   const int64_t j = p / L;
@@ -217,13 +352,13 @@ __global__ void __launch_bounds__(kNttThreads) k_ntt_ternary(uint64_t* dst, uint
 #pragma unroll
     for (int h = 0; h < 8; ++h) {
       uint32_t half = (uint32_t)(w.v[h >> 1] >> (32 * (h & 1)));
-      lds[blk * 8 + h] = small_to_mod(ternary32(half), lc.q);
+      lds[lpad(blk * 8 + h)] = small_to_mod(ternary32(half), lc.q);
     }
   }
   __syncthreads();
-  ntt_forward_lds(lds, C.log2n, T.psi + (int64_t)l * n, T.psi_sh + (int64_t)l * n, lc.q);
+  ntt_fwd<LOGN>(lds, T.fw + (int64_t)l * n, lc.q);
   uint64_t* o = dst + p * n;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) o[i] = lds[i];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) o[i] = lds[lpad(i)];
 }
 
 // Pointwise multiply-accumulate over contraction tiles, per NTT slot:
@@ -350,6 +485,7 @@ __global__ void __launch_bounds__(256) k_mac(MacArgs A, Geo G, Consts C) {
 // Output ciphertexts after the inverse NTT: c0 += e0' + flood - round(q s / t),
 // c1 += e1'; the model owner's share is s at the output slots (+ bias).
 // Each thread handles 4 consecutive coefficients of one output ciphertext.
+template <int W>
 __global__ void __launch_bounds__(256) k_flood_mask(uint64_t* ct, int64_t n_out, int64_t* share0,
                                                     const int64_t* bias, Geo G, View OV, uint64_t nonce,
                                                     uint64_t obj_base, Consts C) {
@@ -365,8 +501,8 @@ __global__ void __launch_bounds__(256) k_flood_mask(uint64_t* ct, int64_t n_out,
   U64x4 e1 = philox(blk4, obj, P_RR_E1, 0, C.seed, nonce);
   U64x4 mk0 = philox(2 * blk4, obj, P_MASK, 0, C.seed, nonce);
   U64x4 mk1 = philox(2 * blk4 + 1, obj, P_MASK, 0, C.seed, nonce);
-  const int W = C.flood_words;
-  uint64_t fw[16];  // 4 coefficients x up to 4 words
+  uint64_t fw[4 * W];  // the 4W flood words of these 4 coefficients, in stream order
+#pragma unroll
   for (int b = 0; b < W; ++b) {
     U64x4 f = philox(blk4 * W + b, obj, P_FLOOD, 0, C.seed, nonce);
 #pragma unroll
@@ -397,6 +533,7 @@ __global__ void __launch_bounds__(256) k_flood_mask(uint64_t* ct, int64_t n_out,
       const LimbConst& lc = C.limb[l];
       // flood value V - 2^fb with V the low fb+1 bits of the words, by Horner in base 2^64
       uint64_t v = 0;
+#pragma unroll
       for (int b = W - 1; b >= 0; --b) {
         uint64_t w = fw[z * W + b];
         if (b == W - 1) w &= C.top_mask;
@@ -435,12 +572,13 @@ __global__ void __launch_bounds__(256) k_flood_mask(uint64_t* ct, int64_t n_out,
 
 // Encryption: ct_c = INTT(pk_c * u) + e_c (+ round(q m / t) on c = 0), with m
 // the encoded share at each slot.  Grid: n_ct * 2 * L, u_ntt is [n][L][N].
-__global__ void __launch_bounds__(kNttThreads) k_encrypt(const uint64_t* u_ntt, const int64_t* share, uint64_t* ct,
-                                                         int side, Geo G, View V, const uint64_t* pk_ntt,
-                                                         const uint64_t* pk_sh, uint64_t nonce, uint64_t obj_base,
-                                                         Consts C, Tables T) {
+template <int LOGN>
+__global__ void __launch_bounds__(512, (LOGN >= 14 ? 2 : 4)) k_encrypt(const uint64_t* u_ntt, const int64_t* share, uint64_t* ct, int side,
+                                                  Geo G, View V, const uint64_t* pk_ntt, const uint64_t* pk_sh,
+                                                  uint64_t nonce, uint64_t obj_base, Consts C, Tables T) {
   extern __shared__ uint64_t lds[];
-  const int n = C.n, L = C.L;
+  constexpr int n = 1 << LOGN;
+  const int L = C.L;
   const int64_t p = blockIdx.x;
   const int l = (int)(p % L);
   const int c = (int)((p / L) % 2);
@@ -449,9 +587,9 @@ __global__ void __launch_bounds__(kNttThreads) k_encrypt(const uint64_t* u_ntt, 
   const uint64_t* u = u_ntt + (j * L + l) * n;
   const uint64_t* pk = pk_ntt + ((int64_t)c * L + l) * n;
   const uint64_t* pks = pk_sh + ((int64_t)c * L + l) * n;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) lds[i] = mul_shoup(u[i], pk[i], pks[i], lc.q);
+  for (int i = threadIdx.x; i < n; i += blockDim.x) lds[lpad(i)] = mul_shoup(u[i], pk[i], pks[i], lc.q);
   __syncthreads();
-  ntt_inverse_lds(lds, C.log2n, T.ipsi + (int64_t)l * n, T.ipsi_sh + (int64_t)l * n, lc.q);
+  ntt_inv<LOGN>(lds, T.iw + (int64_t)l * n, lc.q);
   const uint64_t obj = obj_base + (uint64_t)j;
   uint64_t* o = ct + p * n;
   for (int blk = threadIdx.x; blk < n / 4; blk += blockDim.x) {
@@ -459,7 +597,7 @@ __global__ void __launch_bounds__(kNttThreads) k_encrypt(const uint64_t* u_ntt, 
 #pragma unroll
     for (int z = 0; z < 4; ++z) {
       const int i = blk * 4 + z;
-      uint64_t v = mul_shoup(lds[i], lc.ninv, lc.ninv_sh, lc.q);
+      uint64_t v = mul_shoup(lds[lpad(i)], lc.ninv, lc.ninv_sh, lc.q);
       v = add_mod(v, small_to_mod(cbd21(e.v[z]), lc.q), lc.q);
       if (c == 0) {
         int64_t off = slot_offset(side, G, V, j, i);
@@ -474,27 +612,29 @@ __global__ void __launch_bounds__(kNttThreads) k_encrypt(const uint64_t* u_ntt, 
 }
 
 // Decryption phase per limb: x = c0 + INTT(NTT(c1) * s).  Grid: n * L, x is [n][L][N].
-__global__ void __launch_bounds__(kNttThreads) k_phase(const uint64_t* ct, uint64_t* x, const uint64_t* s_ntt,
-                                                       const uint64_t* s_sh, Consts C, Tables T) {
+template <int LOGN>
+__global__ void __launch_bounds__(512) k_phase(const uint64_t* ct, uint64_t* x, const uint64_t* s_ntt,
+                                                const uint64_t* s_sh, Consts C, Tables T) {
   extern __shared__ uint64_t lds[];
-  const int n = C.n, L = C.L;
+  constexpr int n = 1 << LOGN;
+  const int L = C.L;
   const int64_t p = blockIdx.x;
   const int l = (int)(p % L);
   const int64_t j = p / L;
   const LimbConst& lc = C.limb[l];
   const uint64_t* c0 = ct + ((j * 2 + 0) * L + l) * n;
   const uint64_t* c1 = ct + ((j * 2 + 1) * L + l) * n;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) lds[i] = c1[i];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) lds[lpad(i)] = c1[i];
   __syncthreads();
-  ntt_forward_lds(lds, C.log2n, T.psi + (int64_t)l * n, T.psi_sh + (int64_t)l * n, lc.q);
+  ntt_fwd<LOGN>(lds, T.fw + (int64_t)l * n, lc.q);
   const uint64_t* sv = s_ntt + (int64_t)l * n;
   const uint64_t* ss = s_sh + (int64_t)l * n;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) lds[i] = mul_shoup(lds[i], sv[i], ss[i], lc.q);
+  for (int i = threadIdx.x; i < n; i += blockDim.x) lds[lpad(i)] = mul_shoup(lds[lpad(i)], sv[i], ss[i], lc.q);
   __syncthreads();
-  ntt_inverse_lds(lds, C.log2n, T.ipsi + (int64_t)l * n, T.ipsi_sh + (int64_t)l * n, lc.q);
+  ntt_inv<LOGN>(lds, T.iw + (int64_t)l * n, lc.q);
   uint64_t* o = x + p * n;
   for (int i = threadIdx.x; i < n; i += blockDim.x)
-    o[i] = add_mod(c0[i], mul_shoup(lds[i], lc.ninv, lc.ninv_sh, lc.q), lc.q);
+    o[i] = add_mod(c0[i], mul_shoup(lds[lpad(i)], lc.ninv, lc.ninv_sh, lc.q), lc.q);
 }
 
 // Exact decryption of the output slots: with y_l = x_l * (q/q_l)^-1 mod q_l and
@@ -586,27 +726,28 @@ __global__ void __launch_bounds__(256) k_decode(const uint64_t* x, int64_t* shar
 // (stream P_PK_A, limb l, two words per coefficient), e CBD21 (stream P_PK_E);
 // pk = (-(a s + e), a), kept in both coefficient and NTT form.  One LDS buffer;
 // every thread re-reads only the global entries it wrote itself.
-__global__ void __launch_bounds__(kNttThreads) k_keygen(uint64_t* s_ntt, int64_t* s_coeff, uint64_t* pk_coeff,
-                                                        uint64_t* pk_ntt, Consts C, Tables T) {
+template <int LOGN>
+__global__ void __launch_bounds__(512) k_keygen(uint64_t* s_ntt, int64_t* s_coeff, uint64_t* pk_coeff,
+                                                 uint64_t* pk_ntt, Consts C, Tables T) {
   extern __shared__ uint64_t lds[];
-  const int n = C.n, L = C.L;
+  constexpr int n = 1 << LOGN;
+  const int L = C.L;
   const int l = blockIdx.x;
   const LimbConst& lc = C.limb[l];
   const uint64_t nonce = kKeygenNonce;
-  const uint64_t* tw = T.psi + (int64_t)l * n;
-  const uint64_t* tws = T.psi_sh + (int64_t)l * n;
+  const TW* tw = T.fw + (int64_t)l * n;
   for (int blk = threadIdx.x; blk < n / 8; blk += blockDim.x) {
     U64x4 w = philox((uint64_t)blk, 0, P_SK, 0, C.seed, nonce);
 #pragma unroll
     for (int h = 0; h < 8; ++h) {
       int64_t sv = ternary32((uint32_t)(w.v[h >> 1] >> (32 * (h & 1))));
-      lds[blk * 8 + h] = small_to_mod(sv, lc.q);
+      lds[lpad(blk * 8 + h)] = small_to_mod(sv, lc.q);
       if (l == 0) s_coeff[blk * 8 + h] = sv;
     }
   }
   __syncthreads();
-  ntt_forward_lds(lds, C.log2n, tw, tws, lc.q);
-  for (int i = threadIdx.x; i < n; i += blockDim.x) s_ntt[(int64_t)l * n + i] = lds[i];
+  ntt_fwd<LOGN>(lds, tw, lc.q);
+  for (int i = threadIdx.x; i < n; i += blockDim.x) s_ntt[(int64_t)l * n + i] = lds[lpad(i)];
   __syncthreads();
   for (int blk = threadIdx.x; blk < n / 2; blk += blockDim.x) {
     U64x4 w = philox((uint64_t)blk, 0, P_PK_A, (uint64_t)l, C.seed, nonce);
@@ -615,72 +756,82 @@ __global__ void __launch_bounds__(kNttThreads) k_keygen(uint64_t* s_ntt, int64_t
       // (w_lo + 2^64 w_hi) mod q
       uint64_t hi = reduce64(w.v[2 * h + 1], lc.one_sh, lc.q);
       uint64_t v = add_mod(mul_shoup(hi, lc.r64, lc.r64_sh, lc.q), reduce64(w.v[2 * h], lc.one_sh, lc.q), lc.q);
-      lds[blk * 2 + h] = v;
+      lds[lpad(blk * 2 + h)] = v;
       pk_coeff[((int64_t)1 * L + l) * n + blk * 2 + h] = v;
     }
   }
   __syncthreads();
-  ntt_forward_lds(lds, C.log2n, tw, tws, lc.q);
+  ntt_fwd<LOGN>(lds, tw, lc.q);
   // a * s pointwise (128-bit product, Barrett), then inverse transform
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const uint64_t av = lds[i];
+    const uint64_t av = lds[lpad(i)];
     pk_ntt[((int64_t)1 * L + l) * n + i] = av;
     uint64_t ph, pl;
     mul_wide(av, s_ntt[(int64_t)l * n + i], ph, pl);
-    lds[i] = reduce128(ph, pl, lc.q, lc.mu_lo, lc.mu_hi);
+    lds[lpad(i)] = reduce128(ph, pl, lc.q, lc.mu_lo, lc.mu_hi);
   }
   __syncthreads();
-  ntt_inverse_lds(lds, C.log2n, T.ipsi + (int64_t)l * n, T.ipsi_sh + (int64_t)l * n, lc.q);
+  ntt_inv<LOGN>(lds, T.iw + (int64_t)l * n, lc.q);
   for (int blk = threadIdx.x; blk < n / 4; blk += blockDim.x) {
     U64x4 w = philox((uint64_t)blk, 0, P_PK_E, 0, C.seed, nonce);
 #pragma unroll
     for (int z = 0; z < 4; ++z) {
       const int i = blk * 4 + z;
-      uint64_t as = mul_shoup(lds[i], lc.ninv, lc.ninv_sh, lc.q);
+      uint64_t as = mul_shoup(lds[lpad(i)], lc.ninv, lc.ninv_sh, lc.q);
       uint64_t v = add_mod(as, small_to_mod(cbd21(w.v[z]), lc.q), lc.q);
       v = v == 0 ? 0 : lc.q - v;
-      lds[i] = v;
+      lds[lpad(i)] = v;
       pk_coeff[(int64_t)l * n + i] = v;
     }
   }
   __syncthreads();
-  ntt_forward_lds(lds, C.log2n, tw, tws, lc.q);
-  for (int i = threadIdx.x; i < n; i += blockDim.x) pk_ntt[(int64_t)l * n + i] = lds[i];
+  ntt_fwd<LOGN>(lds, tw, lc.q);
+  for (int i = threadIdx.x; i < n; i += blockDim.x) pk_ntt[(int64_t)l * n + i] = lds[lpad(i)];
 }
 
 // ---------------------------------------------------------------- launchers
 
-static inline size_t lds_bytes(const Consts& C) { return (size_t)C.n * sizeof(uint64_t); }
+static inline size_t lds_bytes(const Consts& C) { return (size_t)(C.n + (C.n >> 5)) * sizeof(uint64_t); }
+static inline dim3 ntt_block(const Consts& C) { return dim3((unsigned)(C.n / (C.log2n >= 14 ? 32 : 16))); }
+
+// Instantiate `kern<LOGN>` for the context's degree and launch it.
+#define NTT_DISPATCH(kern, grid, C, s, ...)                                                             \
+  do {                                                                                                  \
+    switch ((C).log2n) {                                                                                \
+      case 10: hipLaunchKernelGGL(kern<10>, grid, ntt_block(C), lds_bytes(C), s, __VA_ARGS__); break;  \
+      case 11: hipLaunchKernelGGL(kern<11>, grid, ntt_block(C), lds_bytes(C), s, __VA_ARGS__); break;  \
+      case 12: hipLaunchKernelGGL(kern<12>, grid, ntt_block(C), lds_bytes(C), s, __VA_ARGS__); break;  \
+      case 13: hipLaunchKernelGGL(kern<13>, grid, ntt_block(C), lds_bytes(C), s, __VA_ARGS__); break;  \
+      case 14: hipLaunchKernelGGL(kern<14>, grid, ntt_block(C), lds_bytes(C), s, __VA_ARGS__); break;  \
+      default: return hipErrorInvalidValue;                                                            \
+    }                                                                                                   \
+  } while (0)
 
 hipError_t launch_ntt_plain(uint64_t* data, int64_t polys, bool inverse, const Consts& C, const Tables& T,
                             hipStream_t s) {
   if (polys <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_ntt_plain, dim3((unsigned)(polys * C.L)), dim3(kNttThreads), lds_bytes(C), s, data,
-                     inverse ? 1 : 0, C, T);
+  NTT_DISPATCH(k_ntt_plain, dim3((unsigned)(polys * C.L)), C, s, data, inverse ? 1 : 0, C, T);
   return hipGetLastError();
 }
 
 hipError_t launch_ntt_ct(const uint64_t* src, uint64_t* dst, int64_t n_ct, const int64_t* share, const Geo& G,
                          const View& V, const Consts& C, const Tables& T, hipStream_t s) {
   if (n_ct <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_ntt_ct, dim3((unsigned)(n_ct * 2 * C.L)), dim3(kNttThreads), lds_bytes(C), s, src, dst,
-                     share, G, V, C, T);
+  NTT_DISPATCH(k_ntt_ct, dim3((unsigned)(n_ct * 2 * C.L)), C, s, src, dst, share, G, V, C, T);
   return hipGetLastError();
 }
 
 hipError_t launch_ntt_pt(const int64_t* tensor, uint64_t* dst, int64_t n_pt, int side, const Geo& G, const View& V,
                          const Consts& C, const Tables& T, hipStream_t s) {
   if (n_pt <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_ntt_pt, dim3((unsigned)(n_pt * C.L)), dim3(kNttThreads), lds_bytes(C), s, tensor, dst, side,
-                     G, V, C, T);
+  NTT_DISPATCH(k_ntt_pt, dim3((unsigned)(n_pt * C.L)), C, s, tensor, dst, side, G, V, C, T);
   return hipGetLastError();
 }
 
 hipError_t launch_ntt_ternary(uint64_t* dst, int64_t count, uint64_t nonce, uint64_t obj_base, uint32_t purpose,
                               const Consts& C, const Tables& T, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_ntt_ternary, dim3((unsigned)(count * C.L)), dim3(kNttThreads), lds_bytes(C), s, dst, nonce,
-                     obj_base, purpose, C, T);
+  NTT_DISPATCH(k_ntt_ternary, dim3((unsigned)(count * C.L)), C, s, dst, nonce, obj_base, purpose, C, T);
   return hipGetLastError();
 }
 
@@ -698,8 +849,14 @@ hipError_t launch_flood_mask(uint64_t* ct, int64_t n_out, int64_t* share0, const
                              const View& outV, uint64_t nonce, uint64_t obj_base, const Consts& C, hipStream_t s) {
   if (n_out <= 0) return hipSuccess;
   const int64_t threads = n_out * (C.n / 4);
-  hipLaunchKernelGGL(k_flood_mask, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, ct, n_out, share0, bias,
-                     G, outV, nonce, obj_base, C);
+  const dim3 grid((unsigned)((threads + 255) / 256));
+  switch (C.flood_words) {
+    case 1: hipLaunchKernelGGL(k_flood_mask<1>, grid, dim3(256), 0, s, ct, n_out, share0, bias, G, outV, nonce, obj_base, C); break;
+    case 2: hipLaunchKernelGGL(k_flood_mask<2>, grid, dim3(256), 0, s, ct, n_out, share0, bias, G, outV, nonce, obj_base, C); break;
+    case 3: hipLaunchKernelGGL(k_flood_mask<3>, grid, dim3(256), 0, s, ct, n_out, share0, bias, G, outV, nonce, obj_base, C); break;
+    case 4: hipLaunchKernelGGL(k_flood_mask<4>, grid, dim3(256), 0, s, ct, n_out, share0, bias, G, outV, nonce, obj_base, C); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -707,16 +864,15 @@ hipError_t launch_encrypt(const uint64_t* u_ntt, const int64_t* share, uint64_t*
                           const Geo& G, const View& V, const uint64_t* pk_ntt, const uint64_t* pk_sh, uint64_t nonce,
                           uint64_t obj_base, const Consts& C, const Tables& T, hipStream_t s) {
   if (n_ct <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_encrypt, dim3((unsigned)(n_ct * 2 * C.L)), dim3(kNttThreads), lds_bytes(C), s, u_ntt, share,
-                     ct, side, G, V, pk_ntt, pk_sh, nonce, obj_base, C, T);
+  NTT_DISPATCH(k_encrypt, dim3((unsigned)(n_ct * 2 * C.L)), C, s, u_ntt, share, ct, side, G, V, pk_ntt, pk_sh, nonce,
+               obj_base, C, T);
   return hipGetLastError();
 }
 
 hipError_t launch_phase(const uint64_t* ct, uint64_t* x, int64_t n_ct, const uint64_t* s_ntt, const uint64_t* s_sh,
                         const Consts& C, const Tables& T, hipStream_t s) {
   if (n_ct <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_phase, dim3((unsigned)(n_ct * C.L)), dim3(kNttThreads), lds_bytes(C), s, ct, x, s_ntt, s_sh, C,
-                     T);
+  NTT_DISPATCH(k_phase, dim3((unsigned)(n_ct * C.L)), C, s, ct, x, s_ntt, s_sh, C, T);
   return hipGetLastError();
 }
 
@@ -731,23 +887,29 @@ hipError_t launch_decode(const uint64_t* x, int64_t* share, int64_t n_out, const
 
 hipError_t launch_keygen(uint64_t* s_ntt, int64_t* s_coeff, uint64_t* pk_coeff, uint64_t* pk_ntt, const Consts& C,
                          const Tables& T, hipStream_t s) {
-  hipLaunchKernelGGL(k_keygen, dim3((unsigned)C.L), dim3(kNttThreads), lds_bytes(C), s, s_ntt, s_coeff, pk_coeff,
-                     pk_ntt, C, T);
+  NTT_DISPATCH(k_keygen, dim3((unsigned)C.L), C, s, s_ntt, s_coeff, pk_coeff, pk_ntt, C, T);
   return hipGetLastError();
 }
 
 // Kernels that stage more than 64 KiB of LDS must opt in once per process.
-hipError_t configure_lds_limits() {
+template <int LOGN>
+static hipError_t raise_lds_limit() {
   const int max_lds = 160 * 1024;
+  const void* fns[] = {(const void*)k_ntt_plain<LOGN>, (const void*)k_ntt_ct<LOGN>, (const void*)k_ntt_pt<LOGN>,
+                       (const void*)k_ntt_ternary<LOGN>, (const void*)k_encrypt<LOGN>, (const void*)k_phase<LOGN>,
+                       (const void*)k_keygen<LOGN>};
   hipError_t e = hipSuccess;
-  const void* fns[] = {(const void*)k_ntt_plain, (const void*)k_ntt_ct,   (const void*)k_ntt_pt,
-                       (const void*)k_ntt_ternary, (const void*)k_encrypt, (const void*)k_phase,
-                       (const void*)k_keygen};
   for (const void* f : fns) {
     hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
     if (r != hipSuccess) e = r;
   }
   return e;
+}
+
+hipError_t configure_lds_limits() {
+  hipError_t e = raise_lds_limit<13>();
+  hipError_t f = raise_lds_limit<14>();
+  return e != hipSuccess ? e : f;
 }
 
 }  // namespace pencil

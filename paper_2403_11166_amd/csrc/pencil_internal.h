@@ -36,12 +36,15 @@ struct Consts {
   uint64_t thr[kMaxLimbs][kMaxWords];   // (2j + 1) * q, j = 0..L-1
 };
 
-// NTT tables, each [L][N]: psi^rev(k), psi^-rev(k) and Shoup companions.
+// A twiddle and its Shoup companion, stored together for one 16-byte load.
+struct alignas(16) TW {
+  uint64_t w, ws;
+};
+
+// NTT tables, each [L][N]: psi^rev(k) (forward) and psi^-rev(k) (inverse).
 struct Tables {
-  const uint64_t* psi;
-  const uint64_t* psi_sh;
-  const uint64_t* ipsi;
-  const uint64_t* ipsi_sh;
+  const TW* fw;
+  const TW* iw;
 };
 
 // Partition of one packed correlation into N-slot tiles.
