@@ -118,3 +118,32 @@ def mul_plain_acc(P, acc, ct, w, t):
             pr = negacyclic_mul(wl, ct[c, l], q)
             acc[c][l] = [(a + int(b)) % q for a, b in zip(acc[c][l], pr)]
     return acc
+
+
+def encrypt_at(P, pk, m, seed, nonce, obj, idx):
+    """Coefficients idx of encrypt(P, pk, m, ...) (each one an O(N) sum)."""
+    from .ring import negacyclic_coeffs
+    n = P.n
+    u = S.ternary(seed, nonce, obj, S.P_ENC_U, n)
+    e = (S.cbd21_at(seed, nonce, obj, S.P_ENC_E0, idx), S.cbd21_at(seed, nonce, obj, S.P_ENC_E1, idx))
+    dm = delta_scale([m[i] for i in idx], P)
+    out = np.empty((2, P.num_limbs, len(idx)), dtype=np.uint64)
+    for l, q in enumerate(P.moduli):
+        ul = residues(u, q)
+        for c in range(2):
+            pu = negacyclic_coeffs(pk[c, l], ul, q, idx)
+            out[c, l] = residues([int(x) + int(y) + (dm[i] if c == 0 else 0) for i, (x, y) in enumerate(zip(pu, e[c]))],
+                                 q)
+    return out
+
+
+def decrypt_at(P, sk, ct, idx):
+    """Coefficients idx of decrypt(P, sk, ct)."""
+    from .ring import negacyclic_coeffs
+    limbs = []
+    for l, q in enumerate(P.moduli):
+        c1s = negacyclic_coeffs(ct[1, l], residues(sk, q), q, idx)
+        limbs.append([(int(ct[0, l][i]) + int(b)) % q for i, b in zip(idx, c1s)])
+    x = crt(limbs, P.moduli)
+    q, t = P.q, P.t
+    return np.array([((2 * t * v + q) // (2 * q)) % t for v in x], dtype=np.int64)

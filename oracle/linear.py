@@ -122,3 +122,53 @@ def layer_op(layer, op, a, b, t, tdot=tensordot_mod_t):
     if op == "dw":
         return conv2d_dw(a, b, layer.pad, layer.k, t, tdot)
     raise ValueError(op)
+
+
+def layer_op_at(layer, op, a, b, t, points):
+    """Selected output elements of layer_op, each summed by its definition in
+    Python integers.  points: index tuples into the output tensor."""
+    a = np.asarray(a)
+    b = np.asarray(b)
+    out = []
+    if layer.kind == "fc":
+        for p in points:
+            if op == "fwd":      # Y[b, o] = sum_i X[b, i] W[o, i]
+                v = sum(int(x) * int(w) for x, w in zip(a[p[0]], b[p[1]]))
+            elif op == "dx":     # dX[b, i] = sum_o dY[b, o] W[o, i]
+                v = sum(int(x) * int(w) for x, w in zip(a[p[0]], b[:, p[1]]))
+            else:                # dW[o, i] = sum_b dY[b, o] X[b, i]
+                v = sum(int(x) * int(g) for x, g in zip(a[:, p[1]], b[:, p[0]]))
+            out.append(v % t)
+        return out
+    k, pad = layer.k, layer.pad
+    h, w = layer.h, layer.w
+    ho, wo = layer.h_out, layer.w_out
+
+    def x_at(x, bb, c, y, xx):
+        y, xx = y - pad, xx - pad
+        return int(x[bb, c, y, xx]) if 0 <= y < h and 0 <= xx < w else 0
+
+    for p in points:
+        v = 0
+        if op == "fwd":          # Y[b, o, y, x] = sum_{c,i,j} Xpad[b, c, y+i, x+j] W[o, c, i, j]
+            bb, o, y, xx = p
+            for c in range(layer.c_in):
+                for i in range(k):
+                    for j in range(k):
+                        v += x_at(a, bb, c, y + i, xx + j) * int(b[o, c, i, j])
+        elif op == "dx":         # dX[b, c, y, x] = sum_{o,i,j} dY[b, o, y+p-i, x+p-j] W[o, c, i, j]
+            bb, c, y, xx = p
+            for o in range(layer.c_out):
+                for i in range(k):
+                    for j in range(k):
+                        yy, xj = y + pad - i, xx + pad - j
+                        if 0 <= yy < ho and 0 <= xj < wo:
+                            v += int(a[bb, o, yy, xj]) * int(b[o, c, i, j])
+        else:                    # dW[o, c, i, j] = sum_{b,y,x} dY[b, o, y, x] Xpad[b, c, y+i, x+j]
+            o, c, i, j = p
+            for bb in range(layer.batch):
+                for y in range(ho):
+                    for xx in range(wo):
+                        v += int(b[bb, o, y, xx]) * x_at(a, bb, c, y + i, xx + j)
+        out.append(v % t)
+    return out

@@ -88,13 +88,19 @@ def mo_product(P, pk, layer, op, tile, terms, seed, nonce, add_share=None, bias=
     n, t, L = P.n, P.t, P.num_limbs
     idx = np.arange(n) if coeff_idx is None else np.asarray(coeff_idx, dtype=np.int64)
 
-    # encode plaintext sides once
+    # encode plaintext tiles on first use
+    a_list = list(E.a_tiles(c))
+    k_list = list(E.k_tiles(c))
     pt_cache = {}
 
-    def pt_polys(which, tensor, side):
-        key = (which, side)
+    def pt_poly(tensor, side, ti):
+        key = (id(tensor), side, ti)
         if key not in pt_cache:
-            pt_cache[key] = [_lift_limbs(P, p) for p in operand_polys(layer, op, tile, n, tensor, side)]
+            if side == "a":
+                poly = E.encode_a(E.virtual_a(layer, op, tensor), g, tile, n, *a_list[ti])
+            else:
+                poly = E.encode_k(E.virtual_k(layer, op, tensor), g, tile, n, *k_list[ti])
+            pt_cache[key] = _lift_limbs(P, poly)
         return pt_cache[key]
 
     ct_cache = {}
@@ -103,8 +109,7 @@ def mo_product(P, pk, layer, op, tile, terms, seed, nonce, add_share=None, bias=
         if add_share is None:
             return cts[ti]
         if ti not in ct_cache:
-            A = E.virtual_a(layer, op, add_share)
-            m = E.encode_a(A, g, tile, n, *list(E.a_tiles(c))[ti])
+            m = E.encode_a(E.virtual_a(layer, op, add_share), g, tile, n, *a_list[ti])
             ct_cache[ti] = bfv.add_plain(P, cts[ti], m)
         return ct_cache[ti]
 
@@ -126,10 +131,10 @@ def mo_product(P, pk, layer, op, tile, terms, seed, nonce, add_share=None, bias=
                     for (akind, aval), (kkind, kval) in terms:
                         if akind == "ct":
                             ct = a_ct(ai, aval)
-                            pl = pt_polys(id(kval), kval, "k")[kk]
+                            pl = pt_poly(kval, "k", kk)
                         else:
                             ct = kval[kk]
-                            pl = pt_polys(id(aval), aval, "a")[ai]
+                            pl = pt_poly(aval, "a", ai)
                         for l, q in enumerate(P.moduli):
                             for cc in range(2):
                                 if coeff_idx is None:

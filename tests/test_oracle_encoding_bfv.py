@@ -293,3 +293,22 @@ def test_output_is_rerandomised_flooded_and_masked():
         assert (int(dec[slot]) + int(y0[m, r])) % T == 0
     assert int(d[1].max()) > P.moduli[0] // 4
     assert bfv.noise(P, keys["sk"], d, dec) > (1 << (P.flood_bits - 4))
+
+
+def test_sampled_helpers_match_full_versions():
+    P = SMALL
+    k = bfv.keygen(P, 13)
+    rng = np.random.default_rng(14)
+    m = rng.integers(0, T, P.n)
+    idx = [0, 3, 100, 255]
+    ct = bfv.encrypt(P, k["pk"], m, 13, 2, 7)
+    assert (bfv.encrypt_at(P, k["pk"], m, 13, 2, 7, idx) == ct[:, :, idx]).all()
+    assert list(bfv.decrypt_at(P, k["sk"], ct, idx)) == list(bfv.decrypt(P, k["sk"], ct)[idx])
+    for layer in (conv(2, 3, 2, 5, k=3, pad=1), fc(3, 6, 4)):
+        X = rng.integers(0, T, layer.x_shape())
+        W = rng.integers(0, T, layer.w_shape())
+        dY = rng.integers(0, T, layer.y_shape())
+        for op, a, b in (("fwd", X, W), ("dx", dY, W), ("dw", X, dY)):
+            full = LN.layer_op(layer, op, a, b, T)
+            pts = [tuple(int(v) for v in np.unravel_index(i, full.shape)) for i in (0, full.size // 2, full.size - 1)]
+            assert LN.layer_op_at(layer, op, a, b, T, pts) == [int(full[p]) for p in pts]
