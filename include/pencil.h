@@ -187,6 +187,14 @@ pencil_status pencil_linear_bwd(pencil_ctx* ctx, const pencil_layer* layer, cons
 pencil_status pencil_decrypt(pencil_ctx* ctx, const pencil_layer* layer, const pencil_plan* plan, int op,
                              const uint64_t* ct, int64_t* share, void* ws, void* stream);
 
+/* Plaintext product over Z_t of two tensors with the layer's operator
+ * (op FWD: a = X, b = W -> Y; DX: a = dY, b = W -> dX; DW: a = X, b = dY -> dW),
+ * exact mod t.  These are the "local" terms of Alg. 2 that each party computes
+ * on its own shares (<dY>_0 o <X>_0 for the MO, <dY>_1 o <X>_1 for the DO);
+ * out is shaped like Y, dX or W. */
+pencil_status pencil_zt_linear(pencil_ctx* ctx, const pencil_layer* layer, int op, const int64_t* a,
+                               const int64_t* b, int64_t* out, void* stream);
+
 /* Negacyclic NTT of `count` polynomials laid out [count][L][N] (limb l of each
  * polynomial mod q_l), in place.  The transform domain is this library's
  * internal order: entry i of the forward transform holds the evaluation at

@@ -79,6 +79,8 @@ SIGNATURES = {
     "pencil_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "pencil_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(KernelStat), ctypes.c_int,
                                            ctypes.POINTER(ctypes.c_int)]),
+    "pencil_zt_linear": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Layer), ctypes.c_int, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "pencil_ntt_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
     "pencil_ntt_inverse": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
 }

@@ -175,6 +175,17 @@ class Context:
                                             _ptr(ct), _ptr(share), _ptr(ws), _stream()))
         return share
 
+    def zt_linear(self, layer, op, a, b):
+        """Exact Z_t product of plaintext tensors with the layer's operator."""
+        opi = OPS.get(op, op)
+        _need(a, "a")
+        _need(b, "b")
+        shape = (_y_shape, _x_shape, _w_shape)[opi](layer)
+        out = torch.empty(shape, dtype=torch.int64, device=self.device)
+        self._check(self.lib.pencil_zt_linear(self.h, ctypes.byref(layer_struct(layer)), opi, _ptr(a), _ptr(b),
+                                              _ptr(out), _stream()))
+        return out
+
     def ntt(self, polys, inverse=False):
         """In-place negacyclic NTT of an int64 tensor [count][L][N] of residues."""
         count = polys.numel() // (self.L * self.n)

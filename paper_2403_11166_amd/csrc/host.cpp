@@ -889,6 +889,26 @@ extern "C" pencil_status pencil_ntt_inverse(pencil_ctx* ctx, uint64_t* polys, in
   return PENCIL_OK;
 }
 
+extern "C" pencil_status pencil_zt_linear(pencil_ctx* ctx, const pencil_layer* L, int op, const int64_t* a,
+                                          const int64_t* b, int64_t* out, void* stream) {
+  if (!ctx) return PENCIL_EINVAL;
+  if (op < 0 || op > 2) return fail(ctx, PENCIL_EINVAL, "op %d invalid", op);
+  TRY(check_ptr(ctx, a, "a"));
+  TRY(check_ptr(ctx, b, "b"));
+  TRY(check_ptr(ctx, out, "out"));
+  pencil_status st = PENCIL_OK;
+  if (!layer_ok(ctx, L, &st)) return st;
+  const OpGeom g = op_geom(L, op);
+  // the whole operand as one tile: only the virtual dimensions are used
+  Geo G{};
+  G.M = g.M; G.R = g.R; G.K = g.K; G.HA = g.HA; G.WA = g.WA; G.KH = g.KH; G.KW = g.KW;
+  G.OH = g.OH(); G.OW = g.OW();
+  hipError_t e = launch_zt_corr(a, b, out, G, view_a(L, op), view_k(L, op), view_out(L, op), ctx->C,
+                                (hipStream_t)stream);
+  if (e != hipSuccess) return fail(ctx, PENCIL_EHIP, "zt_linear launch: %s", hipGetErrorString(e));
+  return PENCIL_OK;
+}
+
 // ------------------------------------------------------------ profiling
 
 extern "C" pencil_status pencil_profile_enable(pencil_ctx* ctx, int enable) {

@@ -789,6 +789,45 @@ __global__ void __launch_bounds__(512) k_keygen(uint64_t* s_ntt, int64_t* s_coef
   for (int i = threadIdx.x; i < n; i += blockDim.x) pk_ntt[(int64_t)l * n + i] = lds[lpad(i)];
 }
 
+// Exact Z_t packed correlation of two plaintext tensors, one thread per output
+// element: out[m, r, y, x] = sum_{k, dy, dx} A[m, k, y+dy, x+dx] K[r, k, dy, dx]
+// mod t, with 128-bit accumulation (41-bit operands, < 2^46 terms).  Used for
+// the local terms of the weight gradient.
+__global__ void __launch_bounds__(256) k_zt_corr(const int64_t* a, const int64_t* kt, int64_t* out, Geo G, View AV,
+                                                 View KV, View OV, Consts C) {
+  const int64_t total = (int64_t)G.M * G.R * G.OH * G.OW;
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  int64_t e = g;
+  const int x = (int)(e % G.OW);
+  e /= G.OW;
+  const int y = (int)(e % G.OH);
+  e /= G.OH;
+  const int r = (int)(e % G.R);
+  const int m = (int)(e / G.R);
+  uint64_t hi = 0, lo = 0;
+  for (int k = 0; k < G.K; ++k)
+    for (int dy = 0; dy < G.KH; ++dy) {
+      const int ys = y + dy - AV.pad;
+      if (ys < 0 || ys >= AV.H) continue;
+      for (int dx = 0; dx < G.KW; ++dx) {
+        const int xs = x + dx - AV.pad;
+        if (xs < 0 || xs >= AV.W) continue;
+        const uint64_t av = (uint64_t)a[m * AV.s0 + k * AV.s1 + ys * AV.sy + xs * AV.sx];
+        const int ky = KV.flip ? KV.KH - 1 - dy : dy, kx = KV.flip ? KV.KW - 1 - dx : dx;
+        const uint64_t kv = (uint64_t)kt[r * KV.s0 + k * KV.s1 + ky * KV.sy + kx * KV.sx];
+        uint64_t ph, pl;
+        mul_wide(av, kv, ph, pl);
+        lo += pl;
+        hi += ph + (lo < pl ? 1 : 0);
+      }
+    }
+  // (hi 2^64 + lo) mod t
+  uint64_t v = add_mod(mul_shoup(reduce64(hi, C.one_sh_t, C.t), C.r64t, C.r64t_sh, C.t),
+                       reduce64(lo, C.one_sh_t, C.t), C.t);
+  out[m * OV.s0 + r * OV.s1 + y * OV.sy + x * OV.sx] = (int64_t)v;
+}
+
 // ---------------------------------------------------------------- launchers
 
 static inline size_t lds_bytes(const Consts& C) { return (size_t)(C.n + (C.n >> 5)) * sizeof(uint64_t); }
@@ -882,6 +921,14 @@ hipError_t launch_decode(const uint64_t* x, int64_t* share, int64_t n_out, const
   const int64_t threads = n_out * per;
   if (threads <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_decode, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, x, share, n_out, G, outV, C);
+  return hipGetLastError();
+}
+
+hipError_t launch_zt_corr(const int64_t* a, const int64_t* k, int64_t* out, const Geo& G, const View& AV,
+                          const View& KV, const View& OV, const Consts& C, hipStream_t s) {
+  const int64_t total = (int64_t)G.M * G.R * G.OH * G.OW;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zt_corr, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a, k, out, G, AV, KV, OV, C);
   return hipGetLastError();
 }
 

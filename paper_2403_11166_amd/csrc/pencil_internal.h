@@ -116,6 +116,8 @@ hipError_t launch_phase(const uint64_t* ct, uint64_t* x, int64_t n_ct, const uin
                         const Consts& C, const Tables& T, hipStream_t s);
 hipError_t launch_decode(const uint64_t* x, int64_t* share, int64_t n_out, const Geo& G, const View& outV,
                          const Consts& C, hipStream_t s);
+hipError_t launch_zt_corr(const int64_t* a, const int64_t* k, int64_t* out, const Geo& G, const View& AV,
+                          const View& KV, const View& OV, const Consts& C, hipStream_t s);
 hipError_t launch_keygen(uint64_t* s_ntt, int64_t* s_coeff, uint64_t* pk_coeff, uint64_t* pk_ntt,
                          const Consts& C, const Tables& T, hipStream_t s);
 

@@ -1,0 +1,119 @@
+"""The autograd wrapper's forward and backward against the oracle's exact
+plaintext layers, exact integer finite differences, the plaintext local-term
+kernel, and torch's own float64 autograd on small integers."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import linear as LN
+from oracle import params as PR
+from workloads import conv, fc, layer_tensors, CONFIGS
+
+from gpu_common import dev, host_i64
+
+pytestmark = pytest.mark.gpu
+
+T = PR.T
+
+
+def centred_np(v):
+    v = np.asarray(v, dtype=np.int64)
+    return np.where(v > (T - 1) // 2, v - T, v)
+
+
+def _engine(layer, seed):
+    from paper_2403_11166_amd import Context
+    from paper_2403_11166_amd.autograd import EncryptedLinearEngine
+    ctx = Context(layer.log2_n, layer.num_limbs, layer.prime_bits, seed)
+    return EncryptedLinearEngine(layer, ctx, seed=seed)
+
+
+LAYERS = [conv(4, 3, 5, 8, k=3, pad=1, log2_n=12, num_limbs=2, prime_bits=50),
+          fc(16, 40, 12, log2_n=12, num_limbs=2, prime_bits=50),
+          CONFIGS[2].layers[0]]
+
+
+@pytest.mark.parametrize("li", range(len(LAYERS)))
+def test_forward_backward_match_fixed_point_gradients(li):
+    layer = LAYERS[li]
+    eng = _engine(layer, 40 + li)
+    from paper_2403_11166_amd.autograd import encrypted_linear
+    ts = layer_tensors(layer, 50 + li)
+    x = torch.tensor(centred_np(ts["X"]), dtype=torch.float64, device="cuda", requires_grad=True)
+    w = torch.tensor(centred_np(ts["W"]), dtype=torch.float64, device="cuda", requires_grad=True)
+    y = encrypted_linear(x, w, eng)
+    g = torch.tensor(centred_np(ts["dY"]), dtype=torch.float64, device="cuda")
+    y.backward(g)
+    torch.cuda.synchronize()
+    Y = LN.layer_op(layer, "fwd", ts["X"], ts["W"], T)
+    dX = LN.layer_op(layer, "dx", ts["dY"], ts["W"], T)
+    dW = LN.layer_op(layer, "dw", ts["X"], ts["dY"], T)
+    assert (np.mod(y.detach().cpu().numpy().astype(np.int64), T) == Y).all()
+    assert (np.mod(x.grad.cpu().numpy().astype(np.int64), T) == dX).all()
+    assert (np.mod(w.grad.cpu().numpy().astype(np.int64), T) == dW).all()
+
+
+def test_matches_torch_autograd_on_small_integers():
+    """With small values nothing wraps mod t, so the result equals torch's float64 autograd."""
+    layer = LAYERS[0]
+    eng = _engine(layer, 60)
+    from paper_2403_11166_amd.autograd import encrypted_linear
+    rng = np.random.default_rng(6)
+    xs = rng.integers(-300, 300, layer.x_shape()).astype(np.float64)
+    ws = rng.integers(-300, 300, layer.w_shape()).astype(np.float64)
+    gs = rng.integers(-300, 300, layer.y_shape()).astype(np.float64)
+    x = torch.tensor(xs, device="cuda", requires_grad=True)
+    w = torch.tensor(ws, device="cuda", requires_grad=True)
+    y = encrypted_linear(x, w, eng)
+    y.backward(torch.tensor(gs, device="cuda"))
+    xr = torch.tensor(xs, requires_grad=True)
+    wr = torch.tensor(ws, requires_grad=True)
+    yr = torch.nn.functional.conv2d(xr, wr, padding=layer.pad)
+    yr.backward(torch.tensor(gs))
+    assert torch.equal(y.detach().cpu(), yr.detach())
+    assert torch.equal(x.grad.cpu(), xr.grad)
+    assert torch.equal(w.grad.cpu(), wr.grad)
+
+
+def test_exact_integer_finite_differences():
+    """<G, f(X + d) - f(X)> = <grad_X, d> and <G, f_{W+e}(X) - f_W(X)> = <grad_W, e> mod t."""
+    layer = LAYERS[1]
+    eng = _engine(layer, 70)
+    from paper_2403_11166_amd.autograd import encrypted_linear
+    ts = layer_tensors(layer, 71)
+    x = torch.tensor(centred_np(ts["X"]), dtype=torch.float64, device="cuda", requires_grad=True)
+    w = torch.tensor(centred_np(ts["W"]), dtype=torch.float64, device="cuda", requires_grad=True)
+    G = torch.tensor(centred_np(ts["dY"]), dtype=torch.float64, device="cuda")
+    y = encrypted_linear(x, w, eng)
+    y.backward(G)
+    ip = lambda a, b: int(np.sum(np.mod(a, T).astype(object) * np.mod(b, T).astype(object))) % T  # noqa: E731
+    Gn = G.cpu().numpy().astype(np.int64)
+    rng = np.random.default_rng(8)
+    for _ in range(3):
+        d = np.zeros(layer.x_shape(), dtype=np.int64)
+        d[tuple(rng.integers(0, s) for s in d.shape)] = int(rng.integers(1, 1000))
+        with torch.no_grad():
+            y2 = encrypted_linear(x + torch.tensor(d, dtype=torch.float64, device="cuda"), w, eng)
+        diff = (y2 - y).detach().cpu().numpy().astype(np.int64)
+        assert ip(Gn, diff) == ip(x.grad.cpu().numpy().astype(np.int64), d)
+        e = np.zeros(layer.w_shape(), dtype=np.int64)
+        e[tuple(rng.integers(0, s) for s in e.shape)] = int(rng.integers(1, 1000))
+        with torch.no_grad():
+            y3 = encrypted_linear(x, w + torch.tensor(e, dtype=torch.float64, device="cuda"), eng)
+        diff = (y3 - y).detach().cpu().numpy().astype(np.int64)
+        assert ip(Gn, diff) == ip(w.grad.cpu().numpy().astype(np.int64), e)
+
+
+@pytest.mark.parametrize("layer", [conv(3, 4, 5, 6, k=3, pad=1, log2_n=10, num_limbs=2, prime_bits=50),
+                                   conv(2, 3, 2, 5, k=2, pad=0, log2_n=10, num_limbs=2, prime_bits=50),
+                                   fc(5, 9, 4, log2_n=10, num_limbs=2, prime_bits=50)])
+def test_zt_linear_matches_oracle(layer):
+    from paper_2403_11166_amd import Context
+    ctx = Context(layer.log2_n, layer.num_limbs, layer.prime_bits, 1)
+    rng = np.random.default_rng(9)
+    X = rng.integers(0, T, layer.x_shape())
+    W = rng.integers(0, T, layer.w_shape())
+    dY = rng.integers(0, T, layer.y_shape())
+    for op, a, b in (("fwd", X, W), ("dx", dY, W), ("dw", X, dY)):
+        got = host_i64(ctx.zt_linear(layer, op, dev(a), dev(b)))
+        assert (got == LN.layer_op(layer, op, a, b, T)).all(), op
