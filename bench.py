@@ -40,6 +40,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU oracle sample budget")
     ap.add_argument("--no-verify", action="store_true")
+    ap.add_argument("--mode", choices=("step", "graph", "layer"), default="step",
+                    help="timed launch path: batched step (phase launches with live kernel events), "
+                         "its captured HIP graph, or one launch sequence per product and layer")
+    ap.add_argument("--compare-steps", type=int, default=3, help="steps timed for the other launch paths")
     return ap.parse_args()
 
 
@@ -123,6 +127,12 @@ def kernel_work(sizes_list):
             add("mac", (2 * n_ct_in + n_pt + n_out + 2 * n_out) * poly, sz.n_products[opi] * 2 * L * n)
             add("intt_out", 2 * n_out * 2 * poly, 2 * n_out * bfly)
             add("flood_mask", 2 * n_out * 2 * poly, 0)
+    # the batched step's phase launches cover the same work
+    get = lambda k: work.get(k, (0, 0))  # noqa: E731
+    work["step_ntt"] = tuple(get("ntt_ct")[i] + get("ntt_pt")[i] + get("ntt_ternary")[i] for i in range(2))
+    work["step_mac"] = get("mac")
+    work["step_intt"] = get("intt_out")
+    work["step_flood"] = get("flood_mask")
     return work
 
 
@@ -195,42 +205,76 @@ def main():
         layers.append(ent)
     torch.cuda.synchronize()
 
-    def step(nonce):
+    def layer_step(nonce):
         for li, e in enumerate(layers):
             L_, c, d = e["layer"], e["ctx"], e["d"]
-            c.linear_fwd(L_, e["plan"], e["ct_x"], d["x0"], d["W"], nonce * 64 + li, ws=e["ws_f"], out=e["out_f"])
+            c.linear_fwd(L_, e["plan"], e["ct_x"], d["x0"], d["W"], nonce + 2 * li, ws=e["ws_f"], out=e["out_f"])
             if "dx" in cfg.ops or "dw" in cfg.ops:
                 c.linear_bwd(L_, e["plan"], e.get("ct_dy_dx"), e.get("ct_x_dw"), e.get("ct_dy_dw"), d["dy0"],
-                             d["x0"], d["W"], nonce * 64 + li + 32, ws=e["ws_b"], out=e["out_b"],
+                             d["x0"], d["W"], nonce + 2 * li + 1, ws=e["ws_b"], out=e["out_b"],
                              do_dx="dx" in cfg.ops, do_dw="dw" in cfg.ops)
 
-    for i in range(args.warmup):
-        step(i + 1)
-    torch.cuda.synchronize()
-    for c in ctxs.values():
-        c._check(c.lib.pencil_profile_enable(c.h, 1))
+    from paper_2403_11166_amd import Step
+    step_obj = Step([(e["ctx"], e["layer"], e["plan"]) for e in layers], ops=cfg.ops)
+    step_ws = torch.empty(step_obj.workspace_bytes(), dtype=torch.uint8, device=dev)
+    step_obj.bind([dict(ct_x1=e["ct_x"], ct_dy_dx=e.get("ct_dy_dx"), ct_x_dw=e.get("ct_x_dw"),
+                        ct_dy_dw=e.get("ct_dy_dw"), x0=e["d"]["x0"], dy0=e["d"]["dy0"], w=e["d"]["W"],
+                        ct_y=e["out_f"][0], y0=e["out_f"][1], ct_dx=e["out_b"][0], dx0=e["out_b"][1],
+                        ct_dw=e["out_b"][2], dw_mask=e["out_b"][3]) for e in layers], step_ws)
+    n_layers = len(layers)
     stream = torch.cuda.current_stream()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, steps, profile):
+        for c in ctxs.values():
+            c._check(c.lib.pencil_profile_enable(c.h, 1 if profile else 0))
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        for i in range(steps):
+            fn(i)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / steps, time.perf_counter() - t0
+
+    def read_stats():
+        stats = {}
+        for c in ctxs.values():
+            arr = (A.KernelStat * 16)()
+            cnt = ctypes.c_int()
+            c._check(c.lib.pencil_profile_read(c.h, arr, 16, ctypes.byref(cnt)))
+            for i in range(cnt.value):
+                nm = arr[i].name.decode()
+                l0, m0 = stats.get(nm, (0, 0.0))
+                stats[nm] = (l0 + arr[i].launches, m0 + arr[i].total_ms)
+            c._check(c.lib.pencil_profile_enable(c.h, 0))
+        return stats
+
+    runners = {
+        "layer": lambda i: layer_step(1000 + 2 * n_layers * i),
+        "step": lambda i: step_obj.run(1000 + 2 * n_layers * i),
+    }
+    for i in range(args.warmup):
+        runners["layer"](i)
+        runners["step"](i)
+    step_obj.capture()
+    step_obj.set_nonce(1000)
+    runners["graph"] = lambda i: step_obj.replay()
+    for i in range(args.warmup):
+        runners["graph"](i)
     torch.cuda.synchronize()
-    t_wall = time.perf_counter()
-    ev0.record(stream)
-    for i in range(args.steps):
-        step(100 + i)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_wall
-    ms_total = ev0.elapsed_time(ev1)
-    ms_step = ms_total / args.steps
-    stats = {}
-    for c in ctxs.values():
-        arr = (A.KernelStat * 16)()
-        cnt = ctypes.c_int()
-        c._check(c.lib.pencil_profile_read(c.h, arr, 16, ctypes.byref(cnt)))
-        for i in range(cnt.value):
-            nm = arr[i].name.decode()
-            l0, m0 = stats.get(nm, (0, 0.0))
-            stats[nm] = (l0 + arr[i].launches, m0 + arr[i].total_ms)
-        c._check(c.lib.pencil_profile_enable(c.h, 0))
+
+    compare = {}
+    for mode in ("layer", "step", "graph"):
+        if mode != args.mode:
+            compare[mode] = round(timed(runners[mode], args.compare_steps, False)[0], 4)
+    # the timed region: kernel events on (graph replays carry no events; their
+    # kernels are timed from an eager run of the same step just after)
+    ms_step, wall = timed(runners[args.mode], args.steps, args.mode != "graph")
+    if args.mode == "graph":
+        timed(runners["step"], args.steps, True)
+    stats = read_stats()
+    compare[args.mode] = round(ms_step, 4)
 
     products = sum(sum(e["sz"].n_products[i] for i, op in enumerate(("fwd", "dx", "dw")) if op in cfg.ops)
                    for e in layers)
@@ -293,9 +337,13 @@ def main():
                    "ops": list(cfg.ops), "products_per_step": int(products),
                    "plans": [{"fwd": e["plan"].fwd.astuple(), "dx": e["plan"].dx.astuple(),
                               "dw": e["plan"].dw.astuple()} for e in layers],
-                   "launch": "one launch sequence per product, per layer"},
+                   "launch": {"step": "batched phase launches (all layers and products)",
+                              "graph": "the batched step replayed as one HIP graph",
+                              "layer": "one launch sequence per product and layer"}[args.mode]},
         "bit_exact": bit_exact,
         "wall_s_timed": round(wall, 3),
+        "launch_paths_ms_per_step": compare,
+        "batched_speedup_vs_unbatched": round(compare["layer"] / min(compare["step"], compare["graph"]), 3),
         "roofline": roof,
         "kernels": breakdown,
         "cpu_baseline": cpu,

@@ -91,6 +91,11 @@ typedef struct {
 
 typedef struct {
     pencil_tile fwd, dx, dw;
+    /* Schedule of each product's multiply-accumulate (chunk of output tiles one
+     * workgroup stages: 0 = 8 x 8, 1 = 4 x 16, 2 = 16 x 4).  Results do not
+     * depend on it; pencil_plan_auto picks by staging volume, pencil_autotune by
+     * measurement. */
+    int32_t sched[3];
 } pencil_plan;
 
 /* Ciphertext operands the DO encrypts (the four layouts of one layer-step). */
@@ -195,12 +200,62 @@ pencil_status pencil_decrypt(pencil_ctx* ctx, const pencil_layer* layer, const p
 pencil_status pencil_zt_linear(pencil_ctx* ctx, const pencil_layer* layer, int op, const int64_t* a,
                                const int64_t* b, int64_t* out, void* stream);
 
+/* Autotuner: time the schedule candidates on this GPU -- the NTT's residues per
+ * thread (16 or 32, per context) and each product's multiply-accumulate chunk
+ * shape (per layer and product, written into plan->sched) -- and keep the
+ * fastest.  Results are bit-identical for every candidate.  cache_path (may be
+ * NULL) is a text file of earlier choices keyed by GPU, ring degree, limbs,
+ * layer shape and product; hits are applied without measuring, new choices are
+ * appended.  Synchronous; allocates and frees its own scratch buffers.  Tune a
+ * context before creating steps on it. */
+pencil_status pencil_autotune(pencil_ctx* ctx, const pencil_layer* layer, pencil_plan* plan /* host, in/out */,
+                              const char* cache_path);
+
 /* Negacyclic NTT of `count` polynomials laid out [count][L][N] (limb l of each
  * polynomial mod q_l), in place.  The transform domain is this library's
  * internal order: entry i of the forward transform holds the evaluation at
  * psi^(2 rev(i) + 1), rev = bit reversal of log2 N bits (Sec. V). */
 pencil_status pencil_ntt_forward(pencil_ctx* ctx, uint64_t* polys, int64_t count, void* stream);
 pencil_status pencil_ntt_inverse(pencil_ctx* ctx, uint64_t* polys, int64_t count, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Batched step: every product of several layers (the forward product, the
+ * input-gradient product and the weight-gradient cross terms of each) runs as
+ * a handful of phase launches -- all forward NTTs, all multiply-accumulates,
+ * all inverse NTTs, all floods -- whatever the layers' shapes, and can be
+ * replayed as one captured HIP graph.  Layer i's products use nonce + 2i
+ * (forward) and nonce + 2i + 1 (backward), so a step equals the per-layer calls
+ * made with those nonces, bit for bit. */
+typedef struct pencil_step pencil_step;
+
+/* Device buffers of one layer in a step: the same arguments as
+ * pencil_linear_fwd / pencil_linear_bwd (unused ones may be NULL). */
+typedef struct {
+    const uint64_t *ct_x1, *ct_dy_dx, *ct_x_dw, *ct_dy_dw;
+    const int64_t *x0, *dy0, *w, *bias;
+    uint64_t *ct_y, *ct_dx, *ct_dw;
+    int64_t *y0, *dx0, *dw_mask;
+} pencil_step_io;
+
+/* n layers, layer i on context ctxs[i] with plan plans[i] (host arrays);
+ * ops: bit 0 forward, bit 1 input gradient, bit 2 weight gradient. */
+pencil_status pencil_step_create(pencil_ctx* const* ctxs, const pencil_layer* layers, const pencil_plan* plans,
+                                 int n, uint32_t ops, pencil_step** out);
+pencil_status pencil_step_destroy(pencil_step* step);
+const char* pencil_step_last_error(const pencil_step* step);
+/* Device workspace the step needs (every product's staging at once). */
+pencil_status pencil_step_workspace(const pencil_step* step, uint64_t* bytes /* host */);
+/* Fix the buffers (io: n host entries) and the workspace; builds the segment
+ * tables on the device.  Synchronous. */
+pencil_status pencil_step_bind(pencil_step* step, const pencil_step_io* io, void* ws);
+/* Run the bound step on `stream` with base nonce `nonce`. */
+pencil_status pencil_step_run(pencil_step* step, uint64_t nonce, void* stream);
+/* Capture one run into a HIP graph whose first node advances the device-side
+ * nonce by 2n, so consecutive replays use fresh nonces. */
+pencil_status pencil_step_graph_capture(pencil_step* step);
+/* The next replay uses base nonce `nonce`. */
+pencil_status pencil_step_set_nonce(pencil_step* step, uint64_t nonce, void* stream);
+pencil_status pencil_step_graph_launch(pencil_step* step, void* stream);
 
 /* Kernel timing: while enabled, every kernel this context launches is bracketed
  * by HIP events recorded on its launch stream.  enable() clears the totals.

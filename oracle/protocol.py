@@ -2,8 +2,8 @@
 ends of them: Alg. 1 (forward), its pattern for the input gradient
 (Sec. III.B.2) and the cross terms of Alg. 2 (weight gradient).
 
-Model owner's product for one output tile o (Alg. 1 lines 2-3, Alg. 2 lines
-2-3):
+Model owner's product for one output tile o (the product and share steps of
+Alg. 1 and Alg. 2):
     acc = sum over contraction tiles and terms of lift(P) * C        (ring products)
     acc += Enc_pk(0) with fresh u', e0', e1'                            (re-randomise)
     c0 += flood - D(s)                                                  (flood, mask)
@@ -76,8 +76,8 @@ def mo_product(P, pk, layer, op, tile, terms, seed, nonce, add_share=None, bias=
 
     terms: list of (a, k) where each of a, k is ("ct", [ciphertexts by tile
     index]) or ("pt", Z_t tensor in the layer's layout).  add_share: the model
-    owner's share added to the A-side ciphertexts before the product (Alg. 1
-    line 2).  outs: output tile indices to compute (default all).  coeff_idx:
+    owner's share added to the A-side ciphertexts before the product (Alg. 1,
+    product step).  outs: output tile indices to compute (default all).  coeff_idx:
     compute only these coefficients of each output ciphertext.
 
     Returns {o: ct [2][L][len]} and the model owner's share tensor (entries of

@@ -7,4 +7,4 @@ C ABI of include/pencil.h.  This package is the binding: argument marshalling
 over ctypes, PyTorch for device memory and streams.
 """
 from ._abi import PencilError, load  # noqa: F401
-from .api import Context, layer_struct, plan_struct, plan_dict  # noqa: F401
+from .api import Context, Step, layer_struct, plan_struct, plan_dict  # noqa: F401

@@ -36,7 +36,7 @@ class Tile(ctypes.Structure):
 
 
 class Plan(ctypes.Structure):
-    _fields_ = [("fwd", Tile), ("dx", Tile), ("dw", Tile)]
+    _fields_ = [("fwd", Tile), ("dx", Tile), ("dw", Tile), ("sched", ctypes.c_int32 * 3)]
 
 
 class Sizes(ctypes.Structure):
@@ -50,6 +50,11 @@ class Info(ctypes.Structure):
     _fields_ = [("log2_n", ctypes.c_uint32), ("num_limbs", ctypes.c_uint32), ("flood_bits", ctypes.c_uint32),
                 ("reserved", ctypes.c_uint32), ("primes", ctypes.c_uint64 * 4), ("psi", ctypes.c_uint64 * 4),
                 ("t", ctypes.c_uint64), ("seed", ctypes.c_uint64)]
+
+
+class StepIO(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in ("ct_x1", "ct_dy_dx", "ct_x_dw", "ct_dy_dw", "x0", "dy0", "w", "bias",
+                                                "ct_y", "ct_dx", "ct_dw", "y0", "dx0", "dw_mask")]
 
 
 class KernelStat(ctypes.Structure):
@@ -81,6 +86,19 @@ SIGNATURES = {
                                            ctypes.POINTER(ctypes.c_int)]),
     "pencil_zt_linear": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Layer), ctypes.c_int, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "pencil_step_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(Layer),
+                                          ctypes.POINTER(Plan), ctypes.c_int, ctypes.c_uint32,
+                                          ctypes.POINTER(ctypes.c_void_p)]),
+    "pencil_step_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "pencil_step_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
+    "pencil_step_workspace": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]),
+    "pencil_step_bind": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(StepIO), ctypes.c_void_p]),
+    "pencil_step_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]),
+    "pencil_step_graph_capture": (ctypes.c_int, [ctypes.c_void_p]),
+    "pencil_step_set_nonce": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]),
+    "pencil_step_graph_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "pencil_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Layer), ctypes.POINTER(Plan),
+                                       ctypes.c_char_p]),
     "pencil_ntt_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
     "pencil_ntt_inverse": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
 }

@@ -32,12 +32,15 @@ def plan_struct(plan):
     if isinstance(plan, A.Plan):
         return plan
     zero = (0,) * 7
-    return A.Plan(tile_struct(plan.get("fwd", zero)), tile_struct(plan.get("dx", zero)),
-                  tile_struct(plan.get("dw", zero)))
+    p = A.Plan(tile_struct(plan.get("fwd", zero)), tile_struct(plan.get("dx", zero)),
+               tile_struct(plan.get("dw", zero)))
+    for i, v in enumerate(plan.get("sched", (0, 0, 0))):
+        p.sched[i] = int(v)
+    return p
 
 
 def plan_dict(p):
-    return {"fwd": p.fwd.astuple(), "dx": p.dx.astuple(), "dw": p.dw.astuple()}
+    return {"fwd": p.fwd.astuple(), "dx": p.dx.astuple(), "dw": p.dw.astuple(), "sched": tuple(p.sched)}
 
 
 def _ptr(t):
@@ -108,6 +111,15 @@ class Context:
         p = A.Plan()
         self._check(self.lib.pencil_plan_auto(self.h, ctypes.byref(layer_struct(layer)), ctypes.byref(p)))
         return p
+
+    def autotune(self, layer, plan, cache_path=None):
+        """Measure the schedule candidates (results are identical) and return the tuned plan."""
+        p = plan_struct(plan)
+        q = A.Plan()
+        ctypes.pointer(q)[0] = p
+        self._check(self.lib.pencil_autotune(self.h, ctypes.byref(layer_struct(layer)), ctypes.byref(q),
+                                             cache_path.encode() if cache_path else None))
+        return q
 
     def layout(self, layer, plan):
         s = A.Sizes()
@@ -218,3 +230,71 @@ def _y_shape(layer):
 def _w_shape(layer):
     ci, co = _get(layer, "c_in"), _get(layer, "c_out")
     return (co, ci) if _is_fc(layer) else (co, ci, _get(layer, "k"), _get(layer, "k"))
+
+
+class Step:
+    """All products of several layers as one batched launch sequence.
+
+    layers: list of (Context, layer, plan); ops: subset of ("fwd", "dx", "dw").
+    Bind once with the device buffers of every layer, then run() or replay a
+    captured graph.  Layer i uses nonce + 2i (forward) and nonce + 2i + 1
+    (backward), matching the per-layer calls made with those nonces.
+    """
+
+    def __init__(self, layers, ops=("fwd", "dx", "dw")):
+        self.lib = A.load()
+        self.entries = [(c, l, plan_struct(p)) for c, l, p in layers]
+        n = len(layers)
+        ctxs = (ctypes.c_void_p * n)(*[c.h.value for c, _, _ in self.entries])
+        lays = (A.Layer * n)(*[layer_struct(l) for _, l, _ in self.entries])
+        plans = (A.Plan * n)(*[p for _, _, p in self.entries])
+        mask = sum(1 << OPS[o] for o in ops)
+        h = ctypes.c_void_p()
+        st = self.lib.pencil_step_create(ctxs, lays, plans, n, mask, ctypes.byref(h))
+        if st != A.PENCIL_OK:
+            raise A.PencilError(st, self.lib.pencil_last_error(None).decode())
+        self.h = h
+        self.ops = ops
+        self._keep = None
+
+    def _check(self, st):
+        if st != A.PENCIL_OK:
+            raise A.PencilError(st, self.lib.pencil_step_last_error(self.h).decode())
+
+    def workspace_bytes(self):
+        b = ctypes.c_uint64()
+        self._check(self.lib.pencil_step_workspace(self.h, ctypes.byref(b)))
+        return b.value
+
+    def bind(self, ios, ws):
+        """ios: one dict per layer with the tensors named as in pencil_step_io."""
+        arr = (A.StepIO * len(ios))()
+        for i, d in enumerate(ios):
+            for k, v in d.items():
+                if v is not None:
+                    setattr(arr[i], k, v.data_ptr())
+        self._keep = (ios, ws)
+        self._check(self.lib.pencil_step_bind(self.h, arr, ctypes.c_void_p(ws.data_ptr())))
+
+    def run(self, nonce):
+        self._check(self.lib.pencil_step_run(self.h, nonce, _stream()))
+
+    def capture(self):
+        self._check(self.lib.pencil_step_graph_capture(self.h))
+
+    def set_nonce(self, nonce):
+        self._check(self.lib.pencil_step_set_nonce(self.h, nonce, _stream()))
+
+    def replay(self):
+        self._check(self.lib.pencil_step_graph_launch(self.h, _stream()))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.pencil_step_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -51,10 +51,11 @@ struct pencil_ctx {
 
 enum KernelId {
   KID_NTT_CT, KID_NTT_PT, KID_NTT_TERNARY, KID_MAC, KID_INTT_OUT, KID_FLOOD, KID_ENCRYPT, KID_PHASE, KID_DECODE,
-  KID_NTT_PLAIN, KID_COUNT
+  KID_NTT_PLAIN, KID_STEP_NTT, KID_STEP_MAC, KID_STEP_INTT, KID_STEP_FLOOD, KID_COUNT
 };
 static const char* kKernelNames[KID_COUNT] = {"ntt_ct", "ntt_pt", "ntt_ternary", "mac", "intt_out",
-                                              "flood_mask", "encrypt", "phase", "decode", "ntt_plain"};
+                                              "flood_mask", "encrypt", "phase", "decode", "ntt_plain",
+                                              "step_ntt", "step_mac", "step_intt", "step_flood"};
 
 static hipEvent_t pool_event(pencil_ctx* ctx) {
   if (!ctx->ev_pool.empty()) {
@@ -264,6 +265,7 @@ static pencil_status resolve_params(const pencil_params* p, pencil_ctx* ctx) {
   C.log2n = (int32_t)p->log2_n;
   C.n = (int32_t)n;
   C.L = (int32_t)p->num_limbs;
+  C.ntt_loge = p->log2_n >= 14 ? 5 : 4;
   C.flood_bits = fb;
   C.flood_words = (int32_t)((fb + 1 + 63) / 64);
   const int topbits = (int)(fb + 1) - 64 * (C.flood_words - 1);
@@ -276,7 +278,6 @@ static pencil_status resolve_params(const pencil_params* p, pencil_ctx* ctx) {
   C.r64t_sh = shoup(C.r64t, t);
   C.one_sh_t = (uint64_t)((((u128)1) << 64) / t);
   C.seed = p->seed;
-  int maxbits = 0;
   for (int l = 0; l < C.L; ++l) {
     const uint64_t ql = I.primes[l];
     LimbConst& lc = C.limb[l];
@@ -303,13 +304,28 @@ static pencil_status resolve_params(const pencil_params* p, pencil_ctx* ctx) {
     for (int w = 0; w < kMaxWords; ++w) C.qhat[l][w] = w < (int)qhat.size() ? qhat[w] : 0;
     Big th = big_mul_small(q, 2 * (uint64_t)l + 1);
     for (int w = 0; w < kMaxWords; ++w) C.thr[l][w] = w < (int)th.size() ? th[w] : 0;
-    maxbits = std::max(maxbits, 64 - __builtin_clzll(ql));
     I.psi[l] = min_root(ql, n);
   }
-  // 128-bit accumulator headroom: c products below 2^(2 maxbits) plus a reduced
-  // residue stay below 2^128 when c <= 2^(127 - 2 maxbits); maxbits <= 61.
-  const int head = 127 - 2 * maxbits;
-  C.mac_chunk = head >= 7 ? 128u : (1u << head);
+  // Multiply-accumulate headroom.  Operands are split into 30-bit halves
+  // a = a0 + a1 2^30 with a1 <= amax = (q - 1) >> 30; one step adds at most
+  // 2 (2^30 - 1) amax to the cross-term partial sum, so mac_fold steps keep all
+  // three 64-bit partial sums in range.  A fold adds at most
+  // F = mac_fold * (q - 1)^2 to the 128-bit total, which holds mac_chunk folds
+  // on top of a reduced residue.
+  {
+    uint64_t qmax = 0;
+    for (int l = 0; l < C.L; ++l) qmax = std::max(qmax, C.limb[l].q);
+    const u128 lo30 = (1u << 30) - 1, amax = (qmax - 1) >> 30;
+    const u128 step_max = std::max(std::max(lo30 * lo30, 2 * lo30 * amax), amax * amax);
+    u128 fold = ((u128)~0ull) / step_max;
+    if (fold > 64) fold = 64;
+    C.mac_fold = (uint32_t)fold;
+    const u128 per_fold = fold * (u128)(qmax - 1) * (qmax - 1);
+    const u128 room = (~(u128)0) - qmax;
+    u128 chunk = room / per_fold;
+    if (chunk > 1024) chunk = 1024;
+    C.mac_chunk = (uint32_t)(chunk < 1 ? 1 : chunk);
+  }
   C.qwords = (uint32_t)q.size();
   return PENCIL_OK;
 }
@@ -639,15 +655,36 @@ static bool plan_op(const pencil_layer* L, int op, int log2n, pencil_tile* best)
   return found;
 }
 
+// Default multiply-accumulate chunk: the shape that stages the fewest padded
+// operand rows per contraction step (A rows count twice: two components).
+static int default_sched(const pencil_layer* L, int op, const pencil_tile& t, int n) {
+  Geo G;
+  if (!make_geo(op_geom(L, op), t, n, &G)) return 0;
+  const int rows = G.nM * G.nOY * G.nOX;
+  int best = 0;
+  int64_t best_v = -1;
+  for (int v = 0; v < 3; ++v) {
+    const int64_t rc = (rows + mac_rows(v) - 1) / mac_rows(v), cc = (G.nR + mac_cols(v) - 1) / mac_cols(v);
+    const int64_t vol = rc * cc * (2 * mac_rows(v) + mac_cols(v));
+    if (best_v < 0 || vol < best_v) {
+      best_v = vol;
+      best = v;
+    }
+  }
+  return best;
+}
+
 extern "C" pencil_status pencil_plan_auto(const pencil_ctx* cctx, const pencil_layer* L, pencil_plan* plan) {
   pencil_ctx* ctx = const_cast<pencil_ctx*>(cctx);
   if (!ctx || !plan) return PENCIL_EINVAL;
   pencil_status st = PENCIL_OK;
   if (!layer_ok(ctx, L, &st)) return st;
   pencil_tile* tiles[3] = {&plan->fwd, &plan->dx, &plan->dw};
-  for (int op = 0; op < 3; ++op)
+  for (int op = 0; op < 3; ++op) {
     if (!plan_op(L, op, ctx->C.log2n, tiles[op]))
       return fail(ctx, PENCIL_EUNSUPPORTED, "no tile of op %d fits N = %d", op, ctx->C.n);
+    plan->sched[op] = default_sched(L, op, *tiles[op], ctx->C.n);
+  }
   return PENCIL_OK;
 }
 
@@ -745,7 +782,8 @@ struct TermIn {
 
 static pencil_status run_product(pencil_ctx* ctx, const pencil_layer* L, int op, const Geo& G, const TermIn* terms,
                                  int n_terms, const int64_t* add_share, const int64_t* bias, uint64_t* ct_out,
-                                 int64_t* share_out, uint8_t* ws, uint64_t nonce, hipStream_t s) {
+                                 int64_t* share_out, uint8_t* ws, uint64_t nonce, int sched, hipStream_t s) {
+  if (sched < 0 || sched > 2) return fail(ctx, PENCIL_EINVAL, "schedule variant %d invalid", sched);
   const Consts& C = ctx->C;
   const int64_t poly = (int64_t)C.L * C.n, ctw = 2 * poly;
   const int64_t na = n_a_tiles(G), nk = n_k_tiles(G), no = n_out_tiles(G);
@@ -753,6 +791,7 @@ static pencil_status run_product(pencil_ctx* ctx, const pencil_layer* L, int op,
   MacArgs A{};
   A.n_terms = n_terms;
   A.m_rows = G.nM * G.nOY * G.nOX;
+  A.variant = sched;
   A.pk = ctx->d_pk_ntt;
   A.out = ct_out;
   for (int i = 0; i < n_terms; ++i) {
@@ -795,7 +834,7 @@ static pencil_status run_product(pencil_ctx* ctx, const pencil_layer* L, int op,
 
 static bool mac_grid_ok(const Geo& G) {
   const int64_t rows = (int64_t)G.nM * G.nOY * G.nOX;
-  return ((rows + 1) / 2) * ((G.nR + 1) / 2) < 65536;
+  return (int64_t)mac_chunks(1, (int)rows, G.nR) < 65536 && (int64_t)mac_chunks(2, (int)rows, G.nR) < 65536;
 }
 
 extern "C" pencil_status pencil_linear_fwd(pencil_ctx* ctx, const pencil_layer* L, const pencil_plan* P,
@@ -813,7 +852,8 @@ extern "C" pencil_status pencil_linear_fwd(pencil_ctx* ctx, const pencil_layer* 
   TRY(get_geo(ctx, L, P, PENCIL_OP_FWD, &G));
   if (!mac_grid_ok(G)) return fail(ctx, PENCIL_EUNSUPPORTED, "too many output tiles for one launch");
   TermIn t{ct_x1, w, 1};
-  return run_product(ctx, L, PENCIL_OP_FWD, G, &t, 1, x0, bias, ct_y, y0, (uint8_t*)ws, nonce, (hipStream_t)stream);
+  return run_product(ctx, L, PENCIL_OP_FWD, G, &t, 1, x0, bias, ct_y, y0, (uint8_t*)ws, nonce, P->sched[0],
+                     (hipStream_t)stream);
 }
 
 extern "C" pencil_status pencil_linear_bwd(pencil_ctx* ctx, const pencil_layer* L, const pencil_plan* P,
@@ -834,7 +874,7 @@ extern "C" pencil_status pencil_linear_bwd(pencil_ctx* ctx, const pencil_layer* 
     TRY(get_geo(ctx, L, P, PENCIL_OP_DX, &G));
     if (!mac_grid_ok(G)) return fail(ctx, PENCIL_EUNSUPPORTED, "too many output tiles for one launch");
     TermIn t{ct_dy_dx, w, 1};
-    TRY(run_product(ctx, L, PENCIL_OP_DX, G, &t, 1, dy0, nullptr, ct_dx, dx0, (uint8_t*)ws, nonce, s));
+    TRY(run_product(ctx, L, PENCIL_OP_DX, G, &t, 1, dy0, nullptr, ct_dx, dx0, (uint8_t*)ws, nonce, P->sched[1], s));
   }
   if (ct_dw || dw_mask) {
     TRY(check_ptr(ctx, ct_x_dw, "ct_x_dw"));
@@ -846,7 +886,8 @@ extern "C" pencil_status pencil_linear_bwd(pencil_ctx* ctx, const pencil_layer* 
     TRY(get_geo(ctx, L, P, PENCIL_OP_DW, &G));
     if (!mac_grid_ok(G)) return fail(ctx, PENCIL_EUNSUPPORTED, "too many output tiles for one launch");
     TermIn t[2] = {{ct_x_dw, dy0, 1}, {ct_dy_dw, x0, 0}};
-    TRY(run_product(ctx, L, PENCIL_OP_DW, G, t, 2, nullptr, nullptr, ct_dw, dw_mask, (uint8_t*)ws, nonce, s));
+    TRY(run_product(ctx, L, PENCIL_OP_DW, G, t, 2, nullptr, nullptr, ct_dw, dw_mask, (uint8_t*)ws, nonce, P->sched[2],
+                    s));
   }
   return PENCIL_OK;
 }
@@ -909,6 +950,550 @@ extern "C" pencil_status pencil_zt_linear(pencil_ctx* ctx, const pencil_layer* L
   return PENCIL_OK;
 }
 
+// ------------------------------------------------------------ batched step
+
+struct pencil_step {
+  struct Entry {
+    int ctx;
+    pencil_layer L;
+    pencil_plan P;
+    Geo G[3];
+    uint64_t ws_off[3];
+  };
+  std::vector<pencil_ctx*> ctxs;
+  std::vector<Entry> layers;
+  uint32_t ops = 0;
+  uint64_t ws_bytes = 0;
+  Consts* d_consts = nullptr;
+  Tables* d_tabs = nullptr;
+  uint64_t* d_nonce = nullptr;
+  struct Phase {
+    int kind;  // 0 ntt, 1 mac, 2 intt, 3 flood
+    int key;   // NTT phases: 8 log2 N + log2(residues per thread); flood: words
+    std::vector<StepSeg> segs;
+    StepSeg* d_segs = nullptr;
+    int64_t blocks = 0;
+  };
+  std::vector<Phase> phases;
+  bool bound = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::string err;
+};
+
+static pencil_status step_fail(pencil_step* st, pencil_status code, const char* msg) {
+  if (st) st->err = msg;
+  else g_create_err = msg;
+  return code;
+}
+
+// Workspace of one product inside a step: the same layout as run_product.
+static uint64_t product_ws(const Consts& C, const Geo& G, int op) {
+  const uint64_t poly = (uint64_t)C.L * C.n * 8, ct = 2 * poly;
+  const uint64_t na = (uint64_t)n_a_tiles(G), nk = (uint64_t)n_k_tiles(G), no = (uint64_t)n_out_tiles(G);
+  if (op == PENCIL_OP_DW) return na * ct + nk * poly + na * poly + nk * ct + no * poly;
+  return na * ct + nk * poly + no * poly;
+}
+
+extern "C" pencil_status pencil_step_create(pencil_ctx* const* ctxs, const pencil_layer* layers,
+                                            const pencil_plan* plans, int n, uint32_t ops, pencil_step** out) {
+  if (!out || !ctxs || !layers || !plans || n < 1 || (ops & ~7u) || ops == 0)
+    return step_fail(nullptr, PENCIL_EINVAL, "bad step arguments");
+  *out = nullptr;
+  pencil_step* st = new pencil_step();
+  st->ops = ops;
+  uint64_t off = 0;
+  for (int i = 0; i < n; ++i) {
+    if (!ctxs[i]) {
+      delete st;
+      return step_fail(nullptr, PENCIL_EINVAL, "NULL context");
+    }
+    int ci = -1;
+    for (size_t k = 0; k < st->ctxs.size(); ++k)
+      if (st->ctxs[k] == ctxs[i]) ci = (int)k;
+    if (ci < 0) {
+      ci = (int)st->ctxs.size();
+      st->ctxs.push_back(ctxs[i]);
+    }
+    pencil_step::Entry e{};
+    e.ctx = ci;
+    e.L = layers[i];
+    e.P = plans[i];
+    for (int op = 0; op < 3; ++op) {
+      if (!(ops & (1u << op))) continue;
+      pencil_status s = get_geo(ctxs[i], &layers[i], &plans[i], op, &e.G[op]);
+      if (s != PENCIL_OK) {
+        std::string m = std::string("layer ") + std::to_string(i) + ": " + ctxs[i]->err;
+        delete st;
+        return step_fail(nullptr, s, m.c_str());
+      }
+      e.ws_off[op] = off;
+      off += (product_ws(ctxs[i]->C, e.G[op], op) + 255) & ~255ull;
+    }
+    st->layers.push_back(e);
+  }
+  st->ws_bytes = off;
+  const size_t nc = st->ctxs.size();
+  std::vector<Consts> cs(nc);
+  std::vector<Tables> ts(nc);
+  for (size_t k = 0; k < nc; ++k) {
+    cs[k] = st->ctxs[k]->C;
+    ts[k] = st->ctxs[k]->T;
+  }
+  if (hipMalloc(&st->d_consts, nc * sizeof(Consts)) != hipSuccess || hipMalloc(&st->d_tabs, nc * sizeof(Tables)) != hipSuccess ||
+      hipMalloc(&st->d_nonce, 256) != hipSuccess) {
+    pencil_step_destroy(st);
+    return step_fail(nullptr, PENCIL_ENOMEM, "step allocation failed");
+  }
+  if (hipMemcpy(st->d_consts, cs.data(), nc * sizeof(Consts), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(st->d_tabs, ts.data(), nc * sizeof(Tables), hipMemcpyHostToDevice) != hipSuccess) {
+    pencil_step_destroy(st);
+    return step_fail(nullptr, PENCIL_EHIP, "step upload failed");
+  }
+  *out = st;
+  return PENCIL_OK;
+}
+
+extern "C" pencil_status pencil_step_destroy(pencil_step* st) {
+  if (!st) return PENCIL_OK;
+  if (st->exec) hipGraphExecDestroy(st->exec);
+  if (st->graph) hipGraphDestroy(st->graph);
+  for (auto& ph : st->phases) hipFree(ph.d_segs);
+  hipFree(st->d_consts);
+  hipFree(st->d_tabs);
+  hipFree(st->d_nonce);
+  delete st;
+  return PENCIL_OK;
+}
+
+extern "C" const char* pencil_step_last_error(const pencil_step* st) { return st ? st->err.c_str() : ""; }
+
+extern "C" pencil_status pencil_step_workspace(const pencil_step* st, uint64_t* bytes) {
+  if (!st || !bytes) return PENCIL_EINVAL;
+  *bytes = st->ws_bytes;
+  return PENCIL_OK;
+}
+
+static pencil_step::Phase& phase_for(pencil_step* st, int kind, int key) {
+  for (auto& ph : st->phases)
+    if (ph.kind == kind && ph.key == key) return ph;
+  pencil_step::Phase ph;
+  ph.kind = kind;
+  ph.key = key;
+  st->phases.push_back(ph);
+  return st->phases.back();
+}
+
+static void add_seg(pencil_step::Phase& ph, StepSeg sg, int64_t blocks) {
+  if (blocks <= 0) return;
+  sg.block_begin = ph.blocks;
+  ph.blocks += blocks;
+  ph.segs.push_back(sg);
+}
+
+extern "C" pencil_status pencil_step_bind(pencil_step* st, const pencil_step_io* io, void* ws) {
+  if (!st || !io || !ws) return step_fail(st, PENCIL_EINVAL, "NULL argument");
+  for (auto& ph : st->phases) hipFree(ph.d_segs);
+  st->phases.clear();
+  if (st->exec) {
+    hipGraphExecDestroy(st->exec);
+    st->exec = nullptr;
+  }
+  if (st->graph) {
+    hipGraphDestroy(st->graph);
+    st->graph = nullptr;
+  }
+  // fixed phase order: forward NTTs, MAC, inverse NTTs, flood (per ring degree / flood width)
+  for (int kind = 0; kind < 4; ++kind)
+    for (auto& e : st->layers) {
+      const Consts& C = st->ctxs[e.ctx]->C;
+      phase_for(st, kind, kind == 3 ? C.flood_words : (kind == 1 ? 0 : C.log2n * 8 + C.ntt_loge));
+    }
+  for (size_t i = 0; i < st->layers.size(); ++i) {
+    const auto& e = st->layers[i];
+    const pencil_step_io& b = io[i];
+    pencil_ctx* ctx = st->ctxs[e.ctx];
+    const Consts& C = ctx->C;
+    const int64_t poly = (int64_t)C.L * C.n, ctw = 2 * poly;
+    for (int op = 0; op < 3; ++op) {
+      if (!(st->ops & (1u << op))) continue;
+      const Geo& G = e.G[op];
+      const int64_t na = n_a_tiles(G), nk = n_k_tiles(G), no = n_out_tiles(G);
+      const pencil_layer* L = &e.L;
+      // inputs and outputs of this product
+      const uint64_t* ct_a = op == 0 ? b.ct_x1 : op == 1 ? b.ct_dy_dx : b.ct_x_dw;
+      const int64_t* add_share = op == 0 ? b.x0 : op == 1 ? b.dy0 : nullptr;
+      const int64_t* pt_k = op == 2 ? b.dy0 : b.w;
+      uint64_t* ct_out = op == 0 ? b.ct_y : op == 1 ? b.ct_dx : b.ct_dw;
+      int64_t* share_out = op == 0 ? b.y0 : op == 1 ? b.dx0 : b.dw_mask;
+      if (!ct_a || !pt_k || !ct_out || !share_out || (op != 2 && !add_share) ||
+          (op == 2 && (!b.x0 || !b.ct_dy_dw)))
+        return step_fail(st, PENCIL_EINVAL, "missing buffer in step io");
+      uint64_t* w = (uint64_t*)((uint8_t*)ws + e.ws_off[op]);
+      const uint64_t nonce_off = 2 * (uint64_t)i + (op == 0 ? 0 : 1);
+      auto& ntt = phase_for(st, 0, C.log2n * 8 + C.ntt_loge);
+      MacArgs A{};
+      A.m_rows = G.nM * G.nOY * G.nOX;
+      A.variant = e.P.sched[op];
+      if (A.variant < 0 || A.variant > 2) return step_fail(st, PENCIL_EINVAL, "schedule variant invalid");
+      A.pk = ctx->d_pk_ntt;
+      A.out = ct_out;
+      StepSeg base{};
+      base.ctx = e.ctx;
+      base.G = G;
+      // term A-side ciphertext
+      {
+        uint64_t* cts = w;
+        w += na * ctw;
+        uint64_t* pts = w;
+        w += nk * poly;
+        StepSeg sc = base;
+        sc.kind = SEG_CT;
+        sc.src = ct_a;
+        sc.dst = cts;
+        sc.tensor = add_share;
+        sc.V = view_a(L, op);
+        add_seg(ntt, sc, na * 2 * C.L);
+        StepSeg sp = base;
+        sp.kind = SEG_PT;
+        sp.side = 1;
+        sp.tensor = pt_k;
+        sp.dst = pts;
+        sp.V = view_k(L, op);
+        add_seg(ntt, sp, nk * C.L);
+        A.term[0] = MacTerm{cts, pts, 1, 0};
+        A.n_terms = 1;
+      }
+      if (op == 2) {  // term B: plaintext <X>_0 on the A side, ciphertext <dY>_1 on the K side
+        uint64_t* pts = w;
+        w += na * poly;
+        uint64_t* cts = w;
+        w += nk * ctw;
+        StepSeg sp = base;
+        sp.kind = SEG_PT;
+        sp.side = 0;
+        sp.tensor = b.x0;
+        sp.dst = pts;
+        sp.V = view_a(L, op);
+        add_seg(ntt, sp, na * C.L);
+        StepSeg sc = base;
+        sc.kind = SEG_CT;
+        sc.src = b.ct_dy_dw;
+        sc.dst = cts;
+        sc.tensor = nullptr;
+        sc.V = view_k(L, op);
+        add_seg(ntt, sc, nk * 2 * C.L);
+        A.term[1] = MacTerm{pts, cts, 0, 0};
+        A.n_terms = 2;
+      }
+      uint64_t* u = w;
+      StepSeg su = base;
+      su.kind = SEG_TERN;
+      su.dst = u;
+      su.nonce_off = nonce_off;
+      su.obj_base = out_object(op, 0);
+      su.purpose = P_RR_U;
+      add_seg(ntt, su, no * C.L);
+      A.u = u;
+      StepSeg sm = base;
+      sm.kind = SEG_MAC;
+      sm.mac = A;
+      sm.slot_blocks = (int64_t)C.n * C.L / 64;
+      const int64_t chunks = mac_chunks(A.variant, A.m_rows, G.nR);
+      add_seg(phase_for(st, 1, 0), sm, sm.slot_blocks * chunks);
+      StepSeg si = base;
+      si.kind = SEG_INTT;
+      si.dst = ct_out;
+      add_seg(phase_for(st, 2, C.log2n * 8 + C.ntt_loge), si, 2 * no * C.L);
+      StepSeg sf = base;
+      sf.kind = SEG_FLOOD;
+      sf.dst = ct_out;
+      sf.count = no;
+      sf.share = share_out;
+      sf.bias = op == 0 ? b.bias : nullptr;
+      sf.V2 = view_out(L, op);
+      sf.nonce_off = nonce_off;
+      sf.obj_base = out_object(op, 0);
+      add_seg(phase_for(st, 3, C.flood_words), sf, (no * (C.n / 4) + 255) / 256);
+    }
+  }
+  for (auto& ph : st->phases) {
+    if (ph.segs.empty()) continue;
+    if (ph.blocks >= (1ll << 31)) return step_fail(st, PENCIL_EUNSUPPORTED, "step phase too large");
+    if (hipMalloc(&ph.d_segs, ph.segs.size() * sizeof(StepSeg)) != hipSuccess)
+      return step_fail(st, PENCIL_ENOMEM, "segment allocation failed");
+    if (hipMemcpy(ph.d_segs, ph.segs.data(), ph.segs.size() * sizeof(StepSeg), hipMemcpyHostToDevice) != hipSuccess)
+      return step_fail(st, PENCIL_EHIP, "segment upload failed");
+  }
+  st->bound = true;
+  return PENCIL_OK;
+}
+
+static hipError_t step_phases(pencil_step* st, hipStream_t s) {
+  for (auto& ph : st->phases) {
+    if (ph.segs.empty()) continue;
+    StepPhase P{};
+    P.segs = ph.d_segs;
+    P.nseg = (int32_t)ph.segs.size();
+    P.consts = st->d_consts;
+    P.tabs = st->d_tabs;
+    P.nonce = st->d_nonce;
+    hipError_t e = hipSuccess;
+    pencil_ctx* pc = st->ctxs[0];
+    if (ph.kind == 0 || ph.kind == 2)
+      e = timed(pc, ph.kind == 0 ? KID_STEP_NTT : KID_STEP_INTT, s,
+                [&] { return launch_step_ntt(ph.key / 8, ph.key % 8, P, ph.blocks, s); });
+    else if (ph.kind == 1)
+      e = timed(pc, KID_STEP_MAC, s, [&] { return launch_step_mac(P, ph.blocks, s); });
+    else
+      e = timed(pc, KID_STEP_FLOOD, s, [&] { return launch_step_flood(ph.key, P, ph.blocks, s); });
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+extern "C" pencil_status pencil_step_run(pencil_step* st, uint64_t nonce, void* stream) {
+  if (!st) return PENCIL_EINVAL;
+  if (!st->bound) return step_fail(st, PENCIL_EINVAL, "step not bound");
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = launch_set_u64(st->d_nonce, nonce, 0, s);
+  if (e == hipSuccess) e = step_phases(st, s);
+  if (e != hipSuccess) return step_fail(st, PENCIL_EHIP, hipGetErrorString(e));
+  return PENCIL_OK;
+}
+
+extern "C" pencil_status pencil_step_graph_capture(pencil_step* st) {
+  if (!st) return PENCIL_EINVAL;
+  if (!st->bound) return step_fail(st, PENCIL_EINVAL, "step not bound");
+  for (auto* c : st->ctxs)
+    if (c->prof_on) return step_fail(st, PENCIL_EINVAL, "disable profiling before capture");
+  if (st->exec) {
+    hipGraphExecDestroy(st->exec);
+    st->exec = nullptr;
+  }
+  if (st->graph) {
+    hipGraphDestroy(st->graph);
+    st->graph = nullptr;
+  }
+  hipStream_t cs = nullptr;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
+    return step_fail(st, PENCIL_EHIP, "capture stream");
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    const uint64_t stride = 2 * (uint64_t)st->layers.size();
+    hipError_t k = launch_set_u64(st->d_nonce, stride, 1, cs);
+    if (k == hipSuccess) k = step_phases(st, cs);
+    e = hipStreamEndCapture(cs, &st->graph);
+    if (k != hipSuccess) e = k;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&st->exec, st->graph, nullptr, nullptr, 0);
+  hipStreamDestroy(cs);
+  if (e != hipSuccess) return step_fail(st, PENCIL_EHIP, hipGetErrorString(e));
+  return PENCIL_OK;
+}
+
+extern "C" pencil_status pencil_step_set_nonce(pencil_step* st, uint64_t nonce, void* stream) {
+  if (!st) return PENCIL_EINVAL;
+  const uint64_t stride = 2 * (uint64_t)st->layers.size();
+  hipError_t e = launch_set_u64(st->d_nonce, nonce - stride, 0, (hipStream_t)stream);
+  if (e != hipSuccess) return step_fail(st, PENCIL_EHIP, hipGetErrorString(e));
+  return PENCIL_OK;
+}
+
+extern "C" pencil_status pencil_step_graph_launch(pencil_step* st, void* stream) {
+  if (!st) return PENCIL_EINVAL;
+  if (!st->exec) return step_fail(st, PENCIL_EINVAL, "no captured graph");
+  hipError_t e = hipGraphLaunch(st->exec, (hipStream_t)stream);
+  if (e != hipSuccess) return step_fail(st, PENCIL_EHIP, hipGetErrorString(e));
+  return PENCIL_OK;
+}
+
+// ------------------------------------------------------------ autotuner
+
+static std::string arch_name(int device) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return "unknown";
+  std::string a = prop.gcnArchName;
+  const size_t c = a.find(':');
+  return c == std::string::npos ? a : a.substr(0, c);
+}
+
+static void cache_read(const char* path, std::vector<std::pair<std::string, int>>* out) {
+  if (!path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  char line[1024];
+  while (std::fgets(line, sizeof line, f)) {
+    const char* k = std::strstr(line, "\"key\": \"");
+    const char* v = std::strstr(line, "\"choice\": ");
+    if (!k || !v) continue;
+    k += 8;
+    const char* e = std::strchr(k, '"');
+    if (!e) continue;
+    out->emplace_back(std::string(k, e), std::atoi(v + 10));
+  }
+  std::fclose(f);
+}
+
+static bool cache_find(const std::vector<std::pair<std::string, int>>& c, const std::string& key, int* v) {
+  for (auto it = c.rbegin(); it != c.rend(); ++it)
+    if (it->first == key) {
+      *v = it->second;
+      return true;
+    }
+  return false;
+}
+
+// Milliseconds per call of fn (one warm-up call, then `reps` timed calls).
+template <class F>
+static float time_ms(F&& fn, int reps) {
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess) return -1;
+  if (hipEventCreate(&b) != hipSuccess) {
+    hipEventDestroy(a);
+    return -1;
+  }
+  float ms = -1;
+  if (fn() == PENCIL_OK && hipDeviceSynchronize() == hipSuccess) {
+    hipEventRecord(a, nullptr);
+    bool ok = true;
+    for (int i = 0; i < reps && ok; ++i) ok = fn() == PENCIL_OK;
+    hipEventRecord(b, nullptr);
+    if (ok && hipEventSynchronize(b) == hipSuccess) {
+      hipEventElapsedTime(&ms, a, b);
+      ms /= reps;
+    }
+  }
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  return ms;
+}
+
+extern "C" pencil_status pencil_autotune(pencil_ctx* ctx, const pencil_layer* L, pencil_plan* P,
+                                         const char* cache_path) {
+  if (!ctx || !P) return PENCIL_EINVAL;
+  Geo G[3];
+  for (int op = 0; op < 3; ++op) TRY(get_geo(ctx, L, P, op, &G[op]));
+  std::vector<std::pair<std::string, int>> cache;
+  cache_read(cache_path, &cache);
+  std::vector<std::string> fresh;
+  const std::string arch = arch_name(ctx->device);
+  Consts& C = ctx->C;
+  char buf[512];
+  const size_t n = (size_t)C.n, Lm = (size_t)C.L;
+  // 1) NTT residues per thread for this ring degree
+  std::snprintf(buf, sizeof buf, "%s N=%d L=%d ntt_loge", arch.c_str(), C.n, C.L);
+  int v = 0;
+  if (cache_find(cache, buf, &v)) {
+    C.ntt_loge = v;
+  } else {
+    std::vector<int> cands;
+    if (C.log2n >= 14) cands = {5};
+    else if (C.log2n >= 12) cands = {4, 5};
+    else cands = {4};
+    uint64_t* polys = nullptr;
+    const int64_t count = 64;
+    if (hipMalloc(&polys, count * Lm * n * 8) != hipSuccess) return fail(ctx, PENCIL_ENOMEM, "autotune scratch");
+    hipMemsetD32((hipDeviceptr_t)polys, 0x00010001, count * Lm * n * 2);
+    float best = -1;
+    int bestv = C.ntt_loge;
+    std::string times;
+    for (int c : cands) {
+      C.ntt_loge = c;
+      float ms = time_ms([&] { return pencil_ntt_forward(ctx, polys, count, nullptr); }, 5);
+      times += (times.empty() ? "" : ", ") + std::to_string(ms);
+      if (ms > 0 && (best < 0 || ms < best)) {
+        best = ms;
+        bestv = c;
+      }
+    }
+    hipFree(polys);
+    C.ntt_loge = bestv;
+    fresh.push_back(std::string("{\"key\": \"") + buf + "\", \"choice\": " + std::to_string(bestv) +
+                    ", \"ms\": [" + times + "]}");
+  }
+  // 2) multiply-accumulate chunk shape per product
+  const int64_t xs = (int64_t)L->batch * L->c_in * L->h * L->w;
+  const int64_t ho = L->h + 2 * L->pad - L->k + 1, wo = L->w + 2 * L->pad - L->k + 1;
+  const int64_t ys = (int64_t)L->batch * L->c_out * ho * wo, wsz = (int64_t)L->c_out * L->c_in * L->k * L->k;
+  pencil_sizes sz;
+  TRY(pencil_layout(ctx, L, P, &sz));
+  const uint64_t ctb = sz.ct_bytes;
+  const uint64_t nin = std::max(sz.n_ct[0], std::max(sz.n_ct[1], sz.n_ct[2] + sz.n_ct[3]));
+  const uint64_t nout = std::max(sz.n_out[0], std::max(sz.n_out[1], sz.n_out[2]));
+  const uint64_t ws_b = std::max(sz.ws_fwd_bytes, sz.ws_bwd_bytes);
+  const int64_t tmax = std::max(xs, std::max(ys, wsz));
+  uint8_t *cin = nullptr, *cout = nullptr, *ws = nullptr;
+  int64_t *t0 = nullptr, *t1 = nullptr, *t2 = nullptr, *tout = nullptr;
+  auto release = [&] {
+    hipFree(cin);
+    hipFree(cout);
+    hipFree(ws);
+    hipFree(t0);
+    hipFree(t1);
+    hipFree(t2);
+    hipFree(tout);
+  };
+  for (int op = 0; op < 3; ++op) {
+    std::snprintf(buf, sizeof buf, "%s N=%d L=%d layer=%d,%d,%d,%d,%d,%d,%d,%d tile=%d,%d,%d,%d,%d,%d,%d op=%d",
+                  arch.c_str(), C.n, C.L, L->kind, L->batch, L->c_in, L->c_out, L->h, L->w, L->k, L->pad,
+                  plan_tile(P, op).m, plan_tile(P, op).r, plan_tile(P, op).k, plan_tile(P, op).oh, plan_tile(P, op).ow,
+                  plan_tile(P, op).kh, plan_tile(P, op).kw, op);
+    if (cache_find(cache, buf, &v) && v >= 0 && v <= 2) {
+      P->sched[op] = v;
+      continue;
+    }
+    if (!cin) {
+      if (hipMalloc(&cin, nin * ctb) != hipSuccess || hipMalloc(&cout, nout * ctb) != hipSuccess ||
+          hipMalloc(&ws, ws_b) != hipSuccess || hipMalloc(&t0, tmax * 8) != hipSuccess ||
+          hipMalloc(&t1, tmax * 8) != hipSuccess || hipMalloc(&t2, tmax * 8) != hipSuccess ||
+          hipMalloc(&tout, tmax * 8) != hipSuccess) {
+        release();
+        return fail(ctx, PENCIL_ENOMEM, "autotune scratch");
+      }
+      hipMemsetD32((hipDeviceptr_t)cin, 0x00010001, nin * ctb / 4);
+      hipMemsetD32((hipDeviceptr_t)t0, 0x00010001, tmax * 2);
+      hipMemsetD32((hipDeviceptr_t)t1, 0x00010001, tmax * 2);
+      hipMemsetD32((hipDeviceptr_t)t2, 0x00010001, tmax * 2);
+    }
+    const uint64_t* cin2 = (const uint64_t*)(cin + sz.n_ct[2] * ctb);
+    float best = -1;
+    int bestv = P->sched[op];
+    std::string times;
+    for (int cand = 0; cand < 3; ++cand) {
+      P->sched[op] = cand;
+      auto run = [&]() -> pencil_status {
+        if (op == 0)
+          return pencil_linear_fwd(ctx, L, P, (const uint64_t*)cin, t0, t1, nullptr, (uint64_t*)cout, tout, ws, 1,
+                                   nullptr);
+        if (op == 1)
+          return pencil_linear_bwd(ctx, L, P, (const uint64_t*)cin, nullptr, nullptr, t0, nullptr, t1,
+                                   (uint64_t*)cout, tout, nullptr, nullptr, ws, 1, nullptr);
+        return pencil_linear_bwd(ctx, L, P, nullptr, (const uint64_t*)cin, cin2, t0, t1, nullptr, nullptr, nullptr,
+                                 (uint64_t*)cout, tout, ws, 1, nullptr);
+      };
+      const float ms = time_ms(run, 2);
+      times += (times.empty() ? "" : ", ") + std::to_string(ms);
+      if (ms > 0 && (best < 0 || ms < best)) {
+        best = ms;
+        bestv = cand;
+      }
+    }
+    P->sched[op] = bestv;
+    fresh.push_back(std::string("{\"key\": \"") + buf + "\", \"choice\": " + std::to_string(bestv) +
+                    ", \"ms\": [" + times + "]}");
+  }
+  release();
+  if (cache_path && !fresh.empty()) {
+    FILE* f = std::fopen(cache_path, "a");
+    if (f) {
+      for (auto& l : fresh) std::fprintf(f, "%s\n", l.c_str());
+      std::fclose(f);
+    }
+  }
+  return PENCIL_OK;
+}
+
 // ------------------------------------------------------------ profiling
 
 extern "C" pencil_status pencil_profile_enable(pencil_ctx* ctx, int enable) {
@@ -957,7 +1542,9 @@ extern "C" pencil_status pencil_plan_auto_n(uint32_t log2_n, const pencil_layer*
   pencil_status st = PENCIL_OK;
   if (!layer_ok(nullptr, L, &st)) return st;
   pencil_tile* tiles[3] = {&plan->fwd, &plan->dx, &plan->dw};
-  for (int op = 0; op < 3; ++op)
+  for (int op = 0; op < 3; ++op) {
     if (!plan_op(L, op, (int)log2_n, tiles[op])) return fail(nullptr, PENCIL_EUNSUPPORTED, "no tile fits");
+    plan->sched[op] = default_sched(L, op, *tiles[op], 1 << log2_n);
+  }
   return PENCIL_OK;
 }

@@ -14,9 +14,9 @@ namespace pencil {
 // word every 32 so that strided passes spread over the banks.
 __device__ __forceinline__ int lpad(int i) { return i + (i >> 5); }
 
-template <int LOGN>
+template <int LOGN, int LOGE_>
 struct NttShape {
-  static constexpr int LOGE = LOGN >= 14 ? 5 : 4;
+  static constexpr int LOGE = LOGE_;
   static constexpr int E = 1 << LOGE;
   static constexpr int T = (1 << LOGN) / E;  // threads per block
   static constexpr int NP = (LOGN + LOGE - 1) / LOGE;
@@ -46,9 +46,9 @@ __device__ __forceinline__ void gs_bfly(uint64_t& u, uint64_t& v, const TW w, ui
 // bit-reversed out) stages S0 .. S0+S-1.  At stage l (t = N >> (l+1)) the pair
 // (i0, i0 + t) of group i = i0 >> (log2 N - l) uses tw[2^l + i].  A thread takes
 // E / 2^S groups of 2^S residues {base + k * 2^LT}, LT = log2 N - S0 - S.
-template <int LOGN, int S0, int S, bool LAST>
+template <int LOGN, int LOGE, int S0, int S, bool LAST>
 __device__ __forceinline__ void fwd_pass(uint64_t* a, const TW* tw, uint64_t q, uint64_t q2) {
-  using Sh = NttShape<LOGN>;
+  using Sh = NttShape<LOGN, LOGE>;
   constexpr int T = Sh::T, G = Sh::E >> S, K = 1 << S, LT = LOGN - S0 - S;
   const int tid = threadIdx.x;
   uint64_t v[Sh::E];
@@ -95,9 +95,9 @@ __device__ __forceinline__ void fwd_pass(uint64_t* a, const TW* tw, uint64_t q, 
 // Inverse (Gentleman-Sande, psi^-rev twiddles; bit-reversed in, natural out)
 // stages with t = 2^L0 .. 2^(L0+S-1): pair (i0, i0 + t), i = i0 >> (l + 1),
 // twiddle itw[(N >> (l + 1)) + i].  Groups are {base + k * 2^L0}.
-template <int LOGN, int L0, int S>
+template <int LOGN, int LOGE, int L0, int S>
 __device__ __forceinline__ void inv_pass(uint64_t* a, const TW* tw, uint64_t q, uint64_t q2) {
-  using Sh = NttShape<LOGN>;
+  using Sh = NttShape<LOGN, LOGE>;
   constexpr int T = Sh::T, G = Sh::E >> S, K = 1 << S;
   const int tid = threadIdx.x;
   uint64_t v[Sh::E];
@@ -137,46 +137,49 @@ __device__ __forceinline__ void inv_pass(uint64_t* a, const TW* tw, uint64_t q, 
 
 // Forward transform of the LDS polynomial (inputs in [0, q), outputs in [0, q)).
 // Callers synchronise before (inputs written) and after (outputs read).
-template <int LOGN>
+template <int LOGN, int LOGE>
 __device__ __forceinline__ void ntt_fwd(uint64_t* a, const TW* tw, uint64_t q) {
-  using Sh = NttShape<LOGN>;
+  using Sh = NttShape<LOGN, LOGE>;
   const uint64_t q2 = 2 * q;
-  fwd_pass<LOGN, Sh::start(0), Sh::size(0), Sh::NP == 1>(a, tw, q, q2);
+  fwd_pass<LOGN, LOGE, Sh::start(0), Sh::size(0), Sh::NP == 1>(a, tw, q, q2);
   __syncthreads();
   if constexpr (Sh::NP > 1) {
-    fwd_pass<LOGN, Sh::start(1), Sh::size(1), Sh::NP == 2>(a, tw, q, q2);
+    fwd_pass<LOGN, LOGE, Sh::start(1), Sh::size(1), Sh::NP == 2>(a, tw, q, q2);
     __syncthreads();
   }
   if constexpr (Sh::NP > 2) {
-    fwd_pass<LOGN, Sh::start(2), Sh::size(2), Sh::NP == 3>(a, tw, q, q2);
+    fwd_pass<LOGN, LOGE, Sh::start(2), Sh::size(2), Sh::NP == 3>(a, tw, q, q2);
     __syncthreads();
   }
   if constexpr (Sh::NP > 3) {
-    fwd_pass<LOGN, Sh::start(3), Sh::size(3), true>(a, tw, q, q2);
+    fwd_pass<LOGN, LOGE, Sh::start(3), Sh::size(3), true>(a, tw, q, q2);
     __syncthreads();
   }
 }
 
 // Inverse transform without the N^-1 factor (inputs in [0, 2q), outputs in [0, 2q)).
-template <int LOGN>
+template <int LOGN, int LOGE>
 __device__ __forceinline__ void ntt_inv(uint64_t* a, const TW* tw, uint64_t q) {
-  using Sh = NttShape<LOGN>;
+  using Sh = NttShape<LOGN, LOGE>;
   const uint64_t q2 = 2 * q;
-  inv_pass<LOGN, Sh::start(0), Sh::size(0)>(a, tw, q, q2);
+  inv_pass<LOGN, LOGE, Sh::start(0), Sh::size(0)>(a, tw, q, q2);
   __syncthreads();
   if constexpr (Sh::NP > 1) {
-    inv_pass<LOGN, Sh::start(1), Sh::size(1)>(a, tw, q, q2);
+    inv_pass<LOGN, LOGE, Sh::start(1), Sh::size(1)>(a, tw, q, q2);
     __syncthreads();
   }
   if constexpr (Sh::NP > 2) {
-    inv_pass<LOGN, Sh::start(2), Sh::size(2)>(a, tw, q, q2);
+    inv_pass<LOGN, LOGE, Sh::start(2), Sh::size(2)>(a, tw, q, q2);
     __syncthreads();
   }
   if constexpr (Sh::NP > 3) {
-    inv_pass<LOGN, Sh::start(3), Sh::size(3)>(a, tw, q, q2);
+    inv_pass<LOGN, LOGE, Sh::start(3), Sh::size(3)>(a, tw, q, q2);
     __syncthreads();
   }
 }
+
+// Staging format of the multiply-accumulate operands: (v mod 2^30) | (v >> 30) << 32.
+__device__ __forceinline__ uint64_t split30(uint64_t v) { return (v & 0x3FFFFFFFull) | ((v >> 30) << 32); }
 
 // ---------------------------------------------------------- encode helpers
 // round(q m / t) mod q_l for m in [0, t): Delta * m + round(rho m / t), rho = q mod t.
@@ -254,36 +257,39 @@ __device__ __forceinline__ int64_t slot_offset(int side, const Geo& G, const Vie
 // ------------------------------------------------------------------ kernels
 
 // In-place forward or inverse NTT of [polys][L][N].
-template <int LOGN>
-__global__ void __launch_bounds__(512, (LOGN >= 14 ? 2 : 4)) k_ntt_plain(uint64_t* data, int inverse, Consts C, Tables T) {
-  extern __shared__ uint64_t lds[];
+template <int LOGN, int LOGE>
+__device__ __forceinline__ void do_ntt_plain(uint64_t* lds, uint64_t* data, int inverse, const Consts& C,
+                                             const Tables& T, int64_t p) {
   constexpr int n = 1 << LOGN;
   const int L = C.L;
-  const int64_t p = blockIdx.x;
   const int l = (int)(p % L);
   const LimbConst& lc = C.limb[l];
   uint64_t* g = data + p * n;
   for (int i = threadIdx.x; i < n; i += blockDim.x) lds[lpad(i)] = g[i];
   __syncthreads();
   if (!inverse) {
-    ntt_fwd<LOGN>(lds, T.fw + (int64_t)l * n, lc.q);
+    ntt_fwd<LOGN, LOGE>(lds, T.fw + (int64_t)l * n, lc.q);
     for (int i = threadIdx.x; i < n; i += blockDim.x) g[i] = lds[lpad(i)];
   } else {
-    ntt_inv<LOGN>(lds, T.iw + (int64_t)l * n, lc.q);
+    ntt_inv<LOGN, LOGE>(lds, T.iw + (int64_t)l * n, lc.q);
     for (int i = threadIdx.x; i < n; i += blockDim.x) g[i] = mul_shoup(lds[lpad(i)], lc.ninv, lc.ninv_sh, lc.q);
   }
 }
 
-// Input ciphertexts: load (coefficient domain), add round(q m / t) of the model
-// owner's share on component 0 (Alg. 1 line 2), forward NTT, store.
-// Grid: n_ct * 2 * L blocks, polynomial p = (j, c, l) in [n][2][L] order.
-template <int LOGN>
-__global__ void __launch_bounds__(512, (LOGN >= 14 ? 2 : 4)) k_ntt_ct(const uint64_t* src, uint64_t* dst, const int64_t* share, Geo G,
-                                                 View V, Consts C, Tables T) {
+template <int LOGN, int LOGE>
+__global__ void __launch_bounds__(512, (LOGE >= 5 ? 2 : 4)) k_ntt_plain(uint64_t* data, int inverse, Consts C, Tables T) {
   extern __shared__ uint64_t lds[];
+  do_ntt_plain<LOGN, LOGE>(lds, data, inverse, C, T, blockIdx.x);
+}
+
+// Input ciphertexts: load (coefficient domain), add round(q m / t) of the model
+// owner's share on component 0 (Alg. 1, product step), forward NTT, store.
+// Grid: n_ct * 2 * L blocks, polynomial p = (j, c, l) in [n][2][L] order.
+template <int LOGN, int LOGE>
+__device__ __forceinline__ void do_ntt_ct(uint64_t* lds, const uint64_t* src, uint64_t* dst, const int64_t* share,
+                                          const Geo& G, const View& V, const Consts& C, const Tables& T, int64_t p) {
   constexpr int n = 1 << LOGN;
   const int L = C.L;
-  const int64_t p = blockIdx.x;
   const int l = (int)(p % L);
   const int c = (int)((p / L) % 2);
   const int64_t j = p / (2 * L);
@@ -302,20 +308,25 @@ __global__ void __launch_bounds__(512, (LOGN >= 14 ? 2 : 4)) k_ntt_ct(const uint
     lds[lpad(i)] = v;
   }
   __syncthreads();
-  ntt_fwd<LOGN>(lds, T.fw + (int64_t)l * n, lc.q);
+  ntt_fwd<LOGN, LOGE>(lds, T.fw + (int64_t)l * n, lc.q);
   uint64_t* o = dst + p * n;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) o[i] = lds[lpad(i)];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) o[i] = split30(lds[lpad(i)]);
+}
+
+template <int LOGN, int LOGE>
+__global__ void __launch_bounds__(512, (LOGE >= 5 ? 2 : 4)) k_ntt_ct(const uint64_t* src, uint64_t* dst, const int64_t* share, Geo G,
+                                                 View V, Consts C, Tables T) {
+  extern __shared__ uint64_t lds[];
+  do_ntt_ct<LOGN, LOGE>(lds, src, dst, share, G, V, C, T, blockIdx.x);
 }
 
 // Plaintext tiles: encode (side 0: forward A tile, 1: reverse K tile), centred
 // lift of Z_t into Z_{q_l}, forward NTT.  Grid: n_pt * L, output [n][L][N].
-template <int LOGN>
-__global__ void __launch_bounds__(512, (LOGN >= 14 ? 2 : 4)) k_ntt_pt(const int64_t* tensor, uint64_t* dst, int side, Geo G, View V,
-                                                 Consts C, Tables T) {
-  extern __shared__ uint64_t lds[];
+template <int LOGN, int LOGE>
+__device__ __forceinline__ void do_ntt_pt(uint64_t* lds, const int64_t* tensor, uint64_t* dst, int side,
+                                          const Geo& G, const View& V, const Consts& C, const Tables& T, int64_t p) {
   constexpr int n = 1 << LOGN;
   const int L = C.L;
-  const int64_t p = blockIdx.x;
   const int l = (int)(p % L);
   const int64_t j = p / L;
   const LimbConst& lc = C.limb[l];
@@ -329,21 +340,26 @@ __global__ void __launch_bounds__(512, (LOGN >= 14 ? 2 : 4)) k_ntt_pt(const int6
     lds[lpad(i)] = v;
   }
   __syncthreads();
-  ntt_fwd<LOGN>(lds, T.fw + (int64_t)l * n, lc.q);
+  ntt_fwd<LOGN, LOGE>(lds, T.fw + (int64_t)l * n, lc.q);
   uint64_t* o = dst + p * n;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) o[i] = lds[lpad(i)];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) o[i] = split30(lds[lpad(i)]);
+}
+
+template <int LOGN, int LOGE>
+__global__ void __launch_bounds__(512, (LOGE >= 5 ? 2 : 4)) k_ntt_pt(const int64_t* tensor, uint64_t* dst, int side, Geo G, View V,
+                                                 Consts C, Tables T) {
+  extern __shared__ uint64_t lds[];
+  do_ntt_pt<LOGN, LOGE>(lds, tensor, dst, side, G, V, C, T, blockIdx.x);
 }
 
 // Fresh ternary polynomials (object obj_base + j, stream `purpose`), lifted and
 // transformed.  Coefficient i uses the 32-bit half i mod 2 of stream word i/2,
 // so one Philox block covers 8 coefficients.  Grid: count * L, output [n][L][N].
-template <int LOGN>
-__global__ void __launch_bounds__(512, (LOGN >= 14 ? 2 : 4)) k_ntt_ternary(uint64_t* dst, uint64_t nonce, uint64_t obj_base,
-                                                      uint32_t purpose, Consts C, Tables T) {
-  extern __shared__ uint64_t lds[];
+template <int LOGN, int LOGE>
+__device__ __forceinline__ void do_ntt_ternary(uint64_t* lds, uint64_t* dst, uint64_t nonce, uint64_t obj_base,
+                                               uint32_t purpose, const Consts& C, const Tables& T, int64_t p) {
   constexpr int n = 1 << LOGN;
   const int L = C.L;
-  const int64_t p = blockIdx.x;
   const int l = (int)(p % L);
   const int64_t j = p / L;
   const LimbConst& lc = C.limb[l];
@@ -356,141 +372,226 @@ __global__ void __launch_bounds__(512, (LOGN >= 14 ? 2 : 4)) k_ntt_ternary(uint6
     }
   }
   __syncthreads();
-  ntt_fwd<LOGN>(lds, T.fw + (int64_t)l * n, lc.q);
+  ntt_fwd<LOGN, LOGE>(lds, T.fw + (int64_t)l * n, lc.q);
   uint64_t* o = dst + p * n;
   for (int i = threadIdx.x; i < n; i += blockDim.x) o[i] = lds[lpad(i)];
 }
 
-// Pointwise multiply-accumulate over contraction tiles, per NTT slot:
-//   out[o][c] = sum_{terms, kappa} A[a(o, kappa)] * K[k(o, kappa)]  +  pk_c * u'_o
-// Each thread owns one (limb, slot) and a TM x TR block of (A-row, K-row)
-// output tiles; products accumulate in 128 bits and are Barrett-reduced every
-// mac_chunk terms.
-template <int TM, int TR>
-__global__ void __launch_bounds__(256) k_mac(MacArgs A, Geo G, Consts C) {
-  const int n = C.n, L = C.L;
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= (int64_t)n * L) return;
-  const int l = (int)(g / n), s = (int)(g % n);
-  const LimbConst& lc = C.limb[l];
-  const int rblocks = (G.nR + TR - 1) / TR;
-  const int mb = blockIdx.y / rblocks, rb = blockIdx.y % rblocks;
-  const int sp = G.nOY * G.nOX;
+template <int LOGN, int LOGE>
+__global__ void __launch_bounds__(512, (LOGE >= 5 ? 2 : 4)) k_ntt_ternary(uint64_t* dst, uint64_t nonce, uint64_t obj_base,
+                                                      uint32_t purpose, Consts C, Tables T) {
+  extern __shared__ uint64_t lds[];
+  do_ntt_ternary<LOGN, LOGE>(lds, dst, nonce, obj_base, purpose, C, T, blockIdx.x);
+}
 
-  uint64_t acc_hi[TM][TR][2], acc_lo[TM][TR][2];
+// LDS-staged multiply-accumulate.  The forward NTTs of the product path store
+// each residue v < 2^61 split as (v mod 2^30) | (v >> 30) << 32, so a modular
+// product-accumulate is four 32 x 32 -> 64-bit multiply-adds into three 64-bit
+// partial sums (low x low, cross terms, high x high).  Every `mac_fold` steps
+// the partial sums fold into a 128-bit total, which is Barrett-reduced every
+// `mac_chunk` folds and at the end.
+//
+// A block owns 64 NTT slots of one limb and a ROWS x COLS chunk of (A-row,
+// K-row) output tiles.  It walks the contraction (contraction tiles x product
+// terms) KB steps at a time: all 512 threads first stage the chunk's A and K
+// values of KB steps for their 64 slots in LDS, then each wave accumulates a
+// 2 x 2 block of its slot's outputs (both components).  Each operand is read
+// from memory once per chunk.  Chunk shapes are schedule variants with the same
+// result: 0 = 4 x 8, 1 = 2 x 16, 2 = 8 x 4.
+constexpr int kMacSlots = 64, kMacKB = 4;
+constexpr int kMacSmemWords = kMacKB * 2 * 18 * kMacSlots;  // ROWS + COLS <= 18
+
+struct Acc {
+  uint64_t s0, s1, s2;  // partial sums of a0 b0, a0 b1 + a1 b0, a1 b1
+  uint64_t lo, hi;      // folded 128-bit total
+};
+
+__device__ __forceinline__ void acc_mac(Acc& x, uint64_t a, uint64_t b) {
+  const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32), b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
+  x.s0 += (uint64_t)a0 * b0;
+  x.s1 += (uint64_t)a0 * b1;
+  x.s1 += (uint64_t)a1 * b0;
+  x.s2 += (uint64_t)a1 * b1;
+}
+
+// total += s0 + s1 2^30 + s2 2^60; the partial sums restart at zero.
+__device__ __forceinline__ void acc_fold(Acc& x) {
+  const uint64_t t1 = x.s1 << 30, t2 = x.s2 << 60;
+  uint64_t lo = x.lo + x.s0;
+  uint64_t c = lo < x.s0 ? 1 : 0;
+  lo += t1;
+  c += lo < t1 ? 1 : 0;
+  lo += t2;
+  c += lo < t2 ? 1 : 0;
+  x.hi += c + (x.s1 >> 34) + (x.s2 >> 4);
+  x.lo = lo;
+  x.s0 = x.s1 = x.s2 = 0;
+}
+
+template <int ROWS, int COLS>
+__device__ __forceinline__ void do_mac_t(uint64_t* smem, const MacArgs& A, const Geo& G, const Consts& C, int bx,
+                                         int by) {
+  constexpr int TM = 2, TR = 2, WC = COLS / TR, KB = kMacKB;
+  static_assert((ROWS / TM) * WC == 8, "8 waves per block");
+  static_assert(ROWS + COLS <= 18, "staging buffer");
+  // sa[b][comp][row][slot], sk[b][comp][col][slot] for the KB staged steps
+  uint64_t(*sa)[2][ROWS][kMacSlots] = reinterpret_cast<uint64_t(*)[2][ROWS][kMacSlots]>(smem);
+  uint64_t(*sk)[2][COLS][kMacSlots] =
+      reinterpret_cast<uint64_t(*)[2][COLS][kMacSlots]>(smem + KB * 2 * ROWS * kMacSlots);
+  const int n = C.n, L = C.L;
+  const int per_limb = n / kMacSlots;
+  const int l = bx / per_limb;
+  const int slot0 = (bx % per_limb) * kMacSlots;
+  const LimbConst& lc = C.limb[l];
+  const int cchunks = (G.nR + COLS - 1) / COLS;
+  const int row0 = (by / cchunks) * ROWS, col0 = (by % cchunks) * COLS;
+  const int tid = threadIdx.x, s = tid & (kMacSlots - 1), grp = tid >> 6;  // grp 0..7
+  const int rg = (grp / WC) * TM, cg = (grp % WC) * TR;  // this wave's rows and cols in the chunk
+  const int sp = G.nOY * G.nOX, kspan = G.nKY * G.nKX;
+  const int64_t ln = (int64_t)l * n + slot0;
+  const int64_t ct_stride = 2 * (int64_t)L * n, pt_stride = (int64_t)L * n;
+  const int nt = A.n_terms;
+  const int steps = G.nK * kspan * nt;
+  const uint32_t fold_every = C.mac_fold, reduce_every = C.mac_chunk;
+
+  Acc acc[TM][TR][2];
 #pragma unroll
   for (int a = 0; a < TM; ++a)
 #pragma unroll
     for (int b = 0; b < TR; ++b)
 #pragma unroll
-      for (int c = 0; c < 2; ++c) acc_hi[a][b][c] = acc_lo[a][b][c] = 0;
+      for (int c = 0; c < 2; ++c) acc[a][b][c] = Acc{0, 0, 0, 0, 0};
 
-  int mi[TM], oyi[TM], oxi[TM];
-  bool mv[TM];
+  uint32_t nmac = 0, nfold = 0;
+  for (int u0 = 0; u0 < steps; u0 += KB) {
+    __syncthreads();
+    // stage KB steps: step u = (ki * kspan + kk) * nt + tt
 #pragma unroll
-  for (int a = 0; a < TM; ++a) {
-    int row = mb * TM + a;
-    mv[a] = row < A.m_rows;
-    row = mv[a] ? row : 0;
-    mi[a] = row / sp;
-    oyi[a] = (row % sp) / G.nOX;
-    oxi[a] = row % G.nOX;
-  }
-  int ri[TR];
-  bool rv[TR];
+    for (int b = 0; b < KB; ++b) {
+      const int u = u0 + b;
+      if (u >= steps) break;
+      const int tt = u % nt, kidx = u / nt;
+      const int ki = kidx / kspan, kk = kidx % kspan;
+      const MacTerm& T = A.term[tt];
+      const bool a_ct = T.a_is_ct;
 #pragma unroll
-  for (int b = 0; b < TR; ++b) {
-    ri[b] = rb * TR + b;
-    rv[b] = ri[b] < G.nR;
-    ri[b] = rv[b] ? ri[b] : 0;
-  }
-
-  const int64_t ln = (int64_t)l * n + s;
-  const int64_t ct_stride = 2 * (int64_t)L * n, pt_stride = (int64_t)L * n;
-  uint32_t cnt = 0;
-  const int kspan = G.nKY * G.nKX;
-  for (int ki = 0; ki < G.nK; ++ki) {
-    for (int kk = 0; kk < kspan; ++kk) {
-      const int kyi = kk / G.nKX, kxi = kk % G.nKX;
-      for (int tt = 0; tt < A.n_terms; ++tt) {
-        const MacTerm& T = A.term[tt];
-        uint64_t av[TM][2], kv[TR][2];
-#pragma unroll
-        for (int a = 0; a < TM; ++a) {
-          int64_t ai = ((((int64_t)mi[a] * G.nK + ki) * G.nOY + oyi[a]) * G.nOX + oxi[a]) * kspan + kk;
-          if (T.a_is_ct) {
-            av[a][0] = T.a[ai * ct_stride + ln];
-            av[a][1] = T.a[ai * ct_stride + pt_stride + ln];
-          } else {
-            av[a][0] = av[a][1] = T.a[ai * pt_stride + ln];
-          }
+      for (int rr = grp; rr < ROWS; rr += 8) {
+        const int row = row0 + rr;
+        if (row < A.m_rows) {
+          const int mi = row / sp, oyi = (row % sp) / G.nOX, oxi = row % G.nOX;
+          const int64_t ai = ((((int64_t)mi * G.nK + ki) * G.nOY + oyi) * G.nOX + oxi) * kspan + kk;
+          const uint64_t* src = T.a + ai * (a_ct ? ct_stride : pt_stride) + ln + s;
+          sa[b][0][rr][s] = src[0];
+          if (a_ct) sa[b][1][rr][s] = src[pt_stride];
         }
+      }
 #pragma unroll
-        for (int b = 0; b < TR; ++b) {
-          int64_t kix = ((int64_t)ri[b] * G.nK + ki) * kspan + kk;
-          if (T.a_is_ct) {
-            kv[b][0] = kv[b][1] = T.k[kix * pt_stride + ln];
-          } else {
-            kv[b][0] = T.k[kix * ct_stride + ln];
-            kv[b][1] = T.k[kix * ct_stride + pt_stride + ln];
-          }
+      for (int cc = grp; cc < COLS; cc += 8) {
+        const int col = col0 + cc;
+        if (col < G.nR) {
+          const int64_t kix = ((int64_t)col * G.nK + ki) * kspan + kk;
+          const uint64_t* src = T.k + kix * (a_ct ? pt_stride : ct_stride) + ln + s;
+          sk[b][0][cc][s] = src[0];
+          if (!a_ct) sk[b][1][cc][s] = src[pt_stride];
         }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < KB; ++b) {
+      const int u = u0 + b;
+      if (u >= steps) break;
+      const int a_ct = A.term[u % nt].a_is_ct ? 1 : 0;  // which side carries the second component
+      uint64_t av[TM][2], kv[TR][2];
+#pragma unroll
+      for (int a = 0; a < TM; ++a) {
+        av[a][0] = sa[b][0][rg + a][s];
+        av[a][1] = sa[b][a_ct][rg + a][s];
+      }
+#pragma unroll
+      for (int c2 = 0; c2 < TR; ++c2) {
+        kv[c2][0] = sk[b][0][cg + c2][s];
+        kv[c2][1] = sk[b][1 - a_ct][cg + c2][s];
+      }
+#pragma unroll
+      for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int c2 = 0; c2 < TR; ++c2)
+#pragma unroll
+          for (int c = 0; c < 2; ++c) acc_mac(acc[a][c2][c], av[a][c], kv[c2][c]);
+      if (++nmac == fold_every) {
+        nmac = 0;
 #pragma unroll
         for (int a = 0; a < TM; ++a)
 #pragma unroll
-          for (int b = 0; b < TR; ++b)
+          for (int c2 = 0; c2 < TR; ++c2)
 #pragma unroll
-            for (int c = 0; c < 2; ++c) {
-              uint64_t ph, pl;
-              mul_wide(av[a][c], kv[b][c], ph, pl);
-              uint64_t lo = acc_lo[a][b][c] + pl;
-              acc_hi[a][b][c] += ph + (lo < pl ? 1 : 0);
-              acc_lo[a][b][c] = lo;
-            }
-        if (++cnt == C.mac_chunk) {
-          cnt = 0;
+            for (int c = 0; c < 2; ++c) acc_fold(acc[a][c2][c]);
+        if (++nfold == reduce_every) {
+          nfold = 0;
 #pragma unroll
           for (int a = 0; a < TM; ++a)
 #pragma unroll
-            for (int b = 0; b < TR; ++b)
+            for (int c2 = 0; c2 < TR; ++c2)
 #pragma unroll
               for (int c = 0; c < 2; ++c) {
-                acc_lo[a][b][c] = reduce128(acc_hi[a][b][c], acc_lo[a][b][c], lc.q, lc.mu_lo, lc.mu_hi);
-                acc_hi[a][b][c] = 0;
+                Acc& x = acc[a][c2][c];
+                x.lo = reduce128(x.hi, x.lo, lc.q, lc.mu_lo, lc.mu_hi);
+                x.hi = 0;
               }
         }
       }
     }
   }
   // re-randomisation term pk_c * u'_o, reduction and store
-  const uint64_t pk0 = A.pk[ln], pk1 = A.pk[pt_stride + ln];
+  const uint64_t pk0 = A.pk[ln + s], pk1 = A.pk[pt_stride + ln + s];
 #pragma unroll
-  for (int a = 0; a < TM; ++a)
+  for (int a = 0; a < TM; ++a) {
+    const int row = row0 + rg + a;
+    if (row >= A.m_rows) continue;
+    const int mi = row / sp, oyi = (row % sp) / G.nOX, oxi = row % G.nOX;
 #pragma unroll
     for (int b = 0; b < TR; ++b) {
-      if (!mv[a] || !rv[b]) continue;
-      const int64_t o = (((int64_t)mi[a] * G.nR + ri[b]) * G.nOY + oyi[a]) * G.nOX + oxi[a];
-      const uint64_t u = A.u[o * pt_stride + ln];
+      const int col = col0 + cg + b;
+      if (col >= G.nR) continue;
+      const int64_t o = (((int64_t)mi * G.nR + col) * G.nOY + oyi) * G.nOX + oxi;
+      const uint64_t u = A.u[o * pt_stride + ln + s];
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
+        Acc& x = acc[a][b][c];
+        acc_fold(x);
         uint64_t ph, pl;
         mul_wide(c ? pk1 : pk0, u, ph, pl);
-        uint64_t r0 = reduce128(acc_hi[a][b][c], acc_lo[a][b][c], lc.q, lc.mu_lo, lc.mu_hi);
-        uint64_t r1 = reduce128(ph, pl, lc.q, lc.mu_lo, lc.mu_hi);
-        A.out[o * ct_stride + (int64_t)c * pt_stride + ln] = add_mod(r0, r1, lc.q);
+        const uint64_t r0 = reduce128(x.hi, x.lo, lc.q, lc.mu_lo, lc.mu_hi);
+        const uint64_t r1 = reduce128(ph, pl, lc.q, lc.mu_lo, lc.mu_hi);
+        A.out[o * ct_stride + (int64_t)c * pt_stride + ln + s] = add_mod(r0, r1, lc.q);
       }
     }
+  }
+}
+
+__device__ __forceinline__ void do_mac(uint64_t* smem, const MacArgs& A, const Geo& G, const Consts& C, int bx,
+                                       int by) {
+  switch (A.variant) {
+    case 1: do_mac_t<2, 16>(smem, A, G, C, bx, by); break;
+    case 2: do_mac_t<8, 4>(smem, A, G, C, bx, by); break;
+    default: do_mac_t<4, 8>(smem, A, G, C, bx, by); break;
+  }
+}
+
+__global__ void __launch_bounds__(512) k_mac_lds(MacArgs A, Geo G, Consts C) {
+  extern __shared__ uint64_t smem[];
+  do_mac(smem, A, G, C, blockIdx.x, blockIdx.y);
 }
 
 // Output ciphertexts after the inverse NTT: c0 += e0' + flood - round(q s / t),
 // c1 += e1'; the model owner's share is s at the output slots (+ bias).
 // Each thread handles 4 consecutive coefficients of one output ciphertext.
 template <int W>
-__global__ void __launch_bounds__(256) k_flood_mask(uint64_t* ct, int64_t n_out, int64_t* share0,
-                                                    const int64_t* bias, Geo G, View OV, uint64_t nonce,
-                                                    uint64_t obj_base, Consts C) {
+__device__ __forceinline__ void do_flood(uint64_t* ct, int64_t n_out, int64_t* share0, const int64_t* bias,
+                                         const Geo& G, const View& OV, uint64_t nonce, uint64_t obj_base,
+                                         const Consts& C, int64_t g) {
   const int n = C.n, L = C.L;
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int per = n / 4;
   if (g >= n_out * per) return;
   const int64_t o = g / per;
@@ -570,10 +671,17 @@ __global__ void __launch_bounds__(256) k_flood_mask(uint64_t* ct, int64_t n_out,
   }
 }
 
+template <int W>
+__global__ void __launch_bounds__(256) k_flood_mask(uint64_t* ct, int64_t n_out, int64_t* share0,
+                                                    const int64_t* bias, Geo G, View OV, uint64_t nonce,
+                                                    uint64_t obj_base, Consts C) {
+  do_flood<W>(ct, n_out, share0, bias, G, OV, nonce, obj_base, C, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 // Encryption: ct_c = INTT(pk_c * u) + e_c (+ round(q m / t) on c = 0), with m
 // the encoded share at each slot.  Grid: n_ct * 2 * L, u_ntt is [n][L][N].
-template <int LOGN>
-__global__ void __launch_bounds__(512, (LOGN >= 14 ? 2 : 4)) k_encrypt(const uint64_t* u_ntt, const int64_t* share, uint64_t* ct, int side,
+template <int LOGN, int LOGE>
+__global__ void __launch_bounds__(512, (LOGE >= 5 ? 2 : 4)) k_encrypt(const uint64_t* u_ntt, const int64_t* share, uint64_t* ct, int side,
                                                   Geo G, View V, const uint64_t* pk_ntt, const uint64_t* pk_sh,
                                                   uint64_t nonce, uint64_t obj_base, Consts C, Tables T) {
   extern __shared__ uint64_t lds[];
@@ -589,7 +697,7 @@ __global__ void __launch_bounds__(512, (LOGN >= 14 ? 2 : 4)) k_encrypt(const uin
   const uint64_t* pks = pk_sh + ((int64_t)c * L + l) * n;
   for (int i = threadIdx.x; i < n; i += blockDim.x) lds[lpad(i)] = mul_shoup(u[i], pk[i], pks[i], lc.q);
   __syncthreads();
-  ntt_inv<LOGN>(lds, T.iw + (int64_t)l * n, lc.q);
+  ntt_inv<LOGN, LOGE>(lds, T.iw + (int64_t)l * n, lc.q);
   const uint64_t obj = obj_base + (uint64_t)j;
   uint64_t* o = ct + p * n;
   for (int blk = threadIdx.x; blk < n / 4; blk += blockDim.x) {
@@ -612,7 +720,7 @@ __global__ void __launch_bounds__(512, (LOGN >= 14 ? 2 : 4)) k_encrypt(const uin
 }
 
 // Decryption phase per limb: x = c0 + INTT(NTT(c1) * s).  Grid: n * L, x is [n][L][N].
-template <int LOGN>
+template <int LOGN, int LOGE>
 __global__ void __launch_bounds__(512) k_phase(const uint64_t* ct, uint64_t* x, const uint64_t* s_ntt,
                                                 const uint64_t* s_sh, Consts C, Tables T) {
   extern __shared__ uint64_t lds[];
@@ -626,12 +734,12 @@ __global__ void __launch_bounds__(512) k_phase(const uint64_t* ct, uint64_t* x, 
   const uint64_t* c1 = ct + ((j * 2 + 1) * L + l) * n;
   for (int i = threadIdx.x; i < n; i += blockDim.x) lds[lpad(i)] = c1[i];
   __syncthreads();
-  ntt_fwd<LOGN>(lds, T.fw + (int64_t)l * n, lc.q);
+  ntt_fwd<LOGN, LOGE>(lds, T.fw + (int64_t)l * n, lc.q);
   const uint64_t* sv = s_ntt + (int64_t)l * n;
   const uint64_t* ss = s_sh + (int64_t)l * n;
   for (int i = threadIdx.x; i < n; i += blockDim.x) lds[lpad(i)] = mul_shoup(lds[lpad(i)], sv[i], ss[i], lc.q);
   __syncthreads();
-  ntt_inv<LOGN>(lds, T.iw + (int64_t)l * n, lc.q);
+  ntt_inv<LOGN, LOGE>(lds, T.iw + (int64_t)l * n, lc.q);
   uint64_t* o = x + p * n;
   for (int i = threadIdx.x; i < n; i += blockDim.x)
     o[i] = add_mod(c0[i], mul_shoup(lds[lpad(i)], lc.ninv, lc.ninv_sh, lc.q), lc.q);
@@ -726,7 +834,7 @@ __global__ void __launch_bounds__(256) k_decode(const uint64_t* x, int64_t* shar
 // (stream P_PK_A, limb l, two words per coefficient), e CBD21 (stream P_PK_E);
 // pk = (-(a s + e), a), kept in both coefficient and NTT form.  One LDS buffer;
 // every thread re-reads only the global entries it wrote itself.
-template <int LOGN>
+template <int LOGN, int LOGE>
 __global__ void __launch_bounds__(512) k_keygen(uint64_t* s_ntt, int64_t* s_coeff, uint64_t* pk_coeff,
                                                  uint64_t* pk_ntt, Consts C, Tables T) {
   extern __shared__ uint64_t lds[];
@@ -746,7 +854,7 @@ __global__ void __launch_bounds__(512) k_keygen(uint64_t* s_ntt, int64_t* s_coef
     }
   }
   __syncthreads();
-  ntt_fwd<LOGN>(lds, tw, lc.q);
+  ntt_fwd<LOGN, LOGE>(lds, tw, lc.q);
   for (int i = threadIdx.x; i < n; i += blockDim.x) s_ntt[(int64_t)l * n + i] = lds[lpad(i)];
   __syncthreads();
   for (int blk = threadIdx.x; blk < n / 2; blk += blockDim.x) {
@@ -761,7 +869,7 @@ __global__ void __launch_bounds__(512) k_keygen(uint64_t* s_ntt, int64_t* s_coef
     }
   }
   __syncthreads();
-  ntt_fwd<LOGN>(lds, tw, lc.q);
+  ntt_fwd<LOGN, LOGE>(lds, tw, lc.q);
   // a * s pointwise (128-bit product, Barrett), then inverse transform
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     const uint64_t av = lds[lpad(i)];
@@ -771,7 +879,7 @@ __global__ void __launch_bounds__(512) k_keygen(uint64_t* s_ntt, int64_t* s_coef
     lds[lpad(i)] = reduce128(ph, pl, lc.q, lc.mu_lo, lc.mu_hi);
   }
   __syncthreads();
-  ntt_inv<LOGN>(lds, T.iw + (int64_t)l * n, lc.q);
+  ntt_inv<LOGN, LOGE>(lds, T.iw + (int64_t)l * n, lc.q);
   for (int blk = threadIdx.x; blk < n / 4; blk += blockDim.x) {
     U64x4 w = philox((uint64_t)blk, 0, P_PK_E, 0, C.seed, nonce);
 #pragma unroll
@@ -785,7 +893,7 @@ __global__ void __launch_bounds__(512) k_keygen(uint64_t* s_ntt, int64_t* s_coef
     }
   }
   __syncthreads();
-  ntt_fwd<LOGN>(lds, tw, lc.q);
+  ntt_fwd<LOGN, LOGE>(lds, tw, lc.q);
   for (int i = threadIdx.x; i < n; i += blockDim.x) pk_ntt[(int64_t)l * n + i] = lds[lpad(i)];
 }
 
@@ -828,22 +936,78 @@ __global__ void __launch_bounds__(256) k_zt_corr(const int64_t* a, const int64_t
   out[m * OV.s0 + r * OV.s1 + y * OV.sy + x * OV.sx] = (int64_t)v;
 }
 
+// --------------------------------------------------------- batched step
+
+__device__ __forceinline__ int find_seg(const StepSeg* segs, int nseg, int64_t b) {
+  int lo = 0, hi = nseg - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (segs[mid].block_begin <= b)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// Every forward and inverse NTT of one phase, for one ring degree.
+template <int LOGN, int LOGE>
+__global__ void __launch_bounds__(512, (LOGE >= 5 ? 2 : 4)) k_step_ntt(StepPhase P) {
+  extern __shared__ uint64_t lds[];
+  const StepSeg& S = P.segs[find_seg(P.segs, P.nseg, blockIdx.x)];
+  const Consts& C = P.consts[S.ctx];
+  const Tables& T = P.tabs[S.ctx];
+  const int64_t p = (int64_t)blockIdx.x - S.block_begin;
+  switch (S.kind) {
+    case SEG_CT: do_ntt_ct<LOGN, LOGE>(lds, S.src, S.dst, S.tensor, S.G, S.V, C, T, p); break;
+    case SEG_PT: do_ntt_pt<LOGN, LOGE>(lds, S.tensor, S.dst, S.side, S.G, S.V, C, T, p); break;
+    case SEG_TERN: do_ntt_ternary<LOGN, LOGE>(lds, S.dst, *P.nonce + S.nonce_off, S.obj_base, S.purpose, C, T, p); break;
+    default: do_ntt_plain<LOGN, LOGE>(lds, S.dst, 1, C, T, p); break;
+  }
+}
+
+// Every multiply-accumulate of one step.
+__global__ void __launch_bounds__(512) k_step_mac(StepPhase P) {
+  const StepSeg& S = P.segs[find_seg(P.segs, P.nseg, blockIdx.x)];
+  __shared__ uint64_t smem[kMacSmemWords];
+  const int64_t local = (int64_t)blockIdx.x - S.block_begin;
+  do_mac(smem, S.mac, S.G, P.consts[S.ctx], (int)(local % S.slot_blocks), (int)(local / S.slot_blocks));
+}
+
+// Every flood-and-mask of one step, for one flood width.
+template <int W>
+__global__ void __launch_bounds__(256) k_step_flood(StepPhase P) {
+  const StepSeg& S = P.segs[find_seg(P.segs, P.nseg, blockIdx.x)];
+  const int64_t g = ((int64_t)blockIdx.x - S.block_begin) * blockDim.x + threadIdx.x;
+  do_flood<W>(S.dst, S.count, S.share, S.bias, S.G, S.V2, *P.nonce + S.nonce_off, S.obj_base, P.consts[S.ctx], g);
+}
+
+__global__ void k_set_u64(uint64_t* p, uint64_t v, int add) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) p[0] = add ? p[0] + v : v;
+}
+
 // ---------------------------------------------------------------- launchers
 
 static inline size_t lds_bytes(const Consts& C) { return (size_t)(C.n + (C.n >> 5)) * sizeof(uint64_t); }
-static inline dim3 ntt_block(const Consts& C) { return dim3((unsigned)(C.n / (C.log2n >= 14 ? 32 : 16))); }
 
 // Instantiate `kern<LOGN>` for the context's degree and launch it.
-#define NTT_DISPATCH(kern, grid, C, s, ...)                                                             \
-  do {                                                                                                  \
-    switch ((C).log2n) {                                                                                \
-      case 10: hipLaunchKernelGGL(kern<10>, grid, ntt_block(C), lds_bytes(C), s, __VA_ARGS__); break;  \
-      case 11: hipLaunchKernelGGL(kern<11>, grid, ntt_block(C), lds_bytes(C), s, __VA_ARGS__); break;  \
-      case 12: hipLaunchKernelGGL(kern<12>, grid, ntt_block(C), lds_bytes(C), s, __VA_ARGS__); break;  \
-      case 13: hipLaunchKernelGGL(kern<13>, grid, ntt_block(C), lds_bytes(C), s, __VA_ARGS__); break;  \
-      case 14: hipLaunchKernelGGL(kern<14>, grid, ntt_block(C), lds_bytes(C), s, __VA_ARGS__); break;  \
-      default: return hipErrorInvalidValue;                                                            \
-    }                                                                                                   \
+#define NTT_CASE(kern, LN, LE, grid, C, s, ...)                                                 \
+  case (LN) * 8 + (LE):                                                                          \
+    hipLaunchKernelGGL((kern<LN, LE>), grid, dim3((1u << (LN)) >> (LE)), lds_bytes(C), s, __VA_ARGS__); \
+    break;
+// Instantiate `kern<LOGN, LOGE>` for the context's degree and per-thread width.
+#define NTT_DISPATCH(kern, grid, C, s, ...)                                                \
+  do {                                                                                     \
+    switch ((C).log2n * 8 + (C).ntt_loge) {                                                \
+      NTT_CASE(kern, 10, 4, grid, C, s, __VA_ARGS__)                                       \
+      NTT_CASE(kern, 11, 4, grid, C, s, __VA_ARGS__)                                       \
+      NTT_CASE(kern, 12, 4, grid, C, s, __VA_ARGS__)                                       \
+      NTT_CASE(kern, 12, 5, grid, C, s, __VA_ARGS__)                                       \
+      NTT_CASE(kern, 13, 4, grid, C, s, __VA_ARGS__)                                       \
+      NTT_CASE(kern, 13, 5, grid, C, s, __VA_ARGS__)                                       \
+      NTT_CASE(kern, 14, 5, grid, C, s, __VA_ARGS__)                                       \
+      default: return hipErrorInvalidValue;                                                \
+    }                                                                                      \
   } while (0)
 
 hipError_t launch_ntt_plain(uint64_t* data, int64_t polys, bool inverse, const Consts& C, const Tables& T,
@@ -876,11 +1040,10 @@ hipError_t launch_ntt_ternary(uint64_t* dst, int64_t count, uint64_t nonce, uint
 
 hipError_t launch_mac(const MacArgs& A, int64_t n_out, const Geo& G, const Consts& C, hipStream_t s) {
   if (n_out <= 0) return hipSuccess;
-  constexpr int TM = 2, TR = 2;
-  const int64_t slots = (int64_t)C.n * C.L;
-  const int mblocks = (A.m_rows + TM - 1) / TM, rblocks = (G.nR + TR - 1) / TR;
-  dim3 grid((unsigned)((slots + 255) / 256), (unsigned)(mblocks * rblocks));
-  hipLaunchKernelGGL((k_mac<TM, TR>), grid, dim3(256), 0, s, A, G, C);
+  const int64_t slot_blocks = (int64_t)C.n * C.L / kMacSlots;
+  const int chunks = mac_chunks(A.variant, A.m_rows, G.nR);
+  dim3 grid((unsigned)slot_blocks, (unsigned)chunks);
+  hipLaunchKernelGGL(k_mac_lds, grid, dim3(512), kMacSmemWords * sizeof(uint64_t), s, A, G, C);
   return hipGetLastError();
 }
 
@@ -932,6 +1095,40 @@ hipError_t launch_zt_corr(const int64_t* a, const int64_t* k, int64_t* out, cons
   return hipGetLastError();
 }
 
+hipError_t launch_step_ntt(int log2n, int loge, const StepPhase& P, int64_t blocks, hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  Consts C{};  // only log2n, n and ntt_loge are read by the dispatch
+  C.log2n = log2n;
+  C.n = 1 << log2n;
+  C.ntt_loge = loge;
+  const dim3 grid((unsigned)blocks);
+  NTT_DISPATCH(k_step_ntt, grid, C, s, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_mac(const StepPhase& P, int64_t blocks, hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_step_mac, dim3((unsigned)blocks), dim3(512), kMacSmemWords * sizeof(uint64_t), s, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_flood(int words, const StepPhase& P, int64_t blocks, hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  switch (words) {
+    case 1: hipLaunchKernelGGL(k_step_flood<1>, dim3((unsigned)blocks), dim3(256), 0, s, P); break;
+    case 2: hipLaunchKernelGGL(k_step_flood<2>, dim3((unsigned)blocks), dim3(256), 0, s, P); break;
+    case 3: hipLaunchKernelGGL(k_step_flood<3>, dim3((unsigned)blocks), dim3(256), 0, s, P); break;
+    case 4: hipLaunchKernelGGL(k_step_flood<4>, dim3((unsigned)blocks), dim3(256), 0, s, P); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_set_u64(uint64_t* p, uint64_t v, int add, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(64), 0, s, p, v, add);
+  return hipGetLastError();
+}
+
 hipError_t launch_keygen(uint64_t* s_ntt, int64_t* s_coeff, uint64_t* pk_coeff, uint64_t* pk_ntt, const Consts& C,
                          const Tables& T, hipStream_t s) {
   NTT_DISPATCH(k_keygen, dim3((unsigned)C.L), C, s, s_ntt, s_coeff, pk_coeff, pk_ntt, C, T);
@@ -939,12 +1136,13 @@ hipError_t launch_keygen(uint64_t* s_ntt, int64_t* s_coeff, uint64_t* pk_coeff, 
 }
 
 // Kernels that stage more than 64 KiB of LDS must opt in once per process.
-template <int LOGN>
+template <int LOGN, int LOGE>
 static hipError_t raise_lds_limit() {
   const int max_lds = 160 * 1024;
-  const void* fns[] = {(const void*)k_ntt_plain<LOGN>, (const void*)k_ntt_ct<LOGN>, (const void*)k_ntt_pt<LOGN>,
-                       (const void*)k_ntt_ternary<LOGN>, (const void*)k_encrypt<LOGN>, (const void*)k_phase<LOGN>,
-                       (const void*)k_keygen<LOGN>};
+  const void* fns[] = {(const void*)k_ntt_plain<LOGN, LOGE>,   (const void*)k_ntt_ct<LOGN, LOGE>,
+                       (const void*)k_ntt_pt<LOGN, LOGE>,      (const void*)k_ntt_ternary<LOGN, LOGE>,
+                       (const void*)k_encrypt<LOGN, LOGE>,     (const void*)k_phase<LOGN, LOGE>,
+                       (const void*)k_keygen<LOGN, LOGE>,      (const void*)k_step_ntt<LOGN, LOGE>};
   hipError_t e = hipSuccess;
   for (const void* f : fns) {
     hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
@@ -954,9 +1152,15 @@ static hipError_t raise_lds_limit() {
 }
 
 hipError_t configure_lds_limits() {
-  hipError_t e = raise_lds_limit<13>();
-  hipError_t f = raise_lds_limit<14>();
-  return e != hipSuccess ? e : f;
+  const int mac_lds = kMacSmemWords * sizeof(uint64_t);
+  hipError_t m1 = hipFuncSetAttribute((const void*)k_mac_lds, hipFuncAttributeMaxDynamicSharedMemorySize, mac_lds);
+  hipError_t m2 = hipFuncSetAttribute((const void*)k_step_mac, hipFuncAttributeMaxDynamicSharedMemorySize, mac_lds);
+  if (m1 != hipSuccess) return m1;
+  if (m2 != hipSuccess) return m2;
+  hipError_t e[3] = {raise_lds_limit<13, 4>(), raise_lds_limit<13, 5>(), raise_lds_limit<14, 5>()};
+  for (hipError_t x : e)
+    if (x != hipSuccess) return x;
+  return hipSuccess;
 }
 
 }  // namespace pencil

@@ -24,7 +24,9 @@ struct LimbConst {
 // Everything a kernel needs about the parameter set; passed by value.
 struct Consts {
   int32_t log2n, n, L, flood_words;
-  uint32_t flood_bits, mac_chunk, qwords, pad0;
+  uint32_t flood_bits, mac_chunk, qwords;
+  int32_t ntt_loge;              // log2 of the residues each NTT thread keeps (4 or 5)
+  uint32_t mac_fold, pad1;       // MAC steps per fold of the 64-bit partial sums
   uint64_t t, t_half;            // t and (t - 1) / 2
   uint64_t rho, rho_sh;          // q mod t, floor(rho * 2^64 / t)
   uint64_t r64t, r64t_sh;        // 2^64 mod t and floor(r64t * 2^64 / t)
@@ -91,10 +93,48 @@ struct MacArgs {
   MacTerm term[2];
   int32_t n_terms;
   int32_t m_rows;      // nM * nOY * nOX
+  int32_t variant;     // chunk shape of the multiply-accumulate (schedule only): 0 4x8, 1 2x16, 2 8x4
+  int32_t pad;
   const uint64_t* pk;  // [2][L][N], NTT domain
   const uint64_t* u;   // [n_out][L][N], NTT domain
   uint64_t* out;       // [n_out][2][L][N]
 };
+
+// A batched step runs every product of several layers as a few phase launches.
+// Each phase launch covers a list of segments; a segment is a contiguous range
+// of blocks that share their arguments (one operand's NTTs, one op's MAC, ...).
+enum SegKind : int32_t { SEG_CT = 0, SEG_PT = 1, SEG_TERN = 2, SEG_INTT = 3, SEG_MAC = 4, SEG_FLOOD = 5 };
+
+struct StepSeg {
+  int64_t block_begin;       // first block of the segment in its phase grid
+  int32_t kind, ctx, side, purpose;
+  int64_t count;             // flood: number of output ciphertexts
+  int64_t slot_blocks;       // mac: blocks along the slot dimension
+  uint64_t nonce_off, obj_base;
+  const uint64_t* src;
+  uint64_t* dst;
+  const int64_t* tensor;
+  const int64_t* bias;
+  int64_t* share;
+  Geo G;
+  View V, V2;
+  MacArgs mac;
+};
+
+struct StepPhase {
+  const StepSeg* segs;
+  int32_t nseg, pad;
+  const Consts* consts;      // per context of the step
+  const Tables* tabs;
+  const uint64_t* nonce;     // base nonce in device memory
+};
+
+// Output-chunk shape of each MAC variant and the number of chunks it needs.
+inline int mac_rows(int variant) { return variant == 1 ? 2 : variant == 2 ? 8 : 4; }
+inline int mac_cols(int variant) { return variant == 1 ? 16 : variant == 2 ? 4 : 8; }
+inline int mac_chunks(int variant, int m_rows, int n_r) {
+  return ((m_rows + mac_rows(variant) - 1) / mac_rows(variant)) * ((n_r + mac_cols(variant) - 1) / mac_cols(variant));
+}
 
 // ---------------------------------------------------------------- launchers
 // (defined in kernels.hip; all enqueue on `stream` and return the launch status)
@@ -118,6 +158,10 @@ hipError_t launch_decode(const uint64_t* x, int64_t* share, int64_t n_out, const
                          const Consts& C, hipStream_t s);
 hipError_t launch_zt_corr(const int64_t* a, const int64_t* k, int64_t* out, const Geo& G, const View& AV,
                           const View& KV, const View& OV, const Consts& C, hipStream_t s);
+hipError_t launch_step_ntt(int log2n, int loge, const StepPhase& P, int64_t blocks, hipStream_t s);
+hipError_t launch_step_mac(const StepPhase& P, int64_t blocks, hipStream_t s);
+hipError_t launch_step_flood(int words, const StepPhase& P, int64_t blocks, hipStream_t s);
+hipError_t launch_set_u64(uint64_t* p, uint64_t v, int add, hipStream_t s);
 hipError_t launch_keygen(uint64_t* s_ntt, int64_t* s_coeff, uint64_t* pk_coeff, uint64_t* pk_ntt,
                          const Consts& C, const Tables& T, hipStream_t s);
 

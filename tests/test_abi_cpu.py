@@ -57,3 +57,36 @@ def test_null_arguments_are_rejected_on_the_host():
     assert lib.pencil_encrypt(None, None, None, 0, None, None, None, 0, None) == _abi.PENCIL_EINVAL
     assert lib.pencil_linear_fwd(None, None, None, *([None] * 7), 0, None) == _abi.PENCIL_EINVAL
     assert lib.pencil_ctx_destroy(None) == _abi.PENCIL_OK
+
+
+def test_planner_tiles_fit_and_cover_every_workload_layer():
+    """The host-only planner returns, for every layer of every workload, tiles that
+    fit N slots and a valid multiply-accumulate schedule; it is deterministic."""
+    from oracle import encoding as E
+    from paper_2403_11166_amd import _abi
+    from paper_2403_11166_amd.api import layer_struct
+    from workloads import CONFIGS, small_cases
+    lib = _abi.load()
+    layers = [l for c in CONFIGS.values() for l in c.layers] + small_cases()
+    for layer in layers:
+        plans = []
+        for _ in range(2):
+            p = _abi.Plan()
+            assert lib.pencil_plan_auto_n(layer.log2_n, ctypes.byref(layer_struct(layer)), ctypes.byref(p)) == 0
+            plans.append((p.fwd.astuple(), p.dx.astuple(), p.dw.astuple(), tuple(p.sched)))
+        assert plans[0] == plans[1]
+        for op, t in zip(("fwd", "dx", "dw"), plans[0][:3]):
+            E.check_tile(E.geometry(layer, op), E.Tile(*t), 1 << layer.log2_n)
+        assert all(0 <= v <= 2 for v in plans[0][3])
+
+
+def test_planner_rejects_unsupported_layers():
+    from paper_2403_11166_amd import _abi
+    lib = _abi.load()
+    p = _abi.Plan()
+    bad = _abi.Layer(1, 2, 3, 4, 8, 8, 3, 3)  # pad > k - 1
+    assert lib.pencil_plan_auto_n(13, ctypes.byref(bad), ctypes.byref(p)) == _abi.PENCIL_EUNSUPPORTED
+    bad = _abi.Layer(0, 2, 3, 4, 2, 1, 1, 0)  # fc with h != 1
+    assert lib.pencil_plan_auto_n(13, ctypes.byref(bad), ctypes.byref(p)) == _abi.PENCIL_EINVAL
+    ok = _abi.Layer(0, 2, 3, 4, 1, 1, 1, 0)
+    assert lib.pencil_plan_auto_n(9, ctypes.byref(ok), ctypes.byref(p)) == _abi.PENCIL_EINVAL
