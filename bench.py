@@ -44,7 +44,64 @@ def parse():
                     help="timed launch path: batched step (phase launches with live kernel events), "
                          "its captured HIP graph, or one launch sequence per product and layer")
     ap.add_argument("--compare-steps", type=int, default=3, help="steps timed for the other launch paths")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (the reference kernel that scales "
+                         "HBM counters into bytes) and print its size and time")
     return ap.parse_args()
+
+
+# ------------------------------------------------------------- hbm traffic
+
+KERNEL_SOURCES = ("kernels.hip", "modarith.h", "pencil_internal.h")
+
+
+def kernel_source_hash():
+    """sha256 over the kernel sources; a traffic record holds for this hash only."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2403_11166_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the rocprofv3 counter
+    summaries under profiles/ (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of
+    known size), or None when none was taken from the current kernel sources."""
+    pdir = os.path.join(ROOT, "profiles")
+    if not os.path.isdir(pdir):
+        return None
+    want = kernel_source_hash()
+    for name in sorted(os.listdir(pdir)):
+        with open(os.path.join(pdir, name)) as f:
+            for line in f:
+                if not line.startswith("traffic:"):
+                    continue
+                kv = dict(tok.split("=", 1) for tok in line.split()[1:] if "=" in tok)
+                if kv.get("kernel") == kernel and kv.get("workload") == workload and kv.get("source_sha256") == want:
+                    return int(kv["fetch_bytes_per_launch"]) + int(kv["write_bytes_per_launch"])
+    return None
+
+
+def copy_probe(mib):
+    import torch
+    n = mib << 20
+    src = torch.ones(n, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 5
+    ev0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    print(json.dumps({"copy_probe_bytes_read": n, "copy_probe_bytes_written": n, "launches": reps + 1,
+                      "avg_ms": round(ms, 4), "GBps_read_plus_write": round(2 * n / (ms / 1e3) / 1e9, 1)}),
+          flush=True)
 
 
 # ------------------------------------------------------------- exact check
@@ -169,6 +226,9 @@ def main():
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
         sys.exit(2)
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     import torch
     from paper_2403_11166_amd import Context
     from paper_2403_11166_amd import _abi as A
@@ -307,7 +367,7 @@ def main():
     gbs = bytes_step / (ms / 1e3) / 1e9
     roof = {"kernel": dom, "launches_per_step": launches, "avg_launch_ms": ms / launches,
             "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": recorded_traffic(dom, cfg.name),
             "alu_work_per_step": ops_step}
     breakdown = {k: {"launches": v[0], "ms": round(v[1], 4),
                      "algo_GBps": round(work.get(k, (0, 0))[0] / (v[1] / 1e3) / 1e9, 1) if v[1] else None}

@@ -91,9 +91,11 @@ typedef struct {
 
 typedef struct {
     pencil_tile fwd, dx, dw;
-    /* Schedule of each product's multiply-accumulate (chunk of output tiles one
-     * workgroup stages: 0 = 8 x 8, 1 = 4 x 16, 2 = 16 x 4).  Results do not
-     * depend on it; pencil_plan_auto picks by staging volume, pencil_autotune by
+    /* Schedule of each product's multiply-accumulate, 0..5: the chunk of
+     * output tiles one workgroup covers (v mod 3: 0 = 4 x 8, 1 = 2 x 16,
+     * 2 = 8 x 4 input-row x weight-row tiles), with operands staged in LDS
+     * (v < 3) or loaded directly by each wave (v >= 3).  Results do not depend
+     * on it; pencil_plan_auto picks by a cost model, pencil_autotune by
      * measurement. */
     int32_t sched[3];
 } pencil_plan;

@@ -324,7 +324,9 @@ static pencil_status resolve_params(const pencil_params* p, pencil_ctx* ctx) {
     const u128 room = (~(u128)0) - qmax;
     u128 chunk = room / per_fold;
     if (chunk > 1024) chunk = 1024;
-    C.mac_chunk = (uint32_t)(chunk < 1 ? 1 : chunk);
+    // the kernels reduce their (at most 8) accumulators in turn, one per fold
+    if (chunk < 8) return fail(nullptr, PENCIL_EUNSUPPORTED, "primes too large for the lazy accumulation");
+    C.mac_chunk = (uint32_t)chunk;
   }
   C.qwords = (uint32_t)q.size();
   return PENCIL_OK;
@@ -655,15 +657,16 @@ static bool plan_op(const pencil_layer* L, int op, int log2n, pencil_tile* best)
   return found;
 }
 
-// Default multiply-accumulate chunk: the shape that stages the fewest padded
-// operand rows per contraction step (A rows count twice: two components).
+// Default multiply-accumulate schedule: direct loads with 2 x 2 wave blocks
+// (variants 3-5), in the chunk shape that loads the fewest padded operand rows
+// per contraction step (A rows count twice: two components).
 static int default_sched(const pencil_layer* L, int op, const pencil_tile& t, int n) {
   Geo G;
-  if (!make_geo(op_geom(L, op), t, n, &G)) return 0;
+  if (!make_geo(op_geom(L, op), t, n, &G)) return 3;
   const int rows = G.nM * G.nOY * G.nOX;
-  int best = 0;
+  int best = 3;
   int64_t best_v = -1;
-  for (int v = 0; v < 3; ++v) {
+  for (int v = 3; v < 6; ++v) {
     const int64_t rc = (rows + mac_rows(v) - 1) / mac_rows(v), cc = (G.nR + mac_cols(v) - 1) / mac_cols(v);
     const int64_t vol = rc * cc * (2 * mac_rows(v) + mac_cols(v));
     if (best_v < 0 || vol < best_v) {
@@ -783,7 +786,7 @@ struct TermIn {
 static pencil_status run_product(pencil_ctx* ctx, const pencil_layer* L, int op, const Geo& G, const TermIn* terms,
                                  int n_terms, const int64_t* add_share, const int64_t* bias, uint64_t* ct_out,
                                  int64_t* share_out, uint8_t* ws, uint64_t nonce, int sched, hipStream_t s) {
-  if (sched < 0 || sched > 2) return fail(ctx, PENCIL_EINVAL, "schedule variant %d invalid", sched);
+  if (sched < 0 || sched >= kMacVariants) return fail(ctx, PENCIL_EINVAL, "schedule variant %d invalid", sched);
   const Consts& C = ctx->C;
   const int64_t poly = (int64_t)C.L * C.n, ctw = 2 * poly;
   const int64_t na = n_a_tiles(G), nk = n_k_tiles(G), no = n_out_tiles(G);
@@ -1107,7 +1110,11 @@ extern "C" pencil_status pencil_step_bind(pencil_step* st, const pencil_step_io*
   for (int kind = 0; kind < 4; ++kind)
     for (auto& e : st->layers) {
       const Consts& C = st->ctxs[e.ctx]->C;
-      phase_for(st, kind, kind == 3 ? C.flood_words : (kind == 1 ? 0 : C.log2n * 8 + C.ntt_loge));
+      if (kind == 1) {  // each multiply-accumulate kernel kind launches separately
+        for (int k = 0; k < kMacVariants / 3; ++k) phase_for(st, 1, k);
+      } else {
+        phase_for(st, kind, kind == 3 ? C.flood_words : C.log2n * 8 + C.ntt_loge);
+      }
     }
   for (size_t i = 0; i < st->layers.size(); ++i) {
     const auto& e = st->layers[i];
@@ -1135,7 +1142,7 @@ extern "C" pencil_status pencil_step_bind(pencil_step* st, const pencil_step_io*
       MacArgs A{};
       A.m_rows = G.nM * G.nOY * G.nOX;
       A.variant = e.P.sched[op];
-      if (A.variant < 0 || A.variant > 2) return step_fail(st, PENCIL_EINVAL, "schedule variant invalid");
+      if (A.variant < 0 || A.variant >= kMacVariants) return step_fail(st, PENCIL_EINVAL, "schedule variant invalid");
       A.pk = ctx->d_pk_ntt;
       A.out = ct_out;
       StepSeg base{};
@@ -1200,7 +1207,7 @@ extern "C" pencil_status pencil_step_bind(pencil_step* st, const pencil_step_io*
       sm.mac = A;
       sm.slot_blocks = (int64_t)C.n * C.L / 64;
       const int64_t chunks = mac_chunks(A.variant, A.m_rows, G.nR);
-      add_seg(phase_for(st, 1, 0), sm, sm.slot_blocks * chunks);
+      add_seg(phase_for(st, 1, A.variant / 3), sm, (sm.slot_blocks * chunks + 7) & ~(int64_t)7);
       StepSeg si = base;
       si.kind = SEG_INTT;
       si.dst = ct_out;
@@ -1244,7 +1251,7 @@ static hipError_t step_phases(pencil_step* st, hipStream_t s) {
       e = timed(pc, ph.kind == 0 ? KID_STEP_NTT : KID_STEP_INTT, s,
                 [&] { return launch_step_ntt(ph.key / 8, ph.key % 8, P, ph.blocks, s); });
     else if (ph.kind == 1)
-      e = timed(pc, KID_STEP_MAC, s, [&] { return launch_step_mac(P, ph.blocks, s); });
+      e = timed(pc, KID_STEP_MAC, s, [&] { return launch_step_mac(P, ph.blocks, ph.key, s); });
     else
       e = timed(pc, KID_STEP_FLOOD, s, [&] { return launch_step_flood(ph.key, P, ph.blocks, s); });
     if (e != hipSuccess) return e;
@@ -1439,7 +1446,7 @@ extern "C" pencil_status pencil_autotune(pencil_ctx* ctx, const pencil_layer* L,
                   arch.c_str(), C.n, C.L, L->kind, L->batch, L->c_in, L->c_out, L->h, L->w, L->k, L->pad,
                   plan_tile(P, op).m, plan_tile(P, op).r, plan_tile(P, op).k, plan_tile(P, op).oh, plan_tile(P, op).ow,
                   plan_tile(P, op).kh, plan_tile(P, op).kw, op);
-    if (cache_find(cache, buf, &v) && v >= 0 && v <= 2) {
+    if (cache_find(cache, buf, &v) && v >= 0 && v < kMacVariants) {
       P->sched[op] = v;
       continue;
     }
@@ -1460,7 +1467,7 @@ extern "C" pencil_status pencil_autotune(pencil_ctx* ctx, const pencil_layer* L,
     float best = -1;
     int bestv = P->sched[op];
     std::string times;
-    for (int cand = 0; cand < 3; ++cand) {
+    for (int cand = 0; cand < kMacVariants; ++cand) {
       P->sched[op] = cand;
       auto run = [&]() -> pencil_status {
         if (op == 0)

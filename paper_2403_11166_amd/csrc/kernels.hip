@@ -392,12 +392,12 @@ __global__ void __launch_bounds__(512, (LOGE >= 5 ? 2 : 4)) k_ntt_ternary(uint64
 // `mac_chunk` folds and at the end.
 //
 // A block owns 64 NTT slots of one limb and a ROWS x COLS chunk of (A-row,
-// K-row) output tiles.  It walks the contraction (contraction tiles x product
-// terms) KB steps at a time: all 512 threads first stage the chunk's A and K
+// K-row) output tiles.  It walks the contraction (product terms x contraction
+// tiles) KB steps at a time: all 512 threads first stage the chunk's A and K
 // values of KB steps for their 64 slots in LDS, then each wave accumulates a
-// 2 x 2 block of its slot's outputs (both components).  Each operand is read
-// from memory once per chunk.  Chunk shapes are schedule variants with the same
-// result: 0 = 4 x 8, 1 = 2 x 16, 2 = 8 x 4.
+// 2 x 2 block of its slot's outputs (both components).  Chunk shapes are
+// schedule variants with the same result: 0 = 4 x 8, 1 = 2 x 16, 2 = 8 x 4.
+// Staging addresses advance by precomputed strides (no division per step).
 constexpr int kMacSlots = 64, kMacKB = 4;
 constexpr int kMacSmemWords = kMacKB * 2 * 18 * kMacSlots;  // ROWS + COLS <= 18
 
@@ -428,31 +428,172 @@ __device__ __forceinline__ void acc_fold(Acc& x) {
   x.s0 = x.s1 = x.s2 = 0;
 }
 
-template <int ROWS, int COLS>
-__device__ __forceinline__ void do_mac_t(uint64_t* smem, const MacArgs& A, const Geo& G, const Consts& C, int bx,
-                                         int by) {
-  constexpr int TM = 2, TR = 2, WC = COLS / TR, KB = kMacKB;
-  static_assert((ROWS / TM) * WC == 8, "8 waves per block");
-  static_assert(ROWS + COLS <= 18, "staging buffer");
-  // sa[b][comp][row][slot], sk[b][comp][col][slot] for the KB staged steps
+// Fold every accumulator of a wave's block (every mac_fold steps) and
+// Barrett-reduce one of them: accumulator i at fold i of each period of
+// mac_chunk folds (mac_chunk >= 8 >= the accumulator count), so each total is
+// reduced once per period while only one reduction's temporaries are live.
+template <int TM, int TR>
+__device__ __forceinline__ void acc_fold_all(Acc (&acc)[TM][TR][2], uint32_t& nfold, uint32_t reduce_every,
+                                             const LimbConst& lc) {
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int c2 = 0; c2 < TR; ++c2)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) acc_fold(acc[a][c2][c]);
+  const uint32_t f = nfold;
+  nfold = f + 1 == reduce_every ? 0 : f + 1;
+  switch (f) {
+#define PENCIL_REDUCE_CASE(i)                                                    \
+  case i:                                                                        \
+    if (i < TM * TR * 2) {                                                       \
+      Acc& x = acc[(i / (2 * TR)) % TM][(i / 2) % TR][i % 2];                     \
+      x.lo = reduce128(x.hi, x.lo, lc.q, lc.mu_lo, lc.mu_hi);                     \
+      x.hi = 0;                                                                  \
+    }                                                                            \
+    break;
+    PENCIL_REDUCE_CASE(0)
+    PENCIL_REDUCE_CASE(1)
+    PENCIL_REDUCE_CASE(2)
+    PENCIL_REDUCE_CASE(3)
+    PENCIL_REDUCE_CASE(4)
+    PENCIL_REDUCE_CASE(5)
+    PENCIL_REDUCE_CASE(6)
+    PENCIL_REDUCE_CASE(7)
+#undef PENCIL_REDUCE_CASE
+    default: break;
+  }
+}
+
+// Loop-invariant facts of one block's share of the multiply-accumulate.
+struct MacBlock {
+  int64_t ln;           // limb * n + first slot of the block
+  int64_t ct_stride, pt_stride;
+  int row0, col0;       // chunk origin
+  int rg, cg;           // this wave's first row and column in the chunk
+  int s, grp;           // lane slot, wave index
+  bool active;          // this wave's 2 x 2 block holds at least one real output
+  uint32_t nmac, nfold; // steps since the last fold, folds since the last reduction
+};
+
+template <int ROWS, int COLS, bool A_CT>
+__device__ __forceinline__ void mac_term(uint64_t* smem, const MacTerm& T, const MacArgs& A, const Geo& G,
+                                         const Consts& C, const LimbConst& lc, MacBlock& B, Acc (&acc)[2][2][2]) {
+  constexpr int TM = 2, TR = 2, KB = kMacKB;
+  constexpr int KC = COLS > 8 ? 2 : 1;  // K columns staged per wave
   uint64_t(*sa)[2][ROWS][kMacSlots] = reinterpret_cast<uint64_t(*)[2][ROWS][kMacSlots]>(smem);
   uint64_t(*sk)[2][COLS][kMacSlots] =
       reinterpret_cast<uint64_t(*)[2][COLS][kMacSlots]>(smem + KB * 2 * ROWS * kMacSlots);
+  const int sp = G.nOY * G.nOX, kspan = G.nKY * G.nKX;
+  const int ksteps = G.nK * kspan;
+  const int64_t sa_str = A_CT ? B.ct_stride : B.pt_stride, sk_str = A_CT ? B.pt_stride : B.ct_stride;
+  const int grp = B.grp, s = B.s;
+  // The A row this wave stages: tile index ((mi nK + ki) sp + rsp) kspan + kk
+  // = arow + ki sp kspan + kk, with arow = (mi nK sp + rsp) kspan.
+  const int srow = B.row0 + grp;
+  const bool have_a = grp < ROWS && srow < A.m_rows;
+  const uint64_t* pa = T.a + B.ln + s;
+  if (have_a) {
+    const int mi = srow / sp, rsp = srow % sp;
+    pa += (((int64_t)mi * G.nK * sp + rsp) * kspan) * sa_str;
+  }
+  const int64_t a_step = sa_str, a_wrap = ((int64_t)(sp - 1) * kspan + 1) * sa_str;
+  // The K columns this wave stages: tile index col ksteps + (ki kspan + kk).
+  bool have_k[KC];
+  const uint64_t* pk[KC];
+#pragma unroll
+  for (int j = 0; j < KC; ++j) {
+    const int cc = grp + 8 * j, col = B.col0 + cc;
+    have_k[j] = cc < COLS && col < G.nR;
+    pk[j] = T.k + B.ln + s + (have_k[j] ? (int64_t)col * ksteps * sk_str : 0);
+  }
+  const uint32_t fold_every = C.mac_fold, reduce_every = C.mac_chunk;
+  int kk = 0;
+  for (int k0 = 0; k0 < ksteps; k0 += KB) {
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < KB; ++b) {
+      if (k0 + b < ksteps) {
+        if (have_a) {
+          sa[b][0][grp][s] = pa[0];
+          if (A_CT) sa[b][1][grp][s] = pa[B.pt_stride];
+        }
+#pragma unroll
+        for (int j = 0; j < KC; ++j) {
+          if (have_k[j]) {
+            sk[b][0][grp + 8 * j][s] = pk[j][0];
+            if (!A_CT) sk[b][1][grp + 8 * j][s] = pk[j][B.pt_stride];
+          }
+          pk[j] += sk_str;
+        }
+        if (++kk == kspan) {
+          kk = 0;
+          pa += a_wrap;
+        } else {
+          pa += a_step;
+        }
+      }
+    }
+    __syncthreads();
+    if (!B.active) continue;
+#pragma unroll 1
+    for (int b = 0; b < KB; ++b) {
+      if (k0 + b >= ksteps) break;
+      uint64_t av[TM][2], kv[TR][2];
+#pragma unroll
+      for (int a = 0; a < TM; ++a) {
+        av[a][0] = sa[b][0][B.rg + a][s];
+        av[a][1] = A_CT ? sa[b][1][B.rg + a][s] : av[a][0];
+      }
+#pragma unroll
+      for (int c2 = 0; c2 < TR; ++c2) {
+        kv[c2][0] = sk[b][0][B.cg + c2][s];
+        kv[c2][1] = A_CT ? kv[c2][0] : sk[b][1][B.cg + c2][s];
+      }
+#pragma unroll
+      for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int c2 = 0; c2 < TR; ++c2)
+#pragma unroll
+          for (int c = 0; c < 2; ++c) acc_mac(acc[a][c2][c], av[a][c], kv[c2][c]);
+      if (++B.nmac == fold_every) {
+        B.nmac = 0;
+        acc_fold_all<TM, TR>(acc, B.nfold, reduce_every, lc);
+      }
+    }
+  }
+}
+
+template <int TM, int TR, bool A_CT>
+__device__ __forceinline__ void mac_term_direct(const MacTerm& T, const MacArgs& A, const Geo& G, const Consts& C,
+                                                const LimbConst& lc, MacBlock& B, Acc (&acc)[TM][TR][2]);
+
+// One block's multiply-accumulate: chunk ROWS x COLS, each wave a TM x TR
+// block of it; operands staged in LDS or (DIRECT) loaded by each wave.
+template <int ROWS, int COLS, int TM, int TR, bool DIRECT>
+__device__ __forceinline__ void do_mac_t(uint64_t* smem, const MacArgs& A, const Geo& G, const Consts& C,
+                                         int slot_block, int chunk) {
+  constexpr int WC = COLS / TR;
+  static_assert(DIRECT || (TM == 2 && TR == 2), "LDS staging uses 2 x 2 wave blocks");
+  static_assert((ROWS / TM) * WC == 8, "8 waves per block");
+  static_assert(ROWS + COLS <= 18 && ROWS <= 8 && COLS <= 16, "staging layout");
   const int n = C.n, L = C.L;
   const int per_limb = n / kMacSlots;
-  const int l = bx / per_limb;
-  const int slot0 = (bx % per_limb) * kMacSlots;
+  const int l = slot_block / per_limb;
   const LimbConst& lc = C.limb[l];
   const int cchunks = (G.nR + COLS - 1) / COLS;
-  const int row0 = (by / cchunks) * ROWS, col0 = (by % cchunks) * COLS;
-  const int tid = threadIdx.x, s = tid & (kMacSlots - 1), grp = tid >> 6;  // grp 0..7
-  const int rg = (grp / WC) * TM, cg = (grp % WC) * TR;  // this wave's rows and cols in the chunk
-  const int sp = G.nOY * G.nOX, kspan = G.nKY * G.nKX;
-  const int64_t ln = (int64_t)l * n + slot0;
-  const int64_t ct_stride = 2 * (int64_t)L * n, pt_stride = (int64_t)L * n;
-  const int nt = A.n_terms;
-  const int steps = G.nK * kspan * nt;
-  const uint32_t fold_every = C.mac_fold, reduce_every = C.mac_chunk;
+  MacBlock B;
+  B.row0 = (chunk / cchunks) * ROWS;
+  B.col0 = (chunk % cchunks) * COLS;
+  B.s = threadIdx.x & (kMacSlots - 1);
+  B.grp = threadIdx.x >> 6;
+  B.rg = (B.grp / WC) * TM;
+  B.cg = (B.grp % WC) * TR;
+  B.ln = (int64_t)l * n + (int64_t)(slot_block % per_limb) * kMacSlots;
+  B.ct_stride = 2 * (int64_t)L * n;
+  B.pt_stride = (int64_t)L * n;
+  B.active = B.row0 + B.rg < A.m_rows && B.col0 + B.cg < G.nR;
+  B.nmac = B.nfold = 0;
 
   Acc acc[TM][TR][2];
 #pragma unroll
@@ -461,98 +602,35 @@ __device__ __forceinline__ void do_mac_t(uint64_t* smem, const MacArgs& A, const
     for (int b = 0; b < TR; ++b)
 #pragma unroll
       for (int c = 0; c < 2; ++c) acc[a][b][c] = Acc{0, 0, 0, 0, 0};
-
-  uint32_t nmac = 0, nfold = 0;
-  for (int u0 = 0; u0 < steps; u0 += KB) {
-    __syncthreads();
-    // stage KB steps: step u = (ki * kspan + kk) * nt + tt
-#pragma unroll
-    for (int b = 0; b < KB; ++b) {
-      const int u = u0 + b;
-      if (u >= steps) break;
-      const int tt = u % nt, kidx = u / nt;
-      const int ki = kidx / kspan, kk = kidx % kspan;
-      const MacTerm& T = A.term[tt];
-      const bool a_ct = T.a_is_ct;
-#pragma unroll
-      for (int rr = grp; rr < ROWS; rr += 8) {
-        const int row = row0 + rr;
-        if (row < A.m_rows) {
-          const int mi = row / sp, oyi = (row % sp) / G.nOX, oxi = row % G.nOX;
-          const int64_t ai = ((((int64_t)mi * G.nK + ki) * G.nOY + oyi) * G.nOX + oxi) * kspan + kk;
-          const uint64_t* src = T.a + ai * (a_ct ? ct_stride : pt_stride) + ln + s;
-          sa[b][0][rr][s] = src[0];
-          if (a_ct) sa[b][1][rr][s] = src[pt_stride];
-        }
-      }
-#pragma unroll
-      for (int cc = grp; cc < COLS; cc += 8) {
-        const int col = col0 + cc;
-        if (col < G.nR) {
-          const int64_t kix = ((int64_t)col * G.nK + ki) * kspan + kk;
-          const uint64_t* src = T.k + kix * (a_ct ? pt_stride : ct_stride) + ln + s;
-          sk[b][0][cc][s] = src[0];
-          if (!a_ct) sk[b][1][cc][s] = src[pt_stride];
-        }
-      }
+  if constexpr (DIRECT) {
+    if (!B.active) return;
+    for (int tt = 0; tt < A.n_terms; ++tt) {
+      if (A.term[tt].a_is_ct)
+        mac_term_direct<TM, TR, true>(A.term[tt], A, G, C, lc, B, acc);
+      else
+        mac_term_direct<TM, TR, false>(A.term[tt], A, G, C, lc, B, acc);
     }
-    __syncthreads();
-#pragma unroll
-    for (int b = 0; b < KB; ++b) {
-      const int u = u0 + b;
-      if (u >= steps) break;
-      const int a_ct = A.term[u % nt].a_is_ct ? 1 : 0;  // which side carries the second component
-      uint64_t av[TM][2], kv[TR][2];
-#pragma unroll
-      for (int a = 0; a < TM; ++a) {
-        av[a][0] = sa[b][0][rg + a][s];
-        av[a][1] = sa[b][a_ct][rg + a][s];
-      }
-#pragma unroll
-      for (int c2 = 0; c2 < TR; ++c2) {
-        kv[c2][0] = sk[b][0][cg + c2][s];
-        kv[c2][1] = sk[b][1 - a_ct][cg + c2][s];
-      }
-#pragma unroll
-      for (int a = 0; a < TM; ++a)
-#pragma unroll
-        for (int c2 = 0; c2 < TR; ++c2)
-#pragma unroll
-          for (int c = 0; c < 2; ++c) acc_mac(acc[a][c2][c], av[a][c], kv[c2][c]);
-      if (++nmac == fold_every) {
-        nmac = 0;
-#pragma unroll
-        for (int a = 0; a < TM; ++a)
-#pragma unroll
-          for (int c2 = 0; c2 < TR; ++c2)
-#pragma unroll
-            for (int c = 0; c < 2; ++c) acc_fold(acc[a][c2][c]);
-        if (++nfold == reduce_every) {
-          nfold = 0;
-#pragma unroll
-          for (int a = 0; a < TM; ++a)
-#pragma unroll
-            for (int c2 = 0; c2 < TR; ++c2)
-#pragma unroll
-              for (int c = 0; c < 2; ++c) {
-                Acc& x = acc[a][c2][c];
-                x.lo = reduce128(x.hi, x.lo, lc.q, lc.mu_lo, lc.mu_hi);
-                x.hi = 0;
-              }
-        }
-      }
+  } else {
+    for (int tt = 0; tt < A.n_terms; ++tt) {
+      if (A.term[tt].a_is_ct)
+        mac_term<ROWS, COLS, true>(smem, A.term[tt], A, G, C, lc, B, acc);
+      else
+        mac_term<ROWS, COLS, false>(smem, A.term[tt], A, G, C, lc, B, acc);
     }
   }
+  if (!B.active) return;
   // re-randomisation term pk_c * u'_o, reduction and store
+  const int64_t ln = B.ln, pt_stride = B.pt_stride, ct_stride = B.ct_stride;
+  const int s = B.s, sp = G.nOY * G.nOX;
   const uint64_t pk0 = A.pk[ln + s], pk1 = A.pk[pt_stride + ln + s];
 #pragma unroll
   for (int a = 0; a < TM; ++a) {
-    const int row = row0 + rg + a;
+    const int row = B.row0 + B.rg + a;
     if (row >= A.m_rows) continue;
     const int mi = row / sp, oyi = (row % sp) / G.nOX, oxi = row % G.nOX;
 #pragma unroll
     for (int b = 0; b < TR; ++b) {
-      const int col = col0 + cg + b;
+      const int col = B.col0 + B.cg + b;
       if (col >= G.nR) continue;
       const int64_t o = (((int64_t)mi * G.nR + col) * G.nOY + oyi) * G.nOX + oxi;
       const uint64_t u = A.u[o * pt_stride + ln + s];
@@ -570,18 +648,120 @@ __device__ __forceinline__ void do_mac_t(uint64_t* smem, const MacArgs& A, const
   }
 }
 
-__device__ __forceinline__ void do_mac(uint64_t* smem, const MacArgs& A, const Geo& G, const Consts& C, int bx,
-                                       int by) {
-  switch (A.variant) {
-    case 1: do_mac_t<2, 16>(smem, A, G, C, bx, by); break;
-    case 2: do_mac_t<8, 4>(smem, A, G, C, bx, by); break;
-    default: do_mac_t<4, 8>(smem, A, G, C, bx, by); break;
+// The same chunks without LDS: each wave loads the operands of its 2 x 2 block
+// straight from memory (the block's other waves read the same rows and columns
+// through L1) with the next step's loads in flight while the current step is
+// accumulated.  No barriers, so waves run independently.
+template <int TM, int TR, bool A_CT>
+__device__ __forceinline__ void mac_term_direct(const MacTerm& T, const MacArgs& A, const Geo& G, const Consts& C,
+                                                const LimbConst& lc, MacBlock& B, Acc (&acc)[TM][TR][2]) {
+  const int sp = G.nOY * G.nOX, kspan = G.nKY * G.nKX;
+  const int ksteps = G.nK * kspan;
+  const int64_t sa_str = A_CT ? B.ct_stride : B.pt_stride, sk_str = A_CT ? B.pt_stride : B.ct_stride;
+  const int64_t pt_stride = B.pt_stride;
+  // Rows or columns past the end read row 0 / column 0 of the chunk instead
+  // (valid memory); their sums are never stored.
+  const uint64_t* pa[TM];
+  const uint64_t* pk[TR];
+#pragma unroll
+  for (int a = 0; a < TM; ++a) {
+    int row = B.row0 + B.rg + a;
+    if (row >= A.m_rows) row = B.row0 + B.rg;
+    const int mi = row / sp, rsp = row % sp;
+    pa[a] = T.a + B.ln + B.s + (((int64_t)mi * G.nK * sp + rsp) * kspan) * sa_str;
+  }
+#pragma unroll
+  for (int c2 = 0; c2 < TR; ++c2) {
+    int col = B.col0 + B.cg + c2;
+    if (col >= G.nR) col = B.col0 + B.cg;
+    pk[c2] = T.k + B.ln + B.s + (int64_t)col * ksteps * sk_str;
+  }
+  const int64_t a_wrap = ((int64_t)(sp - 1) * kspan + 1) * sa_str;
+  const uint32_t fold_every = C.mac_fold, reduce_every = C.mac_chunk;
+  int kk = 0, left = ksteps;  // steps not yet loaded
+  // Two operand sets alternate so the next step's loads are in flight while
+  // the current one accumulates (no register copies between them).  Loads are
+  // unconditional: past the last step the pointers stop advancing and the
+  // last step is read again, so no branch separates a load from its use.
+  uint64_t xa[TM][2], xk[TR][2], ya[TM][2], yk[TR][2];
+  auto load = [&](uint64_t(&va)[TM][2], uint64_t(&vk)[TR][2]) {
+#pragma unroll
+    for (int a = 0; a < TM; ++a) {
+      va[a][0] = pa[a][0];
+      va[a][1] = A_CT ? pa[a][pt_stride] : va[a][0];
+    }
+#pragma unroll
+    for (int c2 = 0; c2 < TR; ++c2) {
+      vk[c2][0] = pk[c2][0];
+      vk[c2][1] = A_CT ? vk[c2][0] : pk[c2][pt_stride];
+    }
+    const bool adv = --left > 0;
+    const int64_t da = !adv ? 0 : (kk + 1 == kspan) ? a_wrap : sa_str;
+    const int64_t dk = adv ? sk_str : 0;
+    kk = (kk + 1 == kspan) ? 0 : kk + 1;
+#pragma unroll
+    for (int a = 0; a < TM; ++a) pa[a] += da;
+#pragma unroll
+    for (int c2 = 0; c2 < TR; ++c2) pk[c2] += dk;
+  };
+  auto step = [&](const uint64_t(&va)[TM][2], const uint64_t(&vk)[TR][2]) {
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+      for (int c2 = 0; c2 < TR; ++c2)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) acc_mac(acc[a][c2][c], va[a][c], vk[c2][c]);
+    if (++B.nmac == fold_every) {
+      B.nmac = 0;
+      acc_fold_all<TM, TR>(acc, B.nfold, reduce_every, lc);
+    }
+  };
+  load(xa, xk);
+  for (int k = 0; k < ksteps; k += 2) {
+    load(ya, yk);
+    step(xa, xk);
+    if (k + 1 >= ksteps) break;
+    load(xa, xk);
+    step(ya, yk);
   }
 }
 
-__global__ void __launch_bounds__(512) k_mac_lds(MacArgs A, Geo G, Consts C) {
+// Kind 0: LDS-staged 2 x 2 wave blocks; 1: direct 2 x 2; 2: direct 1 x 2.
+template <int KIND>
+__device__ __forceinline__ void do_mac(uint64_t* smem, const MacArgs& A, const Geo& G, const Consts& C,
+                                       int slot_block, int chunk) {
+  constexpr bool DIRECT = KIND != 0;
+  constexpr int TM = KIND == 2 ? 1 : 2, TR = 2;
+  switch (A.variant % 3) {
+    case 1: do_mac_t<2, KIND == 2 ? 8 : 16, TM, TR, DIRECT>(smem, A, G, C, slot_block, chunk); break;
+    case 2: do_mac_t<8, KIND == 2 ? 2 : 4, TM, TR, DIRECT>(smem, A, G, C, slot_block, chunk); break;
+    default: do_mac_t<4, KIND == 2 ? 4 : 8, TM, TR, DIRECT>(smem, A, G, C, slot_block, chunk); break;
+  }
+}
+
+// Work item of block `b` of `total`.  Workgroups go to the 8 XCDs round-robin
+// by block index, so XCD x = b mod 8 receives blocks b = x, x + 8, ...; giving
+// it the contiguous work range [x total / 8, (x + 1) total / 8) in order keeps
+// the chunks of one slot range (which share operands) on one L2.
+__device__ __forceinline__ int64_t xcd_work(int64_t b, int64_t total) {
+  const int64_t q = total >> 3, r = total & 7, x = b & 7, j = b >> 3;
+  return x * q + (x < r ? x : r) + j;
+}
+
+__global__ void __launch_bounds__(512) k_mac_lds(MacArgs A, Geo G, Consts C, int chunks, int64_t total) {
   extern __shared__ uint64_t smem[];
-  do_mac(smem, A, G, C, blockIdx.x, blockIdx.y);
+  const int64_t w = xcd_work(blockIdx.x, total);
+  do_mac<0>(smem, A, G, C, (int)(w / chunks), (int)(w % chunks));
+}
+
+__global__ void __launch_bounds__(512) k_mac_direct(MacArgs A, Geo G, Consts C, int chunks, int64_t total) {
+  const int64_t w = xcd_work(blockIdx.x, total);
+  do_mac<1>(nullptr, A, G, C, (int)(w / chunks), (int)(w % chunks));
+}
+
+__global__ void __launch_bounds__(512) k_mac_direct_small(MacArgs A, Geo G, Consts C, int chunks, int64_t total) {
+  const int64_t w = xcd_work(blockIdx.x, total);
+  do_mac<2>(nullptr, A, G, C, (int)(w / chunks), (int)(w % chunks));
 }
 
 // Output ciphertexts after the inverse NTT: c0 += e0' + flood - round(q s / t),
@@ -967,12 +1147,28 @@ __global__ void __launch_bounds__(512, (LOGE >= 5 ? 2 : 4)) k_step_ntt(StepPhase
 }
 
 // Every multiply-accumulate of one step.
-__global__ void __launch_bounds__(512) k_step_mac(StepPhase P) {
+// Every multiply-accumulate of one step with one staging kind.  Segments start
+// at multiples of 8 blocks, so a segment's blocks keep their XCD under the
+// per-segment work remap; padding blocks past the segment's work exit.
+template <int KIND>
+__device__ __forceinline__ void step_mac(const StepPhase& P, uint64_t* smem) {
   const StepSeg& S = P.segs[find_seg(P.segs, P.nseg, blockIdx.x)];
-  __shared__ uint64_t smem[kMacSmemWords];
   const int64_t local = (int64_t)blockIdx.x - S.block_begin;
-  do_mac(smem, S.mac, S.G, P.consts[S.ctx], (int)(local % S.slot_blocks), (int)(local / S.slot_blocks));
+  const int chunks = mac_chunks(S.mac.variant, S.mac.m_rows, S.G.nR);
+  const int64_t work = S.slot_blocks * chunks, padded = (work + 7) & ~(int64_t)7;
+  const int64_t w = xcd_work(local, padded);
+  if (w >= work) return;
+  do_mac<KIND>(smem, S.mac, S.G, P.consts[S.ctx], (int)(w / chunks), (int)(w % chunks));
 }
+
+__global__ void __launch_bounds__(512) k_step_mac(StepPhase P) {
+  __shared__ uint64_t smem[kMacSmemWords];
+  step_mac<0>(P, smem);
+}
+
+__global__ void __launch_bounds__(512) k_step_mac_direct(StepPhase P) { step_mac<1>(P, nullptr); }
+
+__global__ void __launch_bounds__(512) k_step_mac_direct_small(StepPhase P) { step_mac<2>(P, nullptr); }
 
 // Every flood-and-mask of one step, for one flood width.
 template <int W>
@@ -1042,8 +1238,14 @@ hipError_t launch_mac(const MacArgs& A, int64_t n_out, const Geo& G, const Const
   if (n_out <= 0) return hipSuccess;
   const int64_t slot_blocks = (int64_t)C.n * C.L / kMacSlots;
   const int chunks = mac_chunks(A.variant, A.m_rows, G.nR);
-  dim3 grid((unsigned)slot_blocks, (unsigned)chunks);
-  hipLaunchKernelGGL(k_mac_lds, grid, dim3(512), kMacSmemWords * sizeof(uint64_t), s, A, G, C);
+  const int64_t total = slot_blocks * chunks;
+  if (A.variant >= 6)
+    hipLaunchKernelGGL(k_mac_direct_small, dim3((unsigned)total), dim3(512), 0, s, A, G, C, chunks, total);
+  else if (A.variant >= 3)
+    hipLaunchKernelGGL(k_mac_direct, dim3((unsigned)total), dim3(512), 0, s, A, G, C, chunks, total);
+  else
+    hipLaunchKernelGGL(k_mac_lds, dim3((unsigned)total), dim3(512), kMacSmemWords * sizeof(uint64_t), s, A, G, C,
+                       chunks, total);
   return hipGetLastError();
 }
 
@@ -1106,9 +1308,14 @@ hipError_t launch_step_ntt(int log2n, int loge, const StepPhase& P, int64_t bloc
   return hipGetLastError();
 }
 
-hipError_t launch_step_mac(const StepPhase& P, int64_t blocks, hipStream_t s) {
+hipError_t launch_step_mac(const StepPhase& P, int64_t blocks, int kind, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_step_mac, dim3((unsigned)blocks), dim3(512), kMacSmemWords * sizeof(uint64_t), s, P);
+  if (kind == 2)
+    hipLaunchKernelGGL(k_step_mac_direct_small, dim3((unsigned)blocks), dim3(512), 0, s, P);
+  else if (kind == 1)
+    hipLaunchKernelGGL(k_step_mac_direct, dim3((unsigned)blocks), dim3(512), 0, s, P);
+  else
+    hipLaunchKernelGGL(k_step_mac, dim3((unsigned)blocks), dim3(512), 0, s, P);
   return hipGetLastError();
 }
 

@@ -93,7 +93,7 @@ struct MacArgs {
   MacTerm term[2];
   int32_t n_terms;
   int32_t m_rows;      // nM * nOY * nOX
-  int32_t variant;     // chunk shape of the multiply-accumulate (schedule only): 0 4x8, 1 2x16, 2 8x4
+  int32_t variant;     // multiply-accumulate schedule (0..kMacVariants-1), see mac_rows
   int32_t pad;
   const uint64_t* pk;  // [2][L][N], NTT domain
   const uint64_t* u;   // [n_out][L][N], NTT domain
@@ -109,7 +109,7 @@ struct StepSeg {
   int64_t block_begin;       // first block of the segment in its phase grid
   int32_t kind, ctx, side, purpose;
   int64_t count;             // flood: number of output ciphertexts
-  int64_t slot_blocks;       // mac: blocks along the slot dimension
+  int64_t slot_blocks;       // mac: 64-slot groups (work items = slot_blocks x chunks)
   uint64_t nonce_off, obj_base;
   const uint64_t* src;
   uint64_t* dst;
@@ -130,9 +130,17 @@ struct StepPhase {
 };
 
 // Output-chunk shape of each MAC variant and the number of chunks it needs.
-inline int mac_rows(int variant) { return variant == 1 ? 2 : variant == 2 ? 8 : 4; }
-inline int mac_cols(int variant) { return variant == 1 ? 16 : variant == 2 ? 4 : 8; }
-inline int mac_chunks(int variant, int m_rows, int n_r) {
+// Variant v = 3 kind + shape.  Kind 0 stages operands in LDS for 2 x 2 wave
+// blocks, kind 1 loads them directly for 2 x 2 wave blocks, kind 2 directly
+// for 1 x 2 wave blocks.  The shape picks the chunk (A rows x K rows) of the
+// block's 8 waves: 4 x 8, 2 x 16, 8 x 4 (kinds 0, 1) or 4 x 4, 2 x 8, 8 x 2.
+constexpr int kMacVariants = 9;
+__host__ __device__ inline int mac_rows(int variant) { return variant % 3 == 1 ? 2 : variant % 3 == 2 ? 8 : 4; }
+__host__ __device__ inline int mac_cols(int variant) {
+  const int c = variant % 3 == 1 ? 16 : variant % 3 == 2 ? 4 : 8;
+  return variant >= 6 ? c / 2 : c;
+}
+__host__ __device__ inline int mac_chunks(int variant, int m_rows, int n_r) {
   return ((m_rows + mac_rows(variant) - 1) / mac_rows(variant)) * ((n_r + mac_cols(variant) - 1) / mac_cols(variant));
 }
 
@@ -159,7 +167,7 @@ hipError_t launch_decode(const uint64_t* x, int64_t* share, int64_t n_out, const
 hipError_t launch_zt_corr(const int64_t* a, const int64_t* k, int64_t* out, const Geo& G, const View& AV,
                           const View& KV, const View& OV, const Consts& C, hipStream_t s);
 hipError_t launch_step_ntt(int log2n, int loge, const StepPhase& P, int64_t blocks, hipStream_t s);
-hipError_t launch_step_mac(const StepPhase& P, int64_t blocks, hipStream_t s);
+hipError_t launch_step_mac(const StepPhase& P, int64_t blocks, int kind, hipStream_t s);
 hipError_t launch_step_flood(int words, const StepPhase& P, int64_t blocks, hipStream_t s);
 hipError_t launch_set_u64(uint64_t* p, uint64_t v, int add, hipStream_t s);
 hipError_t launch_keygen(uint64_t* s_ntt, int64_t* s_coeff, uint64_t* pk_coeff, uint64_t* pk_ntt,
