@@ -27,8 +27,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# Integer VALU issue peak: 256 CUs x 64 lanes x 2.4 GHz (one int32 op per lane per clock).
-INT_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# 32-bit integer multiply peak: 256 CUs x 64 lanes x 2.4 GHz, at half the VALU
+# issue rate (v_mad_u64_u32 / v_mul_lo_u32 / v_mul_hi_u32 on gfx950).
+MUL32_PEAK_TOPS = 256 * 64 * 2.4e9 / 2 / 1e12
+# 32-bit multiplies the algorithm needs per unit of work with 60-bit residues:
+# a Shoup butterfly (4 for the quotient estimate, 3 + 3 for the two low
+# products) and a multiply-accumulate of two split 30-bit operands.
+MUL32_PER_BUTTERFLY = 10
+MUL32_PER_MAC = 4
 
 
 def parse():
@@ -155,11 +161,13 @@ def exact_mod_t(layer, op, a, b, t):
 # ------------------------------------------------------------- work model
 
 def kernel_work(sizes_list):
-    """Algorithmic HBM bytes and int work per kernel kind over one step.
+    """Algorithmic HBM bytes and 32-bit multiplies per kernel kind over one step.
 
     bytes: every polynomial the kernel must read and write once (8-byte
-    residues); NTT butterflies: (N/2) log2 N per limb-polynomial; MAC: one
-    64 x 64 -> 128-bit multiply-accumulate per product, component, limb, slot.
+    residues); multiplies: MUL32_PER_BUTTERFLY per butterfly ((N/2) log2 N per
+    limb-polynomial) and MUL32_PER_MAC per multiply-accumulate (one per
+    product, component, limb and slot).  The flood's Philox and reductions are
+    not counted (0).
     """
     work = {}
     for ctx_, sz, ops in sizes_list:
@@ -178,11 +186,13 @@ def kernel_work(sizes_list):
             else:
                 n_ct_in, n_pt = sz.n_ct[2] + sz.n_ct[3], sz.n_pt[2]
             add = lambda k, b, o: work.__setitem__(k, (work.get(k, (0, 0))[0] + b, work.get(k, (0, 0))[1] + o))  # noqa
-            add("ntt_ct", 2 * n_ct_in * 2 * poly, 2 * n_ct_in * bfly)
-            add("ntt_pt", n_pt * poly, n_pt * bfly)
-            add("ntt_ternary", n_out * poly, n_out * bfly)
-            add("mac", (2 * n_ct_in + n_pt + n_out + 2 * n_out) * poly, sz.n_products[opi] * 2 * L * n)
-            add("intt_out", 2 * n_out * 2 * poly, 2 * n_out * bfly)
+            b10 = MUL32_PER_BUTTERFLY * bfly
+            add("ntt_ct", 2 * n_ct_in * 2 * poly, 2 * n_ct_in * b10)
+            add("ntt_pt", n_pt * poly, n_pt * b10)
+            add("ntt_ternary", n_out * poly, n_out * b10)
+            add("mac", (2 * n_ct_in + n_pt + n_out + 2 * n_out) * poly,
+                MUL32_PER_MAC * sz.n_products[opi] * 2 * L * n)
+            add("intt_out", 2 * n_out * 2 * poly, 2 * n_out * b10)
             add("flood_mask", 2 * n_out * 2 * poly, 0)
     # the batched step's phase launches cover the same work
     get = lambda k: work.get(k, (0, 0))  # noqa: E731
@@ -364,13 +374,20 @@ def main():
     dom = max(per_step, key=lambda k: per_step[k][1])
     launches, ms = per_step[dom]
     bytes_step, ops_step = work.get(dom, (0, 0))
-    gbs = bytes_step / (ms / 1e3) / 1e9
-    roof = {"kernel": dom, "launches_per_step": launches, "avg_launch_ms": ms / launches,
-            "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": recorded_traffic(dom, cfg.name),
-            "alu_work_per_step": ops_step}
+    # per launch: algorithmic work of one launch over its average duration
+    avg_ms = ms / launches
+    gbs = bytes_step / launches / (avg_ms / 1e3) / 1e9
+    tops = ops_step / launches / (avg_ms / 1e3) / 1e12
+    roof = {"kernel": dom, "launches_per_step": launches, "avg_launch_ms": round(avg_ms, 5),
+            "bound": "alu", "achieved": round(tops, 3), "peak": round(MUL32_PEAK_TOPS, 3),
+            "unit": "T int32-multiply/s", "frac": round(tops / MUL32_PEAK_TOPS, 4),
+            "traffic": recorded_traffic(dom, cfg.name),
+            "work_per_launch": {"mul32": int(ops_step / launches), "algo_bytes": int(bytes_step / launches)},
+            "hbm": {"achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(gbs / HBM_PEAK_GBS, 4)}}
     breakdown = {k: {"launches": v[0], "ms": round(v[1], 4),
-                     "algo_GBps": round(work.get(k, (0, 0))[0] / (v[1] / 1e3) / 1e9, 1) if v[1] else None}
+                     "algo_GBps": round(work.get(k, (0, 0))[0] / (v[1] / 1e3) / 1e9, 1) if v[1] else None,
+                     "mul32_Tps": round(work.get(k, (0, 0))[1] / (v[1] / 1e3) / 1e12, 3) if v[1] else None}
                  for k, v in sorted(per_step.items(), key=lambda kv: -kv[1][1])}
 
     cpu = None

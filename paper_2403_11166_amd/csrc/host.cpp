@@ -34,6 +34,7 @@ struct pencil_ctx {
   uint64_t* d_s_sh = nullptr;    // [L][N]
   uint64_t* d_pk_ntt = nullptr;  // [2][L][N]
   uint64_t* d_pk_sh = nullptr;   // [2][L][N]
+  uint64_t* d_pk_split = nullptr;  // [2][L][N], the multiply-accumulate's split operand form
   uint64_t* d_pk_coeff = nullptr;
   int64_t* d_s_coeff = nullptr;
   std::string err;
@@ -284,6 +285,8 @@ static pencil_status resolve_params(const pencil_params* p, pencil_ctx* ctx) {
     lc.q = ql;
     lc.r64 = (uint64_t)(((u128)1 << 64) % ql);
     lc.r64_sh = shoup(lc.r64, ql);
+    lc.r128 = (uint64_t)(((u128)lc.r64 * lc.r64) % ql);
+    lc.r192 = (uint64_t)(((u128)lc.r128 * lc.r64) % ql);
     lc.one_sh = (uint64_t)((((u128)1) << 64) / ql);
     lc.ninv = powmod(n, ql - 2, ql);
     lc.ninv_sh = shoup(lc.ninv, ql);
@@ -370,6 +373,7 @@ extern "C" pencil_status pencil_ctx_create(const pencil_params* params, pencil_c
   if (hipMalloc(&ctx->d_tables, 2 * L * n * sizeof(TW)) != hipSuccess || hipMalloc(&ctx->d_s_ntt, ln) != hipSuccess ||
       hipMalloc(&ctx->d_s_sh, ln) != hipSuccess || hipMalloc(&ctx->d_pk_ntt, 2 * ln) != hipSuccess ||
       hipMalloc(&ctx->d_pk_sh, 2 * ln) != hipSuccess || hipMalloc(&ctx->d_pk_coeff, 2 * ln) != hipSuccess ||
+      hipMalloc(&ctx->d_pk_split, 2 * ln) != hipSuccess ||
       hipMalloc(&ctx->d_s_coeff, n * sizeof(int64_t)) != hipSuccess)
     return cleanup(fail(nullptr, PENCIL_ENOMEM, "device allocation failed"));
   if (hipMemcpy(ctx->d_tables, tab.data(), 2 * L * n * sizeof(TW), hipMemcpyHostToDevice) != hipSuccess)
@@ -394,6 +398,10 @@ extern "C" pencil_status pencil_ctx_create(const pencil_params* params, pencil_c
       for (size_t i = 0; i < n; ++i) hs[(c * L + l) * n + i] = shoup(h[(c * L + l) * n + i], C.limb[l].q);
   if (hipMemcpy(ctx->d_pk_sh, hs.data(), 2 * ln, hipMemcpyHostToDevice) != hipSuccess)
     return cleanup(fail(nullptr, PENCIL_EHIP, "key upload failed"));
+  // pk^ split into 30-bit halves, (v mod 2^30) | (v >> 30) << 32
+  for (size_t i = 0; i < 2 * L * n; ++i) hs[i] = (h[i] & 0x3FFFFFFFull) | ((h[i] >> 30) << 32);
+  if (hipMemcpy(ctx->d_pk_split, hs.data(), 2 * ln, hipMemcpyHostToDevice) != hipSuccess)
+    return cleanup(fail(nullptr, PENCIL_EHIP, "key upload failed"));
   *out = ctx;
   return PENCIL_OK;
 }
@@ -405,6 +413,7 @@ extern "C" pencil_status pencil_ctx_destroy(pencil_ctx* ctx) {
   hipFree(ctx->d_s_sh);
   hipFree(ctx->d_pk_ntt);
   hipFree(ctx->d_pk_sh);
+  hipFree(ctx->d_pk_split);
   hipFree(ctx->d_pk_coeff);
   hipFree(ctx->d_s_coeff);
   for (auto& r : ctx->pending) {
@@ -766,7 +775,7 @@ extern "C" pencil_status pencil_encrypt(pencil_ctx* ctx, const pencil_layer* L, 
   const int64_t count = side ? n_k_tiles(G) : n_a_tiles(G);
   hipStream_t s = (hipStream_t)stream;
   uint64_t* u = (uint64_t*)ws;  // u^ of every ciphertext, [count][L][N]
-  hipError_t e = timed(ctx, KID_NTT_TERNARY, s, [&] { return launch_ntt_ternary(u, count, nonce, enc_object(operand, 0), P_ENC_U, ctx->C, ctx->T, s); });
+  hipError_t e = timed(ctx, KID_NTT_TERNARY, s, [&] { return launch_ntt_ternary(u, count, nonce, enc_object(operand, 0), P_ENC_U, 0, ctx->C, ctx->T, s); });
   if (e == hipSuccess)
     e = timed(ctx, KID_ENCRYPT, s, [&] {
       return launch_encrypt(u, share, ct, count, side, G, V, ctx->d_pk_ntt, ctx->d_pk_sh, nonce,
@@ -795,7 +804,7 @@ static pencil_status run_product(pencil_ctx* ctx, const pencil_layer* L, int op,
   A.n_terms = n_terms;
   A.m_rows = G.nM * G.nOY * G.nOX;
   A.variant = sched;
-  A.pk = ctx->d_pk_ntt;
+  A.pk = ctx->d_pk_split;
   A.out = ct_out;
   for (int i = 0; i < n_terms; ++i) {
     const TermIn& T = terms[i];
@@ -823,7 +832,7 @@ static pencil_status run_product(pencil_ctx* ctx, const pencil_layer* L, int op,
   }
   uint64_t* u = w;
   const uint64_t obj = out_object(op, 0);
-  hipError_t e = timed(ctx, KID_NTT_TERNARY, s, [&] { return launch_ntt_ternary(u, no, nonce, obj, P_RR_U, C, ctx->T, s); });
+  hipError_t e = timed(ctx, KID_NTT_TERNARY, s, [&] { return launch_ntt_ternary(u, no, nonce, obj, P_RR_U, 1, C, ctx->T, s); });
   A.u = u;
   if (e == hipSuccess) e = timed(ctx, KID_MAC, s, [&] { return launch_mac(A, no, G, C, s); });
   if (e == hipSuccess) e = timed(ctx, KID_INTT_OUT, s, [&] { return launch_ntt_plain(ct_out, 2 * no, true, C, ctx->T, s); });
@@ -1143,7 +1152,7 @@ extern "C" pencil_status pencil_step_bind(pencil_step* st, const pencil_step_io*
       A.m_rows = G.nM * G.nOY * G.nOX;
       A.variant = e.P.sched[op];
       if (A.variant < 0 || A.variant >= kMacVariants) return step_fail(st, PENCIL_EINVAL, "schedule variant invalid");
-      A.pk = ctx->d_pk_ntt;
+      A.pk = ctx->d_pk_split;
       A.out = ct_out;
       StepSeg base{};
       base.ctx = e.ctx;
@@ -1249,7 +1258,7 @@ static hipError_t step_phases(pencil_step* st, hipStream_t s) {
     pencil_ctx* pc = st->ctxs[0];
     if (ph.kind == 0 || ph.kind == 2)
       e = timed(pc, ph.kind == 0 ? KID_STEP_NTT : KID_STEP_INTT, s,
-                [&] { return launch_step_ntt(ph.key / 8, ph.key % 8, P, ph.blocks, s); });
+                [&] { return launch_step_ntt(ph.key / 8, ph.key % 8, ph.kind == 2, P, ph.blocks, s); });
     else if (ph.kind == 1)
       e = timed(pc, KID_STEP_MAC, s, [&] { return launch_step_mac(P, ph.blocks, ph.key, s); });
     else

@@ -25,20 +25,45 @@ struct NttShape {
   static constexpr int start(int i) { return i == 0 ? 0 : start(i - 1) + size(i - 1); }
 };
 
-// Harvey's lazy Cooley-Tukey butterfly: x, y in [0, 4q) -> [0, 4q), q < 2^62.
-__device__ __forceinline__ void ct_bfly(uint64_t& x, uint64_t& y, const TW w, uint64_t q, uint64_t q2) {
-  const uint64_t a = x >= q2 ? x - q2 : x;
-  const uint64_t t = mul_shoup_lazy(y, w.w, w.ws, q);
+// Butterfly constants of one modulus: 2q, 2^64 - q, 2^64 - 2q and 2q + 1.  They
+// are hidden from the optimiser so that x - q stays the single 64-bit addition
+// x + (2^64 - q) instead of a borrow chain.
+struct BflyK {
+  uint64_t q2, nq, nq2, q2p1;
+};
+
+__device__ __forceinline__ BflyK bfly_consts(uint64_t q) {
+  BflyK k{2 * q, 0 - q, 0 - 2 * q, 2 * q + 1};
+  asm volatile("" : "+s"(k.q2), "+s"(k.nq), "+s"(k.nq2), "+s"(k.q2p1));
+  return k;
+}
+
+// x - 2q if x >= 2q, else x, for x < 2^63: the sign of x - 2q decides.
+__device__ __forceinline__ uint64_t csub2q(uint64_t x, const BflyK& k) {
+  const uint64_t d = x + k.nq2;
+  const uint32_t m = (uint32_t)((int32_t)(uint32_t)(d >> 32) >> 31);
+  const uint64_t back = ((uint64_t)((uint32_t)(k.q2 >> 32) & m) << 32) | ((uint32_t)k.q2 & m);
+  return d + back;
+}
+
+// Shoup's lazy product y w mod q in [0, 2q): y w - floor(y ws / 2^64) q.
+__device__ __forceinline__ uint64_t shoup_lazy(uint64_t y, const TW w, const BflyK& k) {
+  return y * w.w + __umul64hi(y, w.ws) * k.nq;
+}
+
+// Harvey's lazy Cooley-Tukey butterfly: x, y in [0, 4q) -> [0, 4q), q < 2^61.
+__device__ __forceinline__ void ct_bfly(uint64_t& x, uint64_t& y, const TW w, const BflyK& k) {
+  const uint64_t a = csub2q(x, k);
+  const uint64_t t = shoup_lazy(y, w, k);
   x = a + t;
-  y = a - t + q2;
+  y = (a + k.q2p1) + ~t;  // a - t + 2q
 }
 
 // Lazy Gentleman-Sande butterfly: u, v in [0, 2q) -> [0, 2q).
-__device__ __forceinline__ void gs_bfly(uint64_t& u, uint64_t& v, const TW w, uint64_t q, uint64_t q2) {
-  uint64_t s = u + v;
-  s = s >= q2 ? s - q2 : s;
-  const uint64_t d = u - v + q2;
-  v = mul_shoup_lazy(d, w.w, w.ws, q);
+__device__ __forceinline__ void gs_bfly(uint64_t& u, uint64_t& v, const TW w, const BflyK& k) {
+  const uint64_t s = csub2q(u + v, k);
+  const uint64_t d = (u + k.q2p1) + ~v;  // u - v + 2q
+  v = shoup_lazy(d, w, k);
   u = s;
 }
 
@@ -47,7 +72,7 @@ __device__ __forceinline__ void gs_bfly(uint64_t& u, uint64_t& v, const TW w, ui
 // (i0, i0 + t) of group i = i0 >> (log2 N - l) uses tw[2^l + i].  A thread takes
 // E / 2^S groups of 2^S residues {base + k * 2^LT}, LT = log2 N - S0 - S.
 template <int LOGN, int LOGE, int S0, int S, bool LAST>
-__device__ __forceinline__ void fwd_pass(uint64_t* a, const TW* tw, uint64_t q, uint64_t q2) {
+__device__ __forceinline__ void fwd_pass(uint64_t* a, const TW* tw, uint64_t q, const BflyK& bk) {
   using Sh = NttShape<LOGN, LOGE>;
   constexpr int T = Sh::T, G = Sh::E >> S, K = 1 << S, LT = LOGN - S0 - S;
   const int tid = threadIdx.x;
@@ -71,7 +96,7 @@ __device__ __forceinline__ void fwd_pass(uint64_t* a, const TW* tw, uint64_t q, 
 #pragma unroll
         for (int k = j << (S - s); k < ((j + 1) << (S - s)); ++k) {
           if (k & h) continue;
-          ct_bfly(v[r * K + k], v[r * K + k + h], w, q, q2);
+          ct_bfly(v[r * K + k], v[r * K + k + h], w, bk);
         }
       }
     }
@@ -84,7 +109,7 @@ __device__ __forceinline__ void fwd_pass(uint64_t* a, const TW* tw, uint64_t q, 
     for (int k = 0; k < K; ++k) {
       uint64_t x = v[r * K + k];
       if (LAST) {
-        x = x >= q2 ? x - q2 : x;
+        x = csub2q(x, bk);
         x = x >= q ? x - q : x;
       }
       a[lpad(base + (k << LT))] = x;
@@ -96,7 +121,7 @@ __device__ __forceinline__ void fwd_pass(uint64_t* a, const TW* tw, uint64_t q, 
 // stages with t = 2^L0 .. 2^(L0+S-1): pair (i0, i0 + t), i = i0 >> (l + 1),
 // twiddle itw[(N >> (l + 1)) + i].  Groups are {base + k * 2^L0}.
 template <int LOGN, int LOGE, int L0, int S>
-__device__ __forceinline__ void inv_pass(uint64_t* a, const TW* tw, uint64_t q, uint64_t q2) {
+__device__ __forceinline__ void inv_pass(uint64_t* a, const TW* tw, uint64_t q, const BflyK& bk) {
   using Sh = NttShape<LOGN, LOGE>;
   constexpr int T = Sh::T, G = Sh::E >> S, K = 1 << S;
   const int tid = threadIdx.x;
@@ -121,7 +146,7 @@ __device__ __forceinline__ void inv_pass(uint64_t* a, const TW* tw, uint64_t q, 
 #pragma unroll
         for (int k = j << (s + 1); k < ((j + 1) << (s + 1)); ++k) {
           if (k & h) continue;
-          gs_bfly(v[r * K + k], v[r * K + k + h], w, q, q2);
+          gs_bfly(v[r * K + k], v[r * K + k + h], w, bk);
         }
       }
     }
@@ -140,19 +165,19 @@ __device__ __forceinline__ void inv_pass(uint64_t* a, const TW* tw, uint64_t q, 
 template <int LOGN, int LOGE>
 __device__ __forceinline__ void ntt_fwd(uint64_t* a, const TW* tw, uint64_t q) {
   using Sh = NttShape<LOGN, LOGE>;
-  const uint64_t q2 = 2 * q;
-  fwd_pass<LOGN, LOGE, Sh::start(0), Sh::size(0), Sh::NP == 1>(a, tw, q, q2);
+  const BflyK bk = bfly_consts(q);
+  fwd_pass<LOGN, LOGE, Sh::start(0), Sh::size(0), Sh::NP == 1>(a, tw, q, bk);
   __syncthreads();
   if constexpr (Sh::NP > 1) {
-    fwd_pass<LOGN, LOGE, Sh::start(1), Sh::size(1), Sh::NP == 2>(a, tw, q, q2);
+    fwd_pass<LOGN, LOGE, Sh::start(1), Sh::size(1), Sh::NP == 2>(a, tw, q, bk);
     __syncthreads();
   }
   if constexpr (Sh::NP > 2) {
-    fwd_pass<LOGN, LOGE, Sh::start(2), Sh::size(2), Sh::NP == 3>(a, tw, q, q2);
+    fwd_pass<LOGN, LOGE, Sh::start(2), Sh::size(2), Sh::NP == 3>(a, tw, q, bk);
     __syncthreads();
   }
   if constexpr (Sh::NP > 3) {
-    fwd_pass<LOGN, LOGE, Sh::start(3), Sh::size(3), true>(a, tw, q, q2);
+    fwd_pass<LOGN, LOGE, Sh::start(3), Sh::size(3), true>(a, tw, q, bk);
     __syncthreads();
   }
 }
@@ -161,19 +186,19 @@ __device__ __forceinline__ void ntt_fwd(uint64_t* a, const TW* tw, uint64_t q) {
 template <int LOGN, int LOGE>
 __device__ __forceinline__ void ntt_inv(uint64_t* a, const TW* tw, uint64_t q) {
   using Sh = NttShape<LOGN, LOGE>;
-  const uint64_t q2 = 2 * q;
-  inv_pass<LOGN, LOGE, Sh::start(0), Sh::size(0)>(a, tw, q, q2);
+  const BflyK bk = bfly_consts(q);
+  inv_pass<LOGN, LOGE, Sh::start(0), Sh::size(0)>(a, tw, q, bk);
   __syncthreads();
   if constexpr (Sh::NP > 1) {
-    inv_pass<LOGN, LOGE, Sh::start(1), Sh::size(1)>(a, tw, q, q2);
+    inv_pass<LOGN, LOGE, Sh::start(1), Sh::size(1)>(a, tw, q, bk);
     __syncthreads();
   }
   if constexpr (Sh::NP > 2) {
-    inv_pass<LOGN, LOGE, Sh::start(2), Sh::size(2)>(a, tw, q, q2);
+    inv_pass<LOGN, LOGE, Sh::start(2), Sh::size(2)>(a, tw, q, bk);
     __syncthreads();
   }
   if constexpr (Sh::NP > 3) {
-    inv_pass<LOGN, LOGE, Sh::start(3), Sh::size(3)>(a, tw, q, q2);
+    inv_pass<LOGN, LOGE, Sh::start(3), Sh::size(3)>(a, tw, q, bk);
     __syncthreads();
   }
 }
@@ -354,10 +379,12 @@ __global__ void __launch_bounds__(512, (LOGE >= 5 ? 2 : 4)) k_ntt_pt(const int64
 
 // Fresh ternary polynomials (object obj_base + j, stream `purpose`), lifted and
 // transformed.  Coefficient i uses the 32-bit half i mod 2 of stream word i/2,
-// so one Philox block covers 8 coefficients.  Grid: count * L, output [n][L][N].
+// so one Philox block covers 8 coefficients.  Grid: count * L, output [n][L][N],
+// in the multiply-accumulate's split form when `split` is set.
 template <int LOGN, int LOGE>
 __device__ __forceinline__ void do_ntt_ternary(uint64_t* lds, uint64_t* dst, uint64_t nonce, uint64_t obj_base,
-                                               uint32_t purpose, const Consts& C, const Tables& T, int64_t p) {
+                                               uint32_t purpose, int split, const Consts& C, const Tables& T,
+                                               int64_t p) {
   constexpr int n = 1 << LOGN;
   const int L = C.L;
   const int l = (int)(p % L);
@@ -374,14 +401,17 @@ __device__ __forceinline__ void do_ntt_ternary(uint64_t* lds, uint64_t* dst, uin
   __syncthreads();
   ntt_fwd<LOGN, LOGE>(lds, T.fw + (int64_t)l * n, lc.q);
   uint64_t* o = dst + p * n;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) o[i] = lds[lpad(i)];
+  if (split)
+    for (int i = threadIdx.x; i < n; i += blockDim.x) o[i] = split30(lds[lpad(i)]);
+  else
+    for (int i = threadIdx.x; i < n; i += blockDim.x) o[i] = lds[lpad(i)];
 }
 
 template <int LOGN, int LOGE>
 __global__ void __launch_bounds__(512, (LOGE >= 5 ? 2 : 4)) k_ntt_ternary(uint64_t* dst, uint64_t nonce, uint64_t obj_base,
-                                                      uint32_t purpose, Consts C, Tables T) {
+                                                      uint32_t purpose, int split, Consts C, Tables T) {
   extern __shared__ uint64_t lds[];
-  do_ntt_ternary<LOGN, LOGE>(lds, dst, nonce, obj_base, purpose, C, T, blockIdx.x);
+  do_ntt_ternary<LOGN, LOGE>(lds, dst, nonce, obj_base, purpose, split, C, T, blockIdx.x);
 }
 
 // LDS-staged multiply-accumulate.  The forward NTTs of the product path store
@@ -636,13 +666,11 @@ __device__ __forceinline__ void do_mac_t(uint64_t* smem, const MacArgs& A, const
       const uint64_t u = A.u[o * pt_stride + ln + s];
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
+        // one more step (the partial sums hold fewer than mac_fold steps)
         Acc& x = acc[a][b][c];
+        acc_mac(x, c ? pk1 : pk0, u);
         acc_fold(x);
-        uint64_t ph, pl;
-        mul_wide(c ? pk1 : pk0, u, ph, pl);
-        const uint64_t r0 = reduce128(x.hi, x.lo, lc.q, lc.mu_lo, lc.mu_hi);
-        const uint64_t r1 = reduce128(ph, pl, lc.q, lc.mu_lo, lc.mu_hi);
-        A.out[o * ct_stride + (int64_t)c * pt_stride + ln + s] = add_mod(r0, r1, lc.q);
+        A.out[o * ct_stride + (int64_t)c * pt_stride + ln + s] = reduce128(x.hi, x.lo, lc.q, lc.mu_lo, lc.mu_hi);
       }
     }
   }
@@ -764,6 +792,8 @@ __global__ void __launch_bounds__(512) k_mac_direct_small(MacArgs A, Geo G, Cons
   do_mac<2>(nullptr, A, G, C, (int)(w / chunks), (int)(w % chunks));
 }
 
+typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
+
 // Output ciphertexts after the inverse NTT: c0 += e0' + flood - round(q s / t),
 // c1 += e1'; the model owner's share is s at the output slots (+ bias).
 // Each thread handles 4 consecutive coefficients of one output ciphertext.
@@ -800,34 +830,58 @@ __device__ __forceinline__ void do_flood(uint64_t* ct, int64_t n_out, int64_t* s
   ti /= G.nOY;
   const int ri = (int)(ti % G.nR);
   const int mi = (int)(ti / G.nR);
+  // per-coefficient draws: re-randomisation errors, the mask s = (wlo + 2^64 whi) mod t
+  int64_t ev0[4], ev1[4];
+  uint64_t sv[4], rrv[4];
+#pragma unroll
+  for (int z = 0; z < 4; ++z) {
+    ev0[z] = cbd21(e0.v[z]);
+    ev1[z] = cbd21(e1.v[z]);
+    const uint64_t wlo = (z < 2 ? mk0 : mk1).v[(2 * z) & 3], whi = (z < 2 ? mk0 : mk1).v[(2 * z + 1) & 3];
+    uint64_t sh = reduce64(whi, C.one_sh_t, C.t);
+    uint64_t sz = mul_shoup(sh, C.r64t, C.r64t_sh, C.t) + reduce64(wlo, C.one_sh_t, C.t);
+    if (sz >= C.t) sz -= C.t;
+    sv[z] = sz;
+    rrv[z] = round_rho(sz, C);
+  }
+  // the thread's 4 consecutive coefficients of each limb move as two 16-byte words
+  for (int l = 0; l < L; ++l) {
+    const LimbConst& lc = C.limb[l];
+    u64x2* p0 = reinterpret_cast<u64x2*>(c0p + (int64_t)l * n + n0);
+    u64x2* p1 = reinterpret_cast<u64x2*>(c1p + (int64_t)l * n + n0);
+    const u64x2 a0 = p0[0], a1 = p0[1], b0 = p1[0], b1 = p1[1];
+    uint64_t x0[4] = {a0.x, a0.y, a1.x, a1.y}, x1[4] = {b0.x, b0.y, b1.x, b1.y};
+#pragma unroll
+    for (int z = 0; z < 4; ++z) {
+      // flood value V - 2^fb with V = sum_b w_b 2^(64 b) the low fb+1 bits of the
+      // words: sum_b w_b (2^(64 b) mod q) < 2^126 as one 128-bit value, one reduction
+      uint64_t hi = 0, lo = fw[z * W];
+#pragma unroll
+      for (int b = 1; b < W; ++b) {
+        uint64_t w = fw[z * W + b];
+        if (b == W - 1) w &= C.top_mask;
+        uint64_t ph, pl;
+        mul_wide(w, b == 1 ? lc.r64 : b == 2 ? lc.r128 : lc.r192, ph, pl);
+        lo += pl;
+        hi += ph + (lo < pl ? 1 : 0);
+      }
+      if (W == 1) lo &= C.top_mask;
+      uint64_t v = reduce128(hi, lo, lc.q, lc.mu_lo, lc.mu_hi);
+      v = sub_mod(v, lc.flood_off, lc.q);
+      uint64_t c = add_mod(x0[z], small_to_mod(ev0[z], lc.q), lc.q);
+      c = add_mod(c, v, lc.q);
+      x0[z] = sub_mod(c, delta_scale(sv[z], rrv[z], lc), lc.q);
+      x1[z] = add_mod(x1[z], small_to_mod(ev1[z], lc.q), lc.q);
+    }
+    p0[0] = u64x2{x0[0], x0[1]};
+    p0[1] = u64x2{x0[2], x0[3]};
+    p1[0] = u64x2{x1[0], x1[1]};
+    p1[1] = u64x2{x1[2], x1[3]};
+  }
 #pragma unroll
   for (int z = 0; z < 4; ++z) {
     const int i = n0 + z;
-    const int64_t ev0 = cbd21(e0.v[z]), ev1 = cbd21(e1.v[z]);
-    const uint64_t wlo = (z < 2 ? mk0 : mk1).v[(2 * z) & 3], whi = (z < 2 ? mk0 : mk1).v[(2 * z + 1) & 3];
-    // s = (wlo + 2^64 whi) mod t
-    uint64_t sh = reduce64(whi, C.one_sh_t, C.t);
-    uint64_t s = mul_shoup(sh, C.r64t, C.r64t_sh, C.t) + reduce64(wlo, C.one_sh_t, C.t);
-    if (s >= C.t) s -= C.t;
-    const uint64_t rr = round_rho(s, C);
-    for (int l = 0; l < L; ++l) {
-      const LimbConst& lc = C.limb[l];
-      // flood value V - 2^fb with V the low fb+1 bits of the words, by Horner in base 2^64
-      uint64_t v = 0;
-#pragma unroll
-      for (int b = W - 1; b >= 0; --b) {
-        uint64_t w = fw[z * W + b];
-        if (b == W - 1) w &= C.top_mask;
-        v = add_mod(mul_shoup(v, lc.r64, lc.r64_sh, lc.q), reduce64(w, lc.one_sh, lc.q), lc.q);
-      }
-      v = sub_mod(v, lc.flood_off, lc.q);
-      uint64_t x0 = c0p[(int64_t)l * n + i];
-      x0 = add_mod(x0, small_to_mod(ev0, lc.q), lc.q);
-      x0 = add_mod(x0, v, lc.q);
-      x0 = sub_mod(x0, delta_scale(s, rr, lc), lc.q);
-      c0p[(int64_t)l * n + i] = x0;
-      c1p[(int64_t)l * n + i] = add_mod(c1p[(int64_t)l * n + i], small_to_mod(ev1, lc.q), lc.q);
-    }
+    const uint64_t s = sv[z];
     // model owner's share at the output slots: slot = mm*RS + O + rr*S + y*wa + x
     int zz = i - G.O;
     if (zz >= 0) {
@@ -1130,7 +1184,9 @@ __device__ __forceinline__ int find_seg(const StepSeg* segs, int nseg, int64_t b
   return lo;
 }
 
-// Every forward and inverse NTT of one phase, for one ring degree.
+// Every NTT of one phase, for one ring degree: the forward transforms of the
+// inputs (k_step_ntt: ciphertexts, plaintexts, re-randomisation masks) or the
+// inverse transforms of the outputs (k_step_intt).
 template <int LOGN, int LOGE>
 __global__ void __launch_bounds__(512, (LOGE >= 5 ? 2 : 4)) k_step_ntt(StepPhase P) {
   extern __shared__ uint64_t lds[];
@@ -1141,12 +1197,19 @@ __global__ void __launch_bounds__(512, (LOGE >= 5 ? 2 : 4)) k_step_ntt(StepPhase
   switch (S.kind) {
     case SEG_CT: do_ntt_ct<LOGN, LOGE>(lds, S.src, S.dst, S.tensor, S.G, S.V, C, T, p); break;
     case SEG_PT: do_ntt_pt<LOGN, LOGE>(lds, S.tensor, S.dst, S.side, S.G, S.V, C, T, p); break;
-    case SEG_TERN: do_ntt_ternary<LOGN, LOGE>(lds, S.dst, *P.nonce + S.nonce_off, S.obj_base, S.purpose, C, T, p); break;
-    default: do_ntt_plain<LOGN, LOGE>(lds, S.dst, 1, C, T, p); break;
+    case SEG_TERN: do_ntt_ternary<LOGN, LOGE>(lds, S.dst, *P.nonce + S.nonce_off, S.obj_base, S.purpose, 1, C, T, p); break;
+    default: break;
   }
 }
 
-// Every multiply-accumulate of one step.
+template <int LOGN, int LOGE>
+__global__ void __launch_bounds__(512, (LOGE >= 5 ? 2 : 4)) k_step_intt(StepPhase P) {
+  extern __shared__ uint64_t lds[];
+  const StepSeg& S = P.segs[find_seg(P.segs, P.nseg, blockIdx.x)];
+  const int64_t p = (int64_t)blockIdx.x - S.block_begin;
+  do_ntt_plain<LOGN, LOGE>(lds, S.dst, 1, P.consts[S.ctx], P.tabs[S.ctx], p);
+}
+
 // Every multiply-accumulate of one step with one staging kind.  Segments start
 // at multiples of 8 blocks, so a segment's blocks keep their XCD under the
 // per-segment work remap; padding blocks past the segment's work exit.
@@ -1227,10 +1290,10 @@ hipError_t launch_ntt_pt(const int64_t* tensor, uint64_t* dst, int64_t n_pt, int
   return hipGetLastError();
 }
 
-hipError_t launch_ntt_ternary(uint64_t* dst, int64_t count, uint64_t nonce, uint64_t obj_base, uint32_t purpose,
+hipError_t launch_ntt_ternary(uint64_t* dst, int64_t count, uint64_t nonce, uint64_t obj_base, uint32_t purpose, int split,
                               const Consts& C, const Tables& T, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  NTT_DISPATCH(k_ntt_ternary, dim3((unsigned)(count * C.L)), C, s, dst, nonce, obj_base, purpose, C, T);
+  NTT_DISPATCH(k_ntt_ternary, dim3((unsigned)(count * C.L)), C, s, dst, nonce, obj_base, purpose, split, C, T);
   return hipGetLastError();
 }
 
@@ -1297,14 +1360,17 @@ hipError_t launch_zt_corr(const int64_t* a, const int64_t* k, int64_t* out, cons
   return hipGetLastError();
 }
 
-hipError_t launch_step_ntt(int log2n, int loge, const StepPhase& P, int64_t blocks, hipStream_t s) {
+hipError_t launch_step_ntt(int log2n, int loge, bool inverse, const StepPhase& P, int64_t blocks, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
   Consts C{};  // only log2n, n and ntt_loge are read by the dispatch
   C.log2n = log2n;
   C.n = 1 << log2n;
   C.ntt_loge = loge;
   const dim3 grid((unsigned)blocks);
-  NTT_DISPATCH(k_step_ntt, grid, C, s, P);
+  if (inverse)
+    NTT_DISPATCH(k_step_intt, grid, C, s, P);
+  else
+    NTT_DISPATCH(k_step_ntt, grid, C, s, P);
   return hipGetLastError();
 }
 
@@ -1349,7 +1415,8 @@ static hipError_t raise_lds_limit() {
   const void* fns[] = {(const void*)k_ntt_plain<LOGN, LOGE>,   (const void*)k_ntt_ct<LOGN, LOGE>,
                        (const void*)k_ntt_pt<LOGN, LOGE>,      (const void*)k_ntt_ternary<LOGN, LOGE>,
                        (const void*)k_encrypt<LOGN, LOGE>,     (const void*)k_phase<LOGN, LOGE>,
-                       (const void*)k_keygen<LOGN, LOGE>,      (const void*)k_step_ntt<LOGN, LOGE>};
+                       (const void*)k_keygen<LOGN, LOGE>,      (const void*)k_step_ntt<LOGN, LOGE>,
+                       (const void*)k_step_intt<LOGN, LOGE>};
   hipError_t e = hipSuccess;
   for (const void* f : fns) {
     hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);

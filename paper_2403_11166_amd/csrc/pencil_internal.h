@@ -12,6 +12,7 @@ constexpr int kMaxWords = 5;  // multiword integers up to 320 bits (q < 2^244)
 struct LimbConst {
   uint64_t q;
   uint64_t r64, r64_sh;          // 2^64 mod q
+  uint64_t r128, r192;           // 2^128 mod q, 2^192 mod q
   uint64_t one_sh;               // floor(2^64 / q)
   uint64_t ninv, ninv_sh;        // N^-1 mod q
   uint64_t delta, delta_sh;      // floor(q / t) mod q_l
@@ -95,7 +96,7 @@ struct MacArgs {
   int32_t m_rows;      // nM * nOY * nOX
   int32_t variant;     // multiply-accumulate schedule (0..kMacVariants-1), see mac_rows
   int32_t pad;
-  const uint64_t* pk;  // [2][L][N], NTT domain
+  const uint64_t* pk;  // [2][L][N], NTT domain, split form
   const uint64_t* u;   // [n_out][L][N], NTT domain
   uint64_t* out;       // [n_out][2][L][N]
 };
@@ -152,7 +153,7 @@ hipError_t launch_ntt_ct(const uint64_t* src, uint64_t* dst, int64_t n_ct, const
                          const View& V, const Consts& C, const Tables& T, hipStream_t s);
 hipError_t launch_ntt_pt(const int64_t* tensor, uint64_t* dst, int64_t n_pt, int side, const Geo& G, const View& V,
                          const Consts& C, const Tables& T, hipStream_t s);
-hipError_t launch_ntt_ternary(uint64_t* dst, int64_t count, uint64_t nonce, uint64_t obj_base, uint32_t purpose,
+hipError_t launch_ntt_ternary(uint64_t* dst, int64_t count, uint64_t nonce, uint64_t obj_base, uint32_t purpose, int split,
                               const Consts& C, const Tables& T, hipStream_t s);
 hipError_t launch_mac(const MacArgs& A, int64_t n_out, const Geo& G, const Consts& C, hipStream_t s);
 hipError_t launch_flood_mask(uint64_t* ct, int64_t n_out, int64_t* share0, const int64_t* bias, const Geo& G,
@@ -166,7 +167,7 @@ hipError_t launch_decode(const uint64_t* x, int64_t* share, int64_t n_out, const
                          const Consts& C, hipStream_t s);
 hipError_t launch_zt_corr(const int64_t* a, const int64_t* k, int64_t* out, const Geo& G, const View& AV,
                           const View& KV, const View& OV, const Consts& C, hipStream_t s);
-hipError_t launch_step_ntt(int log2n, int loge, const StepPhase& P, int64_t blocks, hipStream_t s);
+hipError_t launch_step_ntt(int log2n, int loge, bool inverse, const StepPhase& P, int64_t blocks, hipStream_t s);
 hipError_t launch_step_mac(const StepPhase& P, int64_t blocks, int kind, hipStream_t s);
 hipError_t launch_step_flood(int words, const StepPhase& P, int64_t blocks, hipStream_t s);
 hipError_t launch_set_u64(uint64_t* p, uint64_t v, int add, hipStream_t s);
