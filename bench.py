@@ -396,7 +396,7 @@ def main():
 
     first = layers[0]
     rec = {
-        "metric": "encrypted linear-layer fwd+bwd products/sec at bit-exact",
+        "metric": "encrypted linear-layer fwd+bwd products/sec at bit-exact; NTT GB/s vs HBM roofline",
         "value": round(value, 1),
         "unit": "products/s",
         "n_gpus": 1,

@@ -462,22 +462,22 @@ __device__ __forceinline__ void acc_fold(Acc& x) {
 // Barrett-reduce one of them: accumulator i at fold i of each period of
 // mac_chunk folds (mac_chunk >= 8 >= the accumulator count), so each total is
 // reduced once per period while only one reduction's temporaries are live.
-template <int TM, int TR>
-__device__ __forceinline__ void acc_fold_all(Acc (&acc)[TM][TR][2], uint32_t& nfold, uint32_t reduce_every,
+template <int TM, int TR, int NC>
+__device__ __forceinline__ void acc_fold_all(Acc (&acc)[TM][TR][NC], uint32_t& nfold, uint32_t reduce_every,
                                              const LimbConst& lc) {
 #pragma unroll
   for (int a = 0; a < TM; ++a)
 #pragma unroll
     for (int c2 = 0; c2 < TR; ++c2)
 #pragma unroll
-      for (int c = 0; c < 2; ++c) acc_fold(acc[a][c2][c]);
+      for (int c = 0; c < NC; ++c) acc_fold(acc[a][c2][c]);
   const uint32_t f = nfold;
   nfold = f + 1 == reduce_every ? 0 : f + 1;
   switch (f) {
 #define PENCIL_REDUCE_CASE(i)                                                    \
   case i:                                                                        \
-    if (i < TM * TR * 2) {                                                       \
-      Acc& x = acc[(i / (2 * TR)) % TM][(i / 2) % TR][i % 2];                     \
+    if (i < TM * TR * NC) {                                                      \
+      Acc& x = acc[(i / (NC * TR)) % TM][(i / NC) % TR][i % NC];                  \
       x.lo = reduce128(x.hi, x.lo, lc.q, lc.mu_lo, lc.mu_hi);                     \
       x.hi = 0;                                                                  \
     }                                                                            \
@@ -502,6 +502,7 @@ struct MacBlock {
   int row0, col0;       // chunk origin
   int rg, cg;           // this wave's first row and column in the chunk
   int s, grp;           // lane slot, wave index
+  int comp;             // the ciphertext component of a one-component wave
   bool active;          // this wave's 2 x 2 block holds at least one real output
   uint32_t nmac, nfold; // steps since the last fold, folds since the last reduction
 };
@@ -588,24 +589,26 @@ __device__ __forceinline__ void mac_term(uint64_t* smem, const MacTerm& T, const
           for (int c = 0; c < 2; ++c) acc_mac(acc[a][c2][c], av[a][c], kv[c2][c]);
       if (++B.nmac == fold_every) {
         B.nmac = 0;
-        acc_fold_all<TM, TR>(acc, B.nfold, reduce_every, lc);
+        acc_fold_all<TM, TR, 2>(acc, B.nfold, reduce_every, lc);
       }
     }
   }
 }
 
-template <int TM, int TR, bool A_CT>
+template <int TM, int TR, int NC, bool A_CT>
 __device__ __forceinline__ void mac_term_direct(const MacTerm& T, const MacArgs& A, const Geo& G, const Consts& C,
-                                                const LimbConst& lc, MacBlock& B, Acc (&acc)[TM][TR][2]);
+                                                const LimbConst& lc, MacBlock& B, Acc (&acc)[TM][TR][NC]);
 
 // One block's multiply-accumulate: chunk ROWS x COLS, each wave a TM x TR
-// block of it; operands staged in LDS or (DIRECT) loaded by each wave.
-template <int ROWS, int COLS, int TM, int TR, bool DIRECT>
+// block of it for both ciphertext components (NC = 2) or one (NC = 1, the
+// block's waves alternate components); operands staged in LDS or (DIRECT)
+// loaded by each wave.
+template <int ROWS, int COLS, int TM, int TR, int NC, bool DIRECT>
 __device__ __forceinline__ void do_mac_t(uint64_t* smem, const MacArgs& A, const Geo& G, const Consts& C,
                                          int slot_block, int chunk) {
   constexpr int WC = COLS / TR;
-  static_assert(DIRECT || (TM == 2 && TR == 2), "LDS staging uses 2 x 2 wave blocks");
-  static_assert((ROWS / TM) * WC == 8, "8 waves per block");
+  static_assert(DIRECT || (TM == 2 && TR == 2 && NC == 2), "LDS staging uses 2 x 2 two-component wave blocks");
+  static_assert((ROWS / TM) * WC * (2 / NC) == 8, "8 waves per block");
   static_assert(ROWS + COLS <= 18 && ROWS <= 8 && COLS <= 16, "staging layout");
   const int n = C.n, L = C.L;
   const int per_limb = n / kMacSlots;
@@ -617,28 +620,30 @@ __device__ __forceinline__ void do_mac_t(uint64_t* smem, const MacArgs& A, const
   B.col0 = (chunk % cchunks) * COLS;
   B.s = threadIdx.x & (kMacSlots - 1);
   B.grp = threadIdx.x >> 6;
-  B.rg = (B.grp / WC) * TM;
-  B.cg = (B.grp % WC) * TR;
+  B.comp = NC == 1 ? (B.grp & 1) : 0;
+  const int tile = NC == 1 ? B.grp >> 1 : B.grp;
+  B.rg = (tile / WC) * TM;
+  B.cg = (tile % WC) * TR;
   B.ln = (int64_t)l * n + (int64_t)(slot_block % per_limb) * kMacSlots;
   B.ct_stride = 2 * (int64_t)L * n;
   B.pt_stride = (int64_t)L * n;
   B.active = B.row0 + B.rg < A.m_rows && B.col0 + B.cg < G.nR;
   B.nmac = B.nfold = 0;
 
-  Acc acc[TM][TR][2];
+  Acc acc[TM][TR][NC];
 #pragma unroll
   for (int a = 0; a < TM; ++a)
 #pragma unroll
     for (int b = 0; b < TR; ++b)
 #pragma unroll
-      for (int c = 0; c < 2; ++c) acc[a][b][c] = Acc{0, 0, 0, 0, 0};
+      for (int c = 0; c < NC; ++c) acc[a][b][c] = Acc{0, 0, 0, 0, 0};
   if constexpr (DIRECT) {
     if (!B.active) return;
     for (int tt = 0; tt < A.n_terms; ++tt) {
       if (A.term[tt].a_is_ct)
-        mac_term_direct<TM, TR, true>(A.term[tt], A, G, C, lc, B, acc);
+        mac_term_direct<TM, TR, NC, true>(A.term[tt], A, G, C, lc, B, acc);
       else
-        mac_term_direct<TM, TR, false>(A.term[tt], A, G, C, lc, B, acc);
+        mac_term_direct<TM, TR, NC, false>(A.term[tt], A, G, C, lc, B, acc);
     }
   } else {
     for (int tt = 0; tt < A.n_terms; ++tt) {
@@ -665,9 +670,10 @@ __device__ __forceinline__ void do_mac_t(uint64_t* smem, const MacArgs& A, const
       const int64_t o = (((int64_t)mi * G.nR + col) * G.nOY + oyi) * G.nOX + oxi;
       const uint64_t u = A.u[o * pt_stride + ln + s];
 #pragma unroll
-      for (int c = 0; c < 2; ++c) {
+      for (int ci = 0; ci < NC; ++ci) {
         // one more step (the partial sums hold fewer than mac_fold steps)
-        Acc& x = acc[a][b][c];
+        const int c = NC == 1 ? B.comp : ci;
+        Acc& x = acc[a][b][ci];
         acc_mac(x, c ? pk1 : pk0, u);
         acc_fold(x);
         A.out[o * ct_stride + (int64_t)c * pt_stride + ln + s] = reduce128(x.hi, x.lo, lc.q, lc.mu_lo, lc.mu_hi);
@@ -680,9 +686,9 @@ __device__ __forceinline__ void do_mac_t(uint64_t* smem, const MacArgs& A, const
 // straight from memory (the block's other waves read the same rows and columns
 // through L1) with the next step's loads in flight while the current step is
 // accumulated.  No barriers, so waves run independently.
-template <int TM, int TR, bool A_CT>
+template <int TM, int TR, int NC, bool A_CT>
 __device__ __forceinline__ void mac_term_direct(const MacTerm& T, const MacArgs& A, const Geo& G, const Consts& C,
-                                                const LimbConst& lc, MacBlock& B, Acc (&acc)[TM][TR][2]) {
+                                                const LimbConst& lc, MacBlock& B, Acc (&acc)[TM][TR][NC]) {
   const int sp = G.nOY * G.nOX, kspan = G.nKY * G.nKX;
   const int ksteps = G.nK * kspan;
   const int64_t sa_str = A_CT ? B.ct_stride : B.pt_stride, sk_str = A_CT ? B.pt_stride : B.ct_stride;
@@ -697,12 +703,14 @@ __device__ __forceinline__ void mac_term_direct(const MacTerm& T, const MacArgs&
     if (row >= A.m_rows) row = B.row0 + B.rg;
     const int mi = row / sp, rsp = row % sp;
     pa[a] = T.a + B.ln + B.s + (((int64_t)mi * G.nK * sp + rsp) * kspan) * sa_str;
+    if (NC == 1 && A_CT) pa[a] += B.comp * pt_stride;  // this wave's component
   }
 #pragma unroll
   for (int c2 = 0; c2 < TR; ++c2) {
     int col = B.col0 + B.cg + c2;
     if (col >= G.nR) col = B.col0 + B.cg;
     pk[c2] = T.k + B.ln + B.s + (int64_t)col * ksteps * sk_str;
+    if (NC == 1 && !A_CT) pk[c2] += B.comp * pt_stride;
   }
   const int64_t a_wrap = ((int64_t)(sp - 1) * kspan + 1) * sa_str;
   const uint32_t fold_every = C.mac_fold, reduce_every = C.mac_chunk;
@@ -711,17 +719,17 @@ __device__ __forceinline__ void mac_term_direct(const MacTerm& T, const MacArgs&
   // the current one accumulates (no register copies between them).  Loads are
   // unconditional: past the last step the pointers stop advancing and the
   // last step is read again, so no branch separates a load from its use.
-  uint64_t xa[TM][2], xk[TR][2], ya[TM][2], yk[TR][2];
-  auto load = [&](uint64_t(&va)[TM][2], uint64_t(&vk)[TR][2]) {
+  uint64_t xa[TM][NC], xk[TR][NC], ya[TM][NC], yk[TR][NC];
+  auto load = [&](uint64_t(&va)[TM][NC], uint64_t(&vk)[TR][NC]) {
 #pragma unroll
     for (int a = 0; a < TM; ++a) {
       va[a][0] = pa[a][0];
-      va[a][1] = A_CT ? pa[a][pt_stride] : va[a][0];
+      if (NC == 2) va[a][NC - 1] = A_CT ? pa[a][pt_stride] : va[a][0];
     }
 #pragma unroll
     for (int c2 = 0; c2 < TR; ++c2) {
       vk[c2][0] = pk[c2][0];
-      vk[c2][1] = A_CT ? vk[c2][0] : pk[c2][pt_stride];
+      if (NC == 2) vk[c2][NC - 1] = A_CT ? vk[c2][0] : pk[c2][pt_stride];
     }
     const bool adv = --left > 0;
     const int64_t da = !adv ? 0 : (kk + 1 == kspan) ? a_wrap : sa_str;
@@ -732,16 +740,16 @@ __device__ __forceinline__ void mac_term_direct(const MacTerm& T, const MacArgs&
 #pragma unroll
     for (int c2 = 0; c2 < TR; ++c2) pk[c2] += dk;
   };
-  auto step = [&](const uint64_t(&va)[TM][2], const uint64_t(&vk)[TR][2]) {
+  auto step = [&](const uint64_t(&va)[TM][NC], const uint64_t(&vk)[TR][NC]) {
 #pragma unroll
     for (int a = 0; a < TM; ++a)
 #pragma unroll
       for (int c2 = 0; c2 < TR; ++c2)
 #pragma unroll
-        for (int c = 0; c < 2; ++c) acc_mac(acc[a][c2][c], va[a][c], vk[c2][c]);
+        for (int c = 0; c < NC; ++c) acc_mac(acc[a][c2][c], va[a][c], vk[c2][c]);
     if (++B.nmac == fold_every) {
       B.nmac = 0;
-      acc_fold_all<TM, TR>(acc, B.nfold, reduce_every, lc);
+      acc_fold_all<TM, TR, NC>(acc, B.nfold, reduce_every, lc);
     }
   };
   load(xa, xk);
@@ -754,16 +762,17 @@ __device__ __forceinline__ void mac_term_direct(const MacTerm& T, const MacArgs&
   }
 }
 
-// Kind 0: LDS-staged 2 x 2 wave blocks; 1: direct 2 x 2; 2: direct 1 x 2.
+// Kind 0: LDS-staged 2 x 2 wave blocks, both components; 1: direct, the same;
+// 2: direct 2 x 2 wave blocks of one component each.
 template <int KIND>
 __device__ __forceinline__ void do_mac(uint64_t* smem, const MacArgs& A, const Geo& G, const Consts& C,
                                        int slot_block, int chunk) {
   constexpr bool DIRECT = KIND != 0;
-  constexpr int TM = KIND == 2 ? 1 : 2, TR = 2;
+  constexpr int NC = KIND == 2 ? 1 : 2;
   switch (A.variant % 3) {
-    case 1: do_mac_t<2, KIND == 2 ? 8 : 16, TM, TR, DIRECT>(smem, A, G, C, slot_block, chunk); break;
-    case 2: do_mac_t<8, KIND == 2 ? 2 : 4, TM, TR, DIRECT>(smem, A, G, C, slot_block, chunk); break;
-    default: do_mac_t<4, KIND == 2 ? 4 : 8, TM, TR, DIRECT>(smem, A, G, C, slot_block, chunk); break;
+    case 1: do_mac_t<2, KIND == 2 ? 8 : 16, 2, 2, NC, DIRECT>(smem, A, G, C, slot_block, chunk); break;
+    case 2: do_mac_t<8, KIND == 2 ? 2 : 4, 2, 2, NC, DIRECT>(smem, A, G, C, slot_block, chunk); break;
+    default: do_mac_t<4, KIND == 2 ? 4 : 8, 2, 2, NC, DIRECT>(smem, A, G, C, slot_block, chunk); break;
   }
 }
 

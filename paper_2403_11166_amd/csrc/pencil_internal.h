@@ -131,10 +131,12 @@ struct StepPhase {
 };
 
 // Output-chunk shape of each MAC variant and the number of chunks it needs.
-// Variant v = 3 kind + shape.  Kind 0 stages operands in LDS for 2 x 2 wave
-// blocks, kind 1 loads them directly for 2 x 2 wave blocks, kind 2 directly
-// for 1 x 2 wave blocks.  The shape picks the chunk (A rows x K rows) of the
-// block's 8 waves: 4 x 8, 2 x 16, 8 x 4 (kinds 0, 1) or 4 x 4, 2 x 8, 8 x 2.
+// Variant v = 3 kind + shape.  Every wave accumulates a 2 x 2 block of
+// (A row, K row) outputs.  Kind 0 stages operands in LDS, kind 1 loads them
+// directly, both for the two ciphertext components; kind 2 loads directly for
+// one component (the block's waves alternate components).  The shape picks the
+// chunk (A rows x K rows) of the block's 8 waves: 4 x 8, 2 x 16, 8 x 4
+// (kinds 0, 1) or 4 x 4, 2 x 8, 8 x 2 (kind 2).
 constexpr int kMacVariants = 9;
 __host__ __device__ inline int mac_rows(int variant) { return variant % 3 == 1 ? 2 : variant % 3 == 2 ? 8 : 4; }
 __host__ __device__ inline int mac_cols(int variant) {
