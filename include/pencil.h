@@ -91,12 +91,14 @@ typedef struct {
 
 typedef struct {
     pencil_tile fwd, dx, dw;
-    /* Schedule of each product's multiply-accumulate, 0..5: the chunk of
-     * output tiles one workgroup covers (v mod 3: 0 = 4 x 8, 1 = 2 x 16,
-     * 2 = 8 x 4 input-row x weight-row tiles), with operands staged in LDS
-     * (v < 3) or loaded directly by each wave (v >= 3).  Results do not depend
-     * on it; pencil_plan_auto picks by a cost model, pencil_autotune by
-     * measurement. */
+    /* Schedule of each product's multiply-accumulate, 0..8.  Each wave of a
+     * 512-lane workgroup accumulates a 2 x 2 block of (input row, weight row)
+     * outputs for 64 NTT slots.  v / 3 is the kind: 0 stages operands in LDS,
+     * 1 loads them directly (both ciphertext components per wave), 2 loads
+     * them directly for one component per wave.  v mod 3 is the workgroup's
+     * chunk: 4 x 8, 2 x 16 or 8 x 4 rows (kinds 0 and 1), 4 x 4, 2 x 8 or 8 x 2
+     * (kind 2).  Results do not depend on it; pencil_plan_auto picks a kind-1
+     * chunk by a cost model, pencil_autotune by measurement. */
     int32_t sched[3];
 } pencil_plan;
 
@@ -204,8 +206,9 @@ pencil_status pencil_zt_linear(pencil_ctx* ctx, const pencil_layer* layer, int o
 
 /* Autotuner: time the schedule candidates on this GPU -- the NTT's residues per
  * thread (16 or 32, per context) and each product's multiply-accumulate chunk
- * shape (per layer and product, written into plan->sched) -- and keep the
- * fastest.  Results are bit-identical for every candidate.  cache_path (may be
+ * shape among the direct-load schedules 3-5 (per layer and product, written
+ * into plan->sched) -- and keep the fastest.  Results are bit-identical for
+ * every candidate.  cache_path (may be
  * NULL) is a text file of earlier choices keyed by GPU, ring degree, limbs,
  * layer shape and product; hits are applied without measuring, new choices are
  * appended.  Synchronous; allocates and frees its own scratch buffers.  Tune a

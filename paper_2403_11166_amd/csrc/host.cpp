@@ -1476,7 +1476,11 @@ extern "C" pencil_status pencil_autotune(pencil_ctx* ctx, const pencil_layer* L,
     float best = -1;
     int bestv = P->sched[op];
     std::string times;
-    for (int cand = 0; cand < kMacVariants; ++cand) {
+    // Candidates: the direct-load chunk shapes.  The LDS-staged and
+    // one-component schedules stay selectable through pencil_plan.sched; they
+    // measured slower on every workload shape, and a batched step launches each
+    // schedule kind separately, so mixing kinds in one step costs a launch.
+    for (int cand = 3; cand < 6; ++cand) {
       P->sched[op] = cand;
       auto run = [&]() -> pencil_status {
         if (op == 0)
@@ -1488,7 +1492,7 @@ extern "C" pencil_status pencil_autotune(pencil_ctx* ctx, const pencil_layer* L,
         return pencil_linear_bwd(ctx, L, P, nullptr, (const uint64_t*)cin, cin2, t0, t1, nullptr, nullptr, nullptr,
                                  (uint64_t*)cout, tout, ws, 1, nullptr);
       };
-      const float ms = time_ms(run, 2);
+      const float ms = time_ms(run, 3);
       times += (times.empty() ? "" : ", ") + std::to_string(ms);
       if (ms > 0 && (best < 0 || ms < best)) {
         best = ms;

@@ -6,6 +6,18 @@
 
 namespace pencil {
 
+// Global-memory views of generic pointers.  Pointers read from device memory
+// (the batched step's segment tables) are generic to the compiler, which then
+// emits flat instructions; flat loads also count against the LDS/scalar wait
+// counter.  Every buffer here is global memory, so the hot loops access it
+// through these address-space-qualified views.
+#define PENCIL_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ PENCIL_GLOBAL T* gview(T* p) {
+  return (PENCIL_GLOBAL T*)p;
+}
+
+
 // ----------------------------------------------------------------- NTT core
 // One workgroup transforms one limb-polynomial held in LDS.  N/E threads each
 // keep E residues in registers (E = 16, or 32 at N = 16384) and run several
@@ -72,7 +84,7 @@ __device__ __forceinline__ void gs_bfly(uint64_t& u, uint64_t& v, const TW w, co
 // (i0, i0 + t) of group i = i0 >> (log2 N - l) uses tw[2^l + i].  A thread takes
 // E / 2^S groups of 2^S residues {base + k * 2^LT}, LT = log2 N - S0 - S.
 template <int LOGN, int LOGE, int S0, int S, bool LAST>
-__device__ __forceinline__ void fwd_pass(uint64_t* a, const TW* tw, uint64_t q, const BflyK& bk) {
+__device__ __forceinline__ void fwd_pass(uint64_t* a, const PENCIL_GLOBAL TW* tw, uint64_t q, const BflyK& bk) {
   using Sh = NttShape<LOGN, LOGE>;
   constexpr int T = Sh::T, G = Sh::E >> S, K = 1 << S, LT = LOGN - S0 - S;
   const int tid = threadIdx.x;
@@ -92,7 +104,8 @@ __device__ __forceinline__ void fwd_pass(uint64_t* a, const TW* tw, uint64_t q, 
       const int blk = (r * T + tid) >> LT;
 #pragma unroll
       for (int j = 0; j < (1 << s); ++j) {
-        const TW w = tw[(1 << (S0 + s)) + (blk << s) + j];
+        const PENCIL_GLOBAL TW* tp = tw + (1 << (S0 + s)) + (blk << s) + j;
+        const TW w{tp->w, tp->ws};
 #pragma unroll
         for (int k = j << (S - s); k < ((j + 1) << (S - s)); ++k) {
           if (k & h) continue;
@@ -121,7 +134,7 @@ __device__ __forceinline__ void fwd_pass(uint64_t* a, const TW* tw, uint64_t q, 
 // stages with t = 2^L0 .. 2^(L0+S-1): pair (i0, i0 + t), i = i0 >> (l + 1),
 // twiddle itw[(N >> (l + 1)) + i].  Groups are {base + k * 2^L0}.
 template <int LOGN, int LOGE, int L0, int S>
-__device__ __forceinline__ void inv_pass(uint64_t* a, const TW* tw, uint64_t q, const BflyK& bk) {
+__device__ __forceinline__ void inv_pass(uint64_t* a, const PENCIL_GLOBAL TW* tw, uint64_t q, const BflyK& bk) {
   using Sh = NttShape<LOGN, LOGE>;
   constexpr int T = Sh::T, G = Sh::E >> S, K = 1 << S;
   const int tid = threadIdx.x;
@@ -142,7 +155,8 @@ __device__ __forceinline__ void inv_pass(uint64_t* a, const TW* tw, uint64_t q, 
       const int blk = (r * T + tid) >> L0;
 #pragma unroll
       for (int j = 0; j < (K >> (s + 1)); ++j) {
-        const TW w = tw[m + (blk << (S - s - 1)) + j];
+        const PENCIL_GLOBAL TW* tp = tw + m + (blk << (S - s - 1)) + j;
+        const TW w{tp->w, tp->ws};
 #pragma unroll
         for (int k = j << (s + 1); k < ((j + 1) << (s + 1)); ++k) {
           if (k & h) continue;
@@ -163,9 +177,10 @@ __device__ __forceinline__ void inv_pass(uint64_t* a, const TW* tw, uint64_t q, 
 // Forward transform of the LDS polynomial (inputs in [0, q), outputs in [0, q)).
 // Callers synchronise before (inputs written) and after (outputs read).
 template <int LOGN, int LOGE>
-__device__ __forceinline__ void ntt_fwd(uint64_t* a, const TW* tw, uint64_t q) {
+__device__ __forceinline__ void ntt_fwd(uint64_t* a, const TW* tw_generic, uint64_t q) {
   using Sh = NttShape<LOGN, LOGE>;
   const BflyK bk = bfly_consts(q);
+  const PENCIL_GLOBAL TW* tw = gview(tw_generic);
   fwd_pass<LOGN, LOGE, Sh::start(0), Sh::size(0), Sh::NP == 1>(a, tw, q, bk);
   __syncthreads();
   if constexpr (Sh::NP > 1) {
@@ -184,9 +199,10 @@ __device__ __forceinline__ void ntt_fwd(uint64_t* a, const TW* tw, uint64_t q) {
 
 // Inverse transform without the N^-1 factor (inputs in [0, 2q), outputs in [0, 2q)).
 template <int LOGN, int LOGE>
-__device__ __forceinline__ void ntt_inv(uint64_t* a, const TW* tw, uint64_t q) {
+__device__ __forceinline__ void ntt_inv(uint64_t* a, const TW* tw_generic, uint64_t q) {
   using Sh = NttShape<LOGN, LOGE>;
   const BflyK bk = bfly_consts(q);
+  const PENCIL_GLOBAL TW* tw = gview(tw_generic);
   inv_pass<LOGN, LOGE, Sh::start(0), Sh::size(0)>(a, tw, q, bk);
   __syncthreads();
   if constexpr (Sh::NP > 1) {
@@ -289,7 +305,7 @@ __device__ __forceinline__ void do_ntt_plain(uint64_t* lds, uint64_t* data, int 
   const int L = C.L;
   const int l = (int)(p % L);
   const LimbConst& lc = C.limb[l];
-  uint64_t* g = data + p * n;
+  PENCIL_GLOBAL uint64_t* g = gview(data + p * n);
   for (int i = threadIdx.x; i < n; i += blockDim.x) lds[lpad(i)] = g[i];
   __syncthreads();
   if (!inverse) {
@@ -319,14 +335,15 @@ __device__ __forceinline__ void do_ntt_ct(uint64_t* lds, const uint64_t* src, ui
   const int c = (int)((p / L) % 2);
   const int64_t j = p / (2 * L);
   const LimbConst& lc = C.limb[l];
-  const uint64_t* g = src + p * n;
+  const PENCIL_GLOBAL uint64_t* g = gview(src + p * n);
+  const PENCIL_GLOBAL int64_t* gshare = gview(share);
   const bool add = share != nullptr && c == 0;
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     uint64_t v = g[i];
     if (add) {
       int64_t off = a_slot_offset(G, V, j, i);
       if (off >= 0) {
-        uint64_t m = (uint64_t)share[off];
+        uint64_t m = (uint64_t)gshare[off];
         v = add_mod(v, delta_scale(m, round_rho(m, C), lc), lc.q);
       }
     }
@@ -334,7 +351,7 @@ __device__ __forceinline__ void do_ntt_ct(uint64_t* lds, const uint64_t* src, ui
   }
   __syncthreads();
   ntt_fwd<LOGN, LOGE>(lds, T.fw + (int64_t)l * n, lc.q);
-  uint64_t* o = dst + p * n;
+  PENCIL_GLOBAL uint64_t* o = gview(dst + p * n);
   for (int i = threadIdx.x; i < n; i += blockDim.x) o[i] = split30(lds[lpad(i)]);
 }
 
@@ -355,18 +372,19 @@ __device__ __forceinline__ void do_ntt_pt(uint64_t* lds, const int64_t* tensor, 
   const int l = (int)(p % L);
   const int64_t j = p / L;
   const LimbConst& lc = C.limb[l];
+  const PENCIL_GLOBAL int64_t* gt = gview(tensor);
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     uint64_t v = 0;
     int64_t off = slot_offset(side, G, V, j, i);
     if (off >= 0) {
-      uint64_t w = (uint64_t)tensor[off];
+      uint64_t w = (uint64_t)gt[off];
       v = w <= C.t_half ? w : lc.q - (C.t - w);
     }
     lds[lpad(i)] = v;
   }
   __syncthreads();
   ntt_fwd<LOGN, LOGE>(lds, T.fw + (int64_t)l * n, lc.q);
-  uint64_t* o = dst + p * n;
+  PENCIL_GLOBAL uint64_t* o = gview(dst + p * n);
   for (int i = threadIdx.x; i < n; i += blockDim.x) o[i] = split30(lds[lpad(i)]);
 }
 
@@ -400,7 +418,7 @@ __device__ __forceinline__ void do_ntt_ternary(uint64_t* lds, uint64_t* dst, uin
   }
   __syncthreads();
   ntt_fwd<LOGN, LOGE>(lds, T.fw + (int64_t)l * n, lc.q);
-  uint64_t* o = dst + p * n;
+  PENCIL_GLOBAL uint64_t* o = gview(dst + p * n);
   if (split)
     for (int i = threadIdx.x; i < n; i += blockDim.x) o[i] = split30(lds[lpad(i)]);
   else
@@ -523,7 +541,7 @@ __device__ __forceinline__ void mac_term(uint64_t* smem, const MacTerm& T, const
   // = arow + ki sp kspan + kk, with arow = (mi nK sp + rsp) kspan.
   const int srow = B.row0 + grp;
   const bool have_a = grp < ROWS && srow < A.m_rows;
-  const uint64_t* pa = T.a + B.ln + s;
+  const PENCIL_GLOBAL uint64_t* pa = gview(T.a) + B.ln + s;
   if (have_a) {
     const int mi = srow / sp, rsp = srow % sp;
     pa += (((int64_t)mi * G.nK * sp + rsp) * kspan) * sa_str;
@@ -531,12 +549,12 @@ __device__ __forceinline__ void mac_term(uint64_t* smem, const MacTerm& T, const
   const int64_t a_step = sa_str, a_wrap = ((int64_t)(sp - 1) * kspan + 1) * sa_str;
   // The K columns this wave stages: tile index col ksteps + (ki kspan + kk).
   bool have_k[KC];
-  const uint64_t* pk[KC];
+  const PENCIL_GLOBAL uint64_t* pk[KC];
 #pragma unroll
   for (int j = 0; j < KC; ++j) {
     const int cc = grp + 8 * j, col = B.col0 + cc;
     have_k[j] = cc < COLS && col < G.nR;
-    pk[j] = T.k + B.ln + s + (have_k[j] ? (int64_t)col * ksteps * sk_str : 0);
+    pk[j] = gview(T.k) + B.ln + s + (have_k[j] ? (int64_t)col * ksteps * sk_str : 0);
   }
   const uint32_t fold_every = C.mac_fold, reduce_every = C.mac_chunk;
   int kk = 0;
@@ -657,7 +675,10 @@ __device__ __forceinline__ void do_mac_t(uint64_t* smem, const MacArgs& A, const
   // re-randomisation term pk_c * u'_o, reduction and store
   const int64_t ln = B.ln, pt_stride = B.pt_stride, ct_stride = B.ct_stride;
   const int s = B.s, sp = G.nOY * G.nOX;
-  const uint64_t pk0 = A.pk[ln + s], pk1 = A.pk[pt_stride + ln + s];
+  const PENCIL_GLOBAL uint64_t* gpk = gview(A.pk);
+  const PENCIL_GLOBAL uint64_t* gu = gview(A.u);
+  PENCIL_GLOBAL uint64_t* gout = gview(A.out);
+  const uint64_t pk0 = gpk[ln + s], pk1 = gpk[pt_stride + ln + s];
 #pragma unroll
   for (int a = 0; a < TM; ++a) {
     const int row = B.row0 + B.rg + a;
@@ -668,7 +689,7 @@ __device__ __forceinline__ void do_mac_t(uint64_t* smem, const MacArgs& A, const
       const int col = B.col0 + B.cg + b;
       if (col >= G.nR) continue;
       const int64_t o = (((int64_t)mi * G.nR + col) * G.nOY + oyi) * G.nOX + oxi;
-      const uint64_t u = A.u[o * pt_stride + ln + s];
+      const uint64_t u = gu[o * pt_stride + ln + s];
 #pragma unroll
       for (int ci = 0; ci < NC; ++ci) {
         // one more step (the partial sums hold fewer than mac_fold steps)
@@ -676,7 +697,7 @@ __device__ __forceinline__ void do_mac_t(uint64_t* smem, const MacArgs& A, const
         Acc& x = acc[a][b][ci];
         acc_mac(x, c ? pk1 : pk0, u);
         acc_fold(x);
-        A.out[o * ct_stride + (int64_t)c * pt_stride + ln + s] = reduce128(x.hi, x.lo, lc.q, lc.mu_lo, lc.mu_hi);
+        gout[o * ct_stride + (int64_t)c * pt_stride + ln + s] = reduce128(x.hi, x.lo, lc.q, lc.mu_lo, lc.mu_hi);
       }
     }
   }
@@ -695,31 +716,32 @@ __device__ __forceinline__ void mac_term_direct(const MacTerm& T, const MacArgs&
   const int64_t pt_stride = B.pt_stride;
   // Rows or columns past the end read row 0 / column 0 of the chunk instead
   // (valid memory); their sums are never stored.
-  const uint64_t* pa[TM];
-  const uint64_t* pk[TR];
+  const PENCIL_GLOBAL uint64_t* pa[TM];
+  const PENCIL_GLOBAL uint64_t* pk[TR];
 #pragma unroll
   for (int a = 0; a < TM; ++a) {
     int row = B.row0 + B.rg + a;
     if (row >= A.m_rows) row = B.row0 + B.rg;
     const int mi = row / sp, rsp = row % sp;
-    pa[a] = T.a + B.ln + B.s + (((int64_t)mi * G.nK * sp + rsp) * kspan) * sa_str;
+    pa[a] = gview(T.a) + B.ln + B.s + (((int64_t)mi * G.nK * sp + rsp) * kspan) * sa_str;
     if (NC == 1 && A_CT) pa[a] += B.comp * pt_stride;  // this wave's component
   }
 #pragma unroll
   for (int c2 = 0; c2 < TR; ++c2) {
     int col = B.col0 + B.cg + c2;
     if (col >= G.nR) col = B.col0 + B.cg;
-    pk[c2] = T.k + B.ln + B.s + (int64_t)col * ksteps * sk_str;
+    pk[c2] = gview(T.k) + B.ln + B.s + (int64_t)col * ksteps * sk_str;
     if (NC == 1 && !A_CT) pk[c2] += B.comp * pt_stride;
   }
   const int64_t a_wrap = ((int64_t)(sp - 1) * kspan + 1) * sa_str;
   const uint32_t fold_every = C.mac_fold, reduce_every = C.mac_chunk;
   int kk = 0, left = ksteps;  // steps not yet loaded
-  // Two operand sets alternate so the next step's loads are in flight while
-  // the current one accumulates (no register copies between them).  Loads are
-  // unconditional: past the last step the pointers stop advancing and the
-  // last step is read again, so no branch separates a load from its use.
-  uint64_t xa[TM][NC], xk[TR][NC], ya[TM][NC], yk[TR][NC];
+  // Three operand sets rotate so that the loads of the next two steps are in
+  // flight while the current one accumulates (no register copies between
+  // them).  Loads are unconditional: past the last step the pointers stop
+  // advancing and the last step is read again, so no branch separates a load
+  // from its use.
+  uint64_t xa[TM][NC], xk[TR][NC], ya[TM][NC], yk[TR][NC], za[TM][NC], zk[TR][NC];
   auto load = [&](uint64_t(&va)[TM][NC], uint64_t(&vk)[TR][NC]) {
 #pragma unroll
     for (int a = 0; a < TM; ++a) {
@@ -753,12 +775,16 @@ __device__ __forceinline__ void mac_term_direct(const MacTerm& T, const MacArgs&
     }
   };
   load(xa, xk);
-  for (int k = 0; k < ksteps; k += 2) {
-    load(ya, yk);
+  load(ya, yk);
+  for (int k = 0; k < ksteps; k += 3) {
+    load(za, zk);
     step(xa, xk);
     if (k + 1 >= ksteps) break;
     load(xa, xk);
     step(ya, yk);
+    if (k + 2 >= ksteps) break;
+    load(ya, yk);
+    step(za, zk);
   }
 }
 
@@ -829,8 +855,8 @@ __device__ __forceinline__ void do_flood(uint64_t* ct, int64_t n_out, int64_t* s
     for (int z = 0; z < 4; ++z) fw[b * 4 + z] = f.v[z];
   }
   const int64_t ct_stride = 2 * (int64_t)L * n;
-  uint64_t* c0p = ct + o * ct_stride;
-  uint64_t* c1p = c0p + (int64_t)L * n;
+  PENCIL_GLOBAL uint64_t* c0p = gview(ct) + o * ct_stride;
+  PENCIL_GLOBAL uint64_t* c1p = c0p + (int64_t)L * n;
   // output-tile coordinates of o = ((mi*nR + ri)*nOY + oyi)*nOX + oxi
   int64_t ti = o;
   const int oxi = (int)(ti % G.nOX);
@@ -856,8 +882,8 @@ __device__ __forceinline__ void do_flood(uint64_t* ct, int64_t n_out, int64_t* s
   // the thread's 4 consecutive coefficients of each limb move as two 16-byte words
   for (int l = 0; l < L; ++l) {
     const LimbConst& lc = C.limb[l];
-    u64x2* p0 = reinterpret_cast<u64x2*>(c0p + (int64_t)l * n + n0);
-    u64x2* p1 = reinterpret_cast<u64x2*>(c1p + (int64_t)l * n + n0);
+    PENCIL_GLOBAL u64x2* p0 = (PENCIL_GLOBAL u64x2*)(c0p + (int64_t)l * n + n0);
+    PENCIL_GLOBAL u64x2* p1 = (PENCIL_GLOBAL u64x2*)(c1p + (int64_t)l * n + n0);
     const u64x2 a0 = p0[0], a1 = p0[1], b0 = p1[0], b1 = p1[1];
     uint64_t x0[4] = {a0.x, a0.y, a1.x, a1.y}, x1[4] = {b0.x, b0.y, b1.x, b1.y};
 #pragma unroll
@@ -904,10 +930,10 @@ __device__ __forceinline__ void do_flood(uint64_t* ct, int64_t n_out, int64_t* s
         if (m < G.M && r < G.R && yy < G.OH && xx < G.OW) {
           uint64_t val = s;
           if (bias) {
-            val += (uint64_t)bias[r];
+            val += (uint64_t)gview(bias)[r];
             if (val >= C.t) val -= C.t;
           }
-          share0[m * OV.s0 + r * OV.s1 + yy * OV.sy + xx * OV.sx] = (int64_t)val;
+          gview(share0)[m * OV.s0 + r * OV.s1 + yy * OV.sy + xx * OV.sx] = (int64_t)val;
         }
       }
     }
@@ -1197,57 +1223,68 @@ __device__ __forceinline__ int find_seg(const StepSeg* segs, int nseg, int64_t b
 // inputs (k_step_ntt: ciphertexts, plaintexts, re-randomisation masks) or the
 // inverse transforms of the outputs (k_step_intt).
 template <int LOGN, int LOGE>
-__global__ void __launch_bounds__(512, (LOGE >= 5 ? 2 : 4)) k_step_ntt(StepPhase P) {
+__global__ void __launch_bounds__(512, (LOGE >= 5 ? 2 : 4))
+    k_step_ntt(const StepSeg* __restrict__ segs, int nseg, const Consts* __restrict__ consts,
+               const Tables* __restrict__ tabs, const uint64_t* __restrict__ nonce) {
   extern __shared__ uint64_t lds[];
-  const StepSeg& S = P.segs[find_seg(P.segs, P.nseg, blockIdx.x)];
-  const Consts& C = P.consts[S.ctx];
-  const Tables& T = P.tabs[S.ctx];
+  const StepSeg& S = segs[find_seg(segs, nseg, blockIdx.x)];
+  const Consts& C = consts[S.ctx];
+  const Tables& T = tabs[S.ctx];
   const int64_t p = (int64_t)blockIdx.x - S.block_begin;
   switch (S.kind) {
     case SEG_CT: do_ntt_ct<LOGN, LOGE>(lds, S.src, S.dst, S.tensor, S.G, S.V, C, T, p); break;
     case SEG_PT: do_ntt_pt<LOGN, LOGE>(lds, S.tensor, S.dst, S.side, S.G, S.V, C, T, p); break;
-    case SEG_TERN: do_ntt_ternary<LOGN, LOGE>(lds, S.dst, *P.nonce + S.nonce_off, S.obj_base, S.purpose, 1, C, T, p); break;
+    case SEG_TERN: do_ntt_ternary<LOGN, LOGE>(lds, S.dst, *nonce + S.nonce_off, S.obj_base, S.purpose, 1, C, T, p); break;
     default: break;
   }
 }
 
 template <int LOGN, int LOGE>
-__global__ void __launch_bounds__(512, (LOGE >= 5 ? 2 : 4)) k_step_intt(StepPhase P) {
+__global__ void __launch_bounds__(512, (LOGE >= 5 ? 2 : 4))
+    k_step_intt(const StepSeg* __restrict__ segs, int nseg, const Consts* __restrict__ consts,
+                const Tables* __restrict__ tabs) {
   extern __shared__ uint64_t lds[];
-  const StepSeg& S = P.segs[find_seg(P.segs, P.nseg, blockIdx.x)];
+  const StepSeg& S = segs[find_seg(segs, nseg, blockIdx.x)];
   const int64_t p = (int64_t)blockIdx.x - S.block_begin;
-  do_ntt_plain<LOGN, LOGE>(lds, S.dst, 1, P.consts[S.ctx], P.tabs[S.ctx], p);
+  do_ntt_plain<LOGN, LOGE>(lds, S.dst, 1, consts[S.ctx], tabs[S.ctx], p);
 }
 
 // Every multiply-accumulate of one step with one staging kind.  Segments start
 // at multiples of 8 blocks, so a segment's blocks keep their XCD under the
 // per-segment work remap; padding blocks past the segment's work exit.
 template <int KIND>
-__device__ __forceinline__ void step_mac(const StepPhase& P, uint64_t* smem) {
-  const StepSeg& S = P.segs[find_seg(P.segs, P.nseg, blockIdx.x)];
+__device__ __forceinline__ void step_mac(const StepSeg* __restrict__ segs, int nseg,
+                                         const Consts* __restrict__ consts, uint64_t* smem) {
+  const StepSeg& S = segs[find_seg(segs, nseg, blockIdx.x)];
   const int64_t local = (int64_t)blockIdx.x - S.block_begin;
   const int chunks = mac_chunks(S.mac.variant, S.mac.m_rows, S.G.nR);
   const int64_t work = S.slot_blocks * chunks, padded = (work + 7) & ~(int64_t)7;
   const int64_t w = xcd_work(local, padded);
   if (w >= work) return;
-  do_mac<KIND>(smem, S.mac, S.G, P.consts[S.ctx], (int)(w / chunks), (int)(w % chunks));
+  do_mac<KIND>(smem, S.mac, S.G, consts[S.ctx], (int)(w / chunks), (int)(w % chunks));
 }
 
-__global__ void __launch_bounds__(512) k_step_mac(StepPhase P) {
+#define STEP_ARGS const StepSeg *__restrict__ segs, int nseg, const Consts *__restrict__ consts
+__global__ void __launch_bounds__(512) k_step_mac(STEP_ARGS) {
   __shared__ uint64_t smem[kMacSmemWords];
-  step_mac<0>(P, smem);
+  step_mac<0>(segs, nseg, consts, smem);
 }
 
-__global__ void __launch_bounds__(512) k_step_mac_direct(StepPhase P) { step_mac<1>(P, nullptr); }
+__global__ void __launch_bounds__(512) k_step_mac_direct(STEP_ARGS) { step_mac<1>(segs, nseg, consts, nullptr); }
 
-__global__ void __launch_bounds__(512) k_step_mac_direct_small(StepPhase P) { step_mac<2>(P, nullptr); }
+__global__ void __launch_bounds__(512) k_step_mac_direct_small(STEP_ARGS) {
+  step_mac<2>(segs, nseg, consts, nullptr);
+}
+#undef STEP_ARGS
 
 // Every flood-and-mask of one step, for one flood width.
 template <int W>
-__global__ void __launch_bounds__(256) k_step_flood(StepPhase P) {
-  const StepSeg& S = P.segs[find_seg(P.segs, P.nseg, blockIdx.x)];
+__global__ void __launch_bounds__(256) k_step_flood(const StepSeg* __restrict__ segs, int nseg,
+                                                    const Consts* __restrict__ consts,
+                                                    const uint64_t* __restrict__ nonce) {
+  const StepSeg& S = segs[find_seg(segs, nseg, blockIdx.x)];
   const int64_t g = ((int64_t)blockIdx.x - S.block_begin) * blockDim.x + threadIdx.x;
-  do_flood<W>(S.dst, S.count, S.share, S.bias, S.G, S.V2, *P.nonce + S.nonce_off, S.obj_base, P.consts[S.ctx], g);
+  do_flood<W>(S.dst, S.count, S.share, S.bias, S.G, S.V2, *nonce + S.nonce_off, S.obj_base, consts[S.ctx], g);
 }
 
 __global__ void k_set_u64(uint64_t* p, uint64_t v, int add) {
@@ -1377,30 +1414,30 @@ hipError_t launch_step_ntt(int log2n, int loge, bool inverse, const StepPhase& P
   C.ntt_loge = loge;
   const dim3 grid((unsigned)blocks);
   if (inverse)
-    NTT_DISPATCH(k_step_intt, grid, C, s, P);
+    NTT_DISPATCH(k_step_intt, grid, C, s, P.segs, P.nseg, P.consts, P.tabs);
   else
-    NTT_DISPATCH(k_step_ntt, grid, C, s, P);
+    NTT_DISPATCH(k_step_ntt, grid, C, s, P.segs, P.nseg, P.consts, P.tabs, P.nonce);
   return hipGetLastError();
 }
 
 hipError_t launch_step_mac(const StepPhase& P, int64_t blocks, int kind, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
   if (kind == 2)
-    hipLaunchKernelGGL(k_step_mac_direct_small, dim3((unsigned)blocks), dim3(512), 0, s, P);
+    hipLaunchKernelGGL(k_step_mac_direct_small, dim3((unsigned)blocks), dim3(512), 0, s, P.segs, P.nseg, P.consts);
   else if (kind == 1)
-    hipLaunchKernelGGL(k_step_mac_direct, dim3((unsigned)blocks), dim3(512), 0, s, P);
+    hipLaunchKernelGGL(k_step_mac_direct, dim3((unsigned)blocks), dim3(512), 0, s, P.segs, P.nseg, P.consts);
   else
-    hipLaunchKernelGGL(k_step_mac, dim3((unsigned)blocks), dim3(512), 0, s, P);
+    hipLaunchKernelGGL(k_step_mac, dim3((unsigned)blocks), dim3(512), 0, s, P.segs, P.nseg, P.consts);
   return hipGetLastError();
 }
 
 hipError_t launch_step_flood(int words, const StepPhase& P, int64_t blocks, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
   switch (words) {
-    case 1: hipLaunchKernelGGL(k_step_flood<1>, dim3((unsigned)blocks), dim3(256), 0, s, P); break;
-    case 2: hipLaunchKernelGGL(k_step_flood<2>, dim3((unsigned)blocks), dim3(256), 0, s, P); break;
-    case 3: hipLaunchKernelGGL(k_step_flood<3>, dim3((unsigned)blocks), dim3(256), 0, s, P); break;
-    case 4: hipLaunchKernelGGL(k_step_flood<4>, dim3((unsigned)blocks), dim3(256), 0, s, P); break;
+    case 1: hipLaunchKernelGGL(k_step_flood<1>, dim3((unsigned)blocks), dim3(256), 0, s, P.segs, P.nseg, P.consts, P.nonce); break;
+    case 2: hipLaunchKernelGGL(k_step_flood<2>, dim3((unsigned)blocks), dim3(256), 0, s, P.segs, P.nseg, P.consts, P.nonce); break;
+    case 3: hipLaunchKernelGGL(k_step_flood<3>, dim3((unsigned)blocks), dim3(256), 0, s, P.segs, P.nseg, P.consts, P.nonce); break;
+    case 4: hipLaunchKernelGGL(k_step_flood<4>, dim3((unsigned)blocks), dim3(256), 0, s, P.segs, P.nseg, P.consts, P.nonce); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
