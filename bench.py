@@ -50,6 +50,8 @@ def parse():
                     help="timed launch path: batched step (phase launches with live kernel events), "
                          "its captured HIP graph, or one launch sequence per product and layer")
     ap.add_argument("--compare-steps", type=int, default=3, help="steps timed for the other launch paths")
+    ap.add_argument("--no-do-side", action="store_true",
+                    help="skip timing the data owner's encryption and decryption after the measured region")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the planner's default schedules instead of timing the candidates first")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -399,6 +401,38 @@ def main():
                      "mul32_Tps": round(work.get(k, (0, 0))[1] / (v[1] / 1e3) / 1e12, 3) if v[1] else None}
                  for k, v in sorted(per_step.items(), key=lambda kv: -kv[1][1])}
 
+    # ------------------------------------------------------ data owner's ends
+    # Encryption of the first layer's input ciphertexts and decryption of its
+    # forward outputs, timed after the measured region (they are not part of
+    # the model owner's step).
+    do_side = None
+    if not args.no_do_side:
+        e = layers[0]
+        c, L_, plan, sz = e["ctx"], e["layer"], e["plan"], e["sz"]
+        enc_ws = c._ws(sz.ws_enc_bytes)
+        dec_ws = c._ws(sz.ws_dec_bytes)
+        out_ct = c.empty_cts(sz.n_ct[0])
+        reps = 5
+
+        def timed_calls(fn):
+            fn(0)
+            torch.cuda.synchronize()
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ev0.record(stream)
+            for r in range(reps):
+                fn(r + 1)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            return ev0.elapsed_time(ev1) / reps
+
+        enc_ms = timed_calls(lambda r: c.encrypt(L_, plan, "x_fwd", e["d"]["x1"], 9000 + r, out=out_ct, ws=enc_ws))
+        dec_ms = timed_calls(lambda r: c.decrypt(L_, plan, "fwd", e["out_f"][0], ws=dec_ws))
+        do_side = {"encrypt": {"ciphertexts": int(sz.n_ct[0]), "ms": round(enc_ms, 4),
+                               "ciphertexts_per_s": round(sz.n_ct[0] / (enc_ms / 1e3), 1)},
+                   "decrypt": {"ciphertexts": int(sz.n_out[0]), "ms": round(dec_ms, 4),
+                               "ciphertexts_per_s": round(sz.n_out[0] / (dec_ms / 1e3), 1)},
+                   "layer": f"{L_.kind} {L_.c_in}->{L_.c_out} {L_.h}x{L_.w} b{L_.batch}"}
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(cfg.layers[0], args.cpu_seconds)
@@ -434,6 +468,7 @@ def main():
         "roofline": roof,
         "kernels": breakdown,
         "cpu_baseline": cpu,
+        "data_owner_ends": do_side,
     }
     print(json.dumps(rec), flush=True)
 
