@@ -204,6 +204,17 @@ pencil_status pencil_decrypt(pencil_ctx* ctx, const pencil_layer* layer, const p
 pencil_status pencil_zt_linear(pencil_ctx* ctx, const pencil_layer* layer, int op, const int64_t* a,
                                const int64_t* b, int64_t* out, void* stream);
 
+/* Z_t linear combination, element-wise: out = base + sum_i coeffs[i] * terms[i]
+ * (mod t) over `count` int64 entries in [0, t).  These are the masked operands
+ * u~ = u - sum k_i u'_i, v~ = v - sum l_j v'_j and the share combinations of the
+ * online phase of the preprocessed products (Sec. IV.C, Alg. 3).
+ * terms: host array of n_terms device pointers (n_terms >= 0; any number, the
+ * library chains launches of 16 terms); coeffs: host array of n_terms values in
+ * [0, t) (use t - c for -c); base: device pointer or NULL (zero); out: device,
+ * may alias base but no term.  Enqueued on `stream`. */
+pencil_status pencil_zt_combine(pencil_ctx* ctx, int64_t count, int n_terms, const int64_t* const* terms,
+                                const uint64_t* coeffs, const int64_t* base, int64_t* out, void* stream);
+
 /* Autotuner: time the schedule candidates on this GPU -- the NTT's residues per
  * thread (16 or 32, per context) and each product's multiply-accumulate chunk
  * shape among the direct-load schedules 3-5 (per layer and product, written

@@ -86,6 +86,9 @@ SIGNATURES = {
                                            ctypes.POINTER(ctypes.c_int)]),
     "pencil_zt_linear": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Layer), ctypes.c_int, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "pencil_zt_combine": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
+                                         ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_uint64),
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "pencil_step_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(Layer),
                                           ctypes.POINTER(Plan), ctypes.c_int, ctypes.c_uint32,
                                           ctypes.POINTER(ctypes.c_void_p)]),

@@ -198,6 +198,22 @@ class Context:
                                               _ptr(out), _stream()))
         return out
 
+    def zt_combine(self, terms, coeffs, base=None, out=None):
+        """out = base + sum_i coeffs[i] * terms[i] mod t, element-wise (int64 tensors in [0, t));
+        coefficients may be negative integers (taken mod t)."""
+        terms = list(terms)
+        like = base if base is not None else terms[0]
+        for x in terms + ([base] if base is not None else []):
+            _need(x, "term")
+            if x.shape != like.shape:
+                raise ValueError("zt_combine: shape mismatch")
+        out = torch.empty_like(like) if out is None else out
+        n = len(terms)
+        ptrs = (ctypes.c_void_p * max(n, 1))(*[x.data_ptr() for x in terms])
+        cs = (ctypes.c_uint64 * max(n, 1))(*[int(c) % self.t for c in coeffs])
+        self._check(self.lib.pencil_zt_combine(self.h, like.numel(), n, ptrs, cs, _ptr(base), _ptr(out), _stream()))
+        return out
+
     def ntt(self, polys, inverse=False):
         """In-place negacyclic NTT of an int64 tensor [count][L][N] of residues."""
         count = polys.numel() // (self.L * self.n)

@@ -962,6 +962,35 @@ extern "C" pencil_status pencil_zt_linear(pencil_ctx* ctx, const pencil_layer* L
   return PENCIL_OK;
 }
 
+extern "C" pencil_status pencil_zt_combine(pencil_ctx* ctx, int64_t count, int n_terms, const int64_t* const* terms,
+                                           const uint64_t* coeffs, const int64_t* base, int64_t* out, void* stream) {
+  if (!ctx) return PENCIL_EINVAL;
+  if (count < 0 || n_terms < 0) return fail(ctx, PENCIL_EINVAL, "negative count or term count");
+  if (n_terms > 0 && (!terms || !coeffs)) return fail(ctx, PENCIL_EINVAL, "terms or coeffs is NULL");
+  TRY(check_ptr(ctx, out, "out"));
+  for (int i = 0; i < n_terms; ++i) {
+    TRY(check_ptr(ctx, terms[i], "terms[i]"));
+    if (coeffs[i] >= ctx->C.t) return fail(ctx, PENCIL_EINVAL, "coeffs[%d] not below t", i);
+    if (terms[i] == out) return fail(ctx, PENCIL_EINVAL, "terms[%d] aliases out", i);
+  }
+  // chunks of kZtTerms terms; each later chunk adds onto the previous result
+  const int64_t* b = base;
+  int i = 0;
+  do {
+    ZtTerms T{};
+    T.n = std::min(kZtTerms, n_terms - i);
+    for (int j = 0; j < T.n; ++j) {
+      T.x[j] = terms[i + j];
+      T.c[j] = coeffs[i + j];
+    }
+    hipError_t e = launch_zt_combine(T, b, out, count, ctx->C, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(ctx, PENCIL_EHIP, "zt_combine launch: %s", hipGetErrorString(e));
+    b = out;
+    i += T.n;
+  } while (i < n_terms);
+  return PENCIL_OK;
+}
+
 // ------------------------------------------------------------ batched step
 
 struct pencil_step {

@@ -1205,6 +1205,26 @@ __global__ void __launch_bounds__(256) k_zt_corr(const int64_t* a, const int64_t
   out[m * OV.s0 + r * OV.s1 + y * OV.sy + x * OV.sx] = (int64_t)v;
 }
 
+// Z_t linear combination out = base + sum_i c_i x_i (mod t), one thread per
+// element: the masked operands and share combinations of the preprocessed
+// products (Pencil+, online phase).  Operands and coefficients are below
+// t < 2^42, so each product fits 84 bits and 16 of them plus base fit 128.
+__global__ void __launch_bounds__(256) k_zt_combine(ZtTerms T, const int64_t* base, int64_t* out, int64_t count,
+                                                    Consts C) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= count) return;
+  uint64_t hi = 0, lo = base ? (uint64_t)gview(base)[g] : 0;
+  for (int i = 0; i < T.n; ++i) {
+    uint64_t ph, pl;
+    mul_wide((uint64_t)gview(T.x[i])[g], T.c[i], ph, pl);
+    lo += pl;
+    hi += ph + (lo < pl ? 1 : 0);
+  }
+  const uint64_t v = add_mod(mul_shoup(reduce64(hi, C.one_sh_t, C.t), C.r64t, C.r64t_sh, C.t),
+                             reduce64(lo, C.one_sh_t, C.t), C.t);
+  gview(out)[g] = (int64_t)v;
+}
+
 // --------------------------------------------------------- batched step
 
 __device__ __forceinline__ int find_seg(const StepSeg* segs, int nseg, int64_t b) {
@@ -1395,6 +1415,13 @@ hipError_t launch_decode(const uint64_t* x, int64_t* share, int64_t n_out, const
   const int64_t threads = n_out * per;
   if (threads <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_decode, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, x, share, n_out, G, outV, C);
+  return hipGetLastError();
+}
+
+hipError_t launch_zt_combine(const ZtTerms& T, const int64_t* base, int64_t* out, int64_t count, const Consts& C,
+                             hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zt_combine, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, T, base, out, count, C);
   return hipGetLastError();
 }
 

@@ -167,6 +167,15 @@ hipError_t launch_phase(const uint64_t* ct, uint64_t* x, int64_t n_ct, const uin
                         const Consts& C, const Tables& T, hipStream_t s);
 hipError_t launch_decode(const uint64_t* x, int64_t* share, int64_t n_out, const Geo& G, const View& outV,
                          const Consts& C, hipStream_t s);
+// Up to kZtTerms terms of a Z_t linear combination, by value (kernel argument).
+constexpr int kZtTerms = 16;
+struct ZtTerms {
+  const int64_t* x[kZtTerms];
+  uint64_t c[kZtTerms];
+  int32_t n, pad;
+};
+hipError_t launch_zt_combine(const ZtTerms& T, const int64_t* base, int64_t* out, int64_t count, const Consts& C,
+                             hipStream_t s);
 hipError_t launch_zt_corr(const int64_t* a, const int64_t* k, int64_t* out, const Geo& G, const View& AV,
                           const View& KV, const View& OV, const Consts& C, hipStream_t s);
 hipError_t launch_step_ntt(int log2n, int loge, bool inverse, const StepPhase& P, int64_t blocks, hipStream_t s);

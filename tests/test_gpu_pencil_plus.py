@@ -1,0 +1,114 @@
+"""Pencil+ on the GPU (preprocessed products, Alg. 3 and Alg. 4) against the
+oracle: the Z_t combinations, the online phase on oracle-defined
+preprocessing shares (bit for bit), and the homomorphic preprocessing (its
+shares reconstruct the mask products)."""
+import numpy as np
+import pytest
+
+from oracle import pencil_plus as PP
+from workloads import CONFIGS, T_PLAIN, conv, fc
+
+from gpu_common import dev, host_i64
+
+pytestmark = pytest.mark.gpu
+
+T = T_PLAIN
+SMALL = [fc(3, 7, 5, log2_n=12, num_limbs=2, prime_bits=50),
+         conv(2, 3, 2, 5, k=3, pad=1, log2_n=12, num_limbs=2, prime_bits=50)]
+_ctx = {}
+
+
+def context(layer, seed=21):
+    from paper_2403_11166_amd import Context
+    key = (layer.log2_n, layer.num_limbs, layer.prime_bits, seed)
+    if key not in _ctx:
+        _ctx[key] = Context(layer.log2_n, layer.num_limbs, layer.prime_bits, seed)
+    return _ctx[key]
+
+
+def rnd(rng, shape):
+    return rng.integers(0, T, size=shape, dtype=np.int64)
+
+
+def instance(layer, kind, m, seed):
+    rng = np.random.default_rng(seed)
+    su, sv, so = PP.operand_shapes(layer, kind)
+    u, v = rnd(rng, su), rnd(rng, sv)
+    um = [rnd(rng, su) for _ in range(m)]
+    vm = [rnd(rng, sv) for _ in range(m)]
+    s = [[rnd(rng, so) for _ in range(m)] for _ in range(m)]
+    k = rng.integers(1, T, size=m)
+    l = rng.integers(1, T, size=m)
+    return u, v, um, vm, s, k, l
+
+
+@pytest.mark.parametrize("n_terms", [0, 1, 3, 16, 21])
+def test_zt_combine_matches_oracle(n_terms):
+    ctx = context(SMALL[0])
+    rng = np.random.default_rng(n_terms)
+    xs = [rnd(rng, (37, 11)) for _ in range(n_terms)]
+    base = rnd(rng, (37, 11))
+    c = [int(v) - T // 2 for v in rng.integers(0, T, size=n_terms)]   # negative coefficients too
+    got = ctx.zt_combine([dev(x) for x in xs], c, base=dev(base))
+    want = PP.combine(xs, [ci % T for ci in c], T, base=base)
+    assert np.array_equal(host_i64(got), want)
+    if n_terms:
+        # out aliasing base
+        b = dev(base)
+        ctx.zt_combine([dev(x) for x in xs], c, base=b, out=b)
+        assert np.array_equal(host_i64(b), want)
+        # no base
+        got = ctx.zt_combine([dev(x) for x in xs], c)
+        assert np.array_equal(host_i64(got), PP.combine(xs, [ci % T for ci in c], T))
+
+
+@pytest.mark.parametrize("li", range(len(SMALL)))
+@pytest.mark.parametrize("kind", PP.KINDS)
+def test_online_phase_bit_exact(li, kind):
+    from paper_2403_11166_amd import pencil_plus as GP
+    layer = SMALL[li]
+    ctx = context(layer)
+    m = 3
+    u, v, um, vm, s, k, l = instance(layer, kind, m, 100 + li)
+    sh0, sh1 = PP.prep(layer, kind, um, vm, s, T)
+    want = PP.online(layer, kind, u, v, um, vm, sh0, sh1, k, l, T)
+    got = GP.online(ctx, layer, kind, dev(u), dev(v), [dev(x) for x in um], [dev(x) for x in vm],
+                    [[dev(x) for x in row] for row in sh0], [[dev(x) for x in row] for row in sh1], k, l)
+    for g, w in zip(got, want):
+        assert np.array_equal(host_i64(g), w)
+
+
+def test_online_phase_bit_exact_fc784x128():
+    """The default workload's layer (FC 784 -> 128, batch 64), weight-gradient
+    cross term (the largest output), m = 2."""
+    from paper_2403_11166_amd import pencil_plus as GP
+    layer = CONFIGS[2].layers[0]
+    ctx = context(layer)
+    m = 2
+    u, v, um, vm, s, k, l = instance(layer, "dw01", m, 7)
+    sh0, sh1 = PP.prep(layer, "dw01", um, vm, s, T)
+    want = PP.online(layer, "dw01", u, v, um, vm, sh0, sh1, k, l, T)
+    got = GP.online(ctx, layer, "dw01", dev(u), dev(v), [dev(x) for x in um], [dev(x) for x in vm],
+                    [[dev(x) for x in row] for row in sh0], [[dev(x) for x in row] for row in sh1], k, l)
+    for g, w in zip(got, want):
+        assert np.array_equal(host_i64(g), w)
+
+
+@pytest.mark.parametrize("kind", PP.KINDS)
+def test_preprocessing_and_online_end_to_end(kind):
+    """Homomorphic preprocessing on the GPU: every pair's shares reconstruct
+    u'_i o v'_j; the online phase on those shares reconstructs u o v."""
+    from paper_2403_11166_amd import pencil_plus as GP
+    layer = SMALL[1]
+    ctx = context(layer)
+    plan = ctx.plan_auto(layer)
+    m = 2
+    u, v, um, vm, _, k, l = instance(layer, kind, m, 300)
+    sh0, sh1 = GP.prep(ctx, layer, plan, kind, [dev(x) for x in um], [dev(x) for x in vm], 5000)
+    for i in range(m):
+        for j in range(m):
+            rec = (host_i64(sh0[i][j]) + host_i64(sh1[i][j])) % T
+            assert np.array_equal(rec, PP.apply(layer, kind, um[i], vm[j], T)), (i, j)
+    out0, out1, _, _ = GP.online(ctx, layer, kind, dev(u), dev(v), [dev(x) for x in um], [dev(x) for x in vm],
+                                 sh0, sh1, k, l)
+    assert np.array_equal((host_i64(out0) + host_i64(out1)) % T, PP.apply(layer, kind, u, v, T))
