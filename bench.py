@@ -50,6 +50,9 @@ def parse():
                     help="timed launch path: batched step (phase launches with live kernel events), "
                          "its captured HIP graph, or one launch sequence per product and layer")
     ap.add_argument("--compare-steps", type=int, default=3, help="steps timed for the other launch paths")
+    ap.add_argument("--pencil-plus", type=int, default=-1, metavar="M",
+                    help="also measure Pencil+ (preprocessed products, M masks per party) on the first "
+                         "layer; default 8 on the default workload, 0 (off) on the others")
     ap.add_argument("--no-do-side", action="store_true",
                     help="skip timing the data owner's encryption and decryption after the measured region")
     ap.add_argument("--no-autotune", action="store_true",
@@ -205,6 +208,67 @@ def kernel_work(sizes_list):
     work["step_intt"] = get("intt_out")
     work["step_flood"] = get("flood_mask")
     return work
+
+
+# ------------------------------------------------------------- Pencil+
+
+def pencil_plus_bench(e, m, he_step_ms, torch):
+    """Pencil+ on one layer (Alg. 3, Alg. 4): the homomorphic preprocessing of the
+    four operators (m^2 products each) and the online phase of one training
+    step (the four operators' online phases), timed after the main region.
+    The online results are reconstructed and checked against exact modular
+    linear algebra."""
+    from paper_2403_11166_amd import pencil_plus as GP
+    ctx, L_, plan, d = e["ctx"], e["layer"], e["plan"], e["d"]
+    t = ctx.t
+    gen = torch.Generator(device="cpu").manual_seed(1234)
+
+    def rnd(shape):
+        return torch.randint(0, t, shape, generator=gen, dtype=torch.int64).cuda()
+
+    ops = {"fwd": (d["W"], d["x1"]), "dx": (d["W"], d["dy1"]), "dw01": (d["dy0"], d["x1"]), "dw10": (d["x0"], d["dy1"])}
+    masks, shares, prep_ms, prep_products = {}, {}, 0.0, 0
+    sz = e["sz"]
+    per_op = {"fwd": sz.n_products[0], "dx": sz.n_products[1], "dw01": sz.n_products[2] // 2,
+              "dw10": sz.n_products[2] // 2}
+    for i, (kind, (u, v)) in enumerate(ops.items()):
+        um = [rnd(tuple(u.shape)) for _ in range(m)]
+        vm = [rnd(tuple(v.shape)) for _ in range(m)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sh = GP.prep(ctx, L_, plan, kind, um, vm, 50000 + 1000 * i)
+        torch.cuda.synchronize()
+        prep_ms += (time.perf_counter() - t0) * 1e3
+        prep_products += m * m * per_op[kind]
+        masks[kind], shares[kind] = (um, vm), sh
+    k = [int(x) for x in torch.randint(1, t, (m,), generator=gen)]
+    l = [int(x) for x in torch.randint(1, t, (m,), generator=gen)]
+
+    def online_step():
+        return {kind: GP.online(ctx, L_, kind, u, v, masks[kind][0], masks[kind][1], shares[kind][0],
+                                shares[kind][1], k, l) for kind, (u, v) in ops.items()}
+
+    res = online_step()
+    torch.cuda.synchronize()
+    reps = 5
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        online_step()
+    ev1.record()
+    torch.cuda.synchronize()
+    online_ms = ev0.elapsed_time(ev1) / reps
+    want = {"fwd": exact_mod_t(L_, "fwd", d["x1"], d["W"], t), "dx": exact_mod_t(L_, "dx", d["dy1"], d["W"], t),
+            "dw01": exact_mod_t(L_, "dw", d["x1"], d["dy0"], t), "dw10": exact_mod_t(L_, "dw", d["x0"], d["dy1"], t)}
+    exact = all(torch.equal(torch.remainder(res[kd][0] + res[kd][1], t), want[kd]) for kd in ops)
+    return {"m": m, "layer": f"{L_.kind} {L_.c_in}->{L_.c_out} {L_.h}x{L_.w} b{L_.batch}",
+            "prep": {"products": int(prep_products), "wall_ms": round(prep_ms, 2),
+                     "products_per_s": round(prep_products / (prep_ms / 1e3), 1),
+                     "note": "per-call launches from Python, wall clock, includes the data owner's "
+                             "encryptions and decryptions"},
+            "online": {"ms_per_step": round(online_ms, 4), "operators": list(ops),
+                       "he_step_ms": round(he_step_ms, 4), "speedup_vs_he_step": round(he_step_ms / online_ms, 2),
+                       "bit_exact": bool(exact)}}
 
 
 # ------------------------------------------------------------- cpu baseline
@@ -433,6 +497,12 @@ def main():
                                "ciphertexts_per_s": round(sz.n_out[0] / (dec_ms / 1e3), 1)},
                    "layer": f"{L_.kind} {L_.c_in}->{L_.c_out} {L_.h}x{L_.w} b{L_.batch}"}
 
+    # ------------------------------------------------------ Pencil+
+    plus = None
+    m_plus = args.pencil_plus if args.pencil_plus >= 0 else (8 if args.config == 2 else 0)
+    if m_plus > 0:
+        plus = pencil_plus_bench(layers[0], m_plus, compare["step"] if "step" in compare else ms_step, torch)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(cfg.layers[0], args.cpu_seconds)
@@ -469,6 +539,7 @@ def main():
         "kernels": breakdown,
         "cpu_baseline": cpu,
         "data_owner_ends": do_side,
+        "pencil_plus": plus,
     }
     print(json.dumps(rec), flush=True)
 
