@@ -1205,6 +1205,125 @@ __global__ void __launch_bounds__(256) k_zt_corr(const int64_t* a, const int64_t
   out[m * OV.s0 + r * OV.s1 + y * OV.sy + x * OV.sx] = (int64_t)v;
 }
 
+// The same correlation as a tiled contraction.  A workgroup of nw waves owns a
+// (8 TI) x (8 TI) tile of (output position, output channel) pairs, each lane a
+// TI x TI block, and the waves split the contraction (k, dy, dx) nw ways.
+// Operands (< t < 2^42) are split into 21-bit halves, so a product is four
+// 32 x 32 multiply-adds into three 64-bit partial sums that hold 2^22 terms;
+// each wave reduces its totals mod t and the waves' results are summed through
+// LDS.  The launcher picks TI and nw so that small outputs or short
+// contractions still fill the GPU.
+constexpr int kZtWaves = 16;
+template <int TI>
+__global__ void __launch_bounds__(1024) k_zt_gemm(const int64_t* a, const int64_t* kt, int64_t* out, Geo G, View AV,
+                                                  View KV, View OV, Consts C) {
+  constexpr int NO = 64 * TI * TI;  // outputs per workgroup
+  __shared__ uint64_t red[kZtWaves][NO];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int P = G.M * G.OH * G.OW, R = G.R, ohw = G.OH * G.OW;
+  const PENCIL_GLOBAL int64_t* ga = gview(a);
+  const PENCIL_GLOBAL int64_t* gk = gview(kt);
+  int64_t abase[TI];
+  int ay[TI], ax[TI];
+  bool rv[TI];
+#pragma unroll
+  for (int i = 0; i < TI; ++i) {
+    const int row = blockIdx.x * 8 * TI + (lane >> 3) * TI + i;
+    rv[i] = row < P;
+    const int rr = rv[i] ? row : 0;
+    const int m = rr / ohw, rem = rr - m * ohw, y = rem / G.OW, x = rem - y * G.OW;
+    abase[i] = (int64_t)m * AV.s0;
+    ay[i] = y - AV.pad;
+    ax[i] = x - AV.pad;
+  }
+  int64_t kbase[TI];
+  bool cv[TI];
+#pragma unroll
+  for (int j = 0; j < TI; ++j) {
+    const int col = blockIdx.y * 8 * TI + (lane & 7) * TI + j;
+    cv[j] = col < R;
+    kbase[j] = (int64_t)(cv[j] ? col : 0) * KV.s0;
+  }
+  const int kk = G.KH * G.KW;
+  const int64_t ctot = (int64_t)G.K * kk, per = (ctot + nw - 1) / nw;
+  const int64_t c_begin = wv * per, c_end = c_begin + per < ctot ? c_begin + per : ctot;
+  uint64_t s0[TI][TI] = {}, s1[TI][TI] = {}, s2[TI][TI] = {};
+  int k = 0, dy = 0, dx = 0;
+  if (c_begin < c_end) {
+    k = (int)(c_begin / kk);
+    const int rem = (int)(c_begin - (int64_t)k * kk);
+    dy = rem / G.KW;
+    dx = rem - dy * G.KW;
+  }
+  constexpr uint64_t kLo = (1ull << 21) - 1;
+  // Chunks of U contraction steps: all loads of a chunk are issued before its
+  // multiply-adds.
+  constexpr int U = 4;
+  for (int64_t c0 = c_begin; c0 < c_end; c0 += U) {
+    uint64_t av[U][TI], bv[U][TI];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool live = c0 + u < c_end;
+      const int ky = KV.flip ? KV.KH - 1 - dy : dy, kx = KV.flip ? KV.KW - 1 - dx : dx;
+      const int64_t koff = (int64_t)k * KV.s1 + (int64_t)ky * KV.sy + (int64_t)kx * KV.sx;
+#pragma unroll
+      for (int j = 0; j < TI; ++j) bv[u][j] = live && cv[j] ? (uint64_t)gk[kbase[j] + koff] : 0;
+#pragma unroll
+      for (int i = 0; i < TI; ++i) {
+        const int ys = ay[i] + dy, xs = ax[i] + dx;
+        const bool in = live && rv[i] && ys >= 0 && ys < AV.H && xs >= 0 && xs < AV.W;
+        av[u][i] = in ? (uint64_t)ga[abase[i] + (int64_t)k * AV.s1 + (int64_t)ys * AV.sy + (int64_t)xs * AV.sx] : 0;
+      }
+      if (++dx == G.KW) {
+        dx = 0;
+        if (++dy == G.KH) {
+          dy = 0;
+          ++k;
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+      for (int i = 0; i < TI; ++i) {
+        const uint32_t a0 = (uint32_t)(av[u][i] & kLo), a1 = (uint32_t)(av[u][i] >> 21);
+#pragma unroll
+        for (int j = 0; j < TI; ++j) {
+          const uint32_t b0 = (uint32_t)(bv[u][j] & kLo), b1 = (uint32_t)(bv[u][j] >> 21);
+          s0[i][j] += (uint64_t)a0 * b0;
+          s1[i][j] += (uint64_t)a0 * b1;
+          s1[i][j] += (uint64_t)a1 * b0;
+          s2[i][j] += (uint64_t)a1 * b1;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+#pragma unroll
+    for (int j = 0; j < TI; ++j) {
+      // s0 + s1 2^21 + s2 2^42 as a 128-bit value, then mod t
+      const uint64_t t1 = s1[i][j] << 21, t2 = s2[i][j] << 42;
+      uint64_t lo = s0[i][j] + t1;
+      uint64_t hi = (lo < t1 ? 1 : 0) + (s1[i][j] >> 43) + (s2[i][j] >> 22);
+      lo += t2;
+      hi += lo < t2 ? 1 : 0;
+      red[wv][(lane * TI + i) * TI + j] = add_mod(mul_shoup(reduce64(hi, C.one_sh_t, C.t), C.r64t, C.r64t_sh, C.t),
+                                                  reduce64(lo, C.one_sh_t, C.t), C.t);
+    }
+  __syncthreads();
+  for (int o = threadIdx.x; o < NO; o += blockDim.x) {
+    const int ol = o / (TI * TI), i = (o / TI) % TI, j = o % TI;
+    uint64_t v = 0;
+    for (int w = 0; w < nw; ++w) v = add_mod(v, red[w][o], C.t);
+    const int row = blockIdx.x * 8 * TI + (ol >> 3) * TI + i, col = blockIdx.y * 8 * TI + (ol & 7) * TI + j;
+    if (row < P && col < R) {
+      const int m = row / ohw, rem = row - m * ohw, y = rem / G.OW, x = rem - y * G.OW;
+      gview(out)[(int64_t)m * OV.s0 + (int64_t)col * OV.s1 + (int64_t)y * OV.sy + (int64_t)x * OV.sx] = (int64_t)v;
+    }
+  }
+}
+
 // Z_t linear combination out = base + sum_i c_i x_i (mod t), one thread per
 // element: the masked operands and share combinations of the preprocessed
 // products (Pencil+, online phase).  Operands and coefficients are below
@@ -1429,6 +1548,23 @@ hipError_t launch_zt_corr(const int64_t* a, const int64_t* k, int64_t* out, cons
                           const View& KV, const View& OV, const Consts& C, hipStream_t s) {
   const int64_t total = (int64_t)G.M * G.R * G.OH * G.OW;
   if (total <= 0) return hipSuccess;
+  const int64_t rows = (int64_t)G.M * G.OH * G.OW, ctot = (int64_t)G.K * G.KH * G.KW;
+  // Tiled kernel: 2 x 2 outputs per lane when that still gives >= 512
+  // workgroups, else 1; about 16 contraction steps per wave, at most 16 waves.
+  // Its partial sums hold 2^22 terms per wave.
+  const int64_t blocks2 = ((rows + 15) / 16) * ((G.R + 15) / 16);
+  const int ti = blocks2 >= 512 ? 2 : 1;
+  const int64_t steps16 = ctot / 16;
+  const int nw = steps16 < 1 ? 1 : steps16 > kZtWaves ? kZtWaves : (int)steps16;
+  const int64_t gx = (rows + 8 * ti - 1) / (8 * ti), gy = ((int64_t)G.R + 8 * ti - 1) / (8 * ti);
+  if ((ctot + nw - 1) / nw <= (1ll << 22) && gx < (1ll << 31) && gy < 65536) {
+    const dim3 grid((unsigned)gx, (unsigned)gy);
+    if (ti == 2)
+      hipLaunchKernelGGL(k_zt_gemm<2>, grid, dim3(64 * nw), 0, s, a, k, out, G, AV, KV, OV, C);
+    else
+      hipLaunchKernelGGL(k_zt_gemm<1>, grid, dim3(64 * nw), 0, s, a, k, out, G, AV, KV, OV, C);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_zt_corr, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a, k, out, G, AV, KV, OV, C);
   return hipGetLastError();
 }

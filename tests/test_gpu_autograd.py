@@ -106,7 +106,11 @@ def test_exact_integer_finite_differences():
 
 @pytest.mark.parametrize("layer", [conv(3, 4, 5, 6, k=3, pad=1, log2_n=10, num_limbs=2, prime_bits=50),
                                    conv(2, 3, 2, 5, k=2, pad=0, log2_n=10, num_limbs=2, prime_bits=50),
-                                   fc(5, 9, 4, log2_n=10, num_limbs=2, prime_bits=50)])
+                                   fc(5, 9, 4, log2_n=10, num_limbs=2, prime_bits=50),
+                                   # several output tiles, ragged edges, long contractions
+                                   fc(64, 784, 128, log2_n=10, num_limbs=2, prime_bits=50),
+                                   conv(4, 5, 19, 13, k=3, pad=1, log2_n=10, num_limbs=2, prime_bits=50),
+                                   conv(3, 17, 6, 10, k=5, pad=2, log2_n=10, num_limbs=2, prime_bits=50)])
 def test_zt_linear_matches_oracle(layer):
     from paper_2403_11166_amd import Context
     ctx = Context(layer.log2_n, layer.num_limbs, layer.prime_bits, 1)
