@@ -518,6 +518,49 @@ def main():
                                "ciphertexts_per_s": round(sz.n_out[0] / (dec_ms / 1e3), 1)},
                    "layer": f"{L_.kind} {L_.c_in}->{L_.c_out} {L_.h}x{L_.w} b{L_.batch}"}
 
+    # ------------------------------------------- bias gradient and DP noise
+    # The weight-update terms that finish Alg. 2 (Sec. III.B.2) on every layer
+    # of the workload: the bias-gradient share of dY and the DO's perturbation
+    # of its dW and db shares.  Both are HBM-bound streams; the bias gradient
+    # is checked against an int64 sum in torch.
+    wupd = None
+    if not args.no_do_side:
+        reps = 10
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+        def time_reps(fn):
+            fn(0)
+            torch.cuda.synchronize()
+            ev0.record(stream)
+            for r in range(reps):
+                fn(r + 1)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            return ev0.elapsed_time(ev1) / reps
+
+        bg_ms = dp_ms = 0.0
+        bg_bytes = dp_bytes = 0
+        bg_ok = True
+        for e in layers:
+            c, L_, d = e["ctx"], e["layer"], e["d"]
+            dy = d["dy1"]
+            db = c.bias_grad(L_, dy)
+            dims = [i for i in range(dy.dim()) if i != 1]
+            bg_ok = bg_ok and bool(torch.equal(db, dy.sum(dim=dims) % c.t))
+            bg_ms += time_reps(lambda r: c.bias_grad(L_, dy))
+            bg_bytes += 8 * (dy.numel() + db.numel())
+            dwt = d["W"].clone()
+            dp_ms += time_reps(lambda r: c.dp_noise_(dwt, 2.0 ** 24 * 0.05, 7000 + r, 0))
+            dp_bytes += 16 * dwt.numel()
+        wupd = {"bias_grad": {"ms": round(bg_ms, 4), "GBps": round(bg_bytes / (bg_ms / 1e3) / 1e9, 1),
+                              "hbm_frac": round(bg_bytes / (bg_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                              "algo_bytes": bg_bytes, "matches_torch_sum": bg_ok},
+                "dp_noise_dW": {"ms": round(dp_ms, 4), "GBps": round(dp_bytes / (dp_ms / 1e3) / 1e9, 1),
+                                "hbm_frac": round(dp_bytes / (dp_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                                "algo_bytes": dp_bytes,
+                                "normals_per_s": round(dp_bytes / 16 / (dp_ms / 1e3), 1)},
+                "layers": len(layers)}
+
     # ------------------------------------------------------ Pencil+
     plus = None
     m_plus = args.pencil_plus if args.pencil_plus >= 0 else (8 if args.config == 2 else 0)
@@ -560,6 +603,7 @@ def main():
         "kernels": breakdown,
         "cpu_baseline": cpu,
         "data_owner_ends": do_side,
+        "weight_update_terms": wupd,
         "pencil_plus": plus,
     }
     print(json.dumps(rec), flush=True)

@@ -215,6 +215,28 @@ pencil_status pencil_zt_linear(pencil_ctx* ctx, const pencil_layer* layer, int o
 pencil_status pencil_zt_combine(pencil_ctx* ctx, int64_t count, int n_terms, const int64_t* const* terms,
                                 const uint64_t* coeffs, const int64_t* base, int64_t* out, void* stream);
 
+/* Bias-gradient share (Sec. III.B.2): db[o] = sum of dy over the batch and,
+ * for a convolution, over the output rows and columns, mod t.  Each party runs
+ * it on its own share of dY; the DO perturbs its result (pencil_dp_noise) and
+ * sends it to the MO.  dy: device, int64 in [0, t), the layer's dY layout
+ * (batch, c_out[, h_out, w_out]); db: device, c_out entries.  EUNSUPPORTED if
+ * batch * h_out * w_out > 2^22.  Enqueued on `stream`. */
+pencil_status pencil_bias_grad(pencil_ctx* ctx, const pencil_layer* layer, const int64_t* dy, int64_t* db,
+                               void* stream);
+
+/* The DO's differential-privacy perturbation (Sec. III.B.2: DPSGD noise
+ * N(0, sigma^2 C^2 / B) on its share of the weight gradient after Alg. 2's
+ * decryption, and on its bias-gradient share): x[i] = x[i] + floor(sd * z_i)
+ * mod t, in place, for count int64 entries in [0, t).  sd is the standard
+ * deviation in fixed-point units (sigma C / sqrt(B) * 2^scale; scale 2f for
+ * dW, f for db), 0 <= sd <= 2^52.  z_i are standard normals from Box-Muller on
+ * the context's Philox stream (nonce, object): entries 2i and 2i+1 share
+ * stream words 2i (radius) and 2i+1 (angle); the logarithm, sine and cosine are
+ * fixed sequences of IEEE double operations, so the draws are reproducible.
+ * Use a distinct (nonce, object) per tensor.  Enqueued on `stream`. */
+pencil_status pencil_dp_noise(pencil_ctx* ctx, int64_t count, double sd, uint64_t nonce, uint64_t object,
+                              int64_t* x, void* stream);
+
 /* Autotuner: time the schedule candidates on this GPU -- the NTT's residues per
  * thread (16 or 32, per context) and each product's multiply-accumulate chunk
  * shape among the direct-load schedules 3-5 (per layer and product, written

@@ -89,6 +89,10 @@ SIGNATURES = {
     "pencil_zt_combine": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
                                          ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_uint64),
                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "pencil_bias_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Layer), ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p]),
+    "pencil_dp_noise": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64,
+                                       ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p]),
     "pencil_step_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(Layer),
                                           ctypes.POINTER(Plan), ctypes.c_int, ctypes.c_uint32,
                                           ctypes.POINTER(ctypes.c_void_p)]),

@@ -214,6 +214,23 @@ class Context:
         self._check(self.lib.pencil_zt_combine(self.h, like.numel(), n, ptrs, cs, _ptr(base), _ptr(out), _stream()))
         return out
 
+    def bias_grad(self, layer, dy):
+        """Bias-gradient share: dy summed over every axis but the channel axis, mod t."""
+        _need(dy, "dy")
+        if tuple(dy.shape) != tuple(_y_shape(layer)):
+            raise ValueError("bias_grad: dy has the wrong shape")
+        out = torch.empty(_get(layer, "c_out"), dtype=torch.int64, device=self.device)
+        self._check(self.lib.pencil_bias_grad(self.h, ctypes.byref(layer_struct(layer)), _ptr(dy), _ptr(out),
+                                              _stream()))
+        return out
+
+    def dp_noise_(self, x, sd, nonce, obj):
+        """In place: x + floor(sd * z) mod t with z standard normal draws of the stream (nonce, obj)."""
+        _need(x, "x")
+        self._check(self.lib.pencil_dp_noise(self.h, x.numel(), float(sd), int(nonce) & ((1 << 64) - 1),
+                                             int(obj) & ((1 << 64) - 1), _ptr(x), _stream()))
+        return x
+
     def ntt(self, polys, inverse=False):
         """In-place negacyclic NTT of an int64 tensor [count][L][N] of residues."""
         count = polys.numel() // (self.L * self.n)

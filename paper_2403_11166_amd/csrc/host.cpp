@@ -991,6 +991,34 @@ extern "C" pencil_status pencil_zt_combine(pencil_ctx* ctx, int64_t count, int n
   return PENCIL_OK;
 }
 
+extern "C" pencil_status pencil_bias_grad(pencil_ctx* ctx, const pencil_layer* L, const int64_t* dy, int64_t* db,
+                                          void* stream) {
+  if (!ctx) return PENCIL_EINVAL;
+  TRY(check_ptr(ctx, dy, "dy"));
+  TRY(check_ptr(ctx, db, "db"));
+  pencil_status st = PENCIL_OK;
+  if (!layer_ok(ctx, L, &st)) return st;
+  const int64_t ho = L->h + 2 * L->pad - L->k + 1, wo = L->w + 2 * L->pad - L->k + 1;
+  const int64_t spatial = ho * wo;
+  if ((int64_t)L->batch * spatial > ((int64_t)1 << 22))
+    return fail(ctx, PENCIL_EUNSUPPORTED, "bias gradient sums at most 2^22 entries per channel");
+  hipError_t e = launch_bias_grad(dy, db, L->batch, L->c_out, (int)spatial, ctx->C, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(ctx, PENCIL_EHIP, "bias_grad launch: %s", hipGetErrorString(e));
+  return PENCIL_OK;
+}
+
+extern "C" pencil_status pencil_dp_noise(pencil_ctx* ctx, int64_t count, double sd, uint64_t nonce, uint64_t object,
+                                         int64_t* x, void* stream) {
+  if (!ctx) return PENCIL_EINVAL;
+  if (count < 0) return fail(ctx, PENCIL_EINVAL, "negative count");
+  if (!(sd >= 0.0 && sd <= 4503599627370496.0)) return fail(ctx, PENCIL_EINVAL, "sd must lie in [0, 2^52]");
+  if (count == 0) return PENCIL_OK;
+  TRY(check_ptr(ctx, x, "x"));
+  hipError_t e = launch_dp_noise(x, count, sd, nonce, object, ctx->C, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(ctx, PENCIL_EHIP, "dp_noise launch: %s", hipGetErrorString(e));
+  return PENCIL_OK;
+}
+
 // ------------------------------------------------------------ batched step
 
 struct pencil_step {

@@ -1344,6 +1344,153 @@ __global__ void __launch_bounds__(256) k_zt_combine(ZtTerms T, const int64_t* ba
   gview(out)[g] = (int64_t)v;
 }
 
+// ------------------------------------------ bias gradient and DP noise
+
+// Bias gradient share (Sec. III.B.2): the sum of a dY share over the batch
+// and, for a convolution, over the output positions, mod t.  dy is
+// [batch][channels][spatial].  Entries are below t < 2^42 and at most 2^22 are
+// summed, so a 64-bit total is exact until the final reduction.
+__global__ void __launch_bounds__(256) k_bias_grad_cols(const int64_t* __restrict__ dy, int64_t* __restrict__ db,
+                                                        int batch, int channels, Consts C) {
+  const int o = blockIdx.x * 256 + threadIdx.x;
+  if (o >= channels) return;
+  const PENCIL_GLOBAL int64_t* p = gview(dy) + o;
+  uint64_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+  int b = 0;
+  for (; b + 4 <= batch; b += 4) {
+    a0 += (uint64_t)p[(int64_t)b * channels];
+    a1 += (uint64_t)p[(int64_t)(b + 1) * channels];
+    a2 += (uint64_t)p[(int64_t)(b + 2) * channels];
+    a3 += (uint64_t)p[(int64_t)(b + 3) * channels];
+  }
+  for (; b < batch; ++b) a0 += (uint64_t)p[(int64_t)b * channels];
+  gview(db)[o] = (int64_t)reduce64(a0 + a1 + a2 + a3, C.one_sh_t, C.t);
+}
+
+__global__ void __launch_bounds__(256) k_bias_grad_chan(const int64_t* __restrict__ dy, int64_t* __restrict__ db,
+                                                        int batch, int channels, int spatial, Consts C) {
+  __shared__ uint64_t part[256];
+  const int o = blockIdx.x;
+  const uint32_t total = (uint32_t)batch * (uint32_t)spatial;
+  const PENCIL_GLOBAL int64_t* base = gview(dy) + (int64_t)o * spatial;
+  const int64_t bstride = (int64_t)channels * spatial;
+  uint64_t acc = 0;
+  for (uint32_t i = threadIdx.x; i < total; i += 256) {
+    const uint32_t b = i / (uint32_t)spatial, x = i - b * (uint32_t)spatial;
+    acc += (uint64_t)base[(int64_t)b * bstride + x];
+  }
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) gview(db)[o] = (int64_t)reduce64(part[0], C.one_sh_t, C.t);
+}
+
+// Gaussian perturbation the data owner adds to its weight-gradient and
+// bias-gradient shares (Sec. III.B.2, DPSGD).  Box-Muller from Philox words,
+// every step one IEEE double operation in a fixed order (contraction off), so
+// the draws do not depend on the compiler's scheduling:
+//   ln u, u = k 2^-53: u = m 2^e with m in [1/sqrt 2, sqrt 2), s = (m-1)/(m+1),
+//     ln m = 2 s sum_{j<12} s^2j / (2j+1) (atanh series), ln u = e ln 2 + ln m;
+//   cos, sin of 2 pi b 2^-53: quadrant q = round(b / 2^51), theta = (b - q 2^51)
+//     2^-53 2 pi in [-pi/4, pi/4], Taylor series through theta^23, rotated by q.
+struct DpCoeffs {
+  double lg[12], cc[12], cs[12];
+};
+
+constexpr DpCoeffs make_dp_coeffs() {
+  DpCoeffs c{};
+  for (int j = 0; j < 12; ++j) c.lg[j] = 1.0 / (double)(2 * j + 1);
+  c.cc[0] = 1.0;
+  c.cs[0] = 1.0;
+  for (int j = 1; j < 12; ++j) {
+    c.cc[j] = c.cc[j - 1] / -(double)((2 * j - 1) * (2 * j));
+    c.cs[j] = c.cs[j - 1] / -(double)((2 * j) * (2 * j + 1));
+  }
+  return c;
+}
+
+__device__ __forceinline__ double dp_pow2(int e) {  // 2^e for -1022 <= e <= 1023
+  return __longlong_as_double((long long)((uint64_t)(1023 + e) << 52));
+}
+
+__device__ double dp_log_u(uint64_t k) {  // ln(k 2^-53), 1 <= k <= 2^53
+#pragma clang fp contract(off)
+  constexpr DpCoeffs K = make_dp_coeffs();
+  constexpr double kSqrtHalf = 0.7071067811865476, kLn2 = 0.6931471805599453;
+  const int bl = 64 - __clzll((long long)k);
+  double m = (double)k * dp_pow2(-bl);
+  int e = bl - 53;
+  if (m < kSqrtHalf) {
+    m = m * 2.0;
+    e -= 1;
+  }
+  const double s = (m - 1.0) / (m + 1.0);
+  const double s2 = s * s;
+  double p = K.lg[11];
+#pragma unroll
+  for (int j = 10; j >= 0; --j) p = p * s2 + K.lg[j];
+  const double lnm = (s * p) * 2.0;
+  return (double)e * kLn2 + lnm;
+}
+
+__device__ void dp_cos_sin_turns(uint64_t b, double& co, double& si) {  // of 2 pi b 2^-53, b < 2^53
+#pragma clang fp contract(off)
+  constexpr DpCoeffs K = make_dp_coeffs();
+  constexpr double kTwoPi = 6.283185307179586;
+  const int64_t bb = (int64_t)b;
+  const int64_t q = (bb + (1ll << 50)) >> 51;
+  const int64_t d = bb - (q << 51);
+  const double theta = ((double)d * dp_pow2(-53)) * kTwoPi;
+  const double t2 = theta * theta;
+  double pc = K.cc[11], ps = K.cs[11];
+#pragma unroll
+  for (int j = 10; j >= 0; --j) {
+    pc = pc * t2 + K.cc[j];
+    ps = ps * t2 + K.cs[j];
+  }
+  const double c = pc, s = theta * ps;
+  switch (q & 3) {
+    case 0: co = c; si = s; break;
+    case 1: co = -s; si = c; break;
+    case 2: co = -c; si = -s; break;
+    default: co = s; si = -c; break;
+  }
+}
+
+__device__ __forceinline__ int64_t dp_add(int64_t x, double z, double sd, uint64_t t) {
+#pragma clang fp contract(off)
+  const int64_t e = (int64_t)floor(z * sd);
+  int64_t em = e % (int64_t)t;
+  if (em < 0) em += (int64_t)t;
+  return (int64_t)add_mod((uint64_t)x, (uint64_t)em, t);
+}
+
+// One thread per Philox block: entries 4j .. 4j+3 from words (w0, w1), (w2, w3).
+__global__ void __launch_bounds__(256) k_dp_noise(int64_t* __restrict__ x, int64_t count, double sd, uint64_t nonce,
+                                                  uint64_t obj, Consts C) {
+#pragma clang fp contract(off)
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t i0 = 4 * j;
+  if (i0 >= count) return;
+  const U64x4 w = philox((uint64_t)j, obj, P_DP, 0, C.seed, nonce);
+  double z[4];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const double r = sqrt(dp_log_u((w.v[2 * h] >> 11) + 1) * -2.0);
+    double co, si;
+    dp_cos_sin_turns(w.v[2 * h + 1] >> 11, co, si);
+    z[2 * h] = r * co;
+    z[2 * h + 1] = r * si;
+  }
+  PENCIL_GLOBAL int64_t* px = gview(x) + i0;
+#pragma unroll
+  for (int h = 0; h < 4; ++h)
+    if (i0 + h < count) px[h] = dp_add(px[h], z[h], sd, C.t);
+}
+
 // --------------------------------------------------------- batched step
 
 __device__ __forceinline__ int find_seg(const StepSeg* segs, int nseg, int64_t b) {
@@ -1541,6 +1688,27 @@ hipError_t launch_zt_combine(const ZtTerms& T, const int64_t* base, int64_t* out
                              hipStream_t s) {
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_zt_combine, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, T, base, out, count, C);
+  return hipGetLastError();
+}
+
+hipError_t launch_bias_grad(const int64_t* dy, int64_t* db, int batch, int channels, int spatial, const Consts& C,
+                            hipStream_t s) {
+  if (channels <= 0) return hipSuccess;
+  if (spatial == 1)
+    hipLaunchKernelGGL(k_bias_grad_cols, dim3((unsigned)((channels + 255) / 256)), dim3(256), 0, s, dy, db, batch,
+                       channels, C);
+  else
+    hipLaunchKernelGGL(k_bias_grad_chan, dim3((unsigned)channels), dim3(256), 0, s, dy, db, batch, channels, spatial,
+                       C);
+  return hipGetLastError();
+}
+
+hipError_t launch_dp_noise(int64_t* x, int64_t count, double sd, uint64_t nonce, uint64_t obj, const Consts& C,
+                           hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  const int64_t threads = (count + 3) / 4;
+  hipLaunchKernelGGL(k_dp_noise, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, x, count, sd, nonce, obj,
+                     C);
   return hipGetLastError();
 }
 

@@ -75,6 +75,7 @@ enum Purpose : uint32_t {
   P_SK = 1, P_PK_A = 2, P_PK_E = 3,
   P_ENC_U = 16, P_ENC_E0 = 17, P_ENC_E1 = 18,
   P_RR_U = 32, P_RR_E0 = 33, P_RR_E1 = 34, P_FLOOD = 35, P_MASK = 36,
+  P_DP = 48,
 };
 constexpr uint64_t kKeygenNonce = ~0ull;
 
@@ -176,6 +177,10 @@ struct ZtTerms {
 };
 hipError_t launch_zt_combine(const ZtTerms& T, const int64_t* base, int64_t* out, int64_t count, const Consts& C,
                              hipStream_t s);
+hipError_t launch_bias_grad(const int64_t* dy, int64_t* db, int batch, int channels, int spatial, const Consts& C,
+                            hipStream_t s);
+hipError_t launch_dp_noise(int64_t* x, int64_t count, double sd, uint64_t nonce, uint64_t obj, const Consts& C,
+                           hipStream_t s);
 hipError_t launch_zt_corr(const int64_t* a, const int64_t* k, int64_t* out, const Geo& G, const View& AV,
                           const View& KV, const View& OV, const Consts& C, hipStream_t s);
 hipError_t launch_step_ntt(int log2n, int loge, bool inverse, const StepPhase& P, int64_t blocks, hipStream_t s);
