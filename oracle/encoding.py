@@ -87,27 +87,35 @@ class Tile:
 
 
 def _as4(a):
+    """4-d view: FC tensors (n0, n1) -> (n0, n1, 1, 1); conv1d tensors
+    (n0, n1, len) -> (n0, n1, 1, len)."""
     a = np.asarray(a)
+    if a.ndim == 3:
+        return a.reshape(a.shape[0], a.shape[1], 1, a.shape[2])
     return a.reshape(a.shape + (1,) * (4 - a.ndim)) if a.ndim < 4 else a
 
 
-def _pad(a, p):
-    if p == 0:
+def _pad(a, ph, pw):
+    if ph == 0 and pw == 0:
         return a
-    return np.pad(a, ((0, 0), (0, 0), (p, p), (p, p)))
+    return np.pad(a, ((0, 0), (0, 0), (ph, ph), (pw, pw)))
 
 
 def geometry(layer, op):
-    B, ci, co, h, w, s, p = layer.batch, layer.c_in, layer.c_out, layer.h, layer.w, layer.k, layer.pad
+    """Packed-correlation dimensions of op.  Stride 1 only: a strided layer is
+    encoded through its space-to-depth equivalent."""
+    assert getattr(layer, "stride", 1) == 1, "strided layers have no direct packed encoding"
+    B, ci, co, h, w = layer.batch, layer.c_in, layer.c_out, layer.h, layer.w
+    kh, kw, ph, pw = layer.kh, layer.kw, layer.pad_h, layer.pad_w
     ho, wo = layer.h_out, layer.w_out
     if op == "fwd":
-        return Geometry(B, co, ci, h + 2 * p, w + 2 * p, s, s)
+        return Geometry(B, co, ci, h + 2 * ph, w + 2 * pw, kh, kw)
     if op == "dx":
-        q = s - 1 - p
-        assert q >= 0, "padding larger than kernel-1 is not covered"
-        return Geometry(B, ci, co, ho + 2 * q, wo + 2 * q, s, s)
+        qh, qw = kh - 1 - ph, kw - 1 - pw
+        assert qh >= 0 and qw >= 0, "padding larger than kernel-1 is not covered"
+        return Geometry(B, ci, co, ho + 2 * qh, wo + 2 * qw, kh, kw)
     if op == "dw":
-        return Geometry(ci, co, B, h + 2 * p, w + 2 * p, ho, wo)
+        return Geometry(ci, co, B, h + 2 * ph, w + 2 * pw, ho, wo)
     raise ValueError(op)
 
 
@@ -115,11 +123,11 @@ def virtual_a(layer, op, t):
     """The A operand (M, K, HA, WA) of op from tensor t (x for fwd/dw, dy for dx)."""
     t4 = _as4(t)
     if op == "fwd":
-        return _pad(t4, layer.pad)
+        return _pad(t4, layer.pad_h, layer.pad_w)
     if op == "dx":
-        return _pad(t4, layer.k - 1 - layer.pad)
+        return _pad(t4, layer.kh - 1 - layer.pad_h, layer.kw - 1 - layer.pad_w)
     if op == "dw":
-        return _pad(t4, layer.pad).transpose(1, 0, 2, 3)
+        return _pad(t4, layer.pad_h, layer.pad_w).transpose(1, 0, 2, 3)
     raise ValueError(op)
 
 

@@ -2,9 +2,11 @@
 operators (Sec. III.A), by their textbook definitions.
 
   FC:     Y = X W^T,  dX = dY W,  dW = dY^T X              (PyTorch layout)
-  Conv2d: Y[b,o,y,x] = sum_{c,i,j} Xpad[b,c,y+i,x+j] W[o,c,i,j]   (stride 1)
+  Conv2d: Y[b,o,y,x] = sum_{c,i,j} Xpad[b,c,s*y+i,s*x+j] W[o,c,i,j]   (stride s)
           dX = the adjoint of X -> Y (scatter of dY through W, padding cropped)
-          dW[o,c,i,j] = sum_{b,y,x} dY[b,o,y,x] Xpad[b,c,y+i,x+j]
+          dW[o,c,i,j] = sum_{b,y,x} dY[b,o,y,x] Xpad[b,c,s*y+i,s*x+j]
+  Conv1d: the Conv2d case with one row, a 1 x k kernel and padding along the
+          length only (tensors (batch, channels, length))
 
 All arithmetic is exact modulo t.  Integer tensor contractions are done as
 float64 tensordots of 14-bit digits (every partial sum stays below 2^53, so
@@ -63,43 +65,62 @@ def tensordot_mod_t_object(a, b, axes, t):
     return np.vectorize(lambda v: int(v) % t, otypes=[np.int64])(r) if np.ndim(r) else np.int64(int(r) % t)
 
 
-def _pad(x, p):
-    return x if p == 0 else np.pad(x, ((0, 0), (0, 0), (p, p), (p, p)))
+def _pad(x, ph, pw):
+    return x if ph == 0 and pw == 0 else np.pad(x, ((0, 0), (0, 0), (ph, ph), (pw, pw)))
 
 
-def conv2d(x, W, pad, t, tdot=tensordot_mod_t):
+def _taps(i, n, s):
+    """Rows i, i + s, ..., i + (n - 1) s of a padded input."""
+    return slice(i, i + s * (n - 1) + 1, s)
+
+
+def conv2d(x, W, ph, pw, s, t, tdot=tensordot_mod_t):
+    """Y[b,o,y,x] = sum_{c,i,j} Xpad[b, c, s y + i, s x + j] W[o, c, i, j]."""
     B, ci, h, w = x.shape
-    co, _, s, _ = W.shape
-    xp = _pad(x, pad)
-    ho, wo = h + 2 * pad - s + 1, w + 2 * pad - s + 1
+    co, _, kh, kw = W.shape
+    xp = _pad(x, ph, pw)
+    ho, wo = (h + 2 * ph - kh) // s + 1, (w + 2 * pw - kw) // s + 1
     y = np.zeros((B, co, ho, wo), dtype=np.int64)
-    for i in range(s):
-        for j in range(s):
-            part = tdot(xp[:, :, i:i + ho, j:j + wo], W[:, :, i, j], ([1], [1]), t)  # (B, ho, wo, co)
+    for i in range(kh):
+        for j in range(kw):
+            part = tdot(xp[:, :, _taps(i, ho, s), _taps(j, wo, s)], W[:, :, i, j], ([1], [1]), t)  # (B, ho, wo, co)
             y = np.mod(y + part.transpose(0, 3, 1, 2), t)
     return y
 
 
-def conv2d_dx(dy, W, pad, h, w, t, tdot=tensordot_mod_t):
+def conv2d_dx(dy, W, ph, pw, s, h, w, t, tdot=tensordot_mod_t):
+    """The adjoint of X -> Y: every dY[b,o,y,x] W[o,c,i,j] lands on Xpad[b,c,s y+i,s x+j]; padding cropped."""
     B, co, ho, wo = dy.shape
-    _, ci, s, _ = W.shape
-    dxp = np.zeros((B, ci, h + 2 * pad, w + 2 * pad), dtype=np.int64)
-    for i in range(s):
-        for j in range(s):
-            part = tdot(dy, W[:, :, i, j], ([1], [0]), t)  # (B, ho, wo, ci)
-            dxp[:, :, i:i + ho, j:j + wo] = np.mod(dxp[:, :, i:i + ho, j:j + wo] + part.transpose(0, 3, 1, 2), t)
-    return dxp[:, :, pad:pad + h, pad:pad + w]
+    _, ci, kh, kw = W.shape
+    dxp = np.zeros((B, ci, h + 2 * ph, w + 2 * pw), dtype=np.int64)
+    for i in range(kh):
+        for j in range(kw):
+            part = tdot(dy, W[:, :, i, j], ([1], [0]), t).transpose(0, 3, 1, 2)  # (B, ci, ho, wo)
+            sl = (slice(None), slice(None), _taps(i, ho, s), _taps(j, wo, s))
+            dxp[sl] = np.mod(dxp[sl] + part, t)
+    return dxp[:, :, ph:ph + h, pw:pw + w]
 
 
-def conv2d_dw(x, dy, pad, s, t, tdot=tensordot_mod_t):
-    B, ci, h, w = x.shape
-    _, co, ho, wo = dy.shape
-    xp = _pad(x, pad)
-    dW = np.zeros((co, ci, s, s), dtype=np.int64)
-    for i in range(s):
-        for j in range(s):
-            dW[:, :, i, j] = tdot(dy, xp[:, :, i:i + ho, j:j + wo], ([0, 2, 3], [0, 2, 3]), t)
+def conv2d_dw(x, dy, ph, pw, s, kh, kw, t, tdot=tensordot_mod_t):
+    """dW[o,c,i,j] = sum_{b,y,x} dY[b,o,y,x] Xpad[b, c, s y + i, s x + j]."""
+    _, _, ho, wo = dy.shape
+    xp = _pad(x, ph, pw)
+    ci, co = x.shape[1], dy.shape[1]
+    dW = np.zeros((co, ci, kh, kw), dtype=np.int64)
+    for i in range(kh):
+        for j in range(kw):
+            dW[:, :, i, j] = tdot(dy, xp[:, :, _taps(i, ho, s), _taps(j, wo, s)], ([0, 2, 3], [0, 2, 3]), t)
     return dW
+
+
+def _as4d(layer, v):
+    """A conv1d tensor (n0, n1, len) viewed as (n0, n1, 1, len); others unchanged."""
+    v = np.asarray(v)
+    return v.reshape(v.shape[0], v.shape[1], 1, v.shape[2]) if layer.kind == "conv1d" else v
+
+
+def _from4d(layer, v):
+    return v.reshape(v.shape[0], v.shape[1], v.shape[3]) if layer.kind == "conv1d" else v
 
 
 def layer_op(layer, op, a, b, t, tdot=tensordot_mod_t):
@@ -115,12 +136,13 @@ def layer_op(layer, op, a, b, t, tdot=tensordot_mod_t):
         if op == "dw":
             return tdot(b, a, ([0], [0]), t)
         raise ValueError(op)
+    ph, pw, s = layer.pad_h, layer.pad_w, layer.stride
     if op == "fwd":
-        return conv2d(a, b, layer.pad, t, tdot)
+        return _from4d(layer, conv2d(_as4d(layer, a), _as4d(layer, b), ph, pw, s, t, tdot))
     if op == "dx":
-        return conv2d_dx(a, b, layer.pad, layer.h, layer.w, t, tdot)
+        return _from4d(layer, conv2d_dx(_as4d(layer, a), _as4d(layer, b), ph, pw, s, layer.h, layer.w, t, tdot))
     if op == "dw":
-        return conv2d_dw(a, b, layer.pad, layer.k, t, tdot)
+        return _from4d(layer, conv2d_dw(_as4d(layer, a), _as4d(layer, b), ph, pw, s, layer.kh, layer.kw, t, tdot))
     raise ValueError(op)
 
 
@@ -140,35 +162,43 @@ def layer_op_at(layer, op, a, b, t, points):
                 v = sum(int(x) * int(g) for x, g in zip(a[:, p[1]], b[:, p[0]]))
             out.append(v % t)
         return out
-    k, pad = layer.k, layer.pad
+    kh, kw, ph, pw, st = layer.kh, layer.kw, layer.pad_h, layer.pad_w, layer.stride
     h, w = layer.h, layer.w
     ho, wo = layer.h_out, layer.w_out
+    a4, b4 = _as4d(layer, a), _as4d(layer, b)
 
     def x_at(x, bb, c, y, xx):
-        y, xx = y - pad, xx - pad
+        y, xx = y - ph, xx - pw
         return int(x[bb, c, y, xx]) if 0 <= y < h and 0 <= xx < w else 0
+
+    def at4(p):
+        # conv1d points (n0, n1, pos) address row 0 of the 4-d view
+        return (p[0], p[1], 0, p[2]) if layer.kind == "conv1d" else tuple(p)
 
     for p in points:
         v = 0
-        if op == "fwd":          # Y[b, o, y, x] = sum_{c,i,j} Xpad[b, c, y+i, x+j] W[o, c, i, j]
-            bb, o, y, xx = p
+        if op == "fwd":          # Y[b, o, y, x] = sum_{c,i,j} Xpad[b, c, s y + i, s x + j] W[o, c, i, j]
+            bb, o, y, xx = at4(p)
             for c in range(layer.c_in):
-                for i in range(k):
-                    for j in range(k):
-                        v += x_at(a, bb, c, y + i, xx + j) * int(b[o, c, i, j])
-        elif op == "dx":         # dX[b, c, y, x] = sum_{o,i,j} dY[b, o, y+p-i, x+p-j] W[o, c, i, j]
-            bb, c, y, xx = p
+                for i in range(kh):
+                    for j in range(kw):
+                        v += x_at(a4, bb, c, st * y + i, st * xx + j) * int(b4[o, c, i, j])
+        elif op == "dx":         # dX[b, c, y, x] = sum over (o, i, j, y', x') with s y' + i = y + p, s x' + j = x + p
+            bb, c, y, xx = at4(p)
             for o in range(layer.c_out):
-                for i in range(k):
-                    for j in range(k):
-                        yy, xj = y + pad - i, xx + pad - j
+                for i in range(kh):
+                    for j in range(kw):
+                        ny, nx = y + ph - i, xx + pw - j
+                        if ny % st or nx % st:
+                            continue
+                        yy, xj = ny // st, nx // st
                         if 0 <= yy < ho and 0 <= xj < wo:
-                            v += int(a[bb, o, yy, xj]) * int(b[o, c, i, j])
-        else:                    # dW[o, c, i, j] = sum_{b,y,x} dY[b, o, y, x] Xpad[b, c, y+i, x+j]
-            o, c, i, j = p
+                            v += int(a4[bb, o, yy, xj]) * int(b4[o, c, i, j])
+        else:                    # dW[o, c, i, j] = sum_{b,y,x} dY[b, o, y, x] Xpad[b, c, s y + i, s x + j]
+            o, c, i, j = at4(p)
             for bb in range(layer.batch):
                 for y in range(ho):
                     for xx in range(wo):
-                        v += int(b[bb, o, y, xx]) * x_at(a, bb, c, y + i, xx + j)
+                        v += int(b4[bb, o, y, xx]) * x_at(a4, bb, c, st * y + i, st * xx + j)
         out.append(v % t)
     return out

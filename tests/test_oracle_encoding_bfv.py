@@ -13,7 +13,7 @@ from oracle import linear as LN
 from oracle import params as PR
 from oracle import protocol as PRT
 from oracle import ring as RG
-from workloads import conv, fc, layer_tensors, CONFIGS, config_tensors
+from workloads import conv, conv1d, fc, layer_tensors, CONFIGS, config_tensors
 
 T = PR.T
 
@@ -108,6 +108,10 @@ ENC_CASES = [
     (conv(2, 2, 3, 5, k=3, pad=1), "dw", E.Tile(1, 2, 2, 3, 3, 2, 4), 128),
     (conv(1, 3, 2, 6, k=3, pad=1), "dw", E.Tile(3, 2, 1, 3, 3, 6, 6), 512),
     (conv(2, 1, 1, 5, k=3, pad=2), "fwd", E.Tile(2, 1, 1, 4, 7, 3, 3), 128),
+    # Conv1d: one row, 1 x k kernel, padding along the length only
+    (conv1d(2, 3, 2, 9, k=5, pad=0), "fwd", E.Tile(2, 2, 3, 1, 5, 1, 5), 128),
+    (conv1d(2, 3, 2, 9, k=5, pad=2), "dx", E.Tile(1, 3, 2, 1, 4, 1, 3), 64),
+    (conv1d(3, 2, 2, 8, k=3, pad=1), "dw", E.Tile(2, 2, 2, 1, 2, 1, 5), 64),
 ]
 
 
@@ -304,7 +308,7 @@ def test_sampled_helpers_match_full_versions():
     ct = bfv.encrypt(P, k["pk"], m, 13, 2, 7)
     assert (bfv.encrypt_at(P, k["pk"], m, 13, 2, 7, idx) == ct[:, :, idx]).all()
     assert list(bfv.decrypt_at(P, k["sk"], ct, idx)) == list(bfv.decrypt(P, k["sk"], ct)[idx])
-    for layer in (conv(2, 3, 2, 5, k=3, pad=1), fc(3, 6, 4)):
+    for layer in (conv(2, 3, 2, 5, k=3, pad=1), fc(3, 6, 4), conv1d(2, 3, 2, 7, k=3, pad=1)):
         X = rng.integers(0, T, layer.x_shape())
         W = rng.integers(0, T, layer.w_shape())
         dY = rng.integers(0, T, layer.y_shape())

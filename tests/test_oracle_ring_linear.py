@@ -6,7 +6,7 @@ import torch
 from oracle import linear as LN
 from oracle import params as PR
 from oracle import ring as RG
-from workloads import conv, fc
+from workloads import conv, conv1d, fc
 
 Q60 = PR.ntt_primes(60, 1)[0]
 
@@ -86,7 +86,9 @@ def test_tensordot_digits_match_python_ints():
 
 
 @pytest.mark.parametrize("layer", [conv(2, 3, 4, 6, k=3, pad=1), conv(3, 2, 5, 7, k=2, pad=0),
-                                   conv(1, 4, 2, 5, k=3, pad=2)])
+                                   conv(1, 4, 2, 5, k=3, pad=2),
+                                   conv(2, 1, 5, 12, k=5, pad=2, stride=2), conv(2, 3, 2, 9, k=3, pad=1, stride=2),
+                                   conv(1, 2, 3, 11, k=4, pad=1, stride=3), conv(2, 2, 2, 8, k=3, pad=0, stride=2)])
 def test_conv_matches_torch_autograd(layer):
     """Forward, input gradient and weight gradient vs torch float64 autograd on small integers."""
     rng = np.random.default_rng(1)
@@ -95,7 +97,7 @@ def test_conv_matches_torch_autograd(layer):
     dY, dYs = _small_ints(rng, layer.y_shape())
     xt = torch.tensor(Xs, dtype=torch.float64, requires_grad=True)
     wt = torch.tensor(Ws, dtype=torch.float64, requires_grad=True)
-    yt = torch.nn.functional.conv2d(xt, wt, padding=layer.pad)
+    yt = torch.nn.functional.conv2d(xt, wt, padding=layer.pad, stride=layer.stride)
     yt.backward(torch.tensor(dYs, dtype=torch.float64))
     to_t = lambda v: np.mod(np.rint(v.detach().numpy()).astype(np.int64), T)  # noqa: E731
     if layer.pad <= layer.k - 1:
@@ -145,3 +147,39 @@ def test_finite_difference_exact():
     dY = rng.integers(0, T, layer.y_shape())
     lhs = int(np.sum(dY.astype(object) * diff.astype(object))) % T
     assert lhs == int(LN.layer_op(layer, "dx", dY, W, T)[1, 0, 2, 3])
+
+
+@pytest.mark.parametrize("layer", [conv1d(2, 6, 4, 11, k=5), conv1d(3, 4, 5, 9, k=3, pad=1),
+                                   conv1d(2, 3, 2, 14, k=5, pad=2, stride=2), conv1d(1, 2, 3, 5, k=5)])
+def test_conv1d_matches_torch_autograd(layer):
+    """Conv1d (the one-row specialisation of Conv2d) vs torch's conv1d."""
+    rng = np.random.default_rng(5)
+    X, Xs = _small_ints(rng, layer.x_shape())
+    W, Ws = _small_ints(rng, layer.w_shape())
+    dY, dYs = _small_ints(rng, layer.y_shape())
+    xt = torch.tensor(Xs, dtype=torch.float64, requires_grad=True)
+    wt = torch.tensor(Ws, dtype=torch.float64, requires_grad=True)
+    yt = torch.nn.functional.conv1d(xt, wt, padding=layer.pad, stride=layer.stride)
+    yt.backward(torch.tensor(dYs, dtype=torch.float64))
+    to_t = lambda v: np.mod(np.rint(v.detach().numpy()).astype(np.int64), T)  # noqa: E731
+    assert (LN.layer_op(layer, "fwd", X, W, T) == to_t(yt)).all()
+    assert (LN.layer_op(layer, "dx", dY, W, T) == to_t(xt.grad)).all()
+    assert (LN.layer_op(layer, "dw", X, dY, T) == to_t(wt.grad)).all()
+
+
+@pytest.mark.parametrize("layer", [conv(2, 2, 3, 9, k=5, pad=2, stride=2), conv1d(2, 3, 2, 13, k=5, pad=1, stride=2),
+                                   conv1d(2, 3, 4, 8, k=3)])
+def test_strided_and_1d_adjoints_and_pointwise(layer):
+    """Adjoint identities with full-size values, and the pointwise sums of
+    layer_op_at against the whole-tensor operators."""
+    rng = np.random.default_rng(6)
+    X = rng.integers(0, T, layer.x_shape())
+    W = rng.integers(0, T, layer.w_shape())
+    dY = rng.integers(0, T, layer.y_shape())
+    ip = lambda a, b: int(np.sum(a.astype(object) * b.astype(object))) % T  # noqa: E731
+    Y = LN.layer_op(layer, "fwd", X, W, T)
+    assert ip(dY, Y) == ip(LN.layer_op(layer, "dx", dY, W, T), X) == ip(LN.layer_op(layer, "dw", X, dY, T), W)
+    for op, a, b in (("fwd", X, W), ("dx", dY, W), ("dw", X, dY)):
+        full = LN.layer_op(layer, op, a, b, T)
+        pts = [tuple(int(v) for v in np.unravel_index(i, full.shape)) for i in range(0, full.size, 7)]
+        assert LN.layer_op_at(layer, op, a, b, T, pts) == [int(full[p]) for p in pts]

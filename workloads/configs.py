@@ -12,12 +12,16 @@ from typing import List, Tuple
 
 @dataclass(frozen=True)
 class LayerSpec:
-    """One linear layer.  kind is "fc" or "conv".
+    """One linear layer.  kind is "fc", "conv" (2-d) or "conv1d".
 
     FC layers are stored as conv layers with h = w = k = 1 and pad = 0: the
     matrix encoding of App. A is the 1x1 case of the convolution encoding.
-    Weight layout is PyTorch's: fc (c_out, c_in), conv (c_out, c_in, k, k).
-    Activations are (batch, c_in, h, w); fc activations are (batch, c_in).
+    A Conv1d is the 2-d case with h = 1, a 1 x k kernel and padding along the
+    length only (the paper evaluates Conv1d as such a specialisation).
+    Weight layout is PyTorch's: fc (c_out, c_in), conv (c_out, c_in, k, k),
+    conv1d (c_out, c_in, k).  Activations are (batch, c_in, h, w), fc
+    (batch, c_in), conv1d (batch, c_in, w).  stride applies to both axes of a
+    conv and to the length of a conv1d.
     """
     kind: str
     batch: int
@@ -27,6 +31,7 @@ class LayerSpec:
     w: int = 1
     k: int = 1
     pad: int = 0
+    stride: int = 1
     # value distributions, consumed by workloads.gen
     x_dist: Tuple = ("normal", 1.0)
     w_dist: Tuple = ("normal", 0.1)
@@ -37,26 +42,48 @@ class LayerSpec:
     prime_bits: int = 60
 
     @property
+    def kh(self):
+        return 1 if self.kind == "conv1d" else self.k
+
+    @property
+    def kw(self):
+        return self.k
+
+    @property
+    def pad_h(self):
+        return 0 if self.kind == "conv1d" else self.pad
+
+    @property
+    def pad_w(self):
+        return self.pad
+
+    @property
     def h_out(self):
-        return self.h + 2 * self.pad - self.k + 1
+        return (self.h + 2 * self.pad_h - self.kh) // self.stride + 1
 
     @property
     def w_out(self):
-        return self.w + 2 * self.pad - self.k + 1
+        return (self.w + 2 * self.pad_w - self.kw) // self.stride + 1
 
     def x_shape(self):
         if self.kind == "fc":
             return (self.batch, self.c_in)
+        if self.kind == "conv1d":
+            return (self.batch, self.c_in, self.w)
         return (self.batch, self.c_in, self.h, self.w)
 
     def w_shape(self):
         if self.kind == "fc":
             return (self.c_out, self.c_in)
+        if self.kind == "conv1d":
+            return (self.c_out, self.c_in, self.k)
         return (self.c_out, self.c_in, self.k, self.k)
 
     def y_shape(self):
         if self.kind == "fc":
             return (self.batch, self.c_out)
+        if self.kind == "conv1d":
+            return (self.batch, self.c_out, self.w_out)
         return (self.batch, self.c_out, self.h_out, self.w_out)
 
 
@@ -66,6 +93,10 @@ def fc(batch, c_in, c_out, **kw):
 
 def conv(batch, c_in, c_out, hw, k=3, pad=1, **kw):
     return LayerSpec("conv", batch, c_in, c_out, hw, hw, k, pad, **kw)
+
+
+def conv1d(batch, c_in, c_out, length, k=5, pad=0, **kw):
+    return LayerSpec("conv1d", batch, c_in, c_out, 1, length, k, pad, **kw)
 
 
 def he_std(fan_in):
