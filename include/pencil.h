@@ -74,10 +74,17 @@ typedef struct {
     uint64_t seed;        /* key for every random value                              */
 } pencil_params;
 
-/* One linear layer (Sec. II.D).  kind 0 = FC (h = w = k = 1, pad = 0), 1 = Conv2d
- * with stride 1, square k x k kernel and zero padding pad <= k - 1. */
+/* One linear layer (Sec. II.D).  kind 0 = FC (h = w = k = 1, pad = 0);
+ * 1 = Conv2d with a square k x k kernel and zero padding pad <= k - 1 on every
+ * side; 2 = Conv1d (h = 1, a 1 x k kernel, padding pad at both ends of the
+ * length; App. D evaluates Conv1d as this specialisation of Conv2d).  stride
+ * (0 or 1 = stride 1) applies to both axes of a Conv2d and to the length of a
+ * Conv1d.  The homomorphic entry points take stride-1 layers; a strided layer
+ * runs as its stride-1 equivalent (pencil_stride_map, pencil_stride_relayout).
+ * Tensors use PyTorch layouts: X (batch, c_in, h, w), Y (batch, c_out, h_out,
+ * w_out), W (c_out, c_in, k, k); for FC and Conv1d the unit axes drop out. */
 typedef struct {
-    int32_t kind, batch, c_in, c_out, h, w, k, pad;
+    int32_t kind, batch, c_in, c_out, h, w, k, pad, stride;
 } pencil_layer;
 
 /* Partition of one product into N-slot tiles (App. A: larger operands "could be
@@ -236,6 +243,23 @@ pencil_status pencil_bias_grad(pencil_ctx* ctx, const pencil_layer* layer, const
  * Use a distinct (nonce, object) per tensor.  Enqueued on `stream`. */
 pencil_status pencil_dp_noise(pencil_ctx* ctx, int64_t count, double sd, uint64_t nonce, uint64_t object,
                               int64_t* x, void* stream);
+
+/* Strided layers.  A stride-s correlation equals a stride-1 correlation over
+ * the space-to-depth image (Conv2d: s x s phases; Conv1d: s phases of the
+ * length): channel c * s_y s_x + a s_x + e of X' holds Xpad[c, s_y y + a,
+ * s_x x + e] and the same channel of W' holds W[c, s_y i + a, s_x j + e] (zero
+ * past the kernel).  pencil_stride_map writes that equivalent layer
+ * (c_in s_y s_x channels, ceil(k / s) kernel, pad 0, h_out + k' - 1 by
+ * w_out + k' - 1 inputs; host only, ctx-free).  Both parties relayout their
+ * own shares (the maps are linear), run Alg. 1 / Alg. 2 on the equivalent
+ * layer, and map the gradients back; Y is the same tensor in both.
+ * pencil_stride_relayout: which 0 = X -> X', 1 = W -> W', 2 = dX' -> dX (the
+ * adjoint of 0: padding dropped), 3 = dW' -> dW (taps past the kernel dropped).
+ * in, out: device int64, distinct, shaped as the strided layer's tensor and
+ * its equivalent's.  Enqueued on `stream`. */
+pencil_status pencil_stride_map(const pencil_layer* strided, pencil_layer* equiv /* host */);
+pencil_status pencil_stride_relayout(pencil_ctx* ctx, const pencil_layer* strided, int which, const int64_t* in,
+                                     int64_t* out, void* stream);
 
 /* Autotuner: time the schedule candidates on this GPU -- the NTT's residues per
  * thread (16 or 32, per context) and each product's multiply-accumulate chunk

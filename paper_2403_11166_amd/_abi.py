@@ -25,7 +25,7 @@ class Params(ctypes.Structure):
 
 
 class Layer(ctypes.Structure):
-    _fields_ = [(n, ctypes.c_int32) for n in ("kind", "batch", "c_in", "c_out", "h", "w", "k", "pad")]
+    _fields_ = [(n, ctypes.c_int32) for n in ("kind", "batch", "c_in", "c_out", "h", "w", "k", "pad", "stride")]
 
 
 class Tile(ctypes.Structure):
@@ -93,6 +93,9 @@ SIGNATURES = {
                                         ctypes.c_void_p]),
     "pencil_dp_noise": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64,
                                        ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p]),
+    "pencil_stride_map": (ctypes.c_int, [ctypes.POINTER(Layer), ctypes.POINTER(Layer)]),
+    "pencil_stride_relayout": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Layer), ctypes.c_int, ctypes.c_void_p,
+                                              ctypes.c_void_p, ctypes.c_void_p]),
     "pencil_step_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(Layer),
                                           ctypes.POINTER(Plan), ctypes.c_int, ctypes.c_uint32,
                                           ctypes.POINTER(ctypes.c_void_p)]),

@@ -14,12 +14,26 @@ OPERANDS = {"x_fwd": A.X_FWD, "dy_dx": A.DY_DX, "x_dw": A.X_DW, "dy_dw": A.DY_DW
 OPS = {"fwd": A.OP_FWD, "dx": A.OP_DX, "dw": A.OP_DW}
 
 
+KINDS = {"fc": 0, "conv": 1, "conv1d": 2}
+
+
 def layer_struct(layer):
-    """A pencil_layer from a LayerSpec-like object (kind 'fc' / 'conv') or a dict."""
+    """A pencil_layer from a LayerSpec-like object (kind 'fc' / 'conv' / 'conv1d') or a dict."""
+    if isinstance(layer, A.Layer):
+        return layer
     get = (lambda k: layer[k]) if isinstance(layer, dict) else (lambda k: getattr(layer, k))
-    kind = get("kind")
-    kind = {"fc": 0, "conv": 1}.get(kind, kind)
-    return A.Layer(int(kind), get("batch"), get("c_in"), get("c_out"), get("h"), get("w"), get("k"), get("pad"))
+    kind = KINDS.get(get("kind"), get("kind"))
+    stride = _get(layer, "stride", 1)
+    return A.Layer(int(kind), get("batch"), get("c_in"), get("c_out"), get("h"), get("w"), get("k"), get("pad"),
+                   int(stride))
+
+
+def stride_map(layer):
+    """The stride-1 layer a strided layer runs as (a dict usable wherever a layer is)."""
+    e = A.Layer()
+    A.check(A.load().pencil_stride_map(ctypes.byref(layer_struct(layer)), ctypes.byref(e)))
+    kind = {v: k for k, v in KINDS.items()}[e.kind]
+    return dict(kind=kind, batch=e.batch, c_in=e.c_in, c_out=e.c_out, h=e.h, w=e.w, k=e.k, pad=e.pad, stride=1)
 
 
 def tile_struct(t):
@@ -231,6 +245,21 @@ class Context:
                                              int(obj) & ((1 << 64) - 1), _ptr(x), _stream()))
         return x
 
+    def stride_relayout(self, layer, which, x):
+        """Space-to-depth relayout between a strided layer and its stride-1 equivalent:
+        which 'x' (X -> X'), 'w' (W -> W'), 'dx' (dX' -> dX) or 'dw' (dW' -> dW)."""
+        wi = {"x": 0, "w": 1, "dx": 2, "dw": 3}[which]
+        _need(x, "x")
+        eq = stride_map(layer)
+        shape = (_x_shape(eq), _w_shape(eq), _x_shape(layer), _w_shape(layer))[wi]
+        want_in = (_x_shape(layer), _w_shape(layer), _x_shape(eq), _w_shape(eq))[wi]
+        if tuple(x.shape) != tuple(want_in):
+            raise ValueError(f"stride_relayout: input shape {tuple(x.shape)}, expected {want_in}")
+        out = torch.empty(shape, dtype=torch.int64, device=self.device)
+        self._check(self.lib.pencil_stride_relayout(self.h, ctypes.byref(layer_struct(layer)), wi, _ptr(x),
+                                                    _ptr(out), _stream()))
+        return out
+
     def ntt(self, polys, inverse=False):
         """In-place negacyclic NTT of an int64 tensor [count][L][N] of residues."""
         count = polys.numel() // (self.L * self.n)
@@ -239,17 +268,28 @@ class Context:
         return polys
 
 
-def _get(layer, k):
-    return layer[k] if isinstance(layer, dict) else getattr(layer, k)
+def _get(layer, k, default=None):
+    if isinstance(layer, dict):
+        return layer.get(k, default) if default is not None else layer[k]
+    return getattr(layer, k, default) if default is not None else getattr(layer, k)
+
+
+def _kind(layer):
+    k = _get(layer, "kind")
+    return {v: n for n, v in KINDS.items()}.get(k, k)
 
 
 def _is_fc(layer):
-    return _get(layer, "kind") in ("fc", 0)
+    return _kind(layer) == "fc"
 
 
 def _x_shape(layer):
     B, ci = _get(layer, "batch"), _get(layer, "c_in")
-    return (B, ci) if _is_fc(layer) else (B, ci, _get(layer, "h"), _get(layer, "w"))
+    if _is_fc(layer):
+        return (B, ci)
+    if _kind(layer) == "conv1d":
+        return (B, ci, _get(layer, "w"))
+    return (B, ci, _get(layer, "h"), _get(layer, "w"))
 
 
 def _y_shape(layer):
@@ -257,12 +297,20 @@ def _y_shape(layer):
     if _is_fc(layer):
         return (B, co)
     h, w, k, p = _get(layer, "h"), _get(layer, "w"), _get(layer, "k"), _get(layer, "pad")
-    return (B, co, h + 2 * p - k + 1, w + 2 * p - k + 1)
+    s = max(1, int(_get(layer, "stride", 1)))
+    wo = (w + 2 * p - k) // s + 1
+    if _kind(layer) == "conv1d":
+        return (B, co, wo)
+    return (B, co, (h + 2 * p - k) // s + 1, wo)
 
 
 def _w_shape(layer):
-    ci, co = _get(layer, "c_in"), _get(layer, "c_out")
-    return (co, ci) if _is_fc(layer) else (co, ci, _get(layer, "k"), _get(layer, "k"))
+    ci, co, k = _get(layer, "c_in"), _get(layer, "c_out"), _get(layer, "k")
+    if _is_fc(layer):
+        return (co, ci)
+    if _kind(layer) == "conv1d":
+        return (co, ci, k)
+    return (co, ci, k, k)
 
 
 class Step:

@@ -6,7 +6,8 @@ owner's share is encrypted, the model owner's product adds its share and
 multiplies by W, and the decrypted share plus the model owner's mask
 reconstruct Y = W o X.  Backward: the gradient with respect to X by the same
 pattern with the transposed operator (Sec. III.B.2), and the weight gradient
-as the two encrypted cross terms of Alg. 2 plus the two parties' local terms.
+as the two encrypted cross terms of Alg. 2 plus the two parties' local terms,
+the bias gradient, and optionally the data owner's DP perturbation.
 
 Tensors carry fixed-point integers in float64 (autograd rejects integer
 dtypes; t < 2^53 keeps them exact) in centred form, (-t/2, t/2).  Every Z_t
@@ -15,7 +16,7 @@ draws the share and nonce randomness.
 """
 import torch
 
-from .api import Context
+from .api import Context, _get, stride_map
 
 
 def _to_zt(x, t):
@@ -28,15 +29,24 @@ def _centred(v, t):
 
 
 class EncryptedLinearEngine:
-    """Context, partition and randomness of one layer's encrypted products."""
+    """Context, partition and randomness of one layer's encrypted products.
 
-    def __init__(self, layer, ctx: Context, plan=None, seed=0):
+    A strided layer runs as its stride-1 space-to-depth equivalent: each party
+    relayouts its own shares (the maps are linear) and the gradients map back.
+    dp_sd_w / dp_sd_b: standard deviations, in fixed-point units, of the data
+    owner's perturbation of its weight- and bias-gradient shares (Sec. III.B.2;
+    0 = none)."""
+
+    def __init__(self, layer, ctx: Context, plan=None, seed=0, dp_sd_w=0.0, dp_sd_b=0.0):
         self.layer = layer
+        self.strided = int(_get(layer, "stride", 1)) > 1
+        self.eq = stride_map(layer) if self.strided else layer
         self.ctx = ctx
-        self.plan = ctx.plan_auto(layer) if plan is None else plan
+        self.plan = ctx.plan_auto(self.eq) if plan is None else plan
         self.gen = torch.Generator(device=ctx.device)
         self.gen.manual_seed(seed)
         self.nonce = 1 << 32
+        self.dp_sd_w, self.dp_sd_b = float(dp_sd_w), float(dp_sd_b)
 
     def next_nonce(self):
         self.nonce += 1
@@ -47,24 +57,33 @@ class EncryptedLinearEngine:
         s0 = torch.randint(0, t, v.shape, generator=self.gen, device=v.device, dtype=torch.int64)
         return s0, torch.remainder(v - s0, t)
 
+    def to_eq(self, which, v):
+        return self.ctx.stride_relayout(self.layer, which, v) if self.strided else v
+
+    def from_eq(self, which, v):
+        return self.ctx.stride_relayout(self.layer, which, v) if self.strided else v
+
 
 class EncryptedLinearFunction(torch.autograd.Function):
     @staticmethod
-    def forward(fctx, x, w, engine):
-        c, L, t = engine.ctx, engine.layer, engine.ctx.t
+    def forward(fctx, x, w, b, engine):
+        c, L, t = engine.ctx, engine.eq, engine.ctx.t
         X, W = _to_zt(x, t), _to_zt(w, t)
+        bz = _to_zt(b, t) if b is not None else None
         x0, x1 = engine.shares(X)
+        x0, x1, W = engine.to_eq("x", x0), engine.to_eq("x", x1), engine.to_eq("w", W)
         ct_x = c.encrypt(L, engine.plan, "x_fwd", x1, engine.next_nonce())
-        ct_y, y0 = c.linear_fwd(L, engine.plan, ct_x, x0, W, engine.next_nonce())
+        ct_y, y0 = c.linear_fwd(L, engine.plan, ct_x, x0, W, engine.next_nonce(), bias=bz)
         y1 = c.decrypt(L, engine.plan, "fwd", ct_y)
         fctx.engine = engine
+        fctx.has_bias = b is not None
         fctx.save_for_backward(x0, x1, W)
-        return _centred(torch.remainder(y0 + y1, t), t)
+        return _centred(c.zt_combine([y0, y1], [1, 1]), t)
 
     @staticmethod
     def backward(fctx, grad_y):
         engine = fctx.engine
-        c, L, t = engine.ctx, engine.layer, engine.ctx.t
+        c, L, t = engine.ctx, engine.eq, engine.ctx.t
         x0, x1, W = fctx.saved_tensors
         dY = _to_zt(grad_y, t)
         dy0, dy1 = engine.shares(dY)
@@ -76,14 +95,23 @@ class EncryptedLinearFunction(torch.autograd.Function):
                                                   engine.next_nonce())
         dx1 = c.decrypt(L, engine.plan, "dx", ct_dx)
         dw_dec = c.decrypt(L, engine.plan, "dw", ct_dw)
-        # Alg. 2: the data owner adds its local term to the decryption, the model
-        # owner adds the mask and its own local term
-        dw_do = torch.remainder(dw_dec + c.zt_linear(L, "dw", x1, dy1), t)
-        dW = torch.remainder(dw_do + dw_mask + c.zt_linear(L, "dw", x0, dy0), t)
-        dX = torch.remainder(dx0 + dx1, t)
-        return _centred(dX, t), _centred(dW, t), None
+        dp_nonce = engine.next_nonce()
+        # Alg. 2: the data owner adds its local term to the decryption and its
+        # perturbation; the model owner adds the mask and its own local term
+        dw_do = c.zt_combine([c.zt_linear(L, "dw", x1, dy1)], [1], base=dw_dec, out=dw_dec)
+        if engine.dp_sd_w > 0:
+            c.dp_noise_(dw_do, engine.dp_sd_w, dp_nonce, 0)
+        dW = engine.from_eq("dw", c.zt_combine([dw_mask, c.zt_linear(L, "dw", x0, dy0)], [1, 1], base=dw_do))
+        dX = c.zt_combine([engine.from_eq("dx", dx0), engine.from_eq("dx", dx1)], [1, 1])
+        db = None
+        if fctx.has_bias:
+            db_do = c.bias_grad(L, dy1)
+            if engine.dp_sd_b > 0:
+                c.dp_noise_(db_do, engine.dp_sd_b, dp_nonce, 1)
+            db = _centred(c.zt_combine([c.bias_grad(L, dy0)], [1], base=db_do), t)
+        return _centred(dX, t), _centred(dW, t), db, None
 
 
-def encrypted_linear(x, w, engine):
-    """Y = W o X through the encrypted protocol; differentiable in x and w."""
-    return EncryptedLinearFunction.apply(x, w, engine)
+def encrypted_linear(x, w, engine, b=None):
+    """Y = W o X (+ b) through the encrypted protocol; differentiable in x, w and b."""
+    return EncryptedLinearFunction.apply(x, w, b, engine)

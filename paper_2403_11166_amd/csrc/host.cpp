@@ -452,46 +452,80 @@ struct OpGeom {
   int OW() const { return WA - KW + 1; }
 };
 
-static bool layer_ok(pencil_ctx* ctx, const pencil_layer* L, pencil_status* st) {
+// Kernel extent and zero padding per axis.  A Conv1d (kind 2) is the one-row
+// case of a Conv2d: a 1 x k kernel, padding along the length only.
+static int kh_of(const pencil_layer* L) { return L->kind == 2 ? 1 : L->k; }
+static int kw_of(const pencil_layer* L) { return L->k; }
+static int ph_of(const pencil_layer* L) { return L->kind == 2 ? 0 : L->pad; }
+static int pw_of(const pencil_layer* L) { return L->pad; }
+// Output rows and columns of a stride-1 layer.
+static int ho_of(const pencil_layer* L) { return L->h + 2 * ph_of(L) - kh_of(L) + 1; }
+static int wo_of(const pencil_layer* L) { return L->w + 2 * pw_of(L) - kw_of(L) + 1; }
+
+// Shape checks shared by every entry point; strided layers pass only where
+// allow_stride is set (the stride map and its relayouts).
+static bool layer_shape_ok(pencil_ctx* ctx, const pencil_layer* L, bool allow_stride, pencil_status* st) {
   if (!L) {
     *st = fail(ctx, PENCIL_EINVAL, "layer is NULL");
     return false;
   }
-  if (L->kind != 0 && L->kind != 1) {
-    *st = fail(ctx, PENCIL_EINVAL, "layer kind must be 0 (fc) or 1 (conv)");
+  if (L->kind < 0 || L->kind > 2) {
+    *st = fail(ctx, PENCIL_EINVAL, "layer kind must be 0 (fc), 1 (conv2d) or 2 (conv1d)");
     return false;
   }
-  if (L->batch < 1 || L->c_in < 1 || L->c_out < 1 || L->h < 1 || L->w < 1 || L->k < 1 || L->pad < 0) {
+  if (L->batch < 1 || L->c_in < 1 || L->c_out < 1 || L->h < 1 || L->w < 1 || L->k < 1 || L->pad < 0 ||
+      L->stride < 0) {
     *st = fail(ctx, PENCIL_EINVAL, "layer dimensions must be positive");
     return false;
   }
-  if (L->kind == 0 && (L->h != 1 || L->w != 1 || L->k != 1 || L->pad != 0)) {
-    *st = fail(ctx, PENCIL_EINVAL, "fc layers need h = w = k = 1, pad = 0");
+  const int stride = L->stride == 0 ? 1 : L->stride;
+  if (L->kind == 0 && (L->h != 1 || L->w != 1 || L->k != 1 || L->pad != 0 || stride != 1)) {
+    *st = fail(ctx, PENCIL_EINVAL, "fc layers need h = w = k = 1, pad = 0, stride 1");
+    return false;
+  }
+  if (L->kind == 2 && L->h != 1) {
+    *st = fail(ctx, PENCIL_EINVAL, "conv1d layers need h = 1");
+    return false;
+  }
+  if (stride > 1 && !allow_stride) {
+    *st = fail(ctx, PENCIL_EUNSUPPORTED,
+               "stride %d: run the layer as its stride-1 equivalent (pencil_stride_map, pencil_stride_relayout)",
+               stride);
+    return false;
+  }
+  if (stride > 16) {
+    *st = fail(ctx, PENCIL_EUNSUPPORTED, "stride above 16 is not supported");
     return false;
   }
   if (L->pad > L->k - 1) {
     *st = fail(ctx, PENCIL_EUNSUPPORTED, "padding above k - 1 is not supported");
     return false;
   }
-  if (L->h + 2 * L->pad < L->k || L->w + 2 * L->pad < L->k) {
+  if (L->h + 2 * ph_of(L) < kh_of(L) || L->w + 2 * pw_of(L) < kw_of(L)) {
     *st = fail(ctx, PENCIL_EINVAL, "kernel larger than padded input");
     return false;
   }
   const int64_t big = (int64_t)1 << 31;
-  if ((int64_t)L->batch * L->c_in * L->h * L->w >= big || (int64_t)L->c_out * L->c_in * L->k * L->k >= big) {
+  if ((int64_t)L->batch * L->c_in * L->h * L->w >= big ||
+      (int64_t)L->c_out * L->c_in * kh_of(L) * kw_of(L) * stride * stride >= big) {
     *st = fail(ctx, PENCIL_EINVAL, "layer too large");
     return false;
   }
   return true;
 }
 
+static bool layer_ok(pencil_ctx* ctx, const pencil_layer* L, pencil_status* st) {
+  return layer_shape_ok(ctx, L, false, st);
+}
+
 static OpGeom op_geom(const pencil_layer* L, int op) {
-  const int ho = L->h + 2 * L->pad - L->k + 1, wo = L->w + 2 * L->pad - L->k + 1;
-  const int qd = L->k - 1 - L->pad;
+  const int kh = kh_of(L), kw = kw_of(L), ph = ph_of(L), pw = pw_of(L);
+  const int ho = ho_of(L), wo = wo_of(L);
+  const int qh = kh - 1 - ph, qw = kw - 1 - pw;
   switch (op) {
-    case PENCIL_OP_FWD: return {L->batch, L->c_out, L->c_in, L->h + 2 * L->pad, L->w + 2 * L->pad, L->k, L->k};
-    case PENCIL_OP_DX: return {L->batch, L->c_in, L->c_out, ho + 2 * qd, wo + 2 * qd, L->k, L->k};
-    default: return {L->c_in, L->c_out, L->batch, L->h + 2 * L->pad, L->w + 2 * L->pad, ho, wo};
+    case PENCIL_OP_FWD: return {L->batch, L->c_out, L->c_in, L->h + 2 * ph, L->w + 2 * pw, kh, kw};
+    case PENCIL_OP_DX: return {L->batch, L->c_in, L->c_out, ho + 2 * qh, wo + 2 * qw, kh, kw};
+    default: return {L->c_in, L->c_out, L->batch, L->h + 2 * ph, L->w + 2 * pw, ho, wo};
   }
 }
 
@@ -525,28 +559,29 @@ static int64_t n_products(const Geo& G) { return n_out_tiles(G) * G.nK * G.nKY *
 // Tensor views (strides into the caller's PyTorch-layout tensors).
 static View view_a(const pencil_layer* L, int op) {
   const int64_t h = L->h, w = L->w, ci = L->c_in, co = L->c_out;
-  const int64_t ho = L->h + 2 * L->pad - L->k + 1, wo = L->w + 2 * L->pad - L->k + 1;
+  const int64_t ho = ho_of(L), wo = wo_of(L);
   View v{};
   v.sx = 1;
   if (op == PENCIL_OP_FWD) {  // x [B][ci][h][w], (m, k) = (b, ci)
-    v.s0 = ci * h * w; v.s1 = h * w; v.sy = w; v.pad = L->pad; v.H = (int)h; v.W = (int)w;
+    v.s0 = ci * h * w; v.s1 = h * w; v.sy = w; v.pady = ph_of(L); v.pad = pw_of(L); v.H = (int)h; v.W = (int)w;
   } else if (op == PENCIL_OP_DX) {  // dy [B][co][ho][wo], (m, k) = (b, co)
-    v.s0 = co * ho * wo; v.s1 = ho * wo; v.sy = wo; v.pad = L->k - 1 - L->pad; v.H = (int)ho; v.W = (int)wo;
+    v.s0 = co * ho * wo; v.s1 = ho * wo; v.sy = wo; v.pady = kh_of(L) - 1 - ph_of(L); v.pad = kw_of(L) - 1 - pw_of(L);
+    v.H = (int)ho; v.W = (int)wo;
   } else {  // x viewed (ci, B): (m, k) = (ci, b)
-    v.s0 = h * w; v.s1 = ci * h * w; v.sy = w; v.pad = L->pad; v.H = (int)h; v.W = (int)w;
+    v.s0 = h * w; v.s1 = ci * h * w; v.sy = w; v.pady = ph_of(L); v.pad = pw_of(L); v.H = (int)h; v.W = (int)w;
   }
   return v;
 }
 
 static View view_k(const pencil_layer* L, int op) {
-  const int64_t s = L->k, ci = L->c_in, co = L->c_out;
-  const int64_t ho = L->h + 2 * L->pad - L->k + 1, wo = L->w + 2 * L->pad - L->k + 1;
+  const int64_t kh = kh_of(L), kw = kw_of(L), ci = L->c_in, co = L->c_out;
+  const int64_t ho = ho_of(L), wo = wo_of(L);
   View v{};
   v.sx = 1;
-  if (op == PENCIL_OP_FWD) {  // W [co][ci][s][s], (r, k) = (co, ci)
-    v.s0 = ci * s * s; v.s1 = s * s; v.sy = s;
+  if (op == PENCIL_OP_FWD) {  // W [co][ci][kh][kw], (r, k) = (co, ci)
+    v.s0 = ci * kh * kw; v.s1 = kh * kw; v.sy = kw;
   } else if (op == PENCIL_OP_DX) {  // W viewed (ci, co), flipped
-    v.s0 = s * s; v.s1 = ci * s * s; v.sy = s; v.flip = 1; v.KH = (int)s; v.KW = (int)s;
+    v.s0 = kh * kw; v.s1 = ci * kh * kw; v.sy = kw; v.flip = 1; v.KH = (int)kh; v.KW = (int)kw;
   } else {  // dy viewed (co, B): (r, k) = (co, b)
     v.s0 = ho * wo; v.s1 = co * ho * wo; v.sy = wo;
   }
@@ -554,16 +589,16 @@ static View view_k(const pencil_layer* L, int op) {
 }
 
 static View view_out(const pencil_layer* L, int op) {
-  const int64_t h = L->h, w = L->w, s = L->k, ci = L->c_in, co = L->c_out;
-  const int64_t ho = L->h + 2 * L->pad - L->k + 1, wo = L->w + 2 * L->pad - L->k + 1;
+  const int64_t h = L->h, w = L->w, kh = kh_of(L), kw = kw_of(L), ci = L->c_in, co = L->c_out;
+  const int64_t ho = ho_of(L), wo = wo_of(L);
   View v{};
   v.sx = 1;
   if (op == PENCIL_OP_FWD) {  // Y [B][co][ho][wo]
     v.s0 = co * ho * wo; v.s1 = ho * wo; v.sy = wo;
   } else if (op == PENCIL_OP_DX) {  // dX [B][ci][h][w]
     v.s0 = ci * h * w; v.s1 = h * w; v.sy = w;
-  } else {  // dW [co][ci][s][s] with (m, r) = (ci, co)
-    v.s0 = s * s; v.s1 = ci * s * s; v.sy = s;
+  } else {  // dW [co][ci][kh][kw] with (m, r) = (ci, co)
+    v.s0 = kh * kw; v.s1 = ci * kh * kw; v.sy = kw;
   }
   return v;
 }
@@ -998,8 +1033,7 @@ extern "C" pencil_status pencil_bias_grad(pencil_ctx* ctx, const pencil_layer* L
   TRY(check_ptr(ctx, db, "db"));
   pencil_status st = PENCIL_OK;
   if (!layer_ok(ctx, L, &st)) return st;
-  const int64_t ho = L->h + 2 * L->pad - L->k + 1, wo = L->w + 2 * L->pad - L->k + 1;
-  const int64_t spatial = ho * wo;
+  const int64_t spatial = (int64_t)ho_of(L) * wo_of(L);
   if ((int64_t)L->batch * spatial > ((int64_t)1 << 22))
     return fail(ctx, PENCIL_EUNSUPPORTED, "bias gradient sums at most 2^22 entries per channel");
   hipError_t e = launch_bias_grad(dy, db, L->batch, L->c_out, (int)spatial, ctx->C, (hipStream_t)stream);
@@ -1016,6 +1050,67 @@ extern "C" pencil_status pencil_dp_noise(pencil_ctx* ctx, int64_t count, double 
   TRY(check_ptr(ctx, x, "x"));
   hipError_t e = launch_dp_noise(x, count, sd, nonce, object, ctx->C, (hipStream_t)stream);
   if (e != hipSuccess) return fail(ctx, PENCIL_EHIP, "dp_noise launch: %s", hipGetErrorString(e));
+  return PENCIL_OK;
+}
+
+// The stride-1 layer equal to a stride-s layer over the space-to-depth image
+// (sy = 1 along the single row of a Conv1d): c_in s_y s_x input channels, a
+// ceil(k / s) kernel, no padding, and ho + k' - 1 by wo + k' - 1 inputs so that
+// its outputs are exactly the strided layer's.
+static void stride_equiv(const pencil_layer* L, pencil_layer* E, Relayout* R) {
+  const int s = L->stride <= 1 ? 1 : L->stride;
+  const int sy = L->kind == 2 ? 1 : s, sx = s;
+  const int kh = kh_of(L), kw = kw_of(L), ph = ph_of(L), pw = pw_of(L);
+  const int ho = (L->h + 2 * ph - kh) / sy + 1, wo = (L->w + 2 * pw - kw) / sx + 1;
+  const int kh2 = (kh + sy - 1) / sy, kw2 = (kw + sx - 1) / sx;
+  *E = *L;
+  E->c_in = L->c_in * sy * sx;
+  E->k = kw2;
+  E->h = L->kind == 2 ? 1 : ho + kh2 - 1;
+  E->w = wo + kw2 - 1;
+  E->pad = 0;
+  E->stride = 1;
+  if (R) {
+    *R = Relayout{};
+    R->batch = L->batch; R->ci = L->c_in; R->co = L->c_out;
+    R->h = L->h; R->w = L->w; R->kh = kh; R->kw = kw;
+    R->sy = sy; R->sx = sx; R->ph = ph; R->pw = pw;
+    R->h2 = E->h; R->w2 = E->w; R->kh2 = kh2; R->kw2 = kw2;
+  }
+}
+
+extern "C" pencil_status pencil_stride_map(const pencil_layer* L, pencil_layer* equiv) {
+  pencil_status st = PENCIL_OK;
+  if (!equiv) return fail(nullptr, PENCIL_EINVAL, "equiv is NULL");
+  if (!layer_shape_ok(nullptr, L, true, &st)) return st;
+  stride_equiv(L, equiv, nullptr);
+  if (!layer_shape_ok(nullptr, equiv, false, &st)) return st;
+  return PENCIL_OK;
+}
+
+extern "C" pencil_status pencil_stride_relayout(pencil_ctx* ctx, const pencil_layer* L, int which, const int64_t* in,
+                                                int64_t* out, void* stream) {
+  if (!ctx) return PENCIL_EINVAL;
+  if (which < 0 || which > 3) return fail(ctx, PENCIL_EINVAL, "relayout %d invalid", which);
+  TRY(check_ptr(ctx, in, "in"));
+  TRY(check_ptr(ctx, out, "out"));
+  if ((const void*)in == (const void*)out) return fail(ctx, PENCIL_EINVAL, "in and out alias");
+  pencil_status st = PENCIL_OK;
+  if (!layer_shape_ok(ctx, L, true, &st)) return st;
+  pencil_layer E;
+  Relayout R;
+  stride_equiv(L, &E, &R);
+  if (!layer_shape_ok(ctx, &E, false, &st)) return st;
+  R.mode = which;
+  const int64_t ss = (int64_t)R.sy * R.sx;
+  switch (which) {
+    case 0: R.total = (int64_t)R.batch * R.ci * ss * R.h2 * R.w2; break;
+    case 1: R.total = (int64_t)R.co * R.ci * ss * R.kh2 * R.kw2; break;
+    case 2: R.total = (int64_t)R.batch * R.ci * R.h * R.w; break;
+    default: R.total = (int64_t)R.co * R.ci * R.kh * R.kw; break;
+  }
+  hipError_t e = launch_stride_relayout(R, in, out, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(ctx, PENCIL_EHIP, "stride_relayout launch: %s", hipGetErrorString(e));
   return PENCIL_OK;
 }
 
@@ -1487,8 +1582,8 @@ extern "C" pencil_status pencil_autotune(pencil_ctx* ctx, const pencil_layer* L,
   }
   // 2) multiply-accumulate chunk shape per product
   const int64_t xs = (int64_t)L->batch * L->c_in * L->h * L->w;
-  const int64_t ho = L->h + 2 * L->pad - L->k + 1, wo = L->w + 2 * L->pad - L->k + 1;
-  const int64_t ys = (int64_t)L->batch * L->c_out * ho * wo, wsz = (int64_t)L->c_out * L->c_in * L->k * L->k;
+  const int64_t ho = ho_of(L), wo = wo_of(L);
+  const int64_t ys = (int64_t)L->batch * L->c_out * ho * wo, wsz = (int64_t)L->c_out * L->c_in * kh_of(L) * kw_of(L);
   pencil_sizes sz;
   TRY(pencil_layout(ctx, L, P, &sz));
   const uint64_t ctb = sz.ct_bytes;

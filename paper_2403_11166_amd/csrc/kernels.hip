@@ -259,7 +259,7 @@ __device__ __forceinline__ int64_t a_slot_offset(const Geo& G, const View& V, in
   int m = mi * G.mt + mm, k = ki * G.kt + kk;
   int y = oyi * G.oh + kyi * G.kh + ya, x = oxi * G.ow + kxi * G.kw + xa;
   if (m >= G.M || k >= G.K || y >= G.HA || x >= G.WA) return -1;
-  int ys = y - V.pad, xs = x - V.pad;
+  int ys = y - V.pady, xs = x - V.pad;
   if (ys < 0 || xs < 0 || ys >= V.H || xs >= V.W) return -1;
   return m * V.s0 + k * V.s1 + ys * V.sy + xs * V.sx;
 }
@@ -1185,7 +1185,7 @@ __global__ void __launch_bounds__(256) k_zt_corr(const int64_t* a, const int64_t
   uint64_t hi = 0, lo = 0;
   for (int k = 0; k < G.K; ++k)
     for (int dy = 0; dy < G.KH; ++dy) {
-      const int ys = y + dy - AV.pad;
+      const int ys = y + dy - AV.pady;
       if (ys < 0 || ys >= AV.H) continue;
       for (int dx = 0; dx < G.KW; ++dx) {
         const int xs = x + dx - AV.pad;
@@ -1233,7 +1233,7 @@ __global__ void __launch_bounds__(1024) k_zt_gemm(const int64_t* a, const int64_
     const int rr = rv[i] ? row : 0;
     const int m = rr / ohw, rem = rr - m * ohw, y = rem / G.OW, x = rem - y * G.OW;
     abase[i] = (int64_t)m * AV.s0;
-    ay[i] = y - AV.pad;
+    ay[i] = y - AV.pady;
     ax[i] = x - AV.pad;
   }
   int64_t kbase[TI];
@@ -1491,6 +1491,52 @@ __global__ void __launch_bounds__(256) k_dp_noise(int64_t* __restrict__ x, int64
     if (i0 + h < count) px[h] = dp_add(px[h], z[h], sd, C.t);
 }
 
+// ------------------------------------------------- stride-s relayouts
+
+// A stride-s correlation equals a stride-1 correlation over the space-to-depth
+// image: channel c' = c sy sx + a sx + e holds Xpad[., c, sy y + a, sx x + e]
+// and the kernel W[., c, sy i + a, sx j + e] (zero past the kernel's edge).
+// Each mode gathers one output entry per thread; padding and taps that fall
+// outside either tensor read as zero.
+__global__ void __launch_bounds__(256) k_stride_relayout(Relayout R, const int64_t* __restrict__ in,
+                                                         int64_t* __restrict__ out) {
+  const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (g >= R.total) return;
+  const int ss = R.sy * R.sx;
+  int64_t v = 0;
+  if (R.mode == 0 || R.mode == 1) {  // out [n][c * ss][Y][X] from in [n][c][.][.]
+    const int Y = R.mode == 0 ? R.h2 : R.kh2, X = R.mode == 0 ? R.w2 : R.kw2;
+    const int x2 = (int)(g % X);
+    int64_t r = g / X;
+    const int y2 = (int)(r % Y);
+    r /= Y;
+    const int c2 = (int)(r % ((int64_t)R.ci * ss));
+    const int64_t n = r / ((int64_t)R.ci * ss);
+    const int c = c2 / ss, a = (c2 / R.sx) % R.sy, e = c2 % R.sx;
+    if (R.mode == 0) {
+      const int yy = R.sy * y2 + a - R.ph, xx = R.sx * x2 + e - R.pw;
+      if (yy >= 0 && yy < R.h && xx >= 0 && xx < R.w)
+        v = gview(in)[((n * R.ci + c) * R.h + yy) * R.w + xx];
+    } else {
+      const int i = R.sy * y2 + a, j = R.sx * x2 + e;
+      if (i < R.kh && j < R.kw) v = gview(in)[((n * R.ci + c) * R.kh + i) * R.kw + j];
+    }
+  } else {  // out [n][c][Y][X] from in [n][c * ss][.][.]
+    const int Y = R.mode == 2 ? R.h : R.kh, X = R.mode == 2 ? R.w : R.kw;
+    const int x = (int)(g % X);
+    int64_t r = g / X;
+    const int y = (int)(r % Y);
+    r /= Y;
+    const int c = (int)(r % R.ci);
+    const int64_t n = r / R.ci;
+    const int yy = R.mode == 2 ? y + R.ph : y, xx = R.mode == 2 ? x + R.pw : x;
+    const int y2 = yy / R.sy, x2 = xx / R.sx, c2 = c * ss + (yy % R.sy) * R.sx + xx % R.sx;
+    const int Y2 = R.mode == 2 ? R.h2 : R.kh2, X2 = R.mode == 2 ? R.w2 : R.kw2;
+    if (y2 < Y2 && x2 < X2) v = gview(in)[((n * ((int64_t)R.ci * ss) + c2) * Y2 + y2) * X2 + x2];
+  }
+  gview(out)[g] = v;
+}
+
 // --------------------------------------------------------- batched step
 
 __device__ __forceinline__ int find_seg(const StepSeg* segs, int nseg, int64_t b) {
@@ -1709,6 +1755,12 @@ hipError_t launch_dp_noise(int64_t* x, int64_t count, double sd, uint64_t nonce,
   const int64_t threads = (count + 3) / 4;
   hipLaunchKernelGGL(k_dp_noise, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, x, count, sd, nonce, obj,
                      C);
+  return hipGetLastError();
+}
+
+hipError_t launch_stride_relayout(const Relayout& R, const int64_t* in, int64_t* out, hipStream_t s) {
+  if (R.total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_stride_relayout, dim3((unsigned)((R.total + 255) / 256)), dim3(256), 0, s, R, in, out);
   return hipGetLastError();
 }
 

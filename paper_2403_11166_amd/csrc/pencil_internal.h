@@ -66,8 +66,8 @@ struct Geo {
 // K side: flip mirrors the kernel window.  Output: plain strides.
 struct View {
   int64_t s0, s1, sy, sx;
-  int32_t pad, H, W, flip;
-  int32_t KH, KW, pad2, pad3;
+  int32_t pad, H, W, flip;   // pad: zero columns before the tensor (and rows, see pady)
+  int32_t KH, KW, pady, pad3;
 };
 
 // Philox stream purposes.
@@ -181,6 +181,17 @@ hipError_t launch_bias_grad(const int64_t* dy, int64_t* db, int batch, int chann
                             hipStream_t s);
 hipError_t launch_dp_noise(int64_t* x, int64_t count, double sd, uint64_t nonce, uint64_t obj, const Consts& C,
                            hipStream_t s);
+
+// Space-to-depth relayout between a stride-s layer and its stride-1
+// equivalent.  mode 0: X -> X', 1: W -> W', 2: dX' -> dX, 3: dW' -> dW.
+struct Relayout {
+  int32_t mode, batch, ci, co;
+  int32_t h, w, kh, kw;   // the strided layer: input, kernel
+  int32_t sy, sx, ph, pw; // stride and padding per axis (sy = 1 for conv1d)
+  int32_t h2, w2, kh2, kw2;  // the equivalent layer: input, kernel
+  int64_t total;          // entries of the output tensor
+};
+hipError_t launch_stride_relayout(const Relayout& R, const int64_t* in, int64_t* out, hipStream_t s);
 hipError_t launch_zt_corr(const int64_t* a, const int64_t* k, int64_t* out, const Geo& G, const View& AV,
                           const View& KV, const View& OV, const Consts& C, hipStream_t s);
 hipError_t launch_step_ntt(int log2n, int loge, bool inverse, const StepPhase& P, int64_t blocks, hipStream_t s);

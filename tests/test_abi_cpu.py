@@ -90,3 +90,40 @@ def test_planner_rejects_unsupported_layers():
     assert lib.pencil_plan_auto_n(13, ctypes.byref(bad), ctypes.byref(p)) == _abi.PENCIL_EINVAL
     ok = _abi.Layer(0, 2, 3, 4, 1, 1, 1, 0)
     assert lib.pencil_plan_auto_n(9, ctypes.byref(ok), ctypes.byref(p)) == _abi.PENCIL_EINVAL
+
+
+def test_stride_map_and_conv1d_planning():
+    """Strided layers map to their space-to-depth stride-1 equivalents (host
+    only); product entry points refuse strided layers; Conv1d layers and the
+    equivalents plan into tiles that fit N slots."""
+    from oracle import encoding as E
+    from paper_2403_11166_amd import _abi
+    from paper_2403_11166_amd.api import layer_struct
+    from workloads import LayerSpec, conv, conv1d
+    lib = _abi.load()
+    cases = [(conv(64, 1, 5, 28, k=5, pad=2, stride=2), (1, 64, 4, 5, 16, 16, 3, 0, 1)),
+             (conv(2, 3, 2, 11, k=4, pad=1, stride=3), (1, 2, 27, 2, 5, 5, 2, 0, 1)),
+             (conv1d(2, 3, 4, 14, k=5, pad=2, stride=2), (2, 2, 6, 4, 1, 9, 3, 0, 1))]
+    for layer, want in cases:
+        e = _abi.Layer()
+        assert lib.pencil_stride_map(ctypes.byref(layer_struct(layer)), ctypes.byref(e)) == 0
+        got = tuple(getattr(e, f) for f, _ in _abi.Layer._fields_)
+        assert got == want, (layer, got)
+        p = _abi.Plan()
+        assert lib.pencil_plan_auto_n(13, ctypes.byref(layer_struct(layer)), ctypes.byref(p)) == _abi.PENCIL_EUNSUPPORTED
+        assert b"stride" in lib.pencil_last_error(None)
+        kind = {0: "fc", 1: "conv", 2: "conv1d"}[e.kind]
+        eq = LayerSpec(kind, e.batch, e.c_in, e.c_out, e.h, e.w, e.k, e.pad)
+        assert eq.y_shape() == layer.y_shape()
+        assert lib.pencil_plan_auto_n(13, ctypes.byref(layer_struct(eq)), ctypes.byref(p)) == 0
+        for op, t in zip(("fwd", "dx", "dw"), (p.fwd, p.dx, p.dw)):
+            E.check_tile(E.geometry(eq, op), E.Tile(*t.astuple()), 1 << 13)
+    for layer in (conv1d(64, 256, 128, 64, k=5), conv1d(64, 128, 128, 30, k=5), conv1d(3, 4, 2, 9, k=3, pad=1)):
+        p = _abi.Plan()
+        assert lib.pencil_plan_auto_n(13, ctypes.byref(layer_struct(layer)), ctypes.byref(p)) == 0
+        for op, t in zip(("fwd", "dx", "dw"), (p.fwd, p.dx, p.dw)):
+            E.check_tile(E.geometry(layer, op), E.Tile(*t.astuple()), 1 << 13)
+    bad = conv1d(2, 3, 4, 14, k=5, pad=2)
+    s = layer_struct(bad)
+    s.h = 2
+    assert lib.pencil_plan_auto_n(13, ctypes.byref(s), ctypes.byref(_abi.Plan())) == _abi.PENCIL_EINVAL

@@ -7,7 +7,7 @@ import torch
 
 from oracle import linear as LN
 from oracle import params as PR
-from workloads import conv, fc, layer_tensors, CONFIGS
+from workloads import conv, conv1d, fc, layer_tensors, CONFIGS
 
 from gpu_common import dev, host_i64
 
@@ -121,3 +121,62 @@ def test_zt_linear_matches_oracle(layer):
     for op, a, b in (("fwd", X, W), ("dx", dY, W), ("dw", X, dY)):
         got = host_i64(ctx.zt_linear(layer, op, dev(a), dev(b)))
         assert (got == LN.layer_op(layer, op, a, b, T)).all(), op
+
+
+SHAPES = [conv(3, 1, 4, 12, k=5, pad=2, stride=2, log2_n=12, num_limbs=2, prime_bits=50),
+          conv1d(3, 6, 4, 16, k=5, pad=1, log2_n=12, num_limbs=2, prime_bits=50),
+          conv1d(2, 4, 3, 15, k=3, pad=1, stride=2, log2_n=12, num_limbs=2, prime_bits=50)]
+
+
+@pytest.mark.parametrize("li", range(len(SHAPES)), ids=["conv_s2", "conv1d", "conv1d_s2"])
+def test_strided_and_1d_layers_match_torch_with_bias(li):
+    """Strided Conv2d and Conv1d layers (with bias) against torch's float64
+    autograd on small integers, where nothing wraps mod t."""
+    layer = SHAPES[li]
+    eng = _engine(layer, 70 + li)
+    from paper_2403_11166_amd.autograd import encrypted_linear
+    rng = np.random.default_rng(7 + li)
+    xs = rng.integers(-300, 300, layer.x_shape()).astype(np.float64)
+    ws = rng.integers(-300, 300, layer.w_shape()).astype(np.float64)
+    bs = rng.integers(-300, 300, layer.c_out).astype(np.float64)
+    gs = rng.integers(-300, 300, layer.y_shape()).astype(np.float64)
+    x = torch.tensor(xs, device="cuda", requires_grad=True)
+    w = torch.tensor(ws, device="cuda", requires_grad=True)
+    b = torch.tensor(bs, device="cuda", requires_grad=True)
+    y = encrypted_linear(x, w, eng, b)
+    y.backward(torch.tensor(gs, device="cuda"))
+    xr, wr, br = (torch.tensor(v, requires_grad=True) for v in (xs, ws, bs))
+    f = torch.nn.functional.conv1d if layer.kind == "conv1d" else torch.nn.functional.conv2d
+    yr = f(xr, wr, br, padding=layer.pad, stride=layer.stride)
+    yr.backward(torch.tensor(gs))
+    assert torch.equal(y.detach().cpu(), yr.detach())
+    assert torch.equal(x.grad.cpu(), xr.grad)
+    assert torch.equal(w.grad.cpu(), wr.grad)
+    assert torch.equal(b.grad.cpu(), br.grad)
+
+
+def test_dp_noise_lands_on_weight_and_bias_gradients():
+    """With the data owner's perturbation on, dW and db differ from the exact
+    gradients by exactly the oracle's noise draws for the step's nonce."""
+    from oracle import dp as DP
+    from paper_2403_11166_amd import Context
+    from paper_2403_11166_amd.autograd import EncryptedLinearEngine, encrypted_linear
+    layer = LAYERS[1]
+    ctx = Context(layer.log2_n, layer.num_limbs, layer.prime_bits, 77)
+    sd_w, sd_b = 2.0 ** 24 * 0.01, 2.0 ** 12 * 0.01
+    eng = EncryptedLinearEngine(layer, ctx, seed=77, dp_sd_w=sd_w, dp_sd_b=sd_b)
+    ts = layer_tensors(layer, 78)
+    x = torch.tensor(centred_np(ts["X"]), dtype=torch.float64, device="cuda", requires_grad=True)
+    w = torch.tensor(centred_np(ts["W"]), dtype=torch.float64, device="cuda", requires_grad=True)
+    b = torch.zeros(layer.c_out, dtype=torch.float64, device="cuda", requires_grad=True)
+    y = encrypted_linear(x, w, eng, b)
+    y.backward(torch.tensor(centred_np(ts["dY"]), dtype=torch.float64, device="cuda"))
+    torch.cuda.synchronize()
+    dp_nonce = eng.nonce          # the last nonce drawn in backward is the perturbation's
+    ew = DP.noise(77, dp_nonce, DP.OBJ_DW, int(np.prod(layer.w_shape())), sd_w).reshape(layer.w_shape())
+    eb = DP.noise(77, dp_nonce, DP.OBJ_DB, layer.c_out, sd_b)
+    dW = LN.layer_op(layer, "dw", ts["X"], ts["dY"], T)
+    db = DP.bias_grad(layer, ts["dY"], T)
+    assert (np.mod(w.grad.cpu().numpy().astype(np.int64) - dW - ew, T) == 0).all()
+    assert (np.mod(b.grad.cpu().numpy().astype(np.int64) - db - eb, T) == 0).all()
+    assert (np.mod(x.grad.cpu().numpy().astype(np.int64), T) == LN.layer_op(layer, "dx", ts["dY"], ts["W"], T)).all()

@@ -10,7 +10,7 @@ from oracle import linear as LN
 from oracle import params as PR
 from oracle import protocol as PRT
 from oracle import ring as RG
-from workloads import CONFIGS, config_tensors, layer_tensors, small_cases, conv, fc
+from workloads import CONFIGS, config_tensors, layer_tensors, small_cases, conv, conv1d, fc
 
 from gpu_common import dev, host_i64, host_u64, oracle_keys, oracle_params, cts_list
 
@@ -137,6 +137,9 @@ SMALL_PLANS = [
     (small_cases()[2], {"fwd": (2, 2, 2, 3, 5, 3, 3), "dx": (1, 2, 3, 2, 5, 3, 3), "dw": (2, 2, 1, 3, 3, 2, 5)}),
     (small_cases()[3], {"fwd": (1, 3, 2, 4, 7, 3, 3), "dx": (2, 2, 3, 3, 4, 3, 3), "dw": (3, 4, 1, 3, 3, 4, 7)}),
     (small_cases()[4], {"fwd": (2, 2, 2, 5, 5, 2, 2), "dx": (1, 2, 2, 6, 6, 2, 2), "dw": (2, 2, 2, 2, 2, 5, 5)}),
+    # Conv1d: ragged channel, length and kernel tiles
+    (conv1d(2, 3, 4, 13, k=5, pad=2, log2_n=11, num_limbs=2, prime_bits=50),
+     {"fwd": (2, 3, 2, 1, 6, 1, 3), "dx": (1, 2, 3, 1, 5, 1, 4), "dw": (2, 3, 1, 1, 3, 1, 6)}),
 ]
 
 
