@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", type=int, default=2, help="workload index (1..5)")
+    ap.add_argument("--workload", default="", help="one of the extra layer-shape workloads by name "
+                    "(MNIST CNN with its stride-2 layer, TextCNN's Conv1d layers, FC 2048->1001); overrides --config")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU oracle sample budget")
     ap.add_argument("--no-verify", action="store_true")
@@ -137,17 +139,22 @@ def _lin_f64(layer, op, a, b):
     import torch.nn.functional as F
     if layer.kind == "fc":
         return {"fwd": lambda: a @ b.t(), "dx": lambda: a @ b, "dw": lambda: b.t() @ a}[op]()
-    k, p = layer.k, layer.pad
+    k, p = (layer.kh, layer.kw), (layer.pad_h, layer.pad_w)
+    st = (1, layer.stride) if layer.kind == "conv1d" else (layer.stride, layer.stride)
     ho, wo = layer.h_out, layer.w_out
+    as4 = (lambda v: v.reshape(v.shape[0], v.shape[1], 1, v.shape[-1])) if layer.kind == "conv1d" else (lambda v: v)
+    a, b = as4(a), as4(b)
     if op == "fwd":
-        cols = F.unfold(a, k, padding=p)                           # (B, ci*k*k, ho*wo)
-        return (b.reshape(b.shape[0], -1) @ cols).reshape(a.shape[0], b.shape[0], ho, wo)
-    if op == "dx":                                               # a = dY, b = W
-        cols = b.reshape(b.shape[0], -1).t() @ a.reshape(a.shape[0], a.shape[1], -1)  # (B, ci*k*k, ho*wo)
-        return F.fold(cols, (layer.h, layer.w), k, padding=p)
-    cols = F.unfold(a, k, padding=p)                               # a = X, b = dY
-    g = torch.einsum("bop,bcp->oc", b.reshape(b.shape[0], b.shape[1], -1), cols)
-    return g.reshape(b.shape[1], a.shape[1], k, k)
+        cols = F.unfold(a, k, padding=p, stride=st)                # (B, ci*kh*kw, ho*wo)
+        out = (b.reshape(b.shape[0], -1) @ cols).reshape(a.shape[0], b.shape[0], ho, wo)
+    elif op == "dx":                                             # a = dY, b = W
+        cols = b.reshape(b.shape[0], -1).t() @ a.reshape(a.shape[0], a.shape[1], -1)  # (B, ci*kh*kw, ho*wo)
+        out = F.fold(cols, (layer.h, layer.w), k, padding=p, stride=st)
+    else:
+        cols = F.unfold(a, k, padding=p, stride=st)                # a = X, b = dY
+        g = torch.einsum("bop,bcp->oc", b.reshape(b.shape[0], b.shape[1], -1), cols)
+        out = g.reshape(b.shape[1], a.shape[1], k[0], k[1])
+    return out.reshape(out.shape[0], out.shape[1], out.shape[-1]) if layer.kind == "conv1d" else out
 
 
 def exact_mod_t(layer, op, a, b, t):
@@ -331,22 +338,42 @@ def main():
     import torch
     from paper_2403_11166_amd import Context
     from paper_2403_11166_amd import _abi as A
-    from workloads import CONFIGS
+    from paper_2403_11166_amd.api import stride_map
+    from workloads import CONFIGS, EXTRA_WORKLOADS, LayerSpec
     from workloads.gen import config_tensors
     import ctypes
+    import dataclasses
 
-    cfg = CONFIGS[args.config]
+    cfg = EXTRA_WORKLOADS[args.workload] if args.workload else CONFIGS[args.config]
     tensors = config_tensors(cfg)
     torch.cuda.init()
     dev = torch.device("cuda", 0)
     ctxs = {}
     tuned = {}
     layers = []
+    relayout_ms = 0.0
     for li, (layer, ts) in enumerate(zip(cfg.layers, tensors)):
         key = (layer.log2_n, layer.num_limbs, layer.prime_bits)
         if key not in ctxs:
             ctxs[key] = Context(layer.log2_n, layer.num_limbs, layer.prime_bits, seed=cfg.seed)
         ctx = ctxs[key]
+        strided = None
+        if layer.stride > 1:
+            # both parties move their shares (and the MO its weights) to the
+            # stride-1 space-to-depth equivalent; the products run on that layer
+            eqd = stride_map(layer)
+            eq = dataclasses.replace(layer, **{k: eqd[k] for k in ("kind", "c_in", "h", "w", "k", "pad", "stride")})
+            d0 = {k: torch.from_numpy(v).to(dev) for k, v in ts.items()}
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            ev0.record()
+            moved = {"x0": ctx.stride_relayout(layer, "x", d0["x0"]), "x1": ctx.stride_relayout(layer, "x", d0["x1"]),
+                     "W": ctx.stride_relayout(layer, "w", d0["W"])}
+            ev1.record()
+            torch.cuda.synchronize()
+            relayout_ms += ev0.elapsed_time(ev1)
+            ts = dict(ts, **{k: v.cpu().numpy() for k, v in moved.items()})
+            strided, layer = (layer, d0), eq
         plan = ctx.plan_auto(layer)
         if not args.no_autotune:
             # schedule-only choices (bit-identical results), timed outside the measured region
@@ -356,7 +383,7 @@ def main():
             plan = tuned[tkey]
         sz = ctx.layout(layer, plan)
         d = {k: torch.from_numpy(v).to(dev) for k, v in ts.items()}
-        ent = dict(layer=layer, ctx=ctx, plan=plan, sz=sz, d=d)
+        ent = dict(layer=layer, ctx=ctx, plan=plan, sz=sz, d=d, strided=strided)
         ent["ct_x"] = ctx.encrypt(layer, plan, "x_fwd", d["x1"], 1000 + li)
         if "dx" in cfg.ops:
             ent["ct_dy_dx"] = ctx.encrypt(layer, plan, "dy_dx", d["dy1"], 2000 + li)
@@ -452,16 +479,21 @@ def main():
         bit_exact = True
         for e in layers:
             L_, c, d, t = e["layer"], e["ctx"], e["d"], e["ctx"].t
+            # a strided layer is checked against its own definition: outputs of
+            # the stride-1 equivalent, gradients mapped back by each party
+            S, o = e["strided"] if e["strided"] else (L_, d)
+            back = (lambda which, v: c.stride_relayout(S, which, v)) if e["strided"] else (lambda which, v: v)
             y1 = c.decrypt(L_, e["plan"], "fwd", e["out_f"][0])
-            ok = torch.equal(torch.remainder(e["out_f"][1] + y1, t), exact_mod_t(L_, "fwd", d["X"], d["W"], t))
+            ok = torch.equal(torch.remainder(e["out_f"][1] + y1, t), exact_mod_t(S, "fwd", d["X"], o["W"], t))
             if "dx" in cfg.ops:
                 dx1 = c.decrypt(L_, e["plan"], "dx", e["out_b"][0])
-                ok &= torch.equal(torch.remainder(e["out_b"][1] + dx1, t), exact_mod_t(L_, "dx", d["dY"], d["W"], t))
+                ok &= torch.equal(torch.remainder(back("dx", e["out_b"][1]) + back("dx", dx1), t),
+                                  exact_mod_t(S, "dx", d["dY"], o["W"], t))
             if "dw" in cfg.ops:
                 dw1 = c.decrypt(L_, e["plan"], "dw", e["out_b"][2])
-                cross = torch.remainder(exact_mod_t(L_, "dw", d["x1"], d["dy0"], t)
-                                        + exact_mod_t(L_, "dw", d["x0"], d["dy1"], t), t)
-                ok &= torch.equal(torch.remainder(e["out_b"][3] + dw1, t), cross)
+                cross = torch.remainder(exact_mod_t(S, "dw", o["x1"], d["dy0"], t)
+                                        + exact_mod_t(S, "dw", o["x0"], d["dy1"], t), t)
+                ok &= torch.equal(torch.remainder(back("dw", e["out_b"][3]) + back("dw", dw1), t), cross)
             bit_exact &= bool(ok)
 
     # ------------------------------------------------------ roofline
@@ -563,13 +595,13 @@ def main():
 
     # ------------------------------------------------------ Pencil+
     plus = None
-    m_plus = args.pencil_plus if args.pencil_plus >= 0 else (8 if args.config == 2 else 0)
+    m_plus = args.pencil_plus if args.pencil_plus >= 0 else (8 if args.config == 2 and not args.workload else 0)
     if m_plus > 0:
         plus = pencil_plus_bench(layers[0], m_plus, compare["step"] if "step" in compare else ms_step, torch)
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(cfg.layers[0], args.cpu_seconds)
+        cpu = cpu_baseline(layers[0]["layer"], args.cpu_seconds)
 
     first = layers[0]
     rec = {
@@ -586,8 +618,9 @@ def main():
         "dtype": "u64",
         "data": "synthetic",
         "config": {"workload": cfg.name, "N": first["ctx"].n, "L": first["ctx"].L,
-                   "layers": [f"{e['layer'].kind} {e['layer'].c_in}->{e['layer'].c_out} "
-                              f"{e['layer'].h}x{e['layer'].w} b{e['layer'].batch}" for e in layers],
+                   "layers": [f"{S.kind} {S.c_in}->{S.c_out} {S.h}x{S.w} k{S.k} s{S.stride} b{S.batch}"
+                              + (" (as its stride-1 equivalent)" if e["strided"] else "")
+                              for e in layers for S in [e["strided"][0] if e["strided"] else e["layer"]]],
                    "ops": list(cfg.ops), "products_per_step": int(products),
                    "plans": [{"fwd": e["plan"].fwd.astuple(), "dx": e["plan"].dx.astuple(),
                               "dw": e["plan"].dw.astuple(), "sched": list(e["plan"].sched)} for e in layers],
@@ -604,6 +637,7 @@ def main():
         "cpu_baseline": cpu,
         "data_owner_ends": do_side,
         "weight_update_terms": wupd,
+        "stride_relayout_ms": round(relayout_ms, 4) if any(e["strided"] for e in layers) else None,
         "pencil_plus": plus,
     }
     print(json.dumps(rec), flush=True)

@@ -146,6 +146,35 @@ CONFIGS = {
 }
 
 
+# More layer shapes of the paper's evaluation networks (App. D, Table V), at
+# batch 64: the MNIST CNN (its stride-2 5x5 convolution, then two FC layers),
+# the AGNews TextCNN's two Conv1d layers (k = 5 over 256 x 64 and 128 x 30
+# inputs), and Table V's largest FC layer 2048 -> 1001.
+EXTRA_WORKLOADS = {
+    "mnist_cnn_b64_n8192": Config(
+        0, "mnist_cnn_b64_n8192",
+        [conv(64, 1, 5, 28, k=5, pad=2, stride=2, x_dist=("uniform", 0.0, 1.0), w_dist=("normal", he_std(25)),
+              log2_n=13, num_limbs=3, prime_bits=60),
+         fc(64, 980, 100, x_dist=("normal", 1.0), w_dist=("normal", he_std(980)), log2_n=13, num_limbs=3,
+            prime_bits=60),
+         fc(64, 100, 10, x_dist=("normal", 1.0), w_dist=("normal", he_std(100)), log2_n=13, num_limbs=3,
+            prime_bits=60)],
+        ops=("fwd", "dx", "dw"), seed=6),
+    "textcnn_b64_n8192": Config(
+        0, "textcnn_b64_n8192",
+        [conv1d(64, 256, 128, 64, k=5, x_dist=("normal", 1.0), w_dist=("normal", he_std(256 * 5)),
+                log2_n=13, num_limbs=3, prime_bits=60),
+         conv1d(64, 128, 128, 30, k=5, x_dist=("normal", 1.0), w_dist=("normal", he_std(128 * 5)),
+                log2_n=13, num_limbs=3, prime_bits=60)],
+        ops=("fwd", "dx", "dw"), seed=7),
+    "fc2048x1001_b64_n8192": Config(
+        0, "fc2048x1001_b64_n8192",
+        [fc(64, 2048, 1001, x_dist=("normal", 1.0), w_dist=("normal", he_std(2048)), log2_n=13, num_limbs=3,
+            prime_bits=60)],
+        ops=("fwd", "dx", "dw"), seed=8),
+}
+
+
 def config_layers(index):
     return CONFIGS[index].layers
 
