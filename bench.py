@@ -288,6 +288,14 @@ def pencil_plus_bench(e, m, he_step_ms, torch):
     want = {"fwd": exact_mod_t(L_, "fwd", d["x1"], d["W"], t), "dx": exact_mod_t(L_, "dx", d["dy1"], d["W"], t),
             "dw01": exact_mod_t(L_, "dw", d["x1"], d["dy0"], t), "dw10": exact_mod_t(L_, "dw", d["x0"], d["dy1"], t)}
     exact = all(torch.equal(torch.remainder(res[kd][0] + res[kd][1], t), want[kd]) for kd in ops)
+    # the online phase's dense part, one Z_t correlation per operator timed alone:
+    # output entries x contraction length multiply-adds, 4 32-bit multiplies each
+    macs = L_.batch * L_.c_out * L_.h_out * L_.w_out * L_.c_in * L_.kh * L_.kw
+    corr = {}
+    for kind, (u, v) in ops.items():
+        ms = timed_reps(lambda: GP.apply(ctx, L_, kind, u, v))
+        corr[kind] = {"ms": round(ms, 4), "mul32_Tps": round(4 * macs / (ms / 1e3) / 1e12, 3),
+                      "frac": round(4 * macs / (ms / 1e3) / 1e12 / MUL32_PEAK_TOPS, 4)}
     return {"m": m, "layer": f"{L_.kind} {L_.c_in}->{L_.c_out} {L_.h}x{L_.w} b{L_.batch}",
             "prep": {"products": int(prep_products), "wall_ms": round(prep_ms, 2),
                      "products_per_s": round(prep_products / (prep_ms / 1e3), 1),
@@ -296,7 +304,9 @@ def pencil_plus_bench(e, m, he_step_ms, torch):
             "online": {"ms_per_step": round(online_ms, 4), "launch": "HIP graph replay",
                        "eager_ms_per_step": round(eager_ms, 4), "operators": list(ops),
                        "he_step_ms": round(he_step_ms, 4), "speedup_vs_he_step": round(he_step_ms / online_ms, 2),
-                       "bit_exact": bool(exact), "graph_replays_match_eager": bool(replay_same)}}
+                       "bit_exact": bool(exact), "graph_replays_match_eager": bool(replay_same)},
+            "zt_correlation": {"macs_per_call": int(macs), "calls_per_step": 4 * (m + 1), "per_operator": corr,
+                               "bound": "alu", "peak_mul32_Tps": MUL32_PEAK_TOPS}}
 
 
 # ------------------------------------------------------------- cpu baseline

@@ -458,6 +458,9 @@ __device__ __forceinline__ void acc_mac(Acc& x, uint64_t a, uint64_t b) {
   const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32), b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
   x.s0 += (uint64_t)a0 * b0;
   x.s1 += (uint64_t)a0 * b1;
+  // keeps the two middle products as two multiply-adds into s1 (summing them
+  // first would cost a separate 64-bit add)
+  asm volatile("" : "+v"(x.s1));
   x.s1 += (uint64_t)a1 * b0;
   x.s2 += (uint64_t)a1 * b1;
 }
@@ -637,7 +640,8 @@ __device__ __forceinline__ void do_mac_t(uint64_t* smem, const MacArgs& A, const
   B.row0 = (chunk / cchunks) * ROWS;
   B.col0 = (chunk % cchunks) * COLS;
   B.s = threadIdx.x & (kMacSlots - 1);
-  B.grp = threadIdx.x >> 6;
+  // wave-uniform: the row and column bookkeeping below runs on the scalar unit
+  B.grp = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   B.comp = NC == 1 ? (B.grp & 1) : 0;
   const int tile = NC == 1 ? B.grp >> 1 : B.grp;
   B.rg = (tile / WC) * TM;
@@ -736,12 +740,12 @@ __device__ __forceinline__ void mac_term_direct(const MacTerm& T, const MacArgs&
   const int64_t a_wrap = ((int64_t)(sp - 1) * kspan + 1) * sa_str;
   const uint32_t fold_every = C.mac_fold, reduce_every = C.mac_chunk;
   int kk = 0, left = ksteps;  // steps not yet loaded
-  // Three operand sets rotate so that the loads of the next two steps are in
+  // Four operand sets rotate so that the loads of the next three steps are in
   // flight while the current one accumulates (no register copies between
   // them).  Loads are unconditional: past the last step the pointers stop
   // advancing and the last step is read again, so no branch separates a load
   // from its use.
-  uint64_t xa[TM][NC], xk[TR][NC], ya[TM][NC], yk[TR][NC], za[TM][NC], zk[TR][NC];
+  uint64_t xa[TM][NC], xk[TR][NC], ya[TM][NC], yk[TR][NC], za[TM][NC], zk[TR][NC], wa[TM][NC], wk[TR][NC];
   auto load = [&](uint64_t(&va)[TM][NC], uint64_t(&vk)[TR][NC]) {
 #pragma unroll
     for (int a = 0; a < TM; ++a) {
@@ -776,8 +780,9 @@ __device__ __forceinline__ void mac_term_direct(const MacTerm& T, const MacArgs&
   };
   load(xa, xk);
   load(ya, yk);
-  for (int k = 0; k < ksteps; k += 3) {
-    load(za, zk);
+  load(za, zk);
+  for (int k = 0; k < ksteps; k += 4) {
+    load(wa, wk);
     step(xa, xk);
     if (k + 1 >= ksteps) break;
     load(xa, xk);
@@ -785,6 +790,9 @@ __device__ __forceinline__ void mac_term_direct(const MacTerm& T, const MacArgs&
     if (k + 2 >= ksteps) break;
     load(ya, yk);
     step(za, zk);
+    if (k + 3 >= ksteps) break;
+    load(za, zk);
+    step(wa, wk);
   }
 }
 
@@ -813,18 +821,18 @@ __device__ __forceinline__ int64_t xcd_work(int64_t b, int64_t total) {
 
 __global__ void __launch_bounds__(512) k_mac_lds(MacArgs A, Geo G, Consts C, int chunks, int64_t total) {
   extern __shared__ uint64_t smem[];
-  const int64_t w = xcd_work(blockIdx.x, total);
-  do_mac<0>(smem, A, G, C, (int)(w / chunks), (int)(w % chunks));
+  const int w = (int)xcd_work(blockIdx.x, total);
+  do_mac<0>(smem, A, G, C, w / chunks, w % chunks);
 }
 
 __global__ void __launch_bounds__(512) k_mac_direct(MacArgs A, Geo G, Consts C, int chunks, int64_t total) {
-  const int64_t w = xcd_work(blockIdx.x, total);
-  do_mac<1>(nullptr, A, G, C, (int)(w / chunks), (int)(w % chunks));
+  const int w = (int)xcd_work(blockIdx.x, total);
+  do_mac<1>(nullptr, A, G, C, w / chunks, w % chunks);
 }
 
 __global__ void __launch_bounds__(512) k_mac_direct_small(MacArgs A, Geo G, Consts C, int chunks, int64_t total) {
-  const int64_t w = xcd_work(blockIdx.x, total);
-  do_mac<2>(nullptr, A, G, C, (int)(w / chunks), (int)(w % chunks));
+  const int w = (int)xcd_work(blockIdx.x, total);
+  do_mac<2>(nullptr, A, G, C, w / chunks, w % chunks);
 }
 
 typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
@@ -1591,9 +1599,9 @@ __device__ __forceinline__ void step_mac(const StepSeg* __restrict__ segs, int n
   const int64_t local = (int64_t)blockIdx.x - S.block_begin;
   const int chunks = mac_chunks(S.mac.variant, S.mac.m_rows, S.G.nR);
   const int64_t work = S.slot_blocks * chunks, padded = (work + 7) & ~(int64_t)7;
-  const int64_t w = xcd_work(local, padded);
+  const int w = (int)xcd_work(local, padded);  // work items per launch stay below 2^31
   if (w >= work) return;
-  do_mac<KIND>(smem, S.mac, S.G, consts[S.ctx], (int)(w / chunks), (int)(w % chunks));
+  do_mac<KIND>(smem, S.mac, S.G, consts[S.ctx], w / chunks, w % chunks);
 }
 
 #define STEP_ARGS const StepSeg *__restrict__ segs, int nseg, const Consts *__restrict__ consts
@@ -1680,6 +1688,7 @@ hipError_t launch_mac(const MacArgs& A, int64_t n_out, const Geo& G, const Const
   const int64_t slot_blocks = (int64_t)C.n * C.L / kMacSlots;
   const int chunks = mac_chunks(A.variant, A.m_rows, G.nR);
   const int64_t total = slot_blocks * chunks;
+  if (total >= (1ll << 31)) return hipErrorInvalidConfiguration;  // work items are int
   if (A.variant >= 6)
     hipLaunchKernelGGL(k_mac_direct_small, dim3((unsigned)total), dim3(512), 0, s, A, G, C, chunks, total);
   else if (A.variant >= 3)
