@@ -108,3 +108,37 @@ def test_strided_layer_rejected_by_product_entry_points():
     ctx = context(layer.log2_n, layer.num_limbs, layer.prime_bits)
     with pytest.raises(RuntimeError, match="stride"):
         ctx.plan_auto(layer)
+
+
+DEGENERATE = [fc(1, 1, 1, log2_n=10, num_limbs=2, prime_bits=50),
+              fc(1, 1, 300, log2_n=10, num_limbs=2, prime_bits=50),
+              fc(300, 1, 1, log2_n=10, num_limbs=2, prime_bits=50),
+              fc(2, 1500, 3, log2_n=10, num_limbs=2, prime_bits=50),     # contraction longer than N
+              conv(1, 1, 1, 1, k=1, pad=0, log2_n=10, num_limbs=2, prime_bits=50),
+              conv(1, 1, 1, 3, k=3, pad=0, log2_n=10, num_limbs=2, prime_bits=50),   # 1 x 1 output
+              conv(2, 3, 2, 1, k=3, pad=1, log2_n=10, num_limbs=2, prime_bits=50),   # 1 x 1 input, padded
+              conv(1, 2, 2, 40, k=3, pad=1, log2_n=10, num_limbs=2, prime_bits=50),  # image larger than N
+              conv1d(1, 1, 1, 5, k=5, log2_n=10, num_limbs=2, prime_bits=50),
+              conv(1, 2, 3, 5, k=5, pad=0, stride=2, log2_n=10, num_limbs=2, prime_bits=50)]
+
+
+@pytest.mark.parametrize("layer", DEGENERATE, ids=["fc1x1x1", "fc_co300", "fc_b300", "fc_ci1500", "conv1x1",
+                                                   "conv_out1", "conv_in1", "conv_40x40", "conv1d_out1",
+                                                   "conv_s2_out1"])
+def test_degenerate_shapes_reconstruct(layer):
+    from paper_2403_11166_amd.api import stride_map
+    ctx = context(layer.log2_n, layer.num_limbs, layer.prime_bits)
+    ts = layer_tensors(layer, 14)
+    d = {k: dev(v) for k, v in ts.items()}
+    if layer.stride > 1:
+        eq = stride_map(layer)
+        rx = lambda v: ctx.stride_relayout(layer, "x", v)  # noqa: E731
+        Y, (a, b), dWe = run_protocol(ctx, eq, ts, rx(d["x0"]), rx(d["x1"]), d["dy0"], d["dy1"],
+                                      ctx.stride_relayout(layer, "w", d["W"]), 900)
+        dx0, dx1 = ctx.stride_relayout(layer, "dx", a), ctx.stride_relayout(layer, "dx", b)
+        dW = ctx.stride_relayout(layer, "dw", dWe)
+    else:
+        Y, (dx0, dx1), dW = run_protocol(ctx, layer, ts, d["x0"], d["x1"], d["dy0"], d["dy1"], d["W"], 900)
+    assert np.array_equal(host_i64(Y), LN.layer_op(layer, "fwd", ts["X"], ts["W"], T))
+    assert np.array_equal((host_i64(dx0) + host_i64(dx1)) % T, LN.layer_op(layer, "dx", ts["dY"], ts["W"], T))
+    assert np.array_equal(host_i64(dW), LN.layer_op(layer, "dw", ts["X"], ts["dY"], T))
