@@ -147,3 +147,39 @@ def decrypt_at(P, sk, ct, idx):
     x = crt(limbs, P.moduli)
     q, t = P.q, P.t
     return np.array([((2 * t * v + q) // (2 * q)) % t for v in x], dtype=np.int64)
+
+
+def _powers(x, n, q):
+    out = [1] * n
+    for j in range(1, n):
+        out[j] = out[j - 1] * x % q
+    return np.array(out, dtype=object)
+
+
+def encrypt_eval_at(P, pk, m, seed, nonce, obj, roots):
+    """The ciphertext encrypt(P, pk, m, seed, nonce, obj) evaluated at the given
+    roots of X^N + 1 (roots[l]: a list of points mod q_l).  Evaluation at such a
+    root is a ring map of Z_q[X]/(X^N + 1), so each entry is
+    pk_c(x) u(x) + e_c(x) (+ round(q m / t)(x) on c = 0), mod q_l.  At
+    x = psi^(2k+1) this is entry k of the negacyclic NTT.  Returns
+    [2][L][len(roots[l])] Python integers."""
+    n = P.n
+    u = S.ternary(seed, nonce, obj, S.P_ENC_U, n)
+    e = (S.cbd21(seed, nonce, obj, S.P_ENC_E0, n), S.cbd21(seed, nonce, obj, S.P_ENC_E1, n))
+    dm = delta_scale(m, P)
+    out = [[None] * P.num_limbs for _ in range(2)]
+    for l, q in enumerate(P.moduli):
+        uo = np.array([int(v) % q for v in u], dtype=object)
+        e0 = np.array([int(v) % q for v in e[0]], dtype=object)
+        e1 = np.array([int(v) % q for v in e[1]], dtype=object)
+        dmo = np.array([int(v) % q for v in dm], dtype=object)
+        pk0 = np.array([int(v) for v in pk[0, l]], dtype=object)
+        pk1 = np.array([int(v) for v in pk[1, l]], dtype=object)
+        r0, r1 = [], []
+        for x in roots[l]:
+            pw = _powers(int(x), n, q)
+            ux = int(np.dot(uo, pw)) % q
+            r0.append((int(np.dot(pk0, pw)) * ux + int(np.dot(e0, pw)) + int(np.dot(dmo, pw))) % q)
+            r1.append((int(np.dot(pk1, pw)) * ux + int(np.dot(e1, pw))) % q)
+        out[0][l], out[1][l] = r0, r1
+    return out

@@ -299,6 +299,22 @@ def test_output_is_rerandomised_flooded_and_masked():
     assert bfv.noise(P, keys["sk"], d, dec) > (1 << (P.flood_bits - 4))
 
 
+def test_encrypt_eval_at_is_the_ntt_of_the_encryption():
+    """Evaluating the ciphertext at psi^(2k+1) (the ring map to Z_q) equals
+    entry k of the definitional negacyclic NTT of the full encryption."""
+    P = SMALL
+    k = bfv.keygen(P, 17)
+    m = np.random.default_rng(18).integers(0, T, P.n)
+    ct = bfv.encrypt(P, k["pk"], m, 17, 4, 9)
+    ks = [0, 1, 77, P.n - 1]
+    roots = [[pow(psi, 2 * kk + 1, q) for kk in ks] for q, psi in zip(P.moduli, P.psi)]
+    ev = bfv.encrypt_eval_at(P, k["pk"], m, 17, 4, 9, roots)
+    for l, (q, psi) in enumerate(zip(P.moduli, P.psi)):
+        for c in range(2):
+            full = RG.ntt_def(ct[c, l], q, psi)
+            assert [int(full[kk]) for kk in ks] == ev[c][l]
+
+
 def test_sampled_helpers_match_full_versions():
     P = SMALL
     k = bfv.keygen(P, 13)
