@@ -201,7 +201,9 @@ def kernel_work(sizes_list):
                 n_ct_in, n_pt = sz.n_ct[2] + sz.n_ct[3], sz.n_pt[2]
             add = lambda k, b, o: work.__setitem__(k, (work.get(k, (0, 0))[0] + b, work.get(k, (0, 0))[1] + o))  # noqa
             b10 = MUL32_PER_BUTTERFLY * bfly
-            add("ntt_ct", 2 * n_ct_in * 2 * poly, 2 * n_ct_in * b10)
+            # input ciphertexts arrive in the NTT domain: only the model owner's
+            # share (fwd, dx) is transformed, once per ciphertext
+            add("ntt_ct", 2 * n_ct_in * 2 * poly, (n_ct_in if op != "dw" else 0) * b10)
             add("ntt_pt", n_pt * poly, n_pt * b10)
             add("ntt_ternary", n_out * poly, n_out * b10)
             add("mac", (2 * n_ct_in + n_pt + n_out + 2 * n_out) * poly,

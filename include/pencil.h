@@ -171,12 +171,17 @@ pencil_status pencil_layout(const pencil_ctx* ctx, const pencil_layer* layer, co
 /* DO: encode its share (int64 [0,t), the tensor the operand is built from: X for
  * X_FWD / X_DW, dY for DY_DX / DY_DW) with the operand's layout and encrypt it
  * under the public key (ct = (p0 u + e0 + round(q m / t), p1 u + e1)).
- * ct receives n_ct[operand] ciphertexts; ws: ws_enc_bytes of device memory. */
+ * ct receives n_ct[operand] ciphertexts in the NTT domain, the form the
+ * products consume: residue i of each [limb] polynomial is its evaluation at
+ * psi_l^(2 rev(i) + 1) (the order of pencil_ntt_forward).  Output ciphertexts
+ * of the products are in the coefficient domain.  ws: ws_enc_bytes of device
+ * memory. */
 pencil_status pencil_encrypt(pencil_ctx* ctx, const pencil_layer* layer, const pencil_plan* plan,
                              int operand, const int64_t* share, uint64_t* ct, void* ws, uint64_t nonce,
                              void* stream);
 
-/* MO: forward product of Alg. 1.  ct_x1: n_ct[X_FWD] ciphertexts of <X>_1;
+/* MO: forward product of Alg. 1.  ct_x1: n_ct[X_FWD] ciphertexts of <X>_1 in
+ * the NTT domain (as pencil_encrypt writes them);
  * x0: the MO's share of X; w: weights; bias: int64 [c_out] at the output's
  * scale, or NULL.  Writes ct_y (n_out[FWD] ciphertexts for the DO) and y0, the
  * MO's share of Y (same shape as Y).  ws: ws_fwd_bytes of device memory. */
@@ -190,6 +195,7 @@ pencil_status pencil_linear_fwd(pencil_ctx* ctx, const pencil_layer* layer, cons
  * ct_dy_dw (<dY>_1, DY_DW layout) with the MO's shares dy0 and x0; writes
  * ct_dw and dw_mask, the MO's mask s shaped like W.  After decryption,
  * dec(ct_dw) + dw_mask = <dY>_0 o <X>_1 + <dY>_1 o <X>_0 (mod t).
+ * Input ciphertexts are in the NTT domain, outputs in the coefficient domain.
  * Either product may be skipped by passing NULL for its outputs. */
 pencil_status pencil_linear_bwd(pencil_ctx* ctx, const pencil_layer* layer, const pencil_plan* plan,
                                 const uint64_t* ct_dy_dx, const uint64_t* ct_x_dw, const uint64_t* ct_dy_dw,

@@ -323,8 +323,10 @@ __global__ void __launch_bounds__(512, (LOGE >= 5 ? 2 : 4)) k_ntt_plain(uint64_t
   do_ntt_plain<LOGN, LOGE>(lds, data, inverse, C, T, blockIdx.x);
 }
 
-// Input ciphertexts: load (coefficient domain), add round(q m / t) of the model
-// owner's share on component 0 (Alg. 1, product step), forward NTT, store.
+// Input ciphertexts (NTT domain): component 0 gains the transform of
+// round(q m / t) of the model owner's share (Alg. 1, product step); the
+// residues are stored split for the multiply-accumulate.  Only a block with a
+// share to add runs a transform; the others convert and copy.
 // Grid: n_ct * 2 * L blocks, polynomial p = (j, c, l) in [n][2][L] order.
 template <int LOGN, int LOGE>
 __device__ __forceinline__ void do_ntt_ct(uint64_t* lds, const uint64_t* src, uint64_t* dst, const int64_t* share,
@@ -336,23 +338,24 @@ __device__ __forceinline__ void do_ntt_ct(uint64_t* lds, const uint64_t* src, ui
   const int64_t j = p / (2 * L);
   const LimbConst& lc = C.limb[l];
   const PENCIL_GLOBAL uint64_t* g = gview(src + p * n);
+  PENCIL_GLOBAL uint64_t* o = gview(dst + p * n);
+  if (share == nullptr || c != 0) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) o[i] = split30(g[i]);
+    return;
+  }
   const PENCIL_GLOBAL int64_t* gshare = gview(share);
-  const bool add = share != nullptr && c == 0;
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    uint64_t v = g[i];
-    if (add) {
-      int64_t off = a_slot_offset(G, V, j, i);
-      if (off >= 0) {
-        uint64_t m = (uint64_t)gshare[off];
-        v = add_mod(v, delta_scale(m, round_rho(m, C), lc), lc.q);
-      }
+    uint64_t v = 0;
+    const int64_t off = a_slot_offset(G, V, j, i);
+    if (off >= 0) {
+      const uint64_t m = (uint64_t)gshare[off];
+      v = delta_scale(m, round_rho(m, C), lc);
     }
     lds[lpad(i)] = v;
   }
   __syncthreads();
   ntt_fwd<LOGN, LOGE>(lds, T.fw + (int64_t)l * n, lc.q);
-  PENCIL_GLOBAL uint64_t* o = gview(dst + p * n);
-  for (int i = threadIdx.x; i < n; i += blockDim.x) o[i] = split30(lds[lpad(i)]);
+  for (int i = threadIdx.x; i < n; i += blockDim.x) o[i] = split30(add_mod(g[i], lds[lpad(i)], lc.q));
 }
 
 template <int LOGN, int LOGE>
@@ -955,8 +958,9 @@ __global__ void __launch_bounds__(256) k_flood_mask(uint64_t* ct, int64_t n_out,
   do_flood<W>(ct, n_out, share0, bias, G, OV, nonce, obj_base, C, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
-// Encryption: ct_c = INTT(pk_c * u) + e_c (+ round(q m / t) on c = 0), with m
-// the encoded share at each slot.  Grid: n_ct * 2 * L, u_ntt is [n][L][N].
+// Encryption in the NTT domain: ct_c = pk_c * u + NTT(e_c (+ round(q m / t) on
+// c = 0)), with m the encoded share at each slot; the product path consumes
+// ciphertexts in this form.  Grid: n_ct * 2 * L, u_ntt is [n][L][N].
 template <int LOGN, int LOGE>
 __global__ void __launch_bounds__(512, (LOGE >= 5 ? 2 : 4)) k_encrypt(const uint64_t* u_ntt, const int64_t* share, uint64_t* ct, int side,
                                                   Geo G, View V, const uint64_t* pk_ntt, const uint64_t* pk_sh,
@@ -972,18 +976,13 @@ __global__ void __launch_bounds__(512, (LOGE >= 5 ? 2 : 4)) k_encrypt(const uint
   const uint64_t* u = u_ntt + (j * L + l) * n;
   const uint64_t* pk = pk_ntt + ((int64_t)c * L + l) * n;
   const uint64_t* pks = pk_sh + ((int64_t)c * L + l) * n;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) lds[lpad(i)] = mul_shoup(u[i], pk[i], pks[i], lc.q);
-  __syncthreads();
-  ntt_inv<LOGN, LOGE>(lds, T.iw + (int64_t)l * n, lc.q);
   const uint64_t obj = obj_base + (uint64_t)j;
-  uint64_t* o = ct + p * n;
   for (int blk = threadIdx.x; blk < n / 4; blk += blockDim.x) {
     U64x4 e = philox((uint64_t)blk, obj, c ? P_ENC_E1 : P_ENC_E0, 0, C.seed, nonce);
 #pragma unroll
     for (int z = 0; z < 4; ++z) {
       const int i = blk * 4 + z;
-      uint64_t v = mul_shoup(lds[lpad(i)], lc.ninv, lc.ninv_sh, lc.q);
-      v = add_mod(v, small_to_mod(cbd21(e.v[z]), lc.q), lc.q);
+      uint64_t v = small_to_mod(cbd21(e.v[z]), lc.q);
       if (c == 0) {
         int64_t off = slot_offset(side, G, V, j, i);
         if (off >= 0) {
@@ -991,9 +990,14 @@ __global__ void __launch_bounds__(512, (LOGE >= 5 ? 2 : 4)) k_encrypt(const uint
           v = add_mod(v, delta_scale(m, round_rho(m, C), lc), lc.q);
         }
       }
-      o[i] = v;
+      lds[lpad(i)] = v;
     }
   }
+  __syncthreads();
+  ntt_fwd<LOGN, LOGE>(lds, T.fw + (int64_t)l * n, lc.q);
+  uint64_t* o = ct + p * n;
+  for (int i = threadIdx.x; i < n; i += blockDim.x)
+    o[i] = add_mod(mul_shoup(u[i], pk[i], pks[i], lc.q), lds[lpad(i)], lc.q);
 }
 
 // Decryption phase per limb: x = c0 + INTT(NTT(c1) * s).  Grid: n * L, x is [n][L][N].

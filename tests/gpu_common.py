@@ -5,6 +5,7 @@ import torch
 
 from oracle import bfv
 from oracle import params as PR
+from oracle import ring as RG
 
 
 def dev(a):
@@ -36,3 +37,27 @@ def oracle_keys(ctx):
 def cts_list(arr):
     """uint64 [n][2][L][N] -> list of per-ciphertext arrays."""
     return [arr[i] for i in range(arr.shape[0])]
+
+
+def bitrev(i, bits):
+    return int(format(i, f"0{bits}b")[::-1], 2)
+
+
+def ntt_order_roots(P, idx):
+    """Per limb, the points psi^(2 rev(i) + 1) that NTT-domain entries idx of the
+    library's transform order hold (its documented order)."""
+    bits = P.n.bit_length() - 1
+    return [[pow(psi, 2 * bitrev(i, bits) + 1, q) for i in idx] for q, psi in zip(P.moduli, P.psi)]
+
+
+def oracle_ct_ntt(P, ct):
+    """An oracle ciphertext [2][L][N] (coefficient domain) in the NTT-domain
+    form the library's encryption produces: the definitional transform of each
+    component and limb, entry i = evaluation at psi^(2 rev(i) + 1)."""
+    bits = P.n.bit_length() - 1
+    perm = np.array([bitrev(i, bits) for i in range(P.n)])
+    out = np.empty_like(np.asarray(ct, dtype=np.uint64))
+    for c in range(2):
+        for l, (q, psi) in enumerate(zip(P.moduli, P.psi)):
+            out[c, l] = RG.ntt_def(ct[c][l], q, psi)[perm]
+    return out

@@ -19,7 +19,7 @@ from oracle import linear as LN
 from oracle import protocol as PRT
 from workloads import CONFIGS, config_tensors, uniform_residues
 
-from gpu_common import dev, host_i64, host_u64, oracle_keys, oracle_params
+from gpu_common import dev, host_i64, host_u64, ntt_order_roots, oracle_keys, oracle_params
 
 pytestmark = pytest.mark.gpu
 
@@ -123,7 +123,11 @@ def test_products_bit_exact_on_sampled_coefficients(ci, li):
     for name, cnt, seed in (("x", sz.n_ct[0], 1), ("dydx", sz.n_ct[1], 2), ("xdw", sz.n_ct[2], 3),
                             ("dydw", sz.n_ct[3], 4)):
         synth[name] = uniform_residues(1000 * ci + seed, (int(cnt), 2, L, n), ctx.primes)
-    g = lambda a: torch.from_numpy(a.view(np.int64)).cuda()  # noqa: E731
+    # the oracle takes these as coefficient-domain ciphertexts; the library's
+    # product path takes its inputs in the NTT domain, so the device copies are
+    # transformed (by the library's transform, itself checked against the
+    # definition in the NTT parity test)
+    g = lambda a: ctx.ntt(torch.from_numpy(a.copy().view(np.int64)).cuda())  # noqa: E731
     ct_y, y0 = ctx.linear_fwd(layer, plan, g(synth["x"]), dev(ts["x0"]), dev(ts["W"]), 21)
     ct_dx, dx0, ct_dw, dwm = ctx.linear_bwd(layer, plan, g(synth["dydx"]), g(synth["xdw"]), g(synth["dydw"]),
                                             dev(ts["dy0"]), dev(ts["x0"]), dev(ts["W"]), 22)
@@ -173,6 +177,10 @@ def test_products_bit_exact_on_sampled_coefficients(ci, li):
                 m = E.encode_a(E.virtual_a(layer, op, ts[src]), gm, tiles[op], n, *list(E.a_tiles(cc))[j])
             else:
                 m = E.encode_k(E.virtual_k(layer, op, ts[src]), gm, tiles[op], n, *list(E.k_tiles(cc))[j])
-            idx = _sample_idx(n, [], rng, 8)
-            ref = bfv.encrypt_at(P, keys["pk"], m, cfg.seed, 30 + kind, PRT.enc_object(kind, j), idx)
-            assert (ct[j][:, :, idx] == ref).all(), (name, j)
+            idx = _sample_idx(n, [], rng, 4)
+            # the library's ciphertexts are in the NTT domain: entry i is the
+            # evaluation at psi^(2 rev(i) + 1)
+            ref = bfv.encrypt_eval_at(P, keys["pk"], m, cfg.seed, 30 + kind, PRT.enc_object(kind, j),
+                                      ntt_order_roots(P, idx))
+            assert [[[int(v) for v in ct[j][c, l, idx]] for l in range(P.num_limbs)] for c in range(2)] == ref, \
+                (name, j)

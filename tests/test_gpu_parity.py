@@ -12,7 +12,7 @@ from oracle import protocol as PRT
 from oracle import ring as RG
 from workloads import CONFIGS, config_tensors, layer_tensors, small_cases, conv, conv1d, fc
 
-from gpu_common import dev, host_i64, host_u64, oracle_keys, oracle_params, cts_list
+from gpu_common import dev, host_i64, host_u64, oracle_ct_ntt, oracle_keys, oracle_params, cts_list
 
 pytestmark = pytest.mark.gpu
 
@@ -122,7 +122,7 @@ def test_config1_bit_exact():
     keys = oracle_keys(ctx)
     ct_x, ct_y, y0, y1 = _run_fwd(ctx, layer, tiles, ts, 5, 6)
     ref_x = PRT.encrypt_operand(P, keys["pk"], layer, plan, PRT.OPERAND_X_FWD, ts["x1"], cfg.seed, 5)
-    assert (host_u64(ct_x) == np.stack(ref_x)).all()
+    assert (host_u64(ct_x) == np.stack([oracle_ct_ntt(P, c) for c in ref_x])).all()
     out, ref_y0 = PRT.mo_product(P, keys["pk"], layer, "fwd", plan["fwd"], [(("ct", ref_x), ("pt", ts["W"]))],
                                  cfg.seed, 6, add_share=ts["x0"])
     assert (host_u64(ct_y) == np.stack([out[o] for o in range(len(out))])).all()
@@ -156,7 +156,7 @@ def test_small_layers_bit_exact(case):
     # forward
     ct_x, ct_y, y0, y1 = _run_fwd(ctx, layer, tiles, ts, 100, 101)
     ref_x = PRT.encrypt_operand(P, keys["pk"], layer, plan, PRT.OPERAND_X_FWD, ts["x1"], seed, 100)
-    assert (host_u64(ct_x) == np.stack(ref_x)).all()
+    assert (host_u64(ct_x) == np.stack([oracle_ct_ntt(P, c) for c in ref_x])).all()
     out, ref_y0 = PRT.mo_product(P, keys["pk"], layer, "fwd", plan["fwd"], [(("ct", ref_x), ("pt", ts["W"]))],
                                  seed, 101, add_share=ts["x0"])
     assert (host_u64(ct_y) == np.stack([out[o] for o in range(len(out))])).all()
@@ -168,7 +168,7 @@ def test_small_layers_bit_exact(case):
                             ("dy_dw", PRT.OPERAND_DY_DW, "dy1")):
         g = ctx.encrypt(layer, tiles, name, dev(ts[src]), 200)
         r = PRT.encrypt_operand(P, keys["pk"], layer, plan, kind, ts[src], seed, 200)
-        assert (host_u64(g) == np.stack(r)).all(), name
+        assert (host_u64(g) == np.stack([oracle_ct_ntt(P, c) for c in r])).all(), name
         cts[name] = (g, r)
     ct_dx, dx0, ct_dw, dwm = ctx.linear_bwd(layer, tiles, cts["dy_dx"][0], cts["x_dw"][0], cts["dy_dw"][0],
                                             dev(ts["dy0"]), dev(ts["x0"]), dev(ts["W"]), 201)
