@@ -222,7 +222,7 @@ pencil_status pencil_zt_linear(pencil_ctx* ctx, const pencil_layer* layer, int o
  * u~ = u - sum k_i u'_i, v~ = v - sum l_j v'_j and the share combinations of the
  * online phase of the preprocessed products (Sec. IV.C, Alg. 3).
  * terms: host array of n_terms device pointers (n_terms >= 0; any number, the
- * library chains launches of 16 terms); coeffs: host array of n_terms values in
+ * library chains launches of 64 terms); coeffs: host array of n_terms values in
  * [0, t) (use t - c for -c); base: device pointer or NULL (zero); out: device,
  * may alias base but no term.  Enqueued on `stream`. */
 pencil_status pencil_zt_combine(pencil_ctx* ctx, int64_t count, int n_terms, const int64_t* const* terms,

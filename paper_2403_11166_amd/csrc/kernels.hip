@@ -1339,7 +1339,7 @@ __global__ void __launch_bounds__(1024) k_zt_gemm(const int64_t* a, const int64_
 // Z_t linear combination out = base + sum_i c_i x_i (mod t), one thread per
 // element: the masked operands and share combinations of the preprocessed
 // products (Pencil+, online phase).  Operands and coefficients are below
-// t < 2^42, so each product fits 84 bits and 16 of them plus base fit 128.
+// t < 2^48, so each product fits 96 bits and 64 of them plus base fit 128.
 __global__ void __launch_bounds__(256) k_zt_combine(ZtTerms T, const int64_t* base, int64_t* out, int64_t count,
                                                     Consts C) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -169,7 +169,7 @@ hipError_t launch_phase(const uint64_t* ct, uint64_t* x, int64_t n_ct, const uin
 hipError_t launch_decode(const uint64_t* x, int64_t* share, int64_t n_out, const Geo& G, const View& outV,
                          const Consts& C, hipStream_t s);
 // Up to kZtTerms terms of a Z_t linear combination, by value (kernel argument).
-constexpr int kZtTerms = 16;
+constexpr int kZtTerms = 64;
 struct ZtTerms {
   const int64_t* x[kZtTerms];
   uint64_t c[kZtTerms];

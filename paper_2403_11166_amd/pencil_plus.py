@@ -8,8 +8,8 @@ product as the online protocol), and the DO decrypts.  The parties keep
 <u'_i o v'_j>_0 = s_ij and <u'_i o v'_j>_1 = u'_i o v'_j - s_ij.
 
 Online (no homomorphic operation): Z_t linear combinations
-(pencil_zt_combine) and m + 1 plaintext products of the layer's operator
-(pencil_zt_linear).
+(pencil_zt_combine) and one plaintext product of the layer's operator per
+party (pencil_zt_linear), the per-mask products folded by linearity.
 
 Operators (the MO's operand u, the DO's operand v):
     fwd   u = W,      v = <X>_1   -> shaped like Y
@@ -84,13 +84,24 @@ def prep(ctx, layer, plan, kind, u_masks, v_masks, nonce):
 
 
 def online(ctx, layer, kind, u, v, u_masks, v_masks, share0, share1, k, l):
-    """Alg. 3's online phase.  Returns (<u o v>_0, <u o v>_1, u~, v~)."""
+    """Alg. 3's online phase.  Returns (<u o v>_0, <u o v>_1, u~, v~).
+
+    The per-mask terms are folded by linearity before any product:
+    sum_j l_j (u~ o v'_j) = u~ o (sum_j l_j v'_j), and the two-level share sums
+    are one sum with coefficients k_i l_j.  Each party then runs one Z_t
+    correlation per operator instead of m + 1; the outputs are the same
+    integers mod t, and the messages (u~, v~) and what each party uses are
+    unchanged (both parties know k and l)."""
     m = len(u_masks)
+    t = ctx.t
     u_t = ctx.zt_combine(u_masks, [-int(c) for c in k], base=u)                  # MO -> DO
     v_t = ctx.zt_combine(v_masks, [-int(c) for c in l], base=v)                  # DO -> MO
-    uvj0 = [ctx.zt_combine([share0[i][j] for i in range(m)], k) for j in range(m)]          # MO
-    uvj1 = [ctx.zt_combine([share1[i][j] for i in range(m)], k, base=apply(ctx, layer, kind, u_t, v_masks[j]))
-            for j in range(m)]                                                    # DO
-    out0 = ctx.zt_combine(uvj0, l, base=apply(ctx, layer, kind, u, v_t))        # MO
-    out1 = ctx.zt_combine(uvj1, l)                                               # DO
+    kl = [int(k[i]) * int(l[j]) % t for i in range(m) for j in range(m)]
+    # DO: sum_j l_j <u o v'_j>_1 = u~ o (sum_j l_j v'_j) + sum_ij k_i l_j <u'_i o v'_j>_1
+    v_l = ctx.zt_combine(v_masks, [int(c) for c in l])
+    out1 = ctx.zt_combine([share1[i][j] for i in range(m) for j in range(m)], kl,
+                          base=apply(ctx, layer, kind, u_t, v_l))
+    # MO: u o v~ + sum_ij k_i l_j <u'_i o v'_j>_0
+    out0 = ctx.zt_combine([share0[i][j] for i in range(m) for j in range(m)], kl,
+                          base=apply(ctx, layer, kind, u, v_t))
     return out0, out1, u_t, v_t
