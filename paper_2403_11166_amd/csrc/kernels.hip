@@ -1784,13 +1784,18 @@ hipError_t launch_zt_corr(const int64_t* a, const int64_t* k, int64_t* out, cons
   const int64_t rows = (int64_t)G.M * G.OH * G.OW, ctot = (int64_t)G.K * G.KH * G.KW;
   // Tiled kernel: 2 x 2 outputs per lane when that still gives >= 512
   // workgroups, else 1; about 16 contraction steps per wave, at most 16 waves.
-  // Its partial sums hold 2^22 terms per wave.
+  // Operands split at bit 21 (high part h = bitlen(t) - 21 bits): a partial
+  // sum takes terms below 2^42, 2^(22 + h) and 2^(2h), so a wave may sum
+  // 2^(64 - max) of them (2^22 for t < 2^42).
+  const int tb = 64 - __builtin_clzll(C.t), hb = tb > 21 ? tb - 21 : 0;
+  const int mb = std::max(42, std::max(22 + hb, 2 * hb));
+  const int64_t per_wave_max = mb >= 63 ? 1 : (int64_t)1 << (64 - mb);
   const int64_t blocks2 = ((rows + 15) / 16) * ((G.R + 15) / 16);
   const int ti = blocks2 >= 512 ? 2 : 1;
   const int64_t steps16 = ctot / 16;
   const int nw = steps16 < 1 ? 1 : steps16 > kZtWaves ? kZtWaves : (int)steps16;
   const int64_t gx = (rows + 8 * ti - 1) / (8 * ti), gy = ((int64_t)G.R + 8 * ti - 1) / (8 * ti);
-  if ((ctot + nw - 1) / nw <= (1ll << 22) && gx < (1ll << 31) && gy < 65536) {
+  if ((ctot + nw - 1) / nw <= per_wave_max && gx < (1ll << 31) && gy < 65536) {
     const dim3 grid((unsigned)gx, (unsigned)gy);
     if (ti == 2)
       hipLaunchKernelGGL(k_zt_gemm<2>, grid, dim3(64 * nw), 0, s, a, k, out, G, AV, KV, OV, C);

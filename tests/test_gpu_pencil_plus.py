@@ -112,3 +112,24 @@ def test_preprocessing_and_online_end_to_end(kind):
     out0, out1, _, _ = GP.online(ctx, layer, kind, dev(u), dev(v), [dev(x) for x in um], [dev(x) for x in vm],
                                  sh0, sh1, k, l)
     assert np.array_equal((host_i64(out0) + host_i64(out1)) % T, PP.apply(layer, kind, u, v, T))
+
+
+def test_zt_linear_with_a_47_bit_t_and_long_contraction():
+    """A plaintext modulus near 2^47 leaves the tiled correlation fewer terms per
+    wave before its partial sums could overflow; long contractions must still
+    be exact (checked in Python integers)."""
+    from oracle import linear as LN
+    from paper_2403_11166_amd import Context
+    t47 = 140737488355213
+    ctx = Context(12, 2, 50, 5, t=t47)
+    assert ctx.t == t47
+    rng = np.random.default_rng(47)
+    for layer in (fc(2, 20000, 3, log2_n=12, num_limbs=2, prime_bits=50),
+                  fc(3, 70, 5, log2_n=12, num_limbs=2, prime_bits=50)):
+        x = rng.integers(0, t47, layer.x_shape(), dtype=np.int64)
+        w = rng.integers(0, t47, layer.w_shape(), dtype=np.int64)
+        dy = rng.integers(0, t47, layer.y_shape(), dtype=np.int64)
+        got = host_i64(ctx.zt_linear(layer, "fwd", dev(x), dev(w)))
+        assert np.array_equal(got, LN.tensordot_mod_t_object(x, w, ([1], [1]), t47))
+        got = host_i64(ctx.zt_linear(layer, "dx", dev(dy), dev(w)))
+        assert np.array_equal(got, LN.tensordot_mod_t_object(dy, w, ([1], [0]), t47))
