@@ -233,7 +233,8 @@ pencil_status pencil_zt_combine(pencil_ctx* ctx, int64_t count, int n_terms, con
  * it on its own share of dY; the DO perturbs its result (pencil_dp_noise) and
  * sends it to the MO.  dy: device, int64 in [0, t), the layer's dY layout
  * (batch, c_out[, h_out, w_out]); db: device, c_out entries.  EUNSUPPORTED if
- * batch * h_out * w_out > 2^22.  Enqueued on `stream`. */
+ * batch * h_out * w_out > 2^(64 - bitlen(t)) (2^23 for the default t).
+ * Enqueued on `stream`. */
 pencil_status pencil_bias_grad(pencil_ctx* ctx, const pencil_layer* layer, const int64_t* dy, int64_t* db,
                                void* stream);
 

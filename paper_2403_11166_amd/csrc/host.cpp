@@ -1034,8 +1034,10 @@ extern "C" pencil_status pencil_bias_grad(pencil_ctx* ctx, const pencil_layer* L
   pencil_status st = PENCIL_OK;
   if (!layer_ok(ctx, L, &st)) return st;
   const int64_t spatial = (int64_t)ho_of(L) * wo_of(L);
-  if ((int64_t)L->batch * spatial > ((int64_t)1 << 22))
-    return fail(ctx, PENCIL_EUNSUPPORTED, "bias gradient sums at most 2^22 entries per channel");
+  // 64-bit sums of entries below t: at most 2^(64 - bitlen(t)) of them
+  const int tb = 64 - __builtin_clzll(ctx->C.t);
+  if ((int64_t)L->batch * spatial > ((int64_t)1 << (64 - tb)))
+    return fail(ctx, PENCIL_EUNSUPPORTED, "bias gradient sums at most 2^%d entries per channel", 64 - tb);
   hipError_t e = launch_bias_grad(dy, db, L->batch, L->c_out, (int)spatial, ctx->C, (hipStream_t)stream);
   if (e != hipSuccess) return fail(ctx, PENCIL_EHIP, "bias_grad launch: %s", hipGetErrorString(e));
   return PENCIL_OK;

@@ -1360,8 +1360,8 @@ __global__ void __launch_bounds__(256) k_zt_combine(ZtTerms T, const int64_t* ba
 
 // Bias gradient share (Sec. III.B.2): the sum of a dY share over the batch
 // and, for a convolution, over the output positions, mod t.  dy is
-// [batch][channels][spatial].  Entries are below t < 2^42 and at most 2^22 are
-// summed, so a 64-bit total is exact until the final reduction.
+// [batch][channels][spatial].  The host admits at most 2^(64 - bitlen(t))
+// entries per channel, so a 64-bit total is exact until the final reduction.
 __global__ void __launch_bounds__(256) k_bias_grad_cols(const int64_t* __restrict__ dy, int64_t* __restrict__ db,
                                                         int batch, int channels, Consts C) {
   const int o = blockIdx.x * 256 + threadIdx.x;

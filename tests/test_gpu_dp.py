@@ -70,12 +70,13 @@ def test_bias_grad_matches_oracle(layer):
 
 
 def test_bias_grad_limit():
+    """With t < 2^41, 2^23 entries of t - 1 still sum exactly in 64 bits."""
     ctx = context()
-    ok = conv(4, 1, 2, 1024, k=1, pad=0)        # 4 * 1024^2 = 2^22 entries per channel
+    ok = conv(8, 1, 1, 1024, k=1, pad=0)        # 8 * 1024^2 = 2^23 entries per channel
     dy = np.full(ok.y_shape(), T - 1, dtype=np.int64)
     got = host_i64(ctx.bias_grad(ok, dev(dy)))
     assert np.array_equal(got, DP.bias_grad(ok, dy, T))
-    big = conv(5, 1, 1, 1024, k=1, pad=0)
+    big = conv(9, 1, 1, 1024, k=1, pad=0)
     with pytest.raises(RuntimeError):
         ctx.bias_grad(big, dev(np.zeros(big.y_shape(), dtype=np.int64)))
 
