@@ -1336,6 +1336,124 @@ __global__ void __launch_bounds__(1024) k_zt_gemm(const int64_t* a, const int64_
   }
 }
 
+// The same correlation on the fp64 matrix cores.  Each operand, centred into
+// (-t/2, t/2), is split into signed 14-bit digits v = d0 + d1 2^14 + d2 2^28
+// (d0, d1 in [0, 2^14), d2 the signed rest); the nine digit products of a pair
+// land on five diagonals T_s = sum d_i e_j (i + j = s), each a 16 x 16 x 4
+// fp64 multiply-accumulate.  Every digit product and running sum is an
+// integer below 2^53 (the launcher bounds the terms per wave), so the fp64
+// arithmetic is exact; at the end each T_s is reduced mod t and the five are
+// recombined with 2^14s mod t.  A workgroup owns a 16 x 16 output tile and
+// splits the contraction over its waves, four contraction indices per step.
+// Lane l holds A[row l % 16][c + l / 16] and B[c + l / 16][col l % 16], and
+// register r of its accumulator holds output (l / 16 + 4 r, l % 16).
+typedef double zt_v4d __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void zt_digits(uint64_t v, const Consts& C, double (&d)[3]) {
+  const int64_t c = v > C.t_half ? (int64_t)v - (int64_t)C.t : (int64_t)v;
+  const int64_t d0 = c & 0x3FFF, r1 = c >> 14, d1 = r1 & 0x3FFF, d2 = r1 >> 14;
+  d[0] = (double)d0;
+  d[1] = (double)d1;
+  d[2] = (double)d2;
+}
+
+__device__ __forceinline__ uint64_t zt_mod_signed(int64_t x, const Consts& C) {
+  const uint64_t u = x < 0 ? (uint64_t)(-x) : (uint64_t)x;
+  const uint64_t r = reduce64(u, C.one_sh_t, C.t);
+  return x < 0 && r ? C.t - r : r;
+}
+
+__global__ void __launch_bounds__(1024) k_zt_mfma(const int64_t* a, const int64_t* kt, int64_t* out, Geo G, View AV,
+                                                  View KV, View OV, Consts C) {
+  __shared__ uint64_t red[kZtWaves][256];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int P = G.M * G.OH * G.OW, R = G.R, ohw = G.OH * G.OW;
+  const PENCIL_GLOBAL int64_t* ga = gview(a);
+  const PENCIL_GLOBAL int64_t* gk = gview(kt);
+  const int lr = lane & 15, lc = lane >> 4;
+  // this lane's A row and B column
+  const int row = blockIdx.x * 16 + lr, col = blockIdx.y * 16 + lr;
+  const bool rv = row < P, cv = col < R;
+  int64_t abase, kbase;
+  int ay, ax;
+  {
+    const int rr = rv ? row : 0;
+    const int m = rr / ohw, rem = rr - m * ohw, y = rem / G.OW, x = rem - y * G.OW;
+    abase = (int64_t)m * AV.s0;
+    ay = y - AV.pady;
+    ax = x - AV.pad;
+    kbase = (int64_t)(cv ? col : 0) * KV.s0;
+  }
+  const int kk = G.KH * G.KW;
+  const int64_t ctot = (int64_t)G.K * kk;
+  const int64_t steps = (ctot + 3) / 4, per = (steps + nw - 1) / nw;
+  const int64_t s_begin = wv * per, s_end = s_begin + per < steps ? s_begin + per : steps;
+  zt_v4d acc[5];
+#pragma unroll
+  for (int s = 0; s < 5; ++s) acc[s] = zt_v4d{0, 0, 0, 0};
+  constexpr int U = 4;  // contraction steps whose loads are issued together
+  for (int64_t st0 = s_begin; st0 < s_end; st0 += U) {
+    uint64_t av[U], bv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t c = (st0 + u) * 4 + lc;
+      const bool live = st0 + u < s_end && c < ctot;
+      int k = 0, dy = 0, dx = 0;
+      if (kk == 1) {
+        k = (int)c;
+      } else {
+        k = (int)(c / kk);
+        const int rem = (int)(c - (int64_t)k * kk);
+        dy = rem / G.KW;
+        dx = rem - dy * G.KW;
+      }
+      const int ky = KV.flip ? KV.KH - 1 - dy : dy, kx = KV.flip ? KV.KW - 1 - dx : dx;
+      bv[u] = live && cv ? (uint64_t)gk[kbase + (int64_t)k * KV.s1 + (int64_t)ky * KV.sy + (int64_t)kx * KV.sx] : 0;
+      const int ys = ay + dy, xs = ax + dx;
+      const bool in = live && rv && ys >= 0 && ys < AV.H && xs >= 0 && xs < AV.W;
+      av[u] = in ? (uint64_t)ga[abase + (int64_t)k * AV.s1 + (int64_t)ys * AV.sy + (int64_t)xs * AV.sx] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      double da[3], db[3];
+      zt_digits(av[u], C, da);
+      zt_digits(bv[u], C, db);
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) acc[i + j] = __builtin_amdgcn_mfma_f64_16x16x4f64(da[i], db[j], acc[i + j], 0, 0, 0);
+    }
+  }
+  // 2^(14 s) mod t
+  uint64_t pw[5];
+  pw[0] = 1;
+#pragma unroll
+  for (int s = 1; s < 5; ++s) pw[s] = reduce64((uint64_t)1 << (14 * s), C.one_sh_t, C.t);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    uint64_t hi = 0, lo = 0;
+#pragma unroll
+    for (int s = 0; s < 5; ++s) {
+      uint64_t ph, pl;
+      mul_wide(zt_mod_signed((int64_t)acc[s][r], C), pw[s], ph, pl);
+      lo += pl;
+      hi += ph + (lo < pl ? 1 : 0);
+    }
+    red[wv][(lc + 4 * r) * 16 + lr] =
+        add_mod(mul_shoup(reduce64(hi, C.one_sh_t, C.t), C.r64t, C.r64t_sh, C.t), reduce64(lo, C.one_sh_t, C.t), C.t);
+  }
+  __syncthreads();
+  for (int o = threadIdx.x; o < 256; o += blockDim.x) {
+    uint64_t v = 0;
+    for (int w = 0; w < nw; ++w) v = add_mod(v, red[w][o], C.t);
+    const int orow = blockIdx.x * 16 + o / 16, ocol = blockIdx.y * 16 + o % 16;
+    if (orow < P && ocol < R) {
+      const int m = orow / ohw, rem = orow - m * ohw, y = rem / G.OW, x = rem - y * G.OW;
+      gview(out)[(int64_t)m * OV.s0 + (int64_t)ocol * OV.s1 + (int64_t)y * OV.sy + (int64_t)x * OV.sx] = (int64_t)v;
+    }
+  }
+}
+
 // Z_t linear combination out = base + sum_i c_i x_i (mod t), one thread per
 // element: the masked operands and share combinations of the preprocessed
 // products (Pencil+, online phase).  Operands and coefficients are below
@@ -1790,6 +1908,25 @@ hipError_t launch_zt_corr(const int64_t* a, const int64_t* k, int64_t* out, cons
   const int tb = 64 - __builtin_clzll(C.t), hb = tb > 21 ? tb - 21 : 0;
   const int mb = std::max(42, std::max(22 + hb, 2 * hb));
   const int64_t per_wave_max = mb >= 63 ? 1 : (int64_t)1 << (64 - mb);
+  // Matrix-core kernel when there are at least 256 output tiles of 16 x 16
+  // (with fewer, the vector kernel's smaller tiles spread the work wider and
+  // measured faster): four contraction indices per step, about eight steps per
+  // wave, at most 16 waves; a diagonal sum takes per-term values below 2^30
+  // (t < 2^43; 2^(2 bitlen(t) - 58) above), so a wave may run
+  // 2^53 / (4 * that) steps.
+  if (((rows + 15) / 16) * ((G.R + 15) / 16) >= 256) {
+    const int d2b = tb > 29 ? tb - 29 : 0;  // bits of the top digit
+    const int termb = std::max(30, std::max(tb - 13, 2 * d2b));
+    const int64_t steps = (ctot + 3) / 4;
+    const int64_t max_steps = termb >= 51 ? 0 : (int64_t)1 << (51 - termb);
+    int nwm = (int)std::min<int64_t>(kZtWaves, std::max<int64_t>(1, steps / 8));
+    const int64_t gx = (rows + 15) / 16, gy = ((int64_t)G.R + 15) / 16;
+    if ((steps + nwm - 1) / nwm <= max_steps && gx < (1ll << 31) && gy < 65536) {
+      hipLaunchKernelGGL(k_zt_mfma, dim3((unsigned)gx, (unsigned)gy), dim3(64 * nwm), 0, s, a, k, out, G, AV, KV, OV,
+                         C);
+      return hipGetLastError();
+    }
+  }
   const int64_t blocks2 = ((rows + 15) / 16) * ((G.R + 15) / 16);
   const int ti = blocks2 >= 512 ? 2 : 1;
   const int64_t steps16 = ctot / 16;

@@ -133,3 +133,23 @@ def test_zt_linear_with_a_47_bit_t_and_long_contraction():
         assert np.array_equal(got, LN.tensordot_mod_t_object(x, w, ([1], [1]), t47))
         got = host_i64(ctx.zt_linear(layer, "dx", dev(dy), dev(w)))
         assert np.array_equal(got, LN.tensordot_mod_t_object(dy, w, ([1], [0]), t47))
+
+
+def test_zt_linear_matrix_core_path_with_a_47_bit_t():
+    """Weight-gradient-shaped correlations with many 16 x 16 output tiles run on
+    the fp64 matrix-core kernel; with a 47-bit t its top digits are large."""
+    from oracle import linear as LN
+    from paper_2403_11166_amd import Context
+    t47 = 140737488355213
+    ctx = Context(12, 2, 50, 6, t=t47)
+    rng = np.random.default_rng(48)
+    for layer, op in ((fc(64, 600, 500, log2_n=12, num_limbs=2, prime_bits=50), "dw"),
+                      (conv(2, 64, 128, 6, k=3, pad=1, log2_n=12, num_limbs=2, prime_bits=50), "dw"),
+                      (conv(8, 8, 128, 12, k=3, pad=1, log2_n=12, num_limbs=2, prime_bits=50), "fwd")):
+        x = rng.integers(0, t47, layer.x_shape(), dtype=np.int64)
+        w = rng.integers(0, t47, layer.w_shape(), dtype=np.int64)
+        dy = rng.integers(0, t47, layer.y_shape(), dtype=np.int64)
+        a, b = (x, dy) if op == "dw" else (x, w)
+        got = host_i64(ctx.zt_linear(layer, op, dev(a), dev(b)))
+        want = LN.layer_op(layer, op, a, b, t47, tdot=LN.tensordot_mod_t_object)
+        assert np.array_equal(got, want), (layer, op)
