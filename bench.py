@@ -67,7 +67,7 @@ def parse():
 
 # ------------------------------------------------------------- hbm traffic
 
-KERNEL_SOURCES = ("kernels.hip", "modarith.h", "pencil_internal.h")
+KERNEL_SOURCES = ("kernels.hip", "modarith.h", "pencil_internal.h", "host.cpp")  # host.cpp: the planner
 
 
 def kernel_source_hash():
@@ -624,6 +624,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_step, 4),
+        "steps_per_s": round(1e3 / ms_step, 1),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

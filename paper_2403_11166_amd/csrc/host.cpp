@@ -621,10 +621,13 @@ static pencil_status get_geo(pencil_ctx* ctx, const pencil_layer* L, const penci
 
 // ------------------------------------------------------------ planner
 
-// Work model, in units of one pointwise product-accumulate of one residue:
-// an NTT of one limb-polynomial costs about (N/2) log2 N Shoup butterflies of
-// ~2.5 units each; a product costs 2 components per limb.  HBM traffic is
-// charged through the polynomials read and written.
+// Work model, in units of one pointwise product-accumulate of one residue.
+// An NTT of one limb-polynomial costs (N/2) log2 N butterflies of ~1.4 units
+// each, a product 2 components per limb; both weights are calibrated on
+// MI355X step-kernel times (N = 8192: ~88 ns per limb transform, ~19 ns per
+// limb product).  Input ciphertexts arrive in the NTT domain: the MO
+// transforms only its share (component 0 of fwd and dx operands) and splits
+// and copies the rest, a copy of a polynomial costing ~0.36 of its transform.
 struct Cost {
   double ntt_polys, products;
 };
@@ -632,11 +635,14 @@ struct Cost {
 static Cost op_cost(const Geo& G, int op) {
   Cost c{};
   const double na = (double)n_a_tiles(G), nk = (double)n_k_tiles(G), no = (double)n_out_tiles(G);
+  constexpr double kCopy = 0.36;
   if (op == PENCIL_OP_DW) {
-    c.ntt_polys = 3 * na + 3 * nk + 3 * no;  // x1 ct + x0 pt, dy0 pt + dy1 ct, outputs + u'
+    // x1 ct (copied) + x0 pt, dy0 pt + dy1 ct (copied), outputs (2 inverse) + u'
+    c.ntt_polys = na * (1 + 2 * kCopy) + nk * (1 + 2 * kCopy) + 3 * no;
     c.products = 2.0 * (double)n_products(G);
   } else {
-    c.ntt_polys = 2 * na + nk + 3 * no;
+    // ct: share transform + copy of component 1; pt; outputs + u'
+    c.ntt_polys = na * (1 + kCopy) + nk + 3 * no;
     c.products = (double)n_products(G);
   }
   return c;
@@ -644,7 +650,7 @@ static Cost op_cost(const Geo& G, int op) {
 
 static double cost_value(const Cost& c, int log2n) {
   const double n = (double)(1 << log2n);
-  return c.ntt_polys * (n / 2) * log2n * 2.5 + c.products * 2 * n;
+  return c.ntt_polys * (n / 2) * log2n * 1.4 + c.products * 2 * n;
 }
 
 // Candidate tile sizes along a dimension of extent D: the smallest size for each
