@@ -16,6 +16,7 @@ template <class T>
 __device__ __forceinline__ PENCIL_GLOBAL T* gview(T* p) {
   return (PENCIL_GLOBAL T*)p;
 }
+typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
 
 
 // ----------------------------------------------------------------- NTT core
@@ -339,8 +340,13 @@ __device__ __forceinline__ void do_ntt_ct(uint64_t* lds, const uint64_t* src, ui
   const LimbConst& lc = C.limb[l];
   const PENCIL_GLOBAL uint64_t* g = gview(src + p * n);
   PENCIL_GLOBAL uint64_t* o = gview(dst + p * n);
-  if (share == nullptr || c != 0) {
-    for (int i = threadIdx.x; i < n; i += blockDim.x) o[i] = split30(g[i]);
+  if (share == nullptr || c != 0) {  // 16-byte accesses: a polynomial is 16-byte aligned
+    const PENCIL_GLOBAL u64x2* g2 = (const PENCIL_GLOBAL u64x2*)g;
+    PENCIL_GLOBAL u64x2* o2 = (PENCIL_GLOBAL u64x2*)o;
+    for (int i = threadIdx.x; i < n / 2; i += blockDim.x) {
+      const u64x2 v = g2[i];
+      o2[i] = u64x2{split30(v[0]), split30(v[1])};
+    }
     return;
   }
   const PENCIL_GLOBAL int64_t* gshare = gview(share);
@@ -838,7 +844,6 @@ __global__ void __launch_bounds__(512) k_mac_direct_small(MacArgs A, Geo G, Cons
   do_mac<2>(nullptr, A, G, C, w / chunks, w % chunks);
 }
 
-typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
 
 // Output ciphertexts after the inverse NTT: c0 += e0' + flood - round(q s / t),
 // c1 += e1'; the model owner's share is s at the output slots (+ bias).
