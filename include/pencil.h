@@ -19,15 +19,19 @@
  * Conventions
  *   Layouts  Z_t tensors are int64 in [0, t), contiguous, PyTorch layout:
  *            FC activations (B, c_in), weights (c_out, c_in); Conv2d
- *            activations (B, C, H, W), weights (c_out, c_in, k, k).  Stride 1.
+ *            activations (B, C, H, W), weights (c_out, c_in, k, k); Conv1d
+ *            activations (B, C, W), weights (c_out, c_in, k).
  *            A ciphertext is uint64 [2][L][N] (component, RNS limb,
- *            coefficient), coefficient domain; a ciphertext buffer holds
- *            pencil_sizes.n_ct[...] (or n_out[...]) of them back to back, in the
- *            tile order of the plan.
+ *            residue): the DO's input ciphertexts (pencil_encrypt) are in the
+ *            NTT domain, the products' outputs in the coefficient domain; a
+ *            ciphertext buffer holds pencil_sizes.n_ct[...] (or n_out[...]) of
+ *            them back to back, in the tile order of the plan.
  *   Memory   Every tensor, ciphertext and workspace pointer is DEVICE memory
- *            owned by the caller, sized with pencil_layout.  The context owns
- *            only its keys and tables, allocated once in pencil_ctx_create.
- *            Functions marked (host) take host pointers.
+ *            owned by the caller, sized with pencil_layout; ciphertext,
+ *            polynomial and workspace pointers must be 16-byte aligned
+ *            (EINVAL otherwise).  The context owns only its keys and tables,
+ *            allocated once in pencil_ctx_create.  Functions marked (host)
+ *            take host pointers.
  *   Streams  `stream` is a hipStream_t (NULL = default stream).  Calls enqueue
  *            their kernels and return without synchronising, except where
  *            noted.  Buffers must stay valid until the stream reaches them.

@@ -795,6 +795,14 @@ static pencil_status check_ptr(pencil_ctx* ctx, const void* p, const char* name)
   return PENCIL_OK;
 }
 
+// Ciphertext, polynomial and workspace buffers: non-NULL and 16-byte aligned
+// (the transforms move residues in 16-byte pairs).
+static pencil_status check_buf(pencil_ctx* ctx, const void* p, const char* name) {
+  if (!p) return fail(ctx, PENCIL_EINVAL, "%s is NULL", name);
+  if (((uintptr_t)p & 15) != 0) return fail(ctx, PENCIL_EINVAL, "%s is not 16-byte aligned", name);
+  return PENCIL_OK;
+}
+
 #define TRY(x)                          \
   do {                                  \
     pencil_status _s = (x);             \
@@ -806,8 +814,8 @@ extern "C" pencil_status pencil_encrypt(pencil_ctx* ctx, const pencil_layer* L, 
   if (!ctx) return PENCIL_EINVAL;
   if (operand < 0 || operand > 3) return fail(ctx, PENCIL_EINVAL, "operand %d invalid", operand);
   TRY(check_ptr(ctx, share, "share"));
-  TRY(check_ptr(ctx, ct, "ct"));
-  TRY(check_ptr(ctx, ws, "ws"));
+  TRY(check_buf(ctx, ct, "ct"));
+  TRY(check_buf(ctx, ws, "ws"));
   const int op = operand == PENCIL_X_FWD ? PENCIL_OP_FWD : operand == PENCIL_DY_DX ? PENCIL_OP_DX : PENCIL_OP_DW;
   const int side = operand == PENCIL_DY_DW ? 1 : 0;
   Geo G;
@@ -895,12 +903,12 @@ extern "C" pencil_status pencil_linear_fwd(pencil_ctx* ctx, const pencil_layer* 
                                            const int64_t* bias, uint64_t* ct_y, int64_t* y0, void* ws,
                                            uint64_t nonce, void* stream) {
   if (!ctx) return PENCIL_EINVAL;
-  TRY(check_ptr(ctx, ct_x1, "ct_x1"));
+  TRY(check_buf(ctx, ct_x1, "ct_x1"));
   TRY(check_ptr(ctx, x0, "x0"));
   TRY(check_ptr(ctx, w, "w"));
-  TRY(check_ptr(ctx, ct_y, "ct_y"));
+  TRY(check_buf(ctx, ct_y, "ct_y"));
   TRY(check_ptr(ctx, y0, "y0"));
-  TRY(check_ptr(ctx, ws, "ws"));
+  TRY(check_buf(ctx, ws, "ws"));
   Geo G;
   TRY(get_geo(ctx, L, P, PENCIL_OP_FWD, &G));
   if (!mac_grid_ok(G)) return fail(ctx, PENCIL_EUNSUPPORTED, "too many output tiles for one launch");
@@ -915,13 +923,13 @@ extern "C" pencil_status pencil_linear_bwd(pencil_ctx* ctx, const pencil_layer* 
                                            const int64_t* w, uint64_t* ct_dx, int64_t* dx0, uint64_t* ct_dw,
                                            int64_t* dw_mask, void* ws, uint64_t nonce, void* stream) {
   if (!ctx) return PENCIL_EINVAL;
-  TRY(check_ptr(ctx, ws, "ws"));
+  TRY(check_buf(ctx, ws, "ws"));
   TRY(check_ptr(ctx, dy0, "dy0"));
   hipStream_t s = (hipStream_t)stream;
   if (ct_dx || dx0) {
-    TRY(check_ptr(ctx, ct_dy_dx, "ct_dy_dx"));
+    TRY(check_buf(ctx, ct_dy_dx, "ct_dy_dx"));
     TRY(check_ptr(ctx, w, "w"));
-    TRY(check_ptr(ctx, ct_dx, "ct_dx"));
+    TRY(check_buf(ctx, ct_dx, "ct_dx"));
     TRY(check_ptr(ctx, dx0, "dx0"));
     Geo G;
     TRY(get_geo(ctx, L, P, PENCIL_OP_DX, &G));
@@ -930,10 +938,10 @@ extern "C" pencil_status pencil_linear_bwd(pencil_ctx* ctx, const pencil_layer* 
     TRY(run_product(ctx, L, PENCIL_OP_DX, G, &t, 1, dy0, nullptr, ct_dx, dx0, (uint8_t*)ws, nonce, P->sched[1], s));
   }
   if (ct_dw || dw_mask) {
-    TRY(check_ptr(ctx, ct_x_dw, "ct_x_dw"));
-    TRY(check_ptr(ctx, ct_dy_dw, "ct_dy_dw"));
+    TRY(check_buf(ctx, ct_x_dw, "ct_x_dw"));
+    TRY(check_buf(ctx, ct_dy_dw, "ct_dy_dw"));
     TRY(check_ptr(ctx, x0, "x0"));
-    TRY(check_ptr(ctx, ct_dw, "ct_dw"));
+    TRY(check_buf(ctx, ct_dw, "ct_dw"));
     TRY(check_ptr(ctx, dw_mask, "dw_mask"));
     Geo G;
     TRY(get_geo(ctx, L, P, PENCIL_OP_DW, &G));
@@ -949,9 +957,9 @@ extern "C" pencil_status pencil_decrypt(pencil_ctx* ctx, const pencil_layer* L, 
                                         const uint64_t* ct, int64_t* share, void* ws, void* stream) {
   if (!ctx) return PENCIL_EINVAL;
   if (op < 0 || op > 2) return fail(ctx, PENCIL_EINVAL, "op %d invalid", op);
-  TRY(check_ptr(ctx, ct, "ct"));
+  TRY(check_buf(ctx, ct, "ct"));
   TRY(check_ptr(ctx, share, "share"));
-  TRY(check_ptr(ctx, ws, "ws"));
+  TRY(check_buf(ctx, ws, "ws"));
   Geo G;
   TRY(get_geo(ctx, L, P, op, &G));
   const int64_t no = n_out_tiles(G);
@@ -965,7 +973,7 @@ extern "C" pencil_status pencil_decrypt(pencil_ctx* ctx, const pencil_layer* L, 
 
 extern "C" pencil_status pencil_ntt_forward(pencil_ctx* ctx, uint64_t* polys, int64_t count, void* stream) {
   if (!ctx) return PENCIL_EINVAL;
-  TRY(check_ptr(ctx, polys, "polys"));
+  TRY(check_buf(ctx, polys, "polys"));
   if (count < 0) return fail(ctx, PENCIL_EINVAL, "count < 0");
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = timed(ctx, KID_NTT_PLAIN, s, [&] { return launch_ntt_plain(polys, count, false, ctx->C, ctx->T, s); });
@@ -975,7 +983,7 @@ extern "C" pencil_status pencil_ntt_forward(pencil_ctx* ctx, uint64_t* polys, in
 
 extern "C" pencil_status pencil_ntt_inverse(pencil_ctx* ctx, uint64_t* polys, int64_t count, void* stream) {
   if (!ctx) return PENCIL_EINVAL;
-  TRY(check_ptr(ctx, polys, "polys"));
+  TRY(check_buf(ctx, polys, "polys"));
   if (count < 0) return fail(ctx, PENCIL_EINVAL, "count < 0");
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = timed(ctx, KID_NTT_PLAIN, s, [&] { return launch_ntt_plain(polys, count, true, ctx->C, ctx->T, s); });
@@ -1265,6 +1273,13 @@ static void add_seg(pencil_step::Phase& ph, StepSeg sg, int64_t blocks) {
 
 extern "C" pencil_status pencil_step_bind(pencil_step* st, const pencil_step_io* io, void* ws) {
   if (!st || !io || !ws) return step_fail(st, PENCIL_EINVAL, "NULL argument");
+  // ciphertext buffers and the workspace are moved in 16-byte pairs
+  auto misaligned = [](const void* p) { return p && ((uintptr_t)p & 15) != 0; };
+  if (misaligned(ws)) return step_fail(st, PENCIL_EINVAL, "ws is not 16-byte aligned");
+  for (size_t i = 0; i < st->layers.size(); ++i)
+    if (misaligned(io[i].ct_x1) || misaligned(io[i].ct_dy_dx) || misaligned(io[i].ct_x_dw) ||
+        misaligned(io[i].ct_dy_dw) || misaligned(io[i].ct_y) || misaligned(io[i].ct_dx) || misaligned(io[i].ct_dw))
+      return step_fail(st, PENCIL_EINVAL, "a ciphertext buffer is not 16-byte aligned");
   for (auto& ph : st->phases) hipFree(ph.d_segs);
   st->phases.clear();
   if (st->exec) {

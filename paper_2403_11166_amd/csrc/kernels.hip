@@ -306,15 +306,22 @@ __device__ __forceinline__ void do_ntt_plain(uint64_t* lds, uint64_t* data, int 
   const int L = C.L;
   const int l = (int)(p % L);
   const LimbConst& lc = C.limb[l];
-  PENCIL_GLOBAL uint64_t* g = gview(data + p * n);
-  for (int i = threadIdx.x; i < n; i += blockDim.x) lds[lpad(i)] = g[i];
+  // residues move in 16-byte pairs; a pair never straddles an LDS pad word
+  PENCIL_GLOBAL u64x2* g = (PENCIL_GLOBAL u64x2*)gview(data + p * n);
+  for (int i = threadIdx.x; i < n / 2; i += blockDim.x) {
+    const u64x2 v = g[i];
+    lds[lpad(2 * i)] = v[0];
+    lds[lpad(2 * i) + 1] = v[1];
+  }
   __syncthreads();
   if (!inverse) {
     ntt_fwd<LOGN, LOGE>(lds, T.fw + (int64_t)l * n, lc.q);
-    for (int i = threadIdx.x; i < n; i += blockDim.x) g[i] = lds[lpad(i)];
+    for (int i = threadIdx.x; i < n / 2; i += blockDim.x) g[i] = u64x2{lds[lpad(2 * i)], lds[lpad(2 * i) + 1]};
   } else {
     ntt_inv<LOGN, LOGE>(lds, T.iw + (int64_t)l * n, lc.q);
-    for (int i = threadIdx.x; i < n; i += blockDim.x) g[i] = mul_shoup(lds[lpad(i)], lc.ninv, lc.ninv_sh, lc.q);
+    for (int i = threadIdx.x; i < n / 2; i += blockDim.x)
+      g[i] = u64x2{mul_shoup(lds[lpad(2 * i)], lc.ninv, lc.ninv_sh, lc.q),
+                   mul_shoup(lds[lpad(2 * i) + 1], lc.ninv, lc.ninv_sh, lc.q)};
   }
 }
 
@@ -361,7 +368,14 @@ __device__ __forceinline__ void do_ntt_ct(uint64_t* lds, const uint64_t* src, ui
   }
   __syncthreads();
   ntt_fwd<LOGN, LOGE>(lds, T.fw + (int64_t)l * n, lc.q);
-  for (int i = threadIdx.x; i < n; i += blockDim.x) o[i] = split30(add_mod(g[i], lds[lpad(i)], lc.q));
+  {
+    const PENCIL_GLOBAL u64x2* g2 = (const PENCIL_GLOBAL u64x2*)g;
+    PENCIL_GLOBAL u64x2* o2 = (PENCIL_GLOBAL u64x2*)o;
+    for (int i = threadIdx.x; i < n / 2; i += blockDim.x) {
+      const u64x2 v = g2[i];
+      o2[i] = u64x2{split30(add_mod(v[0], lds[lpad(2 * i)], lc.q)), split30(add_mod(v[1], lds[lpad(2 * i) + 1], lc.q))};
+    }
+  }
 }
 
 template <int LOGN, int LOGE>
@@ -394,7 +408,9 @@ __device__ __forceinline__ void do_ntt_pt(uint64_t* lds, const int64_t* tensor, 
   __syncthreads();
   ntt_fwd<LOGN, LOGE>(lds, T.fw + (int64_t)l * n, lc.q);
   PENCIL_GLOBAL uint64_t* o = gview(dst + p * n);
-  for (int i = threadIdx.x; i < n; i += blockDim.x) o[i] = split30(lds[lpad(i)]);
+  PENCIL_GLOBAL u64x2* o2 = (PENCIL_GLOBAL u64x2*)o;
+  for (int i = threadIdx.x; i < n / 2; i += blockDim.x)
+    o2[i] = u64x2{split30(lds[lpad(2 * i)]), split30(lds[lpad(2 * i) + 1])};
 }
 
 template <int LOGN, int LOGE>
@@ -427,11 +443,12 @@ __device__ __forceinline__ void do_ntt_ternary(uint64_t* lds, uint64_t* dst, uin
   }
   __syncthreads();
   ntt_fwd<LOGN, LOGE>(lds, T.fw + (int64_t)l * n, lc.q);
-  PENCIL_GLOBAL uint64_t* o = gview(dst + p * n);
+  PENCIL_GLOBAL u64x2* o2 = (PENCIL_GLOBAL u64x2*)gview(dst + p * n);
   if (split)
-    for (int i = threadIdx.x; i < n; i += blockDim.x) o[i] = split30(lds[lpad(i)]);
+    for (int i = threadIdx.x; i < n / 2; i += blockDim.x)
+      o2[i] = u64x2{split30(lds[lpad(2 * i)]), split30(lds[lpad(2 * i) + 1])};
   else
-    for (int i = threadIdx.x; i < n; i += blockDim.x) o[i] = lds[lpad(i)];
+    for (int i = threadIdx.x; i < n / 2; i += blockDim.x) o2[i] = u64x2{lds[lpad(2 * i)], lds[lpad(2 * i) + 1]};
 }
 
 template <int LOGN, int LOGE>

@@ -202,3 +202,14 @@ def test_bias_is_added_to_model_owner_share():
     _, y0b = ctx.linear_fwd(layer, tiles, ct_x, dev(ts["x0"]), dev(ts["W"]), 8, bias=dev(bias))
     d = (host_i64(y0b) - host_i64(y0)) % ctx.t
     assert (d == bias.reshape(1, -1, 1, 1)).all()
+
+
+def test_misaligned_buffers_are_rejected_on_the_host():
+    """Polynomial and ciphertext buffers move in 16-byte pairs: an 8-byte-offset
+    pointer is refused before any launch."""
+    ctx = context(12, 2, 50, 1)
+    flat = torch.zeros(ctx.L * ctx.n + 1, dtype=torch.int64, device="cuda")
+    with pytest.raises(RuntimeError, match="aligned"):
+        ctx.ntt(flat[1:])
+    ctx.ntt(flat[:-1])   # the aligned view is accepted
+    torch.cuda.synchronize()
