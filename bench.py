@@ -13,7 +13,7 @@ three 60-bit RNS primes (the first layer of the paper's MNIST MLP).  After the
 timed region the outputs are decrypted and checked bit for bit against exact
 modular linear algebra (float64 digit products, exact below 2^53).
 
-Prints one JSON line.  `--gpus N` with N > 1 exits: this build runs on one GPU.
+Prints one JSON line.  `--gpus N` with N > 1 exits: the benchmark runs on one GPU.
 """
 import argparse
 import json
@@ -341,7 +341,7 @@ def cpu_baseline(layer, seconds):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: measures one GPU; --gpus {args.gpus} is not supported "
               "(sharding across GPUs is designed, not built)", file=sys.stderr)
         sys.exit(2)
     if args.copy_probe:

@@ -25,7 +25,7 @@ product is commutative, so a reverse-encoded ciphertext of dY times a
 forward-encoded plaintext of X lands in the same output slots (Alg. 2).
 
 Operands larger than N slots are partitioned (App. A says they "could be
-partitioned"; the scheme is this build's): a tile takes m_t x r_t x k_t
+partitioned"; the scheme is a reading of it): a tile takes m_t x r_t x k_t
 channels and an output window oh_t x ow_t with a kernel window kh_t x kw_t,
 so the A tile is (oh_t + kh_t - 1) x (ow_t + kw_t - 1) and the tile fits when
 m_t * r_t * k_t * HA_t * WA_t <= N.  Partial products over contraction tiles
