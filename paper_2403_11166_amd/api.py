@@ -5,6 +5,8 @@ Ciphertexts are held in int64 tensors whose bits are the uint64 residues
 ([n][2][L][N]); Z_t tensors are int64 in [0, t).
 """
 import ctypes
+import os
+import threading
 
 import torch
 
@@ -70,10 +72,44 @@ def _need(t, name):
         raise ValueError(f"{name} must be a contiguous int64 CUDA tensor")
 
 
-class Context:
-    """A BFV parameter set, its key pair and NTT tables on the current GPU."""
+# Every random value is drawn from Philox keyed by (seed, nonce): two calls that
+# share a seed must not share a nonce.  Nonces drawn automatically (by the
+# autograd engines and Context.reserve_nonces) come from one counter per seed
+# for the whole process, starting at 2^32 so that they stay clear of the small
+# explicit nonces of tests and benchmarks.
+AUTO_NONCE_BASE = 1 << 32
+_auto_nonces = {}
+_auto_lock = threading.Lock()
 
-    def __init__(self, log2_n, num_limbs, prime_bits=60, seed=0, t=0, flood_bits=0, primes=None):
+
+def reserve_nonces(seed, count=1):
+    """Reserve `count` consecutive nonces for key seed `seed`; returns the first.
+    Reservations for one seed never overlap within the process."""
+    if count < 1:
+        raise ValueError("reserve_nonces: count must be positive")
+    with _auto_lock:
+        first = _auto_nonces.get(seed, AUTO_NONCE_BASE)
+        if first + count > 1 << 64:
+            raise RuntimeError("reserve_nonces: nonce space of this seed exhausted")
+        _auto_nonces[seed] = first + count
+    return first
+
+
+def fresh_seed():
+    """A key seed from the operating system's random source."""
+    return int.from_bytes(os.urandom(8), "little")
+
+
+class Context:
+    """A BFV parameter set, its key pair and NTT tables on the current GPU.
+
+    seed keys every random value (the key pair included); None draws a fresh
+    one from the operating system, so that separately created contexts never
+    share keys or random streams by accident."""
+
+    def __init__(self, log2_n, num_limbs, prime_bits=60, seed=None, t=0, flood_bits=0, primes=None):
+        if seed is None:
+            seed = fresh_seed()
         self.lib = A.load()
         p = A.Params()
         p.log2_n, p.num_limbs, p.prime_bits, p.flood_bits = log2_n, num_limbs, prime_bits, flood_bits
@@ -96,8 +132,12 @@ class Context:
         self.device = torch.device("cuda", torch.cuda.current_device())
 
     @classmethod
-    def for_layer(cls, layer, seed=0):
+    def for_layer(cls, layer, seed=None):
         return cls(layer.log2_n, layer.num_limbs, layer.prime_bits, seed)
+
+    def reserve_nonces(self, count=1):
+        """`count` consecutive nonces no other reservation on this key seed holds."""
+        return reserve_nonces(self.seed, count)
 
     def _check(self, st):
         A.check(st, self.h)

@@ -16,7 +16,7 @@ draws the share and nonce randomness.
 """
 import torch
 
-from .api import Context, _get, stride_map
+from .api import Context, _get, fresh_seed, stride_map
 
 
 def _to_zt(x, t):
@@ -37,19 +37,20 @@ class EncryptedLinearEngine:
     owner's perturbation of its weight- and bias-gradient shares (Sec. III.B.2;
     0 = none)."""
 
-    def __init__(self, layer, ctx: Context, plan=None, seed=0, dp_sd_w=0.0, dp_sd_b=0.0):
+    def __init__(self, layer, ctx: Context, plan=None, seed=None, dp_sd_w=0.0, dp_sd_b=0.0):
         self.layer = layer
         self.strided = int(_get(layer, "stride", 1)) > 1
         self.eq = stride_map(layer) if self.strided else layer
         self.ctx = ctx
         self.plan = ctx.plan_auto(self.eq) if plan is None else plan
         self.gen = torch.Generator(device=ctx.device)
-        self.gen.manual_seed(seed)
-        self.nonce = 1 << 32
+        self.gen.manual_seed(fresh_seed() & ((1 << 63) - 1) if seed is None else seed)
+        self.nonce = None  # the last nonce drawn
         self.dp_sd_w, self.dp_sd_b = float(dp_sd_w), float(dp_sd_b)
 
     def next_nonce(self):
-        self.nonce += 1
+        """A nonce no other engine or reservation on the context's key seed uses."""
+        self.nonce = self.ctx.reserve_nonces(1)
         return self.nonce
 
     def shares(self, v):

@@ -180,3 +180,36 @@ def test_dp_noise_lands_on_weight_and_bias_gradients():
     assert (np.mod(w.grad.cpu().numpy().astype(np.int64) - dW - ew, T) == 0).all()
     assert (np.mod(b.grad.cpu().numpy().astype(np.int64) - db - eb, T) == 0).all()
     assert (np.mod(x.grad.cpu().numpy().astype(np.int64), T) == LN.layer_op(layer, "dx", ts["dY"], ts["W"], T)).all()
+
+
+def test_two_engines_on_one_context_draw_disjoint_randomness():
+    """Engines sharing a context (one key seed) take their nonces from one
+    counter, so equal inputs with equal shares still encrypt, mask and flood
+    differently: no two products reuse a Philox stream."""
+    from paper_2403_11166_amd import Context
+    from paper_2403_11166_amd.autograd import EncryptedLinearEngine, encrypted_linear
+    layer = LAYERS[1]
+    ctx = Context(layer.log2_n, layer.num_limbs, layer.prime_bits, 91)
+    seen = {"encrypt": [], "linear_fwd": []}
+    orig = {k: getattr(ctx, k) for k in seen}
+
+    def recorder(name):
+        def call(*a, **kw):
+            out = orig[name](*a, **kw)
+            seen[name].append(out if name == "encrypt" else out[0])
+            return out
+        return call
+
+    for k in seen:
+        setattr(ctx, k, recorder(k))
+    ts = layer_tensors(layer, 92)
+    outs = []
+    for _ in range(2):
+        eng = EncryptedLinearEngine(layer, ctx, seed=5)   # equal share draws in both engines
+        x = torch.tensor(centred_np(ts["X"]), dtype=torch.float64, device="cuda")
+        w = torch.tensor(centred_np(ts["W"]), dtype=torch.float64, device="cuda")
+        outs.append(encrypted_linear(x, w, eng))
+    torch.cuda.synchronize()
+    assert torch.equal(outs[0], outs[1])                  # same layer result
+    assert not torch.equal(seen["encrypt"][0], seen["encrypt"][1])
+    assert not torch.equal(seen["linear_fwd"][0], seen["linear_fwd"][1])
