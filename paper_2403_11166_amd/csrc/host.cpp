@@ -14,10 +14,6 @@
 #include "../../include/pencil.h"
 #include "pencil_internal.h"
 
-namespace pencil {
-hipError_t configure_lds_limits();
-}
-
 using namespace pencil;
 typedef unsigned __int128 u128;
 
@@ -1271,15 +1267,10 @@ static void add_seg(pencil_step::Phase& ph, StepSeg sg, int64_t blocks) {
   ph.segs.push_back(sg);
 }
 
-extern "C" pencil_status pencil_step_bind(pencil_step* st, const pencil_step_io* io, void* ws) {
-  if (!st || !io || !ws) return step_fail(st, PENCIL_EINVAL, "NULL argument");
-  // ciphertext buffers and the workspace are moved in 16-byte pairs
-  auto misaligned = [](const void* p) { return p && ((uintptr_t)p & 15) != 0; };
-  if (misaligned(ws)) return step_fail(st, PENCIL_EINVAL, "ws is not 16-byte aligned");
-  for (size_t i = 0; i < st->layers.size(); ++i)
-    if (misaligned(io[i].ct_x1) || misaligned(io[i].ct_dy_dx) || misaligned(io[i].ct_x_dw) ||
-        misaligned(io[i].ct_dy_dw) || misaligned(io[i].ct_y) || misaligned(io[i].ct_dx) || misaligned(io[i].ct_dw))
-      return step_fail(st, PENCIL_EINVAL, "a ciphertext buffer is not 16-byte aligned");
+// Drop the segment tables and the captured graph: the step is unbound until a
+// bind succeeds again.
+static void step_unbind(pencil_step* st) {
+  st->bound = false;
   for (auto& ph : st->phases) hipFree(ph.d_segs);
   st->phases.clear();
   if (st->exec) {
@@ -1290,6 +1281,33 @@ extern "C" pencil_status pencil_step_bind(pencil_step* st, const pencil_step_io*
     hipGraphDestroy(st->graph);
     st->graph = nullptr;
   }
+}
+
+static pencil_status step_bind_tables(pencil_step* st, const pencil_step_io* io, void* ws);
+
+extern "C" pencil_status pencil_step_bind(pencil_step* st, const pencil_step_io* io, void* ws) {
+  if (!st) return step_fail(st, PENCIL_EINVAL, "NULL argument");
+  // a failed bind leaves the step unbound (run and capture refuse it), never
+  // with partly built segment tables
+  step_unbind(st);
+  if (!io || !ws) return step_fail(st, PENCIL_EINVAL, "NULL argument");
+  const pencil_status s = step_bind_tables(st, io, ws);
+  if (s != PENCIL_OK) {
+    step_unbind(st);
+    return s;
+  }
+  st->bound = true;
+  return PENCIL_OK;
+}
+
+static pencil_status step_bind_tables(pencil_step* st, const pencil_step_io* io, void* ws) {
+  // ciphertext buffers and the workspace are moved in 16-byte pairs
+  auto misaligned = [](const void* p) { return p && ((uintptr_t)p & 15) != 0; };
+  if (misaligned(ws)) return step_fail(st, PENCIL_EINVAL, "ws is not 16-byte aligned");
+  for (size_t i = 0; i < st->layers.size(); ++i)
+    if (misaligned(io[i].ct_x1) || misaligned(io[i].ct_dy_dx) || misaligned(io[i].ct_x_dw) ||
+        misaligned(io[i].ct_dy_dw) || misaligned(io[i].ct_y) || misaligned(io[i].ct_dx) || misaligned(io[i].ct_dw))
+      return step_fail(st, PENCIL_EINVAL, "a ciphertext buffer is not 16-byte aligned");
   // fixed phase order: forward NTTs, MAC, inverse NTTs, flood (per ring degree / flood width)
   for (int kind = 0; kind < 4; ++kind)
     for (auto& e : st->layers) {
@@ -1416,7 +1434,6 @@ extern "C" pencil_status pencil_step_bind(pencil_step* st, const pencil_step_io*
     if (hipMemcpy(ph.d_segs, ph.segs.data(), ph.segs.size() * sizeof(StepSeg), hipMemcpyHostToDevice) != hipSuccess)
       return step_fail(st, PENCIL_EHIP, "segment upload failed");
   }
-  st->bound = true;
   return PENCIL_OK;
 }
 

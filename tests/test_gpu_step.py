@@ -156,3 +156,27 @@ def test_every_schedule_variant_is_bit_identical_and_autotune_picks_one(tmp_path
     again = ctx.autotune(layer, plan, cache)  # cache hit: same choice, no new lines
     assert tuple(again.sched) == tuple(tuned.sched)
     assert open(cache).read() == text
+
+
+def test_failed_rebind_leaves_the_step_unbound():
+    """A bind that fails (here: a missing weight buffer) after a good one must
+    not leave the old or a partial segment table behind: run and capture both
+    refuse the step until a bind succeeds again."""
+    from paper_2403_11166_amd import PencilError
+    tensors = [layer_tensors(l, 97 + i) for i, l in enumerate(MIXED[:2])]
+    ents = build(MIXED[:2], tensors, 9)
+    step, ws = make_step(ents)
+    step.run(5000)
+    bad = [dict(io) for _, _, _, io in ents]
+    bad[1]["w"] = None
+    with pytest.raises(PencilError, match="missing buffer"):
+        step.bind(bad, ws)
+    with pytest.raises(PencilError, match="not bound"):
+        step.run(5000)
+    with pytest.raises(PencilError, match="not bound"):
+        step.capture()
+    with pytest.raises(PencilError, match="no captured graph"):
+        step.replay()
+    step.bind([io for _, _, _, io in ents], ws)
+    step.run(5000)
+    torch.cuda.synchronize()
