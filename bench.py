@@ -67,14 +67,13 @@ def parse():
 
 # ------------------------------------------------------------- hbm traffic
 
-KERNEL_SOURCES = ("kernels.hip", "modarith.h", "pencil_internal.h", "host.cpp")  # host.cpp: the planner
-
-
 def kernel_source_hash():
-    """sha256 over the kernel sources; a traffic record holds for this hash only."""
+    """sha256 over the kernel sources (host.cpp included: the planner); a
+    traffic record holds for this hash only."""
     import hashlib
     h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
+    csrc = os.path.join(ROOT, "paper_2403_11166_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
         with open(os.path.join(ROOT, "paper_2403_11166_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()

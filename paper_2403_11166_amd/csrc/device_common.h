@@ -1,0 +1,142 @@
+// Device helpers shared by the kernel translation units: global-memory views,
+// the encode/lift helpers of the packed encodings, the multiply-accumulate
+// operand form, block-to-work maps and the NTT launch dispatch.
+#pragma once
+#include "pencil_internal.h"
+#include "modarith.h"
+
+namespace pencil {
+
+// Global-memory views of generic pointers.  Pointers read from device memory
+// (the batched step's segment tables) are generic to the compiler, which then
+// emits flat instructions; flat loads also count against the LDS/scalar wait
+// counter.  Every buffer here is global memory, so the hot loops access it
+// through these address-space-qualified views.
+#define PENCIL_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ PENCIL_GLOBAL T* gview(T* p) {
+  return (PENCIL_GLOBAL T*)p;
+}
+typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
+
+// Staging format of the multiply-accumulate operands: (v mod 2^30) | (v >> 30) << 32.
+__device__ __forceinline__ uint64_t split30(uint64_t v) { return (v & 0x3FFFFFFFull) | ((v >> 30) << 32); }
+
+// ---------------------------------------------------------- encode helpers
+// round(q m / t) mod q_l for m in [0, t): Delta * m + round(rho m / t), rho = q mod t.
+__device__ __forceinline__ uint64_t round_rho(uint64_t m, const Consts& C) {
+  uint64_t est = __umul64hi(m, C.rho_sh);
+  uint64_t r = m * C.rho - est * C.t;  // in [0, 2t)
+  if (r >= C.t) {
+    r -= C.t;
+    est += 1;
+  }
+  return est + (2 * r > C.t ? 1 : 0);
+}
+
+__device__ __forceinline__ uint64_t delta_scale(uint64_t m, uint64_t rr, const LimbConst& lc) {
+  return add_mod(mul_shoup(m, lc.delta, lc.delta_sh, lc.q), rr, lc.q);
+}
+
+// Value of the forward-encoded A tile `tile` at polynomial slot `slot`
+// (App. A's pi_v generalised), or -1 for an empty slot.
+__device__ __forceinline__ int64_t a_slot_offset(const Geo& G, const View& V, int64_t tile, int slot) {
+  int mm = slot / G.RS;
+  int rem = slot - mm * G.RS;
+  if (mm >= G.mt || rem >= G.S) return -1;
+  const int hw = G.ha * G.wa;
+  int kk = rem / hw;
+  int rem2 = rem - kk * hw;
+  int ya = rem2 / G.wa, xa = rem2 - (rem2 / G.wa) * G.wa;
+  // tile index = ((((mi*nK + ki)*nOY + oyi)*nOX + oxi)*nKY + kyi)*nKX + kxi
+  int64_t ti = tile;
+  int kxi = (int)(ti % G.nKX); ti /= G.nKX;
+  int kyi = (int)(ti % G.nKY); ti /= G.nKY;
+  int oxi = (int)(ti % G.nOX); ti /= G.nOX;
+  int oyi = (int)(ti % G.nOY); ti /= G.nOY;
+  int ki = (int)(ti % G.nK); ti /= G.nK;
+  int mi = (int)ti;
+  int m = mi * G.mt + mm, k = ki * G.kt + kk;
+  int y = oyi * G.oh + kyi * G.kh + ya, x = oxi * G.ow + kxi * G.kw + xa;
+  if (m >= G.M || k >= G.K || y >= G.HA || x >= G.WA) return -1;
+  int ys = y - V.pady, xs = x - V.pad;
+  if (ys < 0 || xs < 0 || ys >= V.H || xs >= V.W) return -1;
+  return m * V.s0 + k * V.s1 + ys * V.sy + xs * V.sx;
+}
+
+// Value offset of the reverse-encoded K tile `tile` at `slot` (App. A's pi_W).
+__device__ __forceinline__ int64_t k_slot_offset(const Geo& G, const View& V, int64_t tile, int slot) {
+  // slot = O + rr*S - (kk*ha*wa + dy*wa + dx)
+  int z = slot - G.O + G.S - 1;
+  if (z < 0) return -1;
+  int rr = z / G.S;
+  if (rr >= G.rt) return -1;
+  int D = rr * G.S + G.O - slot;
+  const int hw = G.ha * G.wa;
+  int kk = D / hw;
+  int rem = D - kk * hw;
+  int dy = rem / G.wa, dx = rem - (rem / G.wa) * G.wa;
+  if (dy >= G.kh || dx >= G.kw) return -1;
+  int64_t ti = tile;  // ((ri*nK + ki)*nKY + kyi)*nKX + kxi
+  int kxi = (int)(ti % G.nKX); ti /= G.nKX;
+  int kyi = (int)(ti % G.nKY); ti /= G.nKY;
+  int ki = (int)(ti % G.nK); ti /= G.nK;
+  int ri = (int)ti;
+  int r = ri * G.rt + rr, k = ki * G.kt + kk, a = kyi * G.kh + dy, b = kxi * G.kw + dx;
+  if (r >= G.R || k >= G.K || a >= G.KH || b >= G.KW) return -1;
+  if (V.flip) {
+    a = V.KH - 1 - a;
+    b = V.KW - 1 - b;
+  }
+  return r * V.s0 + k * V.s1 + a * V.sy + b * V.sx;
+}
+
+__device__ __forceinline__ int64_t slot_offset(int side, const Geo& G, const View& V, int64_t tile, int slot) {
+  return side == 0 ? a_slot_offset(G, V, tile, slot) : k_slot_offset(G, V, tile, slot);
+}
+
+// Work item of block `b` of `total`.  Workgroups go to the 8 XCDs round-robin
+// by block index, so XCD x = b mod 8 receives blocks b = x, x + 8, ...; giving
+// it the contiguous work range [x total / 8, (x + 1) total / 8) in order keeps
+// the chunks of one slot range (which share operands) on one L2.
+__device__ __forceinline__ int64_t xcd_work(int64_t b, int64_t total) {
+  const int64_t q = total >> 3, r = total & 7, x = b & 7, j = b >> 3;
+  return x * q + (x < r ? x : r) + j;
+}
+
+// Segment of a batched step's phase launch that block b belongs to.
+__device__ __forceinline__ int find_seg(const StepSeg* segs, int nseg, int64_t b) {
+  int lo = 0, hi = nseg - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (segs[mid].block_begin <= b)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+static inline size_t lds_bytes(const Consts& C) { return (size_t)(C.n + (C.n >> 5)) * sizeof(uint64_t); }
+
+// Instantiate `kern<LOGN>` for the context's degree and launch it.
+#define NTT_CASE(kern, LN, LE, grid, C, s, ...)                                                 \
+  case (LN) * 8 + (LE):                                                                          \
+    hipLaunchKernelGGL((kern<LN, LE>), grid, dim3((1u << (LN)) >> (LE)), lds_bytes(C), s, __VA_ARGS__); \
+    break;
+// Instantiate `kern<LOGN, LOGE>` for the context's degree and per-thread width.
+#define NTT_DISPATCH(kern, grid, C, s, ...)                                                \
+  do {                                                                                     \
+    switch ((C).log2n * 8 + (C).ntt_loge) {                                                \
+      NTT_CASE(kern, 10, 4, grid, C, s, __VA_ARGS__)                                       \
+      NTT_CASE(kern, 11, 4, grid, C, s, __VA_ARGS__)                                       \
+      NTT_CASE(kern, 12, 4, grid, C, s, __VA_ARGS__)                                       \
+      NTT_CASE(kern, 12, 5, grid, C, s, __VA_ARGS__)                                       \
+      NTT_CASE(kern, 13, 4, grid, C, s, __VA_ARGS__)                                       \
+      NTT_CASE(kern, 13, 5, grid, C, s, __VA_ARGS__)                                       \
+      NTT_CASE(kern, 14, 5, grid, C, s, __VA_ARGS__)                                       \
+      default: return hipErrorInvalidValue;                                                \
+    }                                                                                      \
+  } while (0)
+
+}  // namespace pencil

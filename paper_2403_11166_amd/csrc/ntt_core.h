@@ -1,0 +1,345 @@
+// Negacyclic NTT of one limb-polynomial per workgroup, staged in LDS, and
+// the forward-transform front ends of the product path (input ciphertexts
+// with the model owner's share, encoded plaintexts, ternary masks).
+#pragma once
+#include "device_common.h"
+
+namespace pencil {
+
+// ----------------------------------------------------------------- NTT core
+// One workgroup transforms one limb-polynomial held in LDS.  N/E threads each
+// keep E residues in registers (E = 16, or 32 at N = 16384) and run several
+// butterfly stages per LDS round trip; the log2 N stages are split into
+// ceil(log2 N / log2 E) passes of near-equal size.  LDS rows are padded by one
+// word every 32 so that strided passes spread over the banks.
+__device__ __forceinline__ int lpad(int i) { return i + (i >> 5); }
+
+template <int LOGN, int LOGE_>
+struct NttShape {
+  static constexpr int LOGE = LOGE_;
+  static constexpr int E = 1 << LOGE;
+  static constexpr int T = (1 << LOGN) / E;  // threads per block
+  static constexpr int NP = (LOGN + LOGE - 1) / LOGE;
+  // stages in pass i: the first LOGN % NP passes take one more
+  static constexpr int size(int i) { return LOGN / NP + (i < LOGN % NP ? 1 : 0); }
+  static constexpr int start(int i) { return i == 0 ? 0 : start(i - 1) + size(i - 1); }
+};
+
+// Butterfly constants of one modulus: 2q, 2^64 - q, 2^64 - 2q and 2q + 1.  They
+// are hidden from the optimiser so that x - q stays the single 64-bit addition
+// x + (2^64 - q) instead of a borrow chain.
+struct BflyK {
+  uint64_t q2, nq, nq2, q2p1;
+};
+
+__device__ __forceinline__ BflyK bfly_consts(uint64_t q) {
+  BflyK k{2 * q, 0 - q, 0 - 2 * q, 2 * q + 1};
+  asm volatile("" : "+s"(k.q2), "+s"(k.nq), "+s"(k.nq2), "+s"(k.q2p1));
+  return k;
+}
+
+// x - 2q if x >= 2q, else x, for x < 2^63: the sign of x - 2q decides.
+__device__ __forceinline__ uint64_t csub2q(uint64_t x, const BflyK& k) {
+  const uint64_t d = x + k.nq2;
+  const uint32_t m = (uint32_t)((int32_t)(uint32_t)(d >> 32) >> 31);
+  const uint64_t back = ((uint64_t)((uint32_t)(k.q2 >> 32) & m) << 32) | ((uint32_t)k.q2 & m);
+  return d + back;
+}
+
+// Shoup's lazy product y w mod q in [0, 2q): y w - floor(y ws / 2^64) q.
+__device__ __forceinline__ uint64_t shoup_lazy(uint64_t y, const TW w, const BflyK& k) {
+  return y * w.w + __umul64hi(y, w.ws) * k.nq;
+}
+
+// Harvey's lazy Cooley-Tukey butterfly: x, y in [0, 4q) -> [0, 4q), q < 2^61.
+__device__ __forceinline__ void ct_bfly(uint64_t& x, uint64_t& y, const TW w, const BflyK& k) {
+  const uint64_t a = csub2q(x, k);
+  const uint64_t t = shoup_lazy(y, w, k);
+  x = a + t;
+  y = (a + k.q2p1) + ~t;  // a - t + 2q
+}
+
+// Lazy Gentleman-Sande butterfly: u, v in [0, 2q) -> [0, 2q).
+__device__ __forceinline__ void gs_bfly(uint64_t& u, uint64_t& v, const TW w, const BflyK& k) {
+  const uint64_t s = csub2q(u + v, k);
+  const uint64_t d = (u + k.q2p1) + ~v;  // u - v + 2q
+  v = shoup_lazy(d, w, k);
+  u = s;
+}
+
+// Forward (merged negacyclic Cooley-Tukey, psi^rev twiddles; natural order in,
+// bit-reversed out) stages S0 .. S0+S-1.  At stage l (t = N >> (l+1)) the pair
+// (i0, i0 + t) of group i = i0 >> (log2 N - l) uses tw[2^l + i].  A thread takes
+// E / 2^S groups of 2^S residues {base + k * 2^LT}, LT = log2 N - S0 - S.
+template <int LOGN, int LOGE, int S0, int S, bool LAST>
+__device__ __forceinline__ void fwd_pass(uint64_t* a, const PENCIL_GLOBAL TW* tw, uint64_t q, const BflyK& bk) {
+  using Sh = NttShape<LOGN, LOGE>;
+  constexpr int T = Sh::T, G = Sh::E >> S, K = 1 << S, LT = LOGN - S0 - S;
+  const int tid = threadIdx.x;
+  uint64_t v[Sh::E];
+#pragma unroll
+  for (int r = 0; r < G; ++r) {
+    const int g = r * T + tid;
+    const int base = ((g >> LT) << (LOGN - S0)) + (g & ((1 << LT) - 1));
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[r * K + k] = a[lpad(base + (k << LT))];
+  }
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int h = 1 << (S - 1 - s);
+#pragma unroll
+    for (int r = 0; r < G; ++r) {
+      const int blk = (r * T + tid) >> LT;
+#pragma unroll
+      for (int j = 0; j < (1 << s); ++j) {
+        const PENCIL_GLOBAL TW* tp = tw + (1 << (S0 + s)) + (blk << s) + j;
+        const TW w{tp->w, tp->ws};
+#pragma unroll
+        for (int k = j << (S - s); k < ((j + 1) << (S - s)); ++k) {
+          if (k & h) continue;
+          ct_bfly(v[r * K + k], v[r * K + k + h], w, bk);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < G; ++r) {
+    const int g = r * T + tid;
+    const int base = ((g >> LT) << (LOGN - S0)) + (g & ((1 << LT) - 1));
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      uint64_t x = v[r * K + k];
+      if (LAST) {
+        x = csub2q(x, bk);
+        x = x >= q ? x - q : x;
+      }
+      a[lpad(base + (k << LT))] = x;
+    }
+  }
+}
+
+// Inverse (Gentleman-Sande, psi^-rev twiddles; bit-reversed in, natural out)
+// stages with t = 2^L0 .. 2^(L0+S-1): pair (i0, i0 + t), i = i0 >> (l + 1),
+// twiddle itw[(N >> (l + 1)) + i].  Groups are {base + k * 2^L0}.
+template <int LOGN, int LOGE, int L0, int S>
+__device__ __forceinline__ void inv_pass(uint64_t* a, const PENCIL_GLOBAL TW* tw, uint64_t q, const BflyK& bk) {
+  using Sh = NttShape<LOGN, LOGE>;
+  constexpr int T = Sh::T, G = Sh::E >> S, K = 1 << S;
+  const int tid = threadIdx.x;
+  uint64_t v[Sh::E];
+#pragma unroll
+  for (int r = 0; r < G; ++r) {
+    const int g = r * T + tid;
+    const int base = ((g >> L0) << (L0 + S)) + (g & ((1 << L0) - 1));
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[r * K + k] = a[lpad(base + (k << L0))];
+  }
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int h = 1 << s;
+    const int m = (1 << LOGN) >> (L0 + s + 1);
+#pragma unroll
+    for (int r = 0; r < G; ++r) {
+      const int blk = (r * T + tid) >> L0;
+#pragma unroll
+      for (int j = 0; j < (K >> (s + 1)); ++j) {
+        const PENCIL_GLOBAL TW* tp = tw + m + (blk << (S - s - 1)) + j;
+        const TW w{tp->w, tp->ws};
+#pragma unroll
+        for (int k = j << (s + 1); k < ((j + 1) << (s + 1)); ++k) {
+          if (k & h) continue;
+          gs_bfly(v[r * K + k], v[r * K + k + h], w, bk);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < G; ++r) {
+    const int g = r * T + tid;
+    const int base = ((g >> L0) << (L0 + S)) + (g & ((1 << L0) - 1));
+#pragma unroll
+    for (int k = 0; k < K; ++k) a[lpad(base + (k << L0))] = v[r * K + k];
+  }
+}
+
+// Forward transform of the LDS polynomial (inputs in [0, q), outputs in [0, q)).
+// Callers synchronise before (inputs written) and after (outputs read).
+template <int LOGN, int LOGE>
+__device__ __forceinline__ void ntt_fwd(uint64_t* a, const TW* tw_generic, uint64_t q) {
+  using Sh = NttShape<LOGN, LOGE>;
+  const BflyK bk = bfly_consts(q);
+  const PENCIL_GLOBAL TW* tw = gview(tw_generic);
+  fwd_pass<LOGN, LOGE, Sh::start(0), Sh::size(0), Sh::NP == 1>(a, tw, q, bk);
+  __syncthreads();
+  if constexpr (Sh::NP > 1) {
+    fwd_pass<LOGN, LOGE, Sh::start(1), Sh::size(1), Sh::NP == 2>(a, tw, q, bk);
+    __syncthreads();
+  }
+  if constexpr (Sh::NP > 2) {
+    fwd_pass<LOGN, LOGE, Sh::start(2), Sh::size(2), Sh::NP == 3>(a, tw, q, bk);
+    __syncthreads();
+  }
+  if constexpr (Sh::NP > 3) {
+    fwd_pass<LOGN, LOGE, Sh::start(3), Sh::size(3), true>(a, tw, q, bk);
+    __syncthreads();
+  }
+}
+
+// Inverse transform without the N^-1 factor (inputs in [0, 2q), outputs in [0, 2q)).
+template <int LOGN, int LOGE>
+__device__ __forceinline__ void ntt_inv(uint64_t* a, const TW* tw_generic, uint64_t q) {
+  using Sh = NttShape<LOGN, LOGE>;
+  const BflyK bk = bfly_consts(q);
+  const PENCIL_GLOBAL TW* tw = gview(tw_generic);
+  inv_pass<LOGN, LOGE, Sh::start(0), Sh::size(0)>(a, tw, q, bk);
+  __syncthreads();
+  if constexpr (Sh::NP > 1) {
+    inv_pass<LOGN, LOGE, Sh::start(1), Sh::size(1)>(a, tw, q, bk);
+    __syncthreads();
+  }
+  if constexpr (Sh::NP > 2) {
+    inv_pass<LOGN, LOGE, Sh::start(2), Sh::size(2)>(a, tw, q, bk);
+    __syncthreads();
+  }
+  if constexpr (Sh::NP > 3) {
+    inv_pass<LOGN, LOGE, Sh::start(3), Sh::size(3)>(a, tw, q, bk);
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ kernels
+
+// In-place forward or inverse NTT of [polys][L][N].
+template <int LOGN, int LOGE>
+__device__ __forceinline__ void do_ntt_plain(uint64_t* lds, uint64_t* data, int inverse, const Consts& C,
+                                             const Tables& T, int64_t p) {
+  constexpr int n = 1 << LOGN;
+  const int L = C.L;
+  const int l = (int)(p % L);
+  const LimbConst& lc = C.limb[l];
+  // residues move in 16-byte pairs; a pair never straddles an LDS pad word
+  PENCIL_GLOBAL u64x2* g = (PENCIL_GLOBAL u64x2*)gview(data + p * n);
+  for (int i = threadIdx.x; i < n / 2; i += blockDim.x) {
+    const u64x2 v = g[i];
+    lds[lpad(2 * i)] = v[0];
+    lds[lpad(2 * i) + 1] = v[1];
+  }
+  __syncthreads();
+  if (!inverse) {
+    ntt_fwd<LOGN, LOGE>(lds, T.fw + (int64_t)l * n, lc.q);
+    for (int i = threadIdx.x; i < n / 2; i += blockDim.x) g[i] = u64x2{lds[lpad(2 * i)], lds[lpad(2 * i) + 1]};
+  } else {
+    ntt_inv<LOGN, LOGE>(lds, T.iw + (int64_t)l * n, lc.q);
+    for (int i = threadIdx.x; i < n / 2; i += blockDim.x)
+      g[i] = u64x2{mul_shoup(lds[lpad(2 * i)], lc.ninv, lc.ninv_sh, lc.q),
+                   mul_shoup(lds[lpad(2 * i) + 1], lc.ninv, lc.ninv_sh, lc.q)};
+  }
+}
+
+// Input ciphertexts (NTT domain): component 0 gains the transform of
+// round(q m / t) of the model owner's share (Alg. 1, product step); the
+// residues are stored split for the multiply-accumulate.  Only a block with a
+// share to add runs a transform; the others convert and copy.
+// Grid: n_ct * 2 * L blocks, polynomial p = (j, c, l) in [n][2][L] order.
+template <int LOGN, int LOGE>
+__device__ __forceinline__ void do_ntt_ct(uint64_t* lds, const uint64_t* src, uint64_t* dst, const int64_t* share,
+                                          const Geo& G, const View& V, const Consts& C, const Tables& T, int64_t p) {
+  constexpr int n = 1 << LOGN;
+  const int L = C.L;
+  const int l = (int)(p % L);
+  const int c = (int)((p / L) % 2);
+  const int64_t j = p / (2 * L);
+  const LimbConst& lc = C.limb[l];
+  const PENCIL_GLOBAL uint64_t* g = gview(src + p * n);
+  PENCIL_GLOBAL uint64_t* o = gview(dst + p * n);
+  if (share == nullptr || c != 0) {  // 16-byte accesses: a polynomial is 16-byte aligned
+    const PENCIL_GLOBAL u64x2* g2 = (const PENCIL_GLOBAL u64x2*)g;
+    PENCIL_GLOBAL u64x2* o2 = (PENCIL_GLOBAL u64x2*)o;
+    for (int i = threadIdx.x; i < n / 2; i += blockDim.x) {
+      const u64x2 v = g2[i];
+      o2[i] = u64x2{split30(v[0]), split30(v[1])};
+    }
+    return;
+  }
+  const PENCIL_GLOBAL int64_t* gshare = gview(share);
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    uint64_t v = 0;
+    const int64_t off = a_slot_offset(G, V, j, i);
+    if (off >= 0) {
+      const uint64_t m = (uint64_t)gshare[off];
+      v = delta_scale(m, round_rho(m, C), lc);
+    }
+    lds[lpad(i)] = v;
+  }
+  __syncthreads();
+  ntt_fwd<LOGN, LOGE>(lds, T.fw + (int64_t)l * n, lc.q);
+  {
+    const PENCIL_GLOBAL u64x2* g2 = (const PENCIL_GLOBAL u64x2*)g;
+    PENCIL_GLOBAL u64x2* o2 = (PENCIL_GLOBAL u64x2*)o;
+    for (int i = threadIdx.x; i < n / 2; i += blockDim.x) {
+      const u64x2 v = g2[i];
+      o2[i] = u64x2{split30(add_mod(v[0], lds[lpad(2 * i)], lc.q)), split30(add_mod(v[1], lds[lpad(2 * i) + 1], lc.q))};
+    }
+  }
+}
+
+// Plaintext tiles: encode (side 0: forward A tile, 1: reverse K tile), centred
+// lift of Z_t into Z_{q_l}, forward NTT.  Grid: n_pt * L, output [n][L][N].
+template <int LOGN, int LOGE>
+__device__ __forceinline__ void do_ntt_pt(uint64_t* lds, const int64_t* tensor, uint64_t* dst, int side,
+                                          const Geo& G, const View& V, const Consts& C, const Tables& T, int64_t p) {
+  constexpr int n = 1 << LOGN;
+  const int L = C.L;
+  const int l = (int)(p % L);
+  const int64_t j = p / L;
+  const LimbConst& lc = C.limb[l];
+  const PENCIL_GLOBAL int64_t* gt = gview(tensor);
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    uint64_t v = 0;
+    int64_t off = slot_offset(side, G, V, j, i);
+    if (off >= 0) {
+      uint64_t w = (uint64_t)gt[off];
+      v = w <= C.t_half ? w : lc.q - (C.t - w);
+    }
+    lds[lpad(i)] = v;
+  }
+  __syncthreads();
+  ntt_fwd<LOGN, LOGE>(lds, T.fw + (int64_t)l * n, lc.q);
+  PENCIL_GLOBAL uint64_t* o = gview(dst + p * n);
+  PENCIL_GLOBAL u64x2* o2 = (PENCIL_GLOBAL u64x2*)o;
+  for (int i = threadIdx.x; i < n / 2; i += blockDim.x)
+    o2[i] = u64x2{split30(lds[lpad(2 * i)]), split30(lds[lpad(2 * i) + 1])};
+}
+
+// Fresh ternary polynomials (object obj_base + j, stream `purpose`), lifted and
+// transformed.  Coefficient i uses the 32-bit half i mod 2 of stream word i/2,
+// so one Philox block covers 8 coefficients.  Grid: count * L, output [n][L][N],
+// in the multiply-accumulate's split form when `split` is set.
+template <int LOGN, int LOGE>
+__device__ __forceinline__ void do_ntt_ternary(uint64_t* lds, uint64_t* dst, uint64_t nonce, uint64_t obj_base,
+                                               uint32_t purpose, int split, const Consts& C, const Tables& T,
+                                               int64_t p) {
+  constexpr int n = 1 << LOGN;
+  const int L = C.L;
+  const int l = (int)(p % L);
+  const int64_t j = p / L;
+  const LimbConst& lc = C.limb[l];
+  for (int blk = threadIdx.x; blk < n / 8; blk += blockDim.x) {
+    U64x4 w = philox((uint64_t)blk, obj_base + j, purpose, 0, C.seed, nonce);
+#pragma unroll
+    for (int h = 0; h < 8; ++h) {
+      uint32_t half = (uint32_t)(w.v[h >> 1] >> (32 * (h & 1)));
+      lds[lpad(blk * 8 + h)] = small_to_mod(ternary32(half), lc.q);
+    }
+  }
+  __syncthreads();
+  ntt_fwd<LOGN, LOGE>(lds, T.fw + (int64_t)l * n, lc.q);
+  PENCIL_GLOBAL u64x2* o2 = (PENCIL_GLOBAL u64x2*)gview(dst + p * n);
+  if (split)
+    for (int i = threadIdx.x; i < n / 2; i += blockDim.x)
+      o2[i] = u64x2{split30(lds[lpad(2 * i)]), split30(lds[lpad(2 * i) + 1])};
+  else
+    for (int i = threadIdx.x; i < n / 2; i += blockDim.x) o2[i] = u64x2{lds[lpad(2 * i)], lds[lpad(2 * i) + 1]};
+}
+
+}  // namespace pencil

@@ -201,4 +201,12 @@ hipError_t launch_set_u64(uint64_t* p, uint64_t v, int add, hipStream_t s);
 hipError_t launch_keygen(uint64_t* s_ntt, int64_t* s_coeff, uint64_t* pk_coeff, uint64_t* pk_ntt,
                          const Consts& C, const Tables& T, hipStream_t s);
 
+// Kernels that stage more than 64 KiB of LDS opt in once per process; one
+// function per translation unit, all called by configure_lds_limits().
+hipError_t configure_lds_ntt();
+hipError_t configure_lds_mac();
+hipError_t configure_lds_do();
+hipError_t configure_lds_step();
+hipError_t configure_lds_limits();
+
 }  // namespace pencil
