@@ -3,8 +3,8 @@ launch configuration bench.py times (the planner's own partition).
 
 * End to end: the data owner's encryptions, the model owner's forward and
   backward products and the decryptions must reconstruct the plaintext layer
-  results exactly (every element where the oracle finishes quickly, a seeded
-  sample of elements otherwise).
+  results exactly, every element of every product (the oracle's plaintext
+  layers finish the largest of these shapes in tens of seconds).
 * Bit for bit: the model owner's products on synthetic uniform ciphertext
   inputs, encryption and decryption are compared with the oracle on sampled
   output tiles and coefficients.
@@ -25,7 +25,7 @@ pytestmark = pytest.mark.gpu
 
 # distinct layer shapes of each workload (config 5 repeats three shapes)
 CASES = [(2, 0), (3, 0), (4, 0), (4, 1), (4, 2), (4, 3), (5, 0), (5, 3), (5, 6)]
-FULL_CHECK_LIMIT = 3e8  # output elements x contraction length the oracle computes in full
+FULL_CHECK_LIMIT = 5e9  # output elements x contraction length the oracle computes in full (every case here)
 
 _ctx = {}
 _tensors = {}
