@@ -8,10 +8,12 @@ multiply-accumulate, re-randomise, inverse NTT, flood and mask), with the data
 owner's ciphertexts and both parties' shares already resident in HBM.
 Encryption and decryption (the data owner's ends) are outside the timed region.
 
-Default workload: FC 784 -> 128, batch 64, forward and backward, N = 8192 with
-three 60-bit RNS primes (the first layer of the paper's MNIST MLP).  After the
-timed region the outputs are decrypted and checked bit for bit against exact
-modular linear algebra (float64 digit products, exact below 2^53).
+Default workload: the eight-layer stack of 3x3 convolutions (3 x 64->64 on
+32x32, 3 x 128->128 on 16x16, 2 x 256->256 on 8x8), batch 64, forward and
+backward, N = 16384 with four 60-bit RNS primes.  `--config 2` is the FC layer
+784 -> 128 (the first layer of the paper's MNIST MLP).  After the timed region
+the outputs are decrypted and checked bit for bit against exact modular linear
+algebra (float64 digit products, exact below 2^53).
 
 Prints one JSON line.  `--gpus N` with N > 1 exits: the benchmark runs on one GPU.
 """
@@ -35,6 +37,9 @@ MUL32_PEAK_TOPS = 256 * 64 * 2.4e9 / 2 / 1e12
 # products) and a multiply-accumulate of two split 30-bit operands.
 MUL32_PER_BUTTERFLY = 10
 MUL32_PER_MAC = 4
+# Schedule choices measured on MI355X, reused so that the benchmark and its
+# rocprofv3 summaries run the same kernels.
+DEFAULT_TUNE_CACHE = os.path.join(ROOT, "paper_2403_11166_amd", "autotune_gfx950.txt")
 
 
 def parse():
@@ -42,7 +47,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=2, help="workload index (1..5)")
+    ap.add_argument("--config", type=int, default=5, help="workload index (1..5); default: the largest, the "
+                    "eight-layer convolution stack at N = 16384")
     ap.add_argument("--workload", default="", help="one of the extra layer-shape workloads by name "
                     "(MNIST CNN with its stride-2 layer, TextCNN's Conv1d layers, FC 2048->1001); overrides --config")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -59,6 +65,8 @@ def parse():
                     help="skip timing the data owner's encryption and decryption after the measured region")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the planner's default schedules instead of timing the candidates first")
+    ap.add_argument("--tune-cache", default=DEFAULT_TUNE_CACHE,
+                    help="autotuner cache file (earlier choices are reused, new ones appended); '' = none")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (the reference kernel that scales "
                          "HBM counters into bytes) and print its size and time")
@@ -312,27 +320,67 @@ def pencil_plus_bench(e, m, he_step_ms, torch):
 
 # ------------------------------------------------------------- cpu baseline
 
+def _host_threads():
+    """Host cores this process may use (its CPU affinity), capped at 16 (one GPU's share of the host)."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return max(1, min(avail, 16))
+
+
 def cpu_baseline(layer, seconds):
-    """The oracle's plaintext x ciphertext product (schoolbook, per limb and
-    component) timed on host cores for about `seconds`."""
+    """The oracle timed on host cores, in two legs.
+
+    (ii) its plaintext x ciphertext product (schoolbook negacyclic
+    multiplication per limb and component, in the oracle's plain-C helper,
+    which releases the GIL) on one thread and then on every usable host core;
+    products/s is the all-core rate.  (i) its plaintext Z_t layer operators
+    (forward, input gradient, weight gradient) on the layer's full shape.
+    About `seconds` of wall time per product leg."""
+    from concurrent.futures import ThreadPoolExecutor
     from oracle import bfv
+    from oracle import linear as LN
     from oracle import params as PR
     P = PR.params_for(layer)
     rng = np.random.default_rng(0)
     ct = np.stack([np.stack([rng.integers(0, q, P.n, dtype=np.uint64) for q in P.moduli]) for _ in range(2)])
     w = rng.integers(0, P.t, P.n)
-    done = 0
-    t0 = time.perf_counter()
-    while True:
+
+    def one_product(_=None):
         acc = [[[0] * P.n for _ in range(P.num_limbs)] for _ in range(2)]
         bfv.mul_plain_acc(P, acc, ct, w, P.t)
-        done += 1
-        el = time.perf_counter() - t0
-        if el >= seconds:
-            break
-    return {"value": done / el, "unit": "products/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} plaintext x ciphertext products at N={P.n}, L={P.num_limbs} "
-                      f"(schoolbook negacyclic, both components, all limbs) in {el:.1f} s, single thread"}
+        return 1
+
+    def rate(threads):
+        done, t0 = 0, time.perf_counter()
+        with ThreadPoolExecutor(threads) as ex:
+            while True:
+                done += sum(ex.map(one_product, range(threads)))
+                el = time.perf_counter() - t0
+                if el >= seconds:
+                    return done, el
+
+    n1, el1 = rate(1)
+    threads = _host_threads()
+    nall, elall = rate(threads) if threads > 1 else (n1, el1)
+    # (i) the plaintext layer operators at full size, once each
+    xs = rng.integers(0, P.t, layer.x_shape(), dtype=np.int64)
+    ws = rng.integers(0, P.t, layer.w_shape(), dtype=np.int64)
+    dys = rng.integers(0, P.t, layer.y_shape(), dtype=np.int64)
+    t0 = time.perf_counter()
+    LN.layer_op(layer, "fwd", xs, ws, P.t)
+    LN.layer_op(layer, "dx", dys, ws, P.t)
+    LN.layer_op(layer, "dw", xs, dys, P.t)
+    plain_s = time.perf_counter() - t0
+    return {"value": round(nall / elall, 3), "unit": "products/s", "cores": threads, "kind": "oracle",
+            "nproc": os.cpu_count(), "single_core_products_per_s": round(n1 / el1, 3),
+            "plaintext_layer_ops_s": round(plain_s, 3),
+            "sample": f"{nall} plaintext x ciphertext products at N={P.n}, L={P.num_limbs} (schoolbook "
+                      f"negacyclic, both components, all limbs) in {elall:.1f} s on {threads} threads, and "
+                      f"{n1} in {el1:.1f} s on one; plaintext leg: the forward, input-gradient and "
+                      f"weight-gradient Z_t operators of {layer.kind} {layer.c_in}->{layer.c_out} "
+                      f"{layer.h}x{layer.w} b{layer.batch} once each (numpy, its own BLAS threads)"}
 
 
 # ------------------------------------------------------------- main
@@ -390,7 +438,7 @@ def main():
             # schedule-only choices (bit-identical results), timed outside the measured region
             tkey = (key, layer.kind, layer.batch, layer.c_in, layer.c_out, layer.h, layer.w, layer.k, layer.pad)
             if tkey not in tuned:
-                tuned[tkey] = ctx.autotune(layer, plan)
+                tuned[tkey] = ctx.autotune(layer, plan, args.tune_cache or None)
             plan = tuned[tkey]
         sz = ctx.layout(layer, plan)
         d = {k: torch.from_numpy(v).to(dev) for k, v in ts.items()}
@@ -529,6 +577,36 @@ def main():
                      "mul32_Tps": round(work.get(k, (0, 0))[1] / (v[1] / 1e3) / 1e12, 3) if v[1] else None}
                  for k, v in sorted(per_step.items(), key=lambda kv: -kv[1][1])}
 
+    # ------------------------------------------------------ NTT throughput
+    # The metric's second figure: forward and inverse negacyclic NTTs over a
+    # batch of the first layer's input ciphertexts (both components, every
+    # limb), 16 N bytes per limb-polynomial (read and write once).
+    e0 = layers[0]
+    c0 = e0["ctx"]
+    polys = e0["ct_x"].clone()
+    npoly = polys.numel() // c0.n
+    lg = c0.n.bit_length() - 1
+
+    def ntt_ms(inverse):
+        c0.ntt(polys, inverse)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(5):
+            c0.ntt(polys, inverse)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / 5
+
+    ntt_rec = {"limb_polys": int(npoly), "N": c0.n, "L": c0.L, "bytes": int(16 * c0.n * npoly)}
+    for name, inv in (("forward", False), ("inverse", True)):
+        ms = ntt_ms(inv)
+        gbs = 16 * c0.n * npoly / (ms / 1e3) / 1e9
+        mul = MUL32_PER_BUTTERFLY * npoly * (c0.n // 2) * lg / (ms / 1e3) / 1e12
+        ntt_rec[name] = {"ms": round(ms, 4), "GBps": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                         "mul32_Tps": round(mul, 3), "mul32_frac": round(mul / MUL32_PEAK_TOPS, 4)}
+    del polys
+
     # ------------------------------------------------------ data owner's ends
     # Encryption of the first layer's input ciphertexts and decryption of its
     # forward outputs, timed after the measured region (they are not part of
@@ -637,6 +715,8 @@ def main():
                    "plans": [{"fwd": e["plan"].fwd.astuple(), "dx": e["plan"].dx.astuple(),
                               "dw": e["plan"].dw.astuple(), "sched": list(e["plan"].sched)} for e in layers],
                    "autotuned": not args.no_autotune,
+                   "autotune_cache": os.path.relpath(args.tune_cache, ROOT) if args.tune_cache else None,
+                   "ntt_loge": {f"N={c.n},L={c.L}": c.ntt_loge() for c in ctxs.values()},
                    "launch": {"step": "batched phase launches (all layers and products)",
                               "graph": "the batched step replayed as one HIP graph",
                               "layer": "one launch sequence per product and layer"}[args.mode]},
@@ -647,6 +727,7 @@ def main():
         "roofline": roof,
         "kernels": breakdown,
         "cpu_baseline": cpu,
+        "ntt": ntt_rec,
         "data_owner_ends": do_side,
         "weight_update_terms": wupd,
         "stride_relayout_ms": round(relayout_ms, 4) if any(e["strided"] for e in layers) else None,

@@ -23,7 +23,8 @@
  *            activations (B, C, W), weights (c_out, c_in, k).
  *            A ciphertext is uint64 [2][L][N] (component, RNS limb,
  *            residue): the DO's input ciphertexts (pencil_encrypt) are in the
- *            NTT domain, the products' outputs in the coefficient domain; a
+ *            NTT domain with residues in a split form, the products' outputs
+ *            in the coefficient domain; a
  *            ciphertext buffer holds pencil_sizes.n_ct[...] (or n_out[...]) of
  *            them back to back, in the tile order of the plan.
  *   Memory   Every tensor, ciphertext and workspace pointer is DEVICE memory
@@ -72,7 +73,7 @@ typedef struct {
                           /* below 2^prime_bits that are 1 mod 2^15, descending;     */
                           /* 40 <= prime_bits <= 60                                  */
     uint32_t flood_bits;  /* 0 = floor(log2 Delta) - 3, Delta = floor(q / t)        */
-    uint64_t primes[4];   /* explicit limbs (each prime, = 1 mod 2N, < 2^61) or 0   */
+    uint64_t primes[4];   /* explicit limbs (each prime, = 1 mod 2N, < 2^60) or 0   */
     uint64_t t;           /* plaintext modulus, odd prime < 2^48; 0 = the largest   */
                           /* prime below 2^41                                        */
     uint64_t seed;        /* key for every random value                              */
@@ -91,8 +92,8 @@ typedef struct {
     int32_t kind, batch, c_in, c_out, h, w, k, pad, stride;
 } pencil_layer;
 
-/* Partition of one product into N-slot tiles (App. A: larger operands "could be
- * partitioned").  The product is the packed correlation
+/* Partition of one product into N-slot tiles (App. A allows operands larger
+ * than N to be split into pieces).  The product is the packed correlation
  *   out[m, r, y, x] = sum_{c, dy, dx} A[m, c, y+dy, x+dx] * K[r, c, dy, dx];
  * a tile takes m x r x k of the (M, R, K) channels, an oh x ow output window and a
  * kh x kw kernel window, and needs m*r*k*(oh+kh-1)*(ow+kw-1) <= N slots. */
@@ -137,7 +138,9 @@ typedef struct {
 
 /* Resolved parameters of a context (host). */
 typedef struct {
-    uint32_t log2_n, num_limbs, flood_bits, reserved;
+    uint32_t log2_n, num_limbs, flood_bits;
+    uint32_t ntt_loge;       /* log2 of the residues each NTT thread keeps (the     */
+                             /* schedule pencil_autotune chose; 4 or 5)             */
     uint64_t primes[4];
     uint64_t psi[4];         /* the smallest primitive 2N-th root of unity per limb  */
     uint64_t t;
@@ -167,25 +170,34 @@ pencil_status pencil_plan_auto(const pencil_ctx* ctx, const pencil_layer* layer,
  * no GPU needed). */
 pencil_status pencil_plan_auto_n(uint32_t log2_n, const pencil_layer* layer, pencil_plan* plan /* host */);
 
-/* Buffer sizes for `layer` under `plan` (host).  A product whose tile is all
- * zero is treated as not planned and reported with zero sizes. */
+/* Buffer sizes for `layer` under `plan` (host): how many ciphertexts each
+ * operand and product needs once the operands are partitioned into N-slot
+ * tiles (App. A allows operands larger than N to be split into N-slot pieces;
+ * the plan fixes that split), plus the workspaces.  A product whose tile is
+ * all zero is treated as not planned and reported with zero sizes.  EINVAL for
+ * a layer or plan that does not fit the context's N. */
 pencil_status pencil_layout(const pencil_ctx* ctx, const pencil_layer* layer, const pencil_plan* plan,
                             pencil_sizes* sizes /* host */);
 
-/* DO: encode its share (int64 [0,t), the tensor the operand is built from: X for
- * X_FWD / X_DW, dY for DY_DX / DY_DW) with the operand's layout and encrypt it
- * under the public key (ct = (p0 u + e0 + round(q m / t), p1 u + e1)).
+/* DO: the encryption that opens Alg. 1 and Alg. 2 (the DO sends [[<X>_1]] or
+ * [[<dY>_1]]; BFV encryption of Sec. II.B).  Encode its share (int64 [0,t),
+ * the tensor the operand is built from: X for X_FWD / X_DW, dY for DY_DX /
+ * DY_DW) with the operand's layout (App. A's encodings) and encrypt it under
+ * the public key (ct = (p0 u + e0 + round(q m / t), p1 u + e1)).  EINVAL for a
+ * bad operand, layer, plan or pointer (nothing is launched).
  * ct receives n_ct[operand] ciphertexts in the NTT domain, the form the
- * products consume: residue i of each [limb] polynomial is its evaluation at
- * psi_l^(2 rev(i) + 1) (the order of pencil_ntt_forward).  Output ciphertexts
- * of the products are in the coefficient domain.  ws: ws_enc_bytes of device
+ * products consume: residue i of each [limb] polynomial is its evaluation
+ * v = a(psi_l^(2 rev(i) + 1)) (the order of pencil_ntt_forward), stored in the
+ * split form (v mod 2^30) + 2^32 floor(v / 2^30) that the products'
+ * multiply-accumulate reads directly.  Output ciphertexts of the products are
+ * plain residues in the coefficient domain.  ws: ws_enc_bytes of device
  * memory. */
 pencil_status pencil_encrypt(pencil_ctx* ctx, const pencil_layer* layer, const pencil_plan* plan,
                              int operand, const int64_t* share, uint64_t* ct, void* ws, uint64_t nonce,
                              void* stream);
 
 /* MO: forward product of Alg. 1.  ct_x1: n_ct[X_FWD] ciphertexts of <X>_1 in
- * the NTT domain (as pencil_encrypt writes them);
+ * the NTT domain, split form (as pencil_encrypt writes them; read only);
  * x0: the MO's share of X; w: weights; bias: int64 [c_out] at the output's
  * scale, or NULL.  Writes ct_y (n_out[FWD] ciphertexts for the DO) and y0, the
  * MO's share of Y (same shape as Y).  ws: ws_fwd_bytes of device memory. */
@@ -207,11 +219,29 @@ pencil_status pencil_linear_bwd(pencil_ctx* ctx, const pencil_layer* layer, cons
                                 uint64_t* ct_dx, int64_t* dx0, uint64_t* ct_dw, int64_t* dw_mask,
                                 void* ws, uint64_t nonce, void* stream);
 
-/* DO: decrypt the n_out[op] output ciphertexts of product `op`
- * (m = round(t [c0 + c1 s]_q / q) mod t, exact CRT) and gather the output
- * slots into share (shaped like Y, dX or W).  ws: ws_dec_bytes. */
+/* DO: the decryption that closes Alg. 1 and Alg. 2 (the DO's share of Y, dX
+ * or of the weight-gradient cross terms is the decryption of what the MO
+ * returns; BFV decryption of Sec. II.B).  Decrypt the n_out[op] output
+ * ciphertexts of product `op` (m = round(t [c0 + c1 s]_q / q) mod t, exact
+ * CRT) and gather the output slots (App. A's output positions) into share
+ * (shaped like Y, dX or W).  ws: ws_dec_bytes.  EINVAL for a bad op, layer,
+ * plan or pointer. */
 pencil_status pencil_decrypt(pencil_ctx* ctx, const pencil_layer* layer, const pencil_plan* plan, int op,
                              const uint64_t* ct, int64_t* share, void* ws, void* stream);
+
+/* DO, debug: pencil_decrypt plus a noise check.  Decryption is correct while
+ * the noise of every coefficient stays below q / (2t) (Sec. II.B); the check
+ * measures, at every output slot, the distance between t [c0 + c1 s]_q / q and
+ * the nearest integer -- the noise as a fraction of q / t -- and returns
+ * PENCIL_ENOISE when the largest reaches 1/4 (the product noise plus the flood,
+ * at most 2^flood_bits, should stay near 1/8 with the default flood_bits; a
+ * larger flood, or product noise close to the budget, makes decryption
+ * unreliable).  noise_frac (host, may be NULL) receives the largest fraction.
+ * Synchronous: waits for `stream`.  Calls on one context must not overlap (one
+ * device word of the context holds the running maximum). */
+pencil_status pencil_decrypt_checked(pencil_ctx* ctx, const pencil_layer* layer, const pencil_plan* plan, int op,
+                                     const uint64_t* ct, int64_t* share, void* ws, double* noise_frac /* host */,
+                                     void* stream);
 
 /* Plaintext product over Z_t of two tensors with the layer's operator
  * (op FWD: a = X, b = W -> Y; DX: a = dY, b = W -> dX; DW: a = X, b = dY -> dW),

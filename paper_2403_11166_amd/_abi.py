@@ -48,7 +48,7 @@ class Sizes(ctypes.Structure):
 
 class Info(ctypes.Structure):
     _fields_ = [("log2_n", ctypes.c_uint32), ("num_limbs", ctypes.c_uint32), ("flood_bits", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32), ("primes", ctypes.c_uint64 * 4), ("psi", ctypes.c_uint64 * 4),
+                ("ntt_loge", ctypes.c_uint32), ("primes", ctypes.c_uint64 * 4), ("psi", ctypes.c_uint64 * 4),
                 ("t", ctypes.c_uint64), ("seed", ctypes.c_uint64)]
 
 
@@ -80,6 +80,9 @@ SIGNATURES = {
                           + [ctypes.c_void_p] * 11 + [ctypes.c_uint64, ctypes.c_void_p]),
     "pencil_decrypt": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Layer), ctypes.POINTER(Plan), ctypes.c_int,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "pencil_decrypt_checked": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Layer), ctypes.POINTER(Plan),
+                                              ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                              ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
     "pencil_plan_auto_n": (ctypes.c_int, [ctypes.c_uint32, ctypes.POINTER(Layer), ctypes.POINTER(Plan)]),
     "pencil_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "pencil_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(KernelStat), ctypes.c_int,

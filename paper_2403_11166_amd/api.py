@@ -175,6 +175,12 @@ class Context:
                                              cache_path.encode() if cache_path else None))
         return q
 
+    def ntt_loge(self):
+        """log2 of the residues each NTT thread keeps (the autotuner's choice for this context)."""
+        info = A.Info()
+        self._check(self.lib.pencil_ctx_info(self.h, ctypes.byref(info)))
+        return info.ntt_loge
+
     def layout(self, layer, plan):
         s = A.Sizes()
         self._check(self.lib.pencil_layout(self.h, ctypes.byref(layer_struct(layer)),
@@ -240,6 +246,22 @@ class Context:
         self._check(self.lib.pencil_decrypt(self.h, ctypes.byref(layer_struct(layer)), ctypes.byref(plan), opi,
                                             _ptr(ct), _ptr(share), _ptr(ws), _stream()))
         return share
+
+    def decrypt_checked(self, layer, plan, op, ct, ws=None):
+        """decrypt() plus the noise check: returns (share, largest noise as a
+        fraction of q/t); raises PencilError(ENOISE) when it reaches 1/4.
+        Waits for the stream."""
+        opi = OPS.get(op, op)
+        plan = plan_struct(plan)
+        sz = self.layout(layer, plan)
+        shape = (_y_shape, _x_shape, _w_shape)[opi](layer)
+        share = torch.empty(shape, dtype=torch.int64, device=self.device)
+        ws = self._ws(sz.ws_dec_bytes) if ws is None else ws
+        frac = ctypes.c_double()
+        self._check(self.lib.pencil_decrypt_checked(self.h, ctypes.byref(layer_struct(layer)), ctypes.byref(plan),
+                                                    opi, _ptr(ct), _ptr(share), _ptr(ws), ctypes.byref(frac),
+                                                    _stream()))
+        return share, frac.value
 
     def zt_linear(self, layer, op, a, b):
         """Exact Z_t product of plaintext tensors with the layer's operator."""

@@ -19,8 +19,11 @@ __device__ __forceinline__ PENCIL_GLOBAL T* gview(T* p) {
 }
 typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
 
-// Staging format of the multiply-accumulate operands: (v mod 2^30) | (v >> 30) << 32.
+// Split form of a residue v < 2^60, the multiply-accumulate's operand format
+// (and the format of the data owner's NTT-domain ciphertexts):
+// (v mod 2^30) | (v >> 30) << 32.
 __device__ __forceinline__ uint64_t split30(uint64_t v) { return (v & 0x3FFFFFFFull) | ((v >> 30) << 32); }
+__device__ __forceinline__ uint64_t unsplit30(uint64_t s) { return (s & 0xFFFFFFFFull) | ((s >> 32) << 30); }
 
 // ---------------------------------------------------------- encode helpers
 // round(q m / t) mod q_l for m in [0, t): Delta * m + round(rho m / t), rho = q mod t.
@@ -38,51 +41,76 @@ __device__ __forceinline__ uint64_t delta_scale(uint64_t m, uint64_t rr, const L
   return add_mod(mul_shoup(m, lc.delta, lc.delta_sh, lc.q), rr, lc.q);
 }
 
-// Value of the forward-encoded A tile `tile` at polynomial slot `slot`
-// (App. A's pi_v generalised), or -1 for an empty slot.
-__device__ __forceinline__ int64_t a_slot_offset(const Geo& G, const View& V, int64_t tile, int slot) {
-  int mm = slot / G.RS;
-  int rem = slot - mm * G.RS;
+// floor(n / d) for n, d < 2^16 from m = ceil(2^32 / d) (m = 0 stands for
+// d = 1): rounding the reciprocal up adds less than n / 2^32 < 2^-16 to n / d,
+// whose fractional part is at most 1 - 1/d <= 1 - 2^-16, so the floor holds.
+__device__ __forceinline__ int fdiv(int n, uint32_t m) { return m ? (int)__umulhi((uint32_t)n, m) : n; }
+
+// Origin of one operand tile in virtual coordinates, decoded once per tile:
+// A side (m, k, y, x) of slot 0's entry; K side (r, k, kernel row, kernel column).
+struct TileOrigin {
+  int i0, i1, y, x;
+};
+
+// A tiles are numbered ((((mi*nK + ki)*nOY + oyi)*nOX + oxi)*nKY + kyi)*nKX + kxi.
+__device__ __forceinline__ TileOrigin a_tile_origin(const Geo& G, int64_t tile) {
+  int64_t ti = tile;
+  const int kxi = (int)(ti % G.nKX); ti /= G.nKX;
+  const int kyi = (int)(ti % G.nKY); ti /= G.nKY;
+  const int oxi = (int)(ti % G.nOX); ti /= G.nOX;
+  const int oyi = (int)(ti % G.nOY); ti /= G.nOY;
+  const int ki = (int)(ti % G.nK); ti /= G.nK;
+  const int mi = (int)ti;
+  return {mi * G.mt, ki * G.kt, oyi * G.oh + kyi * G.kh, oxi * G.ow + kxi * G.kw};
+}
+
+// K tiles are numbered ((ri*nK + ki)*nKY + kyi)*nKX + kxi.
+__device__ __forceinline__ TileOrigin k_tile_origin(const Geo& G, int64_t tile) {
+  int64_t ti = tile;
+  const int kxi = (int)(ti % G.nKX); ti /= G.nKX;
+  const int kyi = (int)(ti % G.nKY); ti /= G.nKY;
+  const int ki = (int)(ti % G.nK); ti /= G.nK;
+  const int ri = (int)ti;
+  return {ri * G.rt, ki * G.kt, kyi * G.kh, kxi * G.kw};
+}
+
+__device__ __forceinline__ TileOrigin tile_origin(int side, const Geo& G, int64_t tile) {
+  return side == 0 ? a_tile_origin(G, tile) : k_tile_origin(G, tile);
+}
+
+// Offset into the caller's tensor of the forward-encoded A tile's value at
+// polynomial slot `slot` (App. A's pi_v generalised: slot = mm*RS + kk*ha*wa +
+// ya*wa + xa), or -1 for an empty slot.
+__device__ __forceinline__ int64_t a_slot_at(const Geo& G, const View& V, const TileOrigin& T, int slot) {
+  const int mm = fdiv(slot, G.dv_rs);
+  const int rem = slot - mm * G.RS;
   if (mm >= G.mt || rem >= G.S) return -1;
   const int hw = G.ha * G.wa;
-  int kk = rem / hw;
-  int rem2 = rem - kk * hw;
-  int ya = rem2 / G.wa, xa = rem2 - (rem2 / G.wa) * G.wa;
-  // tile index = ((((mi*nK + ki)*nOY + oyi)*nOX + oxi)*nKY + kyi)*nKX + kxi
-  int64_t ti = tile;
-  int kxi = (int)(ti % G.nKX); ti /= G.nKX;
-  int kyi = (int)(ti % G.nKY); ti /= G.nKY;
-  int oxi = (int)(ti % G.nOX); ti /= G.nOX;
-  int oyi = (int)(ti % G.nOY); ti /= G.nOY;
-  int ki = (int)(ti % G.nK); ti /= G.nK;
-  int mi = (int)ti;
-  int m = mi * G.mt + mm, k = ki * G.kt + kk;
-  int y = oyi * G.oh + kyi * G.kh + ya, x = oxi * G.ow + kxi * G.kw + xa;
+  const int kk = fdiv(rem, G.dv_hw);
+  const int rem2 = rem - kk * hw;
+  const int ya = fdiv(rem2, G.dv_wa), xa = rem2 - ya * G.wa;
+  const int m = T.i0 + mm, k = T.i1 + kk, y = T.y + ya, x = T.x + xa;
   if (m >= G.M || k >= G.K || y >= G.HA || x >= G.WA) return -1;
-  int ys = y - V.pady, xs = x - V.pad;
+  const int ys = y - V.pady, xs = x - V.pad;
   if (ys < 0 || xs < 0 || ys >= V.H || xs >= V.W) return -1;
   return m * V.s0 + k * V.s1 + ys * V.sy + xs * V.sx;
 }
 
-// Value offset of the reverse-encoded K tile `tile` at `slot` (App. A's pi_W).
-__device__ __forceinline__ int64_t k_slot_offset(const Geo& G, const View& V, int64_t tile, int slot) {
-  // slot = O + rr*S - (kk*ha*wa + dy*wa + dx)
-  int z = slot - G.O + G.S - 1;
+// The same for the reverse-encoded K tile (App. A's pi_W: slot = O + rr*S -
+// (kk*ha*wa + dy*wa + dx)).
+__device__ __forceinline__ int64_t k_slot_at(const Geo& G, const View& V, const TileOrigin& T, int slot) {
+  const int z = slot - G.O + G.S - 1;
   if (z < 0) return -1;
-  int rr = z / G.S;
+  const int rr = fdiv(z, G.dv_s);
   if (rr >= G.rt) return -1;
-  int D = rr * G.S + G.O - slot;
+  const int D = rr * G.S + G.O - slot;  // in [0, S)
   const int hw = G.ha * G.wa;
-  int kk = D / hw;
-  int rem = D - kk * hw;
-  int dy = rem / G.wa, dx = rem - (rem / G.wa) * G.wa;
+  const int kk = fdiv(D, G.dv_hw);
+  const int rem = D - kk * hw;
+  const int dy = fdiv(rem, G.dv_wa), dx = rem - dy * G.wa;
   if (dy >= G.kh || dx >= G.kw) return -1;
-  int64_t ti = tile;  // ((ri*nK + ki)*nKY + kyi)*nKX + kxi
-  int kxi = (int)(ti % G.nKX); ti /= G.nKX;
-  int kyi = (int)(ti % G.nKY); ti /= G.nKY;
-  int ki = (int)(ti % G.nK); ti /= G.nK;
-  int ri = (int)ti;
-  int r = ri * G.rt + rr, k = ki * G.kt + kk, a = kyi * G.kh + dy, b = kxi * G.kw + dx;
+  const int r = T.i0 + rr, k = T.i1 + kk;
+  int a = T.y + dy, b = T.x + dx;
   if (r >= G.R || k >= G.K || a >= G.KH || b >= G.KW) return -1;
   if (V.flip) {
     a = V.KH - 1 - a;
@@ -91,8 +119,8 @@ __device__ __forceinline__ int64_t k_slot_offset(const Geo& G, const View& V, in
   return r * V.s0 + k * V.s1 + a * V.sy + b * V.sx;
 }
 
-__device__ __forceinline__ int64_t slot_offset(int side, const Geo& G, const View& V, int64_t tile, int slot) {
-  return side == 0 ? a_slot_offset(G, V, tile, slot) : k_slot_offset(G, V, tile, slot);
+__device__ __forceinline__ int64_t slot_at(int side, const Geo& G, const View& V, const TileOrigin& T, int slot) {
+  return side == 0 ? a_slot_at(G, V, T, slot) : k_slot_at(G, V, T, slot);
 }
 
 // Work item of block `b` of `total`.  Workgroups go to the 8 XCDs round-robin

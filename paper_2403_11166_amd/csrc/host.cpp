@@ -33,6 +33,7 @@ struct pencil_ctx {
   uint64_t* d_pk_split = nullptr;  // [2][L][N], the multiply-accumulate's split operand form
   uint64_t* d_pk_coeff = nullptr;
   int64_t* d_s_coeff = nullptr;
+  uint64_t* d_noise = nullptr;   // one word: the checked decryption's largest noise fraction
   std::string err;
   // kernel timing with HIP events on the launch stream (pencil_profile_*)
   bool prof_on = false;
@@ -237,8 +238,8 @@ static pencil_status resolve_params(const pencil_params* p, pencil_ctx* ctx) {
   } else {
     for (uint32_t l = 0; l < p->num_limbs; ++l) {
       uint64_t q = p->primes[l];
-      if (q == 0 || q >= (1ull << 61) || !is_prime(q) || (q - 1) % (2 * n) != 0)
-        return fail(nullptr, PENCIL_EINVAL, "prime %u (%llu) must be a prime < 2^61 with q = 1 mod 2N", l,
+      if (q == 0 || q >= (1ull << 60) || !is_prime(q) || (q - 1) % (2 * n) != 0)
+        return fail(nullptr, PENCIL_EINVAL, "prime %u (%llu) must be a prime < 2^60 with q = 1 mod 2N", l,
                     (unsigned long long)q);
       for (uint32_t k = 0; k < l; ++k)
         if (I.primes[k] == q) return fail(nullptr, PENCIL_EINVAL, "repeated prime");
@@ -370,7 +371,8 @@ extern "C" pencil_status pencil_ctx_create(const pencil_params* params, pencil_c
       hipMalloc(&ctx->d_s_sh, ln) != hipSuccess || hipMalloc(&ctx->d_pk_ntt, 2 * ln) != hipSuccess ||
       hipMalloc(&ctx->d_pk_sh, 2 * ln) != hipSuccess || hipMalloc(&ctx->d_pk_coeff, 2 * ln) != hipSuccess ||
       hipMalloc(&ctx->d_pk_split, 2 * ln) != hipSuccess ||
-      hipMalloc(&ctx->d_s_coeff, n * sizeof(int64_t)) != hipSuccess)
+      hipMalloc(&ctx->d_s_coeff, n * sizeof(int64_t)) != hipSuccess ||
+      hipMalloc(&ctx->d_noise, 256) != hipSuccess)
     return cleanup(fail(nullptr, PENCIL_ENOMEM, "device allocation failed"));
   if (hipMemcpy(ctx->d_tables, tab.data(), 2 * L * n * sizeof(TW), hipMemcpyHostToDevice) != hipSuccess)
     return cleanup(fail(nullptr, PENCIL_EHIP, "table upload failed"));
@@ -412,6 +414,7 @@ extern "C" pencil_status pencil_ctx_destroy(pencil_ctx* ctx) {
   hipFree(ctx->d_pk_split);
   hipFree(ctx->d_pk_coeff);
   hipFree(ctx->d_s_coeff);
+  hipFree(ctx->d_noise);
   for (auto& r : ctx->pending) {
     hipEventDestroy(r.a);
     hipEventDestroy(r.b);
@@ -428,6 +431,7 @@ extern "C" const char* pencil_last_error(const pencil_ctx* ctx) {
 extern "C" pencil_status pencil_ctx_info(const pencil_ctx* ctx, pencil_info* out) {
   if (!ctx || !out) return PENCIL_EINVAL;
   *out = ctx->info;
+  out->ntt_loge = (uint32_t)ctx->C.ntt_loge;
   return PENCIL_OK;
 }
 
@@ -544,6 +548,12 @@ static bool make_geo(const OpGeom& g, const pencil_tile& t, int n, Geo* G) {
   o.S = t.k * o.ha * o.wa;
   o.RS = t.r * o.S;
   o.O = (t.k - 1) * o.ha * o.wa + (t.kh - 1) * o.wa + t.kw - 1;
+  // n / d for n, d < 2^16 (slots and in-tile offsets; n <= 16384 here)
+  auto recip = [](int64_t d) { return d <= 1 ? 0u : (uint32_t)(0xFFFFFFFFull / (uint64_t)d + 1); };
+  o.dv_rs = recip(o.RS);
+  o.dv_hw = recip((int64_t)o.ha * o.wa);
+  o.dv_wa = recip(o.wa);
+  o.dv_s = recip(o.S);
   return true;
 }
 
@@ -830,6 +840,12 @@ extern "C" pencil_status pencil_encrypt(pencil_ctx* ctx, const pencil_layer* L, 
   return PENCIL_OK;
 }
 
+// Element offset from a staged component-0 copy to component 1 of the same
+// ciphertext in the caller's buffer (both 8-byte aligned device addresses).
+static int64_t comp1_offset(const uint64_t* staged, const uint64_t* caller, int64_t poly) {
+  return ((int64_t)(uintptr_t)caller - (int64_t)(uintptr_t)staged) / (int64_t)sizeof(uint64_t) + poly;
+}
+
 // One product: NTT of the inputs, MAC (+ pk u'), INTT, flood and mask.
 struct TermIn {
   const uint64_t* ct;     // coefficient-domain ciphertexts (A side if a_is_ct)
@@ -854,25 +870,30 @@ static pencil_status run_product(pencil_ctx* ctx, const pencil_layer* L, int op,
   for (int i = 0; i < n_terms; ++i) {
     const TermIn& T = terms[i];
     if (T.a_is_ct) {
+      // the caller's ciphertexts are read in place; with a share to add,
+      // component 0 is staged (share added) and component 1 stays in place
       uint64_t* cts = w;
       w += na * ctw;
       uint64_t* pts = w;
       w += nk * poly;
-      hipError_t e = timed(ctx, KID_NTT_CT, s, [&] { return launch_ntt_ct(T.ct, cts, na, add_share, G, view_a(L, op), C, ctx->T, s); });
+      hipError_t e = hipSuccess;
+      MacTerm mt{T.ct, pts, poly, 1, 0};
+      if (add_share) {
+        e = timed(ctx, KID_NTT_CT, s, [&] { return launch_ntt_ct(T.ct, cts, na, add_share, G, view_a(L, op), C, ctx->T, s); });
+        mt.a = cts;
+        mt.c1 = comp1_offset(cts, T.ct, poly);
+      }
       if (e == hipSuccess)
         e = timed(ctx, KID_NTT_PT, s, [&] { return launch_ntt_pt(T.pt, pts, nk, 1, G, view_k(L, op), C, ctx->T, s); });
       if (e != hipSuccess) return fail(ctx, PENCIL_EHIP, "ntt launch: %s", hipGetErrorString(e));
-      A.term[i] = MacTerm{cts, pts, 1, 0};
+      A.term[i] = mt;
     } else {
       uint64_t* pts = w;
       w += na * poly;
-      uint64_t* cts = w;
       w += nk * ctw;
       hipError_t e = timed(ctx, KID_NTT_PT, s, [&] { return launch_ntt_pt(T.pt, pts, na, 0, G, view_a(L, op), C, ctx->T, s); });
-      if (e == hipSuccess)
-        e = timed(ctx, KID_NTT_CT, s, [&] { return launch_ntt_ct(T.ct, cts, nk, nullptr, G, view_k(L, op), C, ctx->T, s); });
       if (e != hipSuccess) return fail(ctx, PENCIL_EHIP, "ntt launch: %s", hipGetErrorString(e));
-      A.term[i] = MacTerm{pts, cts, 0, 0};
+      A.term[i] = MacTerm{pts, T.ct, poly, 0, 0};
     }
   }
   uint64_t* u = w;
@@ -962,8 +983,41 @@ extern "C" pencil_status pencil_decrypt(pencil_ctx* ctx, const pencil_layer* L, 
   hipStream_t s = (hipStream_t)stream;
   uint64_t* x = (uint64_t*)ws;
   hipError_t e = timed(ctx, KID_PHASE, s, [&] { return launch_phase(ct, x, no, ctx->d_s_ntt, ctx->d_s_sh, ctx->C, ctx->T, s); });
-  if (e == hipSuccess) e = timed(ctx, KID_DECODE, s, [&] { return launch_decode(x, share, no, G, view_out(L, op), ctx->C, s); });
+  if (e == hipSuccess)
+    e = timed(ctx, KID_DECODE, s, [&] { return launch_decode(x, share, no, G, view_out(L, op), ctx->C, nullptr, s); });
   if (e != hipSuccess) return fail(ctx, PENCIL_EHIP, "decrypt launch: %s", hipGetErrorString(e));
+  return PENCIL_OK;
+}
+
+extern "C" pencil_status pencil_decrypt_checked(pencil_ctx* ctx, const pencil_layer* L, const pencil_plan* P, int op,
+                                                const uint64_t* ct, int64_t* share, void* ws, double* noise_frac,
+                                                void* stream) {
+  if (!ctx) return PENCIL_EINVAL;
+  if (op < 0 || op > 2) return fail(ctx, PENCIL_EINVAL, "op %d invalid", op);
+  TRY(check_buf(ctx, ct, "ct"));
+  TRY(check_ptr(ctx, share, "share"));
+  TRY(check_buf(ctx, ws, "ws"));
+  Geo G;
+  TRY(get_geo(ctx, L, P, op, &G));
+  const int64_t no = n_out_tiles(G);
+  hipStream_t s = (hipStream_t)stream;
+  uint64_t* x = (uint64_t*)ws;
+  uint32_t* nz = (uint32_t*)ctx->d_noise;
+  hipError_t e = launch_set_u64(ctx->d_noise, 0, 0, s);  // a fill kernel, not a memset node
+  if (e == hipSuccess)
+    e = timed(ctx, KID_PHASE, s, [&] { return launch_phase(ct, x, no, ctx->d_s_ntt, ctx->d_s_sh, ctx->C, ctx->T, s); });
+  if (e == hipSuccess)
+    e = timed(ctx, KID_DECODE, s, [&] { return launch_decode(x, share, no, G, view_out(L, op), ctx->C, nz, s); });
+  uint32_t bits = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&bits, nz, sizeof bits, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(ctx, PENCIL_EHIP, "checked decrypt: %s", hipGetErrorString(e));
+  float frac;
+  std::memcpy(&frac, &bits, sizeof frac);
+  if (noise_frac) *noise_frac = frac;
+  if (frac >= 0.25f)
+    return fail(ctx, PENCIL_ENOISE, "decryption noise reaches %.3f of q/t (limit 0.25): the result is unreliable",
+                (double)frac);
   return PENCIL_OK;
 }
 
@@ -1350,19 +1404,26 @@ static pencil_status step_bind_tables(pencil_step* st, const pencil_step_io* io,
       StepSeg base{};
       base.ctx = e.ctx;
       base.G = G;
-      // term A-side ciphertext
+      // term A-side ciphertext: component 0 staged with the share added
+      // (forward, input gradient), component 1 and the weight gradient's
+      // ciphertexts read in place
       {
         uint64_t* cts = w;
         w += na * ctw;
         uint64_t* pts = w;
         w += nk * poly;
-        StepSeg sc = base;
-        sc.kind = SEG_CT;
-        sc.src = ct_a;
-        sc.dst = cts;
-        sc.tensor = add_share;
-        sc.V = view_a(L, op);
-        add_seg(ntt, sc, na * 2 * C.L);
+        MacTerm mt{ct_a, pts, poly, 1, 0};
+        if (add_share) {
+          StepSeg sc = base;
+          sc.kind = SEG_CT;
+          sc.src = ct_a;
+          sc.dst = cts;
+          sc.tensor = add_share;
+          sc.V = view_a(L, op);
+          add_seg(ntt, sc, na * C.L);
+          mt.a = cts;
+          mt.c1 = comp1_offset(cts, ct_a, poly);
+        }
         StepSeg sp = base;
         sp.kind = SEG_PT;
         sp.side = 1;
@@ -1370,13 +1431,12 @@ static pencil_status step_bind_tables(pencil_step* st, const pencil_step_io* io,
         sp.dst = pts;
         sp.V = view_k(L, op);
         add_seg(ntt, sp, nk * C.L);
-        A.term[0] = MacTerm{cts, pts, 1, 0};
+        A.term[0] = mt;
         A.n_terms = 1;
       }
       if (op == 2) {  // term B: plaintext <X>_0 on the A side, ciphertext <dY>_1 on the K side
         uint64_t* pts = w;
         w += na * poly;
-        uint64_t* cts = w;
         w += nk * ctw;
         StepSeg sp = base;
         sp.kind = SEG_PT;
@@ -1385,14 +1445,7 @@ static pencil_status step_bind_tables(pencil_step* st, const pencil_step_io* io,
         sp.dst = pts;
         sp.V = view_a(L, op);
         add_seg(ntt, sp, na * C.L);
-        StepSeg sc = base;
-        sc.kind = SEG_CT;
-        sc.src = b.ct_dy_dw;
-        sc.dst = cts;
-        sc.tensor = nullptr;
-        sc.V = view_k(L, op);
-        add_seg(ntt, sc, nk * 2 * C.L);
-        A.term[1] = MacTerm{pts, cts, 0, 0};
+        A.term[1] = MacTerm{pts, b.ct_dy_dw, poly, 0, 0};
         A.n_terms = 2;
       }
       uint64_t* u = w;

@@ -5,8 +5,9 @@
 namespace pencil {
 
 // Encryption in the NTT domain: ct_c = pk_c * u + NTT(e_c (+ round(q m / t) on
-// c = 0)), with m the encoded share at each slot; the product path consumes
-// ciphertexts in this form.  Grid: n_ct * 2 * L, u_ntt is [n][L][N].
+// c = 0)), with m the encoded share at each slot, each residue stored in the
+// multiply-accumulate's split form; the product path consumes ciphertexts in
+// this form.  Grid: n_ct * 2 * L, u_ntt is [n][L][N].
 template <int LOGN, int LOGE>
 __global__ void __launch_bounds__(512, (LOGE >= 5 ? 2 : 4)) k_encrypt(const uint64_t* u_ntt, const int64_t* share, uint64_t* ct, int side,
                                                   Geo G, View V, const uint64_t* pk_ntt, const uint64_t* pk_sh,
@@ -23,6 +24,7 @@ __global__ void __launch_bounds__(512, (LOGE >= 5 ? 2 : 4)) k_encrypt(const uint
   const uint64_t* pk = pk_ntt + ((int64_t)c * L + l) * n;
   const uint64_t* pks = pk_sh + ((int64_t)c * L + l) * n;
   const uint64_t obj = obj_base + (uint64_t)j;
+  const TileOrigin to = tile_origin(side, G, j);
   for (int blk = threadIdx.x; blk < n / 4; blk += blockDim.x) {
     U64x4 e = philox((uint64_t)blk, obj, c ? P_ENC_E1 : P_ENC_E0, 0, C.seed, nonce);
 #pragma unroll
@@ -30,7 +32,7 @@ __global__ void __launch_bounds__(512, (LOGE >= 5 ? 2 : 4)) k_encrypt(const uint
       const int i = blk * 4 + z;
       uint64_t v = small_to_mod(cbd21(e.v[z]), lc.q);
       if (c == 0) {
-        int64_t off = slot_offset(side, G, V, j, i);
+        const int64_t off = slot_at(side, G, V, to, i);
         if (off >= 0) {
           uint64_t m = (uint64_t)share[off];
           v = add_mod(v, delta_scale(m, round_rho(m, C), lc), lc.q);
@@ -43,7 +45,7 @@ __global__ void __launch_bounds__(512, (LOGE >= 5 ? 2 : 4)) k_encrypt(const uint
   ntt_fwd<LOGN, LOGE>(lds, T.fw + (int64_t)l * n, lc.q);
   uint64_t* o = ct + p * n;
   for (int i = threadIdx.x; i < n; i += blockDim.x)
-    o[i] = add_mod(mul_shoup(u[i], pk[i], pks[i], lc.q), lds[lpad(i)], lc.q);
+    o[i] = split30(add_mod(mul_shoup(u[i], pk[i], pks[i], lc.q), lds[lpad(i)], lc.q));
 }
 
 // Decryption phase per limb: x = c0 + INTT(NTT(c1) * s).  Grid: n * L, x is [n][L][N].
@@ -76,8 +78,12 @@ __global__ void __launch_bounds__(512) k_phase(const uint64_t* ct, uint64_t* x, 
 // y_l t = alpha_l q_l + beta_l,  t x / q = sum alpha_l + sum beta_l / q_l - v t,
 // so m = (sum alpha_l + round(F / q)) mod t with F = sum beta_l (q / q_l); the
 // rounding compares 2F with (2j + 1) q.  One thread per output element.
+// With `noise` set, the distance |F / q - round(F / q)| = |t x / q - m'| (m' the
+// unreduced message), which is the noise as a fraction of q / t, is also
+// computed in double precision (sum of beta_l / q_l, error ~L 2^-53) and its
+// maximum kept in *noise (float bits; non-negative floats order like integers).
 __global__ void __launch_bounds__(256) k_decode(const uint64_t* x, int64_t* share, int64_t n_out, Geo G, View OV,
-                                                Consts C) {
+                                                Consts C, uint32_t* noise) {
   const int n = C.n, L = C.L;
   const int64_t per = (int64_t)G.mt * G.rt * G.oh * G.ow;
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -104,6 +110,7 @@ __global__ void __launch_bounds__(256) k_decode(const uint64_t* x, int64_t* shar
 #pragma unroll
   for (int w = 0; w <= kMaxWords; ++w) F[w] = 0;
   uint64_t alpha = 0;
+  double fsum = 0.0;
   for (int l = 0; l < L; ++l) {
     const LimbConst& lc = C.limb[l];
     const uint64_t xl = x[(o * L + l) * n + slot];
@@ -114,6 +121,7 @@ __global__ void __launch_bounds__(256) k_decode(const uint64_t* x, int64_t* shar
       beta -= lc.q;
       est += 1;
     }
+    if (noise) fsum += (double)beta / (double)lc.q;
     alpha += est;  // each alpha_l < t
     // F += beta * qhat_l
     uint64_t carry = 0;
@@ -155,6 +163,10 @@ __global__ void __launch_bounds__(256) k_decode(const uint64_t* x, int64_t* shar
   }
   uint64_t mres = (alpha % C.t + rnd) % C.t;
   share[m * OV.s0 + r * OV.s1 + yy * OV.sy + xx * OV.sx] = (int64_t)mres;
+  if (noise) {
+    const float frac = (float)fabs(fsum - (double)rnd);
+    atomicMax(noise, __float_as_uint(frac));
+  }
 }
 
 // Key generation, one block per limb: s ternary (stream P_SK), a uniform mod q_l
@@ -241,11 +253,12 @@ hipError_t launch_phase(const uint64_t* ct, uint64_t* x, int64_t n_ct, const uin
 }
 
 hipError_t launch_decode(const uint64_t* x, int64_t* share, int64_t n_out, const Geo& G, const View& outV,
-                         const Consts& C, hipStream_t s) {
+                         const Consts& C, uint32_t* noise, hipStream_t s) {
   const int64_t per = (int64_t)G.mt * G.rt * G.oh * G.ow;
   const int64_t threads = n_out * per;
   if (threads <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_decode, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, x, share, n_out, G, outV, C);
+  hipLaunchKernelGGL(k_decode, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, x, share, n_out, G, outV, C,
+                     noise);
   return hipGetLastError();
 }
 

@@ -139,13 +139,13 @@ __device__ __forceinline__ void mac_term(uint64_t* smem, const MacTerm& T, const
       if (k0 + b < ksteps) {
         if (have_a) {
           sa[b][0][grp][s] = pa[0];
-          if (A_CT) sa[b][1][grp][s] = pa[B.pt_stride];
+          if (A_CT) sa[b][1][grp][s] = pa[T.c1];
         }
 #pragma unroll
         for (int j = 0; j < KC; ++j) {
           if (have_k[j]) {
             sk[b][0][grp + 8 * j][s] = pk[j][0];
-            if (!A_CT) sk[b][1][grp + 8 * j][s] = pk[j][B.pt_stride];
+            if (!A_CT) sk[b][1][grp + 8 * j][s] = pk[j][T.c1];
           }
           pk[j] += sk_str;
         }
@@ -288,7 +288,7 @@ __device__ __forceinline__ void mac_term_direct(const MacTerm& T, const MacArgs&
   const int sp = G.nOY * G.nOX, kspan = G.nKY * G.nKX;
   const int ksteps = G.nK * kspan;
   const int64_t sa_str = A_CT ? B.ct_stride : B.pt_stride, sk_str = A_CT ? B.pt_stride : B.ct_stride;
-  const int64_t pt_stride = B.pt_stride;
+  const int64_t c1 = T.c1;
   // Rows or columns past the end read row 0 / column 0 of the chunk instead
   // (valid memory); their sums are never stored.
   const PENCIL_GLOBAL uint64_t* pa[TM];
@@ -299,14 +299,14 @@ __device__ __forceinline__ void mac_term_direct(const MacTerm& T, const MacArgs&
     if (row >= A.m_rows) row = B.row0 + B.rg;
     const int mi = row / sp, rsp = row % sp;
     pa[a] = gview(T.a) + B.ln + B.s + (((int64_t)mi * G.nK * sp + rsp) * kspan) * sa_str;
-    if (NC == 1 && A_CT) pa[a] += B.comp * pt_stride;  // this wave's component
+    if (NC == 1 && A_CT) pa[a] += B.comp * c1;  // this wave's component
   }
 #pragma unroll
   for (int c2 = 0; c2 < TR; ++c2) {
     int col = B.col0 + B.cg + c2;
     if (col >= G.nR) col = B.col0 + B.cg;
     pk[c2] = gview(T.k) + B.ln + B.s + (int64_t)col * ksteps * sk_str;
-    if (NC == 1 && !A_CT) pk[c2] += B.comp * pt_stride;
+    if (NC == 1 && !A_CT) pk[c2] += B.comp * c1;
   }
   const int64_t a_wrap = ((int64_t)(sp - 1) * kspan + 1) * sa_str;
   const uint32_t fold_every = C.mac_fold, reduce_every = C.mac_chunk;
@@ -321,12 +321,12 @@ __device__ __forceinline__ void mac_term_direct(const MacTerm& T, const MacArgs&
 #pragma unroll
     for (int a = 0; a < TM; ++a) {
       va[a][0] = pa[a][0];
-      if (NC == 2) va[a][NC - 1] = A_CT ? pa[a][pt_stride] : va[a][0];
+      if (NC == 2) va[a][NC - 1] = A_CT ? pa[a][c1] : va[a][0];
     }
 #pragma unroll
     for (int c2 = 0; c2 < TR; ++c2) {
       vk[c2][0] = pk[c2][0];
-      if (NC == 2) vk[c2][NC - 1] = A_CT ? vk[c2][0] : pk[c2][pt_stride];
+      if (NC == 2) vk[c2][NC - 1] = A_CT ? vk[c2][0] : pk[c2][c1];
     }
     const bool adv = --left > 0;
     const int64_t da = !adv ? 0 : (kk + 1 == kspan) ? a_wrap : sa_str;

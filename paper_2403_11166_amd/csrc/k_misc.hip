@@ -97,11 +97,11 @@ __device__ __forceinline__ void do_flood(uint64_t* ct, int64_t n_out, int64_t* s
     // model owner's share at the output slots: slot = mm*RS + O + rr*S + y*wa + x
     int zz = i - G.O;
     if (zz >= 0) {
-      int mm = zz / G.RS;
-      int rem = zz - mm * G.RS;
-      int rr2 = rem / G.S;
-      int rem2 = rem - rr2 * G.S;
-      int y = rem2 / G.wa, x = rem2 - (rem2 / G.wa) * G.wa;
+      const int mm = fdiv(zz, G.dv_rs);
+      const int rem = zz - mm * G.RS;
+      const int rr2 = fdiv(rem, G.dv_s);
+      const int rem2 = rem - rr2 * G.S;
+      const int y = fdiv(rem2, G.dv_wa), x = rem2 - y * G.wa;
       if (mm < G.mt && y < G.oh && x < G.ow) {
         int m = mi * G.mt + mm, r = ri * G.rt + rr2, yy = oyi * G.oh + y, xx = oxi * G.ow + x;
         if (m < G.M && r < G.R && yy < G.OH && xx < G.OW) {

@@ -41,7 +41,7 @@ hipError_t launch_ntt_plain(uint64_t* data, int64_t polys, bool inverse, const C
 hipError_t launch_ntt_ct(const uint64_t* src, uint64_t* dst, int64_t n_ct, const int64_t* share, const Geo& G,
                          const View& V, const Consts& C, const Tables& T, hipStream_t s) {
   if (n_ct <= 0) return hipSuccess;
-  NTT_DISPATCH(k_ntt_ct, dim3((unsigned)(n_ct * 2 * C.L)), C, s, src, dst, share, G, V, C, T);
+  NTT_DISPATCH(k_ntt_ct, dim3((unsigned)(n_ct * C.L)), C, s, src, dst, share, G, V, C, T);
   return hipGetLastError();
 }
 

@@ -25,44 +25,55 @@ struct NttShape {
   static constexpr int start(int i) { return i == 0 ? 0 : start(i - 1) + size(i - 1); }
 };
 
-// Butterfly constants of one modulus: 2q, 2^64 - q, 2^64 - 2q and 2q + 1.  They
-// are hidden from the optimiser so that x - q stays the single 64-bit addition
-// x + (2^64 - q) instead of a borrow chain.
+// Butterfly constants of one modulus q < 2^60: 4q, 2^64 - 4q, 4q + 1, and
+// 2q, 2^64 - 2q, 2^64 - q for the final reduction.  They are hidden from the
+// optimiser so that x - 4q stays the single 64-bit addition x + (2^64 - 4q)
+// instead of a borrow chain.
 struct BflyK {
-  uint64_t q2, nq, nq2, q2p1;
+  uint64_t q4, nq4, q4p1, q2, nq2, nq;
 };
 
 __device__ __forceinline__ BflyK bfly_consts(uint64_t q) {
-  BflyK k{2 * q, 0 - q, 0 - 2 * q, 2 * q + 1};
-  asm volatile("" : "+s"(k.q2), "+s"(k.nq), "+s"(k.nq2), "+s"(k.q2p1));
+  BflyK k{4 * q, 0 - 4 * q, 4 * q + 1, 2 * q, 0 - 2 * q, 0 - q};
+  asm volatile("" : "+s"(k.q4), "+s"(k.nq4), "+s"(k.q4p1), "+s"(k.q2), "+s"(k.nq2), "+s"(k.nq));
   return k;
 }
 
-// x - 2q if x >= 2q, else x, for x < 2^63: the sign of x - 2q decides.
-__device__ __forceinline__ uint64_t csub2q(uint64_t x, const BflyK& k) {
-  const uint64_t d = x + k.nq2;
+// x - c if x >= c, else x, for x < 2^63 and c < 2^62 (nc = 2^64 - c): the sign
+// of x - c decides.
+__device__ __forceinline__ uint64_t csub(uint64_t x, uint64_t c, uint64_t nc) {
+  const uint64_t d = x + nc;
   const uint32_t m = (uint32_t)((int32_t)(uint32_t)(d >> 32) >> 31);
-  const uint64_t back = ((uint64_t)((uint32_t)(k.q2 >> 32) & m) << 32) | ((uint32_t)k.q2 & m);
+  const uint64_t back = ((uint64_t)((uint32_t)(c >> 32) & m) << 32) | ((uint32_t)c & m);
   return d + back;
 }
 
-// Shoup's lazy product y w mod q in [0, 2q): y w - floor(y ws / 2^64) q.
+// Lazy Shoup product y w mod q in [0, 4q) for any y < 2^64, w < q, with
+// companion ws = floor(w 2^64 / q).  Of y ws / 2^64 = y1 ws1 + (y1 ws0 + y0 ws1)
+// / 2^32 + y0 ws0 / 2^64 (32-bit halves) the estimate keeps y1 ws1 +
+// hi(y0 ws1) + hi(y1 ws0): three multiplies instead of four.  The dropped parts
+// sum to less than 3, so the estimate is at most 2 below floor(y ws / 2^64),
+// which is itself at most 1 below floor(y w / q); y w - est q is then below 4q.
 __device__ __forceinline__ uint64_t shoup_lazy(uint64_t y, const TW w, const BflyK& k) {
-  return y * w.w + __umul64hi(y, w.ws) * k.nq;
+  const uint32_t y0 = (uint32_t)y, y1 = (uint32_t)(y >> 32);
+  const uint32_t s0 = (uint32_t)w.ws, s1 = (uint32_t)(w.ws >> 32);
+  uint64_t est = (uint64_t)y1 * s1 + __umulhi(y0, s1);
+  est += __umulhi(y1, s0);
+  return y * w.w + est * k.nq;
 }
 
-// Harvey's lazy Cooley-Tukey butterfly: x, y in [0, 4q) -> [0, 4q), q < 2^61.
+// Lazy Cooley-Tukey butterfly: x, y in [0, 8q) -> [0, 8q) (8q < 2^63).
 __device__ __forceinline__ void ct_bfly(uint64_t& x, uint64_t& y, const TW w, const BflyK& k) {
-  const uint64_t a = csub2q(x, k);
+  const uint64_t a = csub(x, k.q4, k.nq4);
   const uint64_t t = shoup_lazy(y, w, k);
   x = a + t;
-  y = (a + k.q2p1) + ~t;  // a - t + 2q
+  y = (a + k.q4p1) + ~t;  // a - t + 4q
 }
 
-// Lazy Gentleman-Sande butterfly: u, v in [0, 2q) -> [0, 2q).
+// Lazy Gentleman-Sande butterfly: u, v in [0, 4q) -> [0, 4q).
 __device__ __forceinline__ void gs_bfly(uint64_t& u, uint64_t& v, const TW w, const BflyK& k) {
-  const uint64_t s = csub2q(u + v, k);
-  const uint64_t d = (u + k.q2p1) + ~v;  // u - v + 2q
+  const uint64_t s = csub(u + v, k.q4, k.nq4);
+  const uint64_t d = (u + k.q4p1) + ~v;  // u - v + 4q
   v = shoup_lazy(d, w, k);
   u = s;
 }
@@ -110,8 +121,9 @@ __device__ __forceinline__ void fwd_pass(uint64_t* a, const PENCIL_GLOBAL TW* tw
     for (int k = 0; k < K; ++k) {
       uint64_t x = v[r * K + k];
       if (LAST) {
-        x = csub2q(x, bk);
-        x = x >= q ? x - q : x;
+        x = csub(x, bk.q4, bk.nq4);
+        x = csub(x, bk.q2, bk.nq2);
+        x = csub(x, q, bk.nq);
       }
       a[lpad(base + (k << LT))] = x;
     }
@@ -185,7 +197,7 @@ __device__ __forceinline__ void ntt_fwd(uint64_t* a, const TW* tw_generic, uint6
   }
 }
 
-// Inverse transform without the N^-1 factor (inputs in [0, 2q), outputs in [0, 2q)).
+// Inverse transform without the N^-1 factor (inputs in [0, 4q), outputs in [0, 4q)).
 template <int LOGN, int LOGE>
 __device__ __forceinline__ void ntt_inv(uint64_t* a, const TW* tw_generic, uint64_t q) {
   using Sh = NttShape<LOGN, LOGE>;
@@ -236,35 +248,26 @@ __device__ __forceinline__ void do_ntt_plain(uint64_t* lds, uint64_t* data, int 
   }
 }
 
-// Input ciphertexts (NTT domain): component 0 gains the transform of
-// round(q m / t) of the model owner's share (Alg. 1, product step); the
-// residues are stored split for the multiply-accumulate.  Only a block with a
-// share to add runs a transform; the others convert and copy.
-// Grid: n_ct * 2 * L blocks, polynomial p = (j, c, l) in [n][2][L] order.
+// Input ciphertexts (NTT domain, split form) of the products that add the
+// model owner's share: component 0 gains the transform of round(q m / t) of
+// the share (Alg. 1, product step) and is written, split, to the staging
+// copy; component 1 is read in place by the multiply-accumulate.
+// Grid: n_ct * L blocks, polynomial p = (j, l) in [n][L] order; src and dst
+// are [n][2][L][N].
 template <int LOGN, int LOGE>
 __device__ __forceinline__ void do_ntt_ct(uint64_t* lds, const uint64_t* src, uint64_t* dst, const int64_t* share,
                                           const Geo& G, const View& V, const Consts& C, const Tables& T, int64_t p) {
   constexpr int n = 1 << LOGN;
   const int L = C.L;
   const int l = (int)(p % L);
-  const int c = (int)((p / L) % 2);
-  const int64_t j = p / (2 * L);
+  const int64_t j = p / L;
+  const int64_t at = (j * 2 * L + l) * n;  // component 0, limb l of ciphertext j
   const LimbConst& lc = C.limb[l];
-  const PENCIL_GLOBAL uint64_t* g = gview(src + p * n);
-  PENCIL_GLOBAL uint64_t* o = gview(dst + p * n);
-  if (share == nullptr || c != 0) {  // 16-byte accesses: a polynomial is 16-byte aligned
-    const PENCIL_GLOBAL u64x2* g2 = (const PENCIL_GLOBAL u64x2*)g;
-    PENCIL_GLOBAL u64x2* o2 = (PENCIL_GLOBAL u64x2*)o;
-    for (int i = threadIdx.x; i < n / 2; i += blockDim.x) {
-      const u64x2 v = g2[i];
-      o2[i] = u64x2{split30(v[0]), split30(v[1])};
-    }
-    return;
-  }
   const PENCIL_GLOBAL int64_t* gshare = gview(share);
+  const TileOrigin to = a_tile_origin(G, j);
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     uint64_t v = 0;
-    const int64_t off = a_slot_offset(G, V, j, i);
+    const int64_t off = a_slot_at(G, V, to, i);
     if (off >= 0) {
       const uint64_t m = (uint64_t)gshare[off];
       v = delta_scale(m, round_rho(m, C), lc);
@@ -273,13 +276,13 @@ __device__ __forceinline__ void do_ntt_ct(uint64_t* lds, const uint64_t* src, ui
   }
   __syncthreads();
   ntt_fwd<LOGN, LOGE>(lds, T.fw + (int64_t)l * n, lc.q);
-  {
-    const PENCIL_GLOBAL u64x2* g2 = (const PENCIL_GLOBAL u64x2*)g;
-    PENCIL_GLOBAL u64x2* o2 = (PENCIL_GLOBAL u64x2*)o;
-    for (int i = threadIdx.x; i < n / 2; i += blockDim.x) {
-      const u64x2 v = g2[i];
-      o2[i] = u64x2{split30(add_mod(v[0], lds[lpad(2 * i)], lc.q)), split30(add_mod(v[1], lds[lpad(2 * i) + 1], lc.q))};
-    }
+  // 16-byte accesses: a polynomial is 16-byte aligned
+  const PENCIL_GLOBAL u64x2* g2 = (const PENCIL_GLOBAL u64x2*)gview(src + at);
+  PENCIL_GLOBAL u64x2* o2 = (PENCIL_GLOBAL u64x2*)gview(dst + at);
+  for (int i = threadIdx.x; i < n / 2; i += blockDim.x) {
+    const u64x2 v = g2[i];
+    o2[i] = u64x2{split30(add_mod(unsplit30(v[0]), lds[lpad(2 * i)], lc.q)),
+                  split30(add_mod(unsplit30(v[1]), lds[lpad(2 * i) + 1], lc.q))};
   }
 }
 
@@ -294,9 +297,10 @@ __device__ __forceinline__ void do_ntt_pt(uint64_t* lds, const int64_t* tensor, 
   const int64_t j = p / L;
   const LimbConst& lc = C.limb[l];
   const PENCIL_GLOBAL int64_t* gt = gview(tensor);
+  const TileOrigin to = tile_origin(side, G, j);
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     uint64_t v = 0;
-    int64_t off = slot_offset(side, G, V, j, i);
+    const int64_t off = slot_at(side, G, V, to, i);
     if (off >= 0) {
       uint64_t w = (uint64_t)gt[off];
       v = w <= C.t_half ? w : lc.q - (C.t - w);

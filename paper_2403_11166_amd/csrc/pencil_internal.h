@@ -59,6 +59,9 @@ struct Geo {
   int32_t RS;                                   // rt * S: stride of m inside a tile
   int32_t O;                                    // reverse-encoding offset
   int32_t pad1;
+  // Reciprocals ceil(2^32 / d) of the in-tile divisors d = RS, ha*wa, wa and S
+  // (0 for d = 1): floor(n / d) = umulhi(n, m) for n, d < 2^16.
+  uint32_t dv_rs, dv_hw, dv_wa, dv_s;
 };
 
 // Maps virtual coordinates (i0, i1, y, x) of an operand to an element offset of
@@ -83,10 +86,14 @@ inline uint64_t enc_object(int operand, uint64_t i) { return ((uint64_t)(operand
 inline uint64_t out_object(int op, uint64_t i) { return ((uint64_t)(op + 5) << 48) | i; }
 
 // One term of a product: which side holds the ciphertext and where both operands live
-// (NTT domain).  ct: [n][2][L][N]; pt: [n][L][N].
+// (NTT domain, split form).  ct: [n][2][L][N] (component 0 addresses); pt: [n][L][N].
+// A ciphertext's component 1 sits c1 elements after its component 0: L*N in the
+// caller's buffer, or elsewhere when component 0 is a staged copy with the
+// model owner's share added.
 struct MacTerm {
   const uint64_t* a;   // A-side tiles
   const uint64_t* k;   // K-side tiles
+  int64_t c1;          // component-1 offset on the ciphertext side (elements)
   int32_t a_is_ct;     // 1: A side is a ciphertext, K side a plaintext; 0: the reverse
   int32_t pad;
 };
@@ -167,7 +174,7 @@ hipError_t launch_encrypt(const uint64_t* u_ntt, const int64_t* share, uint64_t*
 hipError_t launch_phase(const uint64_t* ct, uint64_t* x, int64_t n_ct, const uint64_t* s_ntt, const uint64_t* s_sh,
                         const Consts& C, const Tables& T, hipStream_t s);
 hipError_t launch_decode(const uint64_t* x, int64_t* share, int64_t n_out, const Geo& G, const View& outV,
-                         const Consts& C, hipStream_t s);
+                         const Consts& C, uint32_t* noise, hipStream_t s);
 // Up to kZtTerms terms of a Z_t linear combination, by value (kernel argument).
 constexpr int kZtTerms = 64;
 struct ZtTerms {

@@ -50,14 +50,27 @@ def ntt_order_roots(P, idx):
     return [[pow(psi, 2 * bitrev(i, bits) + 1, q) for i in idx] for q, psi in zip(P.moduli, P.psi)]
 
 
+def split30(a):
+    """The library's split form of residues v < 2^60: (v mod 2^30) + 2^32 floor(v / 2^30)."""
+    a = np.asarray(a, dtype=np.uint64)
+    return (a & np.uint64(0x3FFFFFFF)) | ((a >> np.uint64(30)) << np.uint64(32))
+
+
+def unsplit30(a):
+    """Residues from the library's split form."""
+    a = np.asarray(a, dtype=np.uint64)
+    return (a & np.uint64(0xFFFFFFFF)) | ((a >> np.uint64(32)) << np.uint64(30))
+
+
 def oracle_ct_ntt(P, ct):
-    """An oracle ciphertext [2][L][N] (coefficient domain) in the NTT-domain
-    form the library's encryption produces: the definitional transform of each
-    component and limb, entry i = evaluation at psi^(2 rev(i) + 1)."""
+    """An oracle ciphertext [2][L][N] (coefficient domain) in the form the
+    library's encryption produces: the definitional transform of each component
+    and limb, entry i = evaluation at psi^(2 rev(i) + 1), each residue in split
+    form."""
     bits = P.n.bit_length() - 1
     perm = np.array([bitrev(i, bits) for i in range(P.n)])
     out = np.empty_like(np.asarray(ct, dtype=np.uint64))
     for c in range(2):
         for l, (q, psi) in enumerate(zip(P.moduli, P.psi)):
             out[c, l] = RG.ntt_def(ct[c][l], q, psi)[perm]
-    return out
+    return split30(out)

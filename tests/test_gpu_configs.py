@@ -19,7 +19,7 @@ from oracle import linear as LN
 from oracle import protocol as PRT
 from workloads import CONFIGS, config_tensors, uniform_residues
 
-from gpu_common import dev, host_i64, host_u64, ntt_order_roots, oracle_keys, oracle_params
+from gpu_common import dev, host_i64, host_u64, ntt_order_roots, oracle_keys, oracle_params, split30, unsplit30
 
 pytestmark = pytest.mark.gpu
 
@@ -124,10 +124,13 @@ def test_products_bit_exact_on_sampled_coefficients(ci, li):
                             ("dydw", sz.n_ct[3], 4)):
         synth[name] = uniform_residues(1000 * ci + seed, (int(cnt), 2, L, n), ctx.primes)
     # the oracle takes these as coefficient-domain ciphertexts; the library's
-    # product path takes its inputs in the NTT domain, so the device copies are
-    # transformed (by the library's transform, itself checked against the
-    # definition in the NTT parity test)
-    g = lambda a: ctx.ntt(torch.from_numpy(a.copy().view(np.int64)).cuda())  # noqa: E731
+    # product path takes its inputs in the NTT domain (split form), so the
+    # device copies are transformed (by the library's transform, itself checked
+    # against the definition in the NTT parity test) and stored split
+    def g(a):
+        t = ctx.ntt(torch.from_numpy(a.copy().view(np.int64)).cuda())
+        return torch.from_numpy(split30(host_u64(t)).view(np.int64)).cuda()
+
     ct_y, y0 = ctx.linear_fwd(layer, plan, g(synth["x"]), dev(ts["x0"]), dev(ts["W"]), 21)
     ct_dx, dx0, ct_dw, dwm = ctx.linear_bwd(layer, plan, g(synth["dydx"]), g(synth["xdw"]), g(synth["dydw"]),
                                             dev(ts["dy0"]), dev(ts["x0"]), dev(ts["W"]), 22)
@@ -168,7 +171,7 @@ def test_products_bit_exact_on_sampled_coefficients(ci, li):
     for kind, src in ((PRT.OPERAND_X_FWD, "x1"), (PRT.OPERAND_DY_DX, "dy1"), (PRT.OPERAND_X_DW, "x1"),
                       (PRT.OPERAND_DY_DW, "dy1")):
         name = ("x_fwd", "dy_dx", "x_dw", "dy_dw")[kind]
-        ct = host_u64(ctx.encrypt(layer, plan, name, dev(ts[src]), 30 + kind))
+        ct = unsplit30(host_u64(ctx.encrypt(layer, plan, name, dev(ts[src]), 30 + kind)))
         op, side = PRT.OPERAND_SIDE[kind]
         for j in sorted({0, ct.shape[0] - 1}):
             gm = E.geometry(layer, op)
@@ -179,7 +182,7 @@ def test_products_bit_exact_on_sampled_coefficients(ci, li):
                 m = E.encode_k(E.virtual_k(layer, op, ts[src]), gm, tiles[op], n, *list(E.k_tiles(cc))[j])
             idx = _sample_idx(n, [], rng, 4)
             # the library's ciphertexts are in the NTT domain: entry i is the
-            # evaluation at psi^(2 rev(i) + 1)
+            # evaluation at psi^(2 rev(i) + 1) (stored split, undone above)
             ref = bfv.encrypt_eval_at(P, keys["pk"], m, cfg.seed, 30 + kind, PRT.enc_object(kind, j),
                                       ntt_order_roots(P, idx))
             assert [[[int(v) for v in ct[j][c, l, idx]] for l in range(P.num_limbs)] for c in range(2)] == ref, \
