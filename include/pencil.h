@@ -302,15 +302,20 @@ pencil_status pencil_stride_map(const pencil_layer* strided, pencil_layer* equiv
 pencil_status pencil_stride_relayout(pencil_ctx* ctx, const pencil_layer* strided, int which, const int64_t* in,
                                      int64_t* out, void* stream);
 
-/* Autotuner: time the schedule candidates on this GPU -- the NTT's residues per
- * thread (16 or 32, per context) and each product's multiply-accumulate chunk
- * shape among the direct-load schedules 3-5 (per layer and product, written
- * into plan->sched) -- and keep the fastest.  Results are bit-identical for
- * every candidate.  cache_path (may be
- * NULL) is a text file of earlier choices keyed by GPU, ring degree, limbs,
- * layer shape and product; hits are applied without measuring, new choices are
- * appended.  Synchronous; allocates and frees its own scratch buffers.  Tune a
- * context before creating steps on it. */
+/* Autotuner: time, on this GPU with synthetic inputs, the choices that leave
+ * the decrypted results unchanged, and keep the fastest -- the NTT's residues
+ * per thread (16 or 32, per context; timed on the layer's three products),
+ * each product's partition among the caller's tile and the planner's best-
+ * ranked ones (App. A leaves the split of large operands open; the choice is
+ * written into the plan's tiles), and each product's multiply-accumulate
+ * schedule among all nine (written into plan->sched).  A partition fixes the
+ * ciphertext layout: tune before the DO encrypts with the plan, and give both
+ * parties the tuned plan.  Output ciphertexts and shares under one plan are
+ * bit-identical for every schedule and NTT width.  cache_path (may be NULL) is
+ * a text file of earlier choices keyed by GPU, ring degree, limbs, layer shape
+ * and product; hits are applied without measuring, new choices are appended.
+ * Synchronous; allocates and frees its own scratch buffers.  Tune a context
+ * before creating steps on it. */
 pencil_status pencil_autotune(pencil_ctx* ctx, const pencil_layer* layer, pencil_plan* plan /* host, in/out */,
                               const char* cache_path);
 

@@ -167,7 +167,8 @@ class Context:
         return p
 
     def autotune(self, layer, plan, cache_path=None):
-        """Measure the schedule candidates (results are identical) and return the tuned plan."""
+        """Measure the NTT width, the planner's best partitions and the nine multiply-accumulate
+        schedules on this GPU and return the tuned plan (tune before encrypting with it)."""
         p = plan_struct(plan)
         q = A.Plan()
         ctypes.pointer(q)[0] = p

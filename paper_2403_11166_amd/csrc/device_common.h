@@ -162,6 +162,7 @@ static inline size_t lds_bytes(const Consts& C) { return (size_t)(C.n + (C.n >> 
       NTT_CASE(kern, 12, 5, grid, C, s, __VA_ARGS__)                                       \
       NTT_CASE(kern, 13, 4, grid, C, s, __VA_ARGS__)                                       \
       NTT_CASE(kern, 13, 5, grid, C, s, __VA_ARGS__)                                       \
+      NTT_CASE(kern, 14, 4, grid, C, s, __VA_ARGS__)                                       \
       NTT_CASE(kern, 14, 5, grid, C, s, __VA_ARGS__)                                       \
       default: return hipErrorInvalidValue;                                                \
     }                                                                                      \

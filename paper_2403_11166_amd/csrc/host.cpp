@@ -643,11 +643,11 @@ static Cost op_cost(const Geo& G, int op) {
   const double na = (double)n_a_tiles(G), nk = (double)n_k_tiles(G), no = (double)n_out_tiles(G);
   constexpr double kCopy = 0.36;
   if (op == PENCIL_OP_DW) {
-    // x1 ct (copied) + x0 pt, dy0 pt + dy1 ct (copied), outputs (2 inverse) + u'
-    c.ntt_polys = na * (1 + 2 * kCopy) + nk * (1 + 2 * kCopy) + 3 * no;
+    // x0 pt, dy0 pt (the ciphertexts are read in place), outputs (2 inverse) + u'
+    c.ntt_polys = na + nk + 3 * no;
     c.products = 2.0 * (double)n_products(G);
   } else {
-    // ct: share transform + copy of component 1; pt; outputs + u'
+    // ct: share transform with the staged copy of component 0; pt; outputs + u'
     c.ntt_polys = na * (1 + kCopy) + nk + 3 * no;
     c.products = (double)n_products(G);
   }
@@ -674,11 +674,16 @@ static std::vector<int> sizes_for(int D) {
   return out;
 }
 
-static bool plan_op(const pencil_layer* L, int op, int log2n, pencil_tile* best) {
+// The packing planner: every partition that fits N (per dimension, the
+// smallest tile size for each tile count), ranked by the cost model; `best`
+// receives the cheapest, `ranked` (optional) the cheapest `keep` in order.
+static bool plan_op(const pencil_layer* L, int op, int log2n, pencil_tile* best,
+                    std::vector<pencil_tile>* ranked = nullptr, size_t keep = 0) {
   const OpGeom g = op_geom(L, op);
   const int n = 1 << log2n;
   double best_cost = 1e300;
   bool found = false;
+  std::vector<std::pair<double, pencil_tile>> all;
   const bool kernel_tiled = op == PENCIL_OP_DW && g.KH > 1;
   std::vector<int> ms = sizes_for(g.M), rs = sizes_for(g.R);
   std::vector<int> ys = kernel_tiled ? sizes_for(g.KH) : sizes_for(g.OH());
@@ -703,6 +708,7 @@ static bool plan_op(const pencil_layer* L, int op, int log2n, pencil_tile* best)
           Geo G;
           if (!make_geo(g, t, n, &G)) continue;
           double cv = cost_value(op_cost(G, op), log2n);
+          if (ranked) all.emplace_back(cv, t);
           if (cv < best_cost) {
             best_cost = cv;
             *best = t;
@@ -710,6 +716,14 @@ static bool plan_op(const pencil_layer* L, int op, int log2n, pencil_tile* best)
           }
         }
     }
+  if (ranked) {
+    std::stable_sort(all.begin(), all.end(),
+                     [](const std::pair<double, pencil_tile>& a, const std::pair<double, pencil_tile>& b) {
+                       return a.first < b.first;
+                     });
+    ranked->clear();
+    for (size_t i = 0; i < all.size() && ranked->size() < keep; ++i) ranked->push_back(all[i].second);
+  }
   return found;
 }
 
@@ -1579,11 +1593,18 @@ static std::string arch_name(int device) {
   return c == std::string::npos ? a : a.substr(0, c);
 }
 
-static void cache_read(const char* path, std::vector<std::pair<std::string, int>>* out) {
+// Autotuner cache: one JSON object per line, {"key": "...", "choice": V, ...}
+// with V an integer or a list of integers.
+struct CacheEntry {
+  std::string key;
+  std::vector<int> v;
+};
+
+static void cache_read(const char* path, std::vector<CacheEntry>* out) {
   if (!path) return;
   FILE* f = std::fopen(path, "r");
   if (!f) return;
-  char line[1024];
+  char line[2048];
   while (std::fgets(line, sizeof line, f)) {
     const char* k = std::strstr(line, "\"key\": \"");
     const char* v = std::strstr(line, "\"choice\": ");
@@ -1591,18 +1612,29 @@ static void cache_read(const char* path, std::vector<std::pair<std::string, int>
     k += 8;
     const char* e = std::strchr(k, '"');
     if (!e) continue;
-    out->emplace_back(std::string(k, e), std::atoi(v + 10));
+    CacheEntry ce{std::string(k, e), {}};
+    v += 10;
+    if (*v == '[') {
+      for (++v; *v && *v != ']';) {
+        char* endp = nullptr;
+        const long x = std::strtol(v, &endp, 10);
+        if (endp == v) break;
+        ce.v.push_back((int)x);
+        v = endp;
+        while (*v == ',' || *v == ' ') ++v;
+      }
+    } else {
+      ce.v.push_back(std::atoi(v));
+    }
+    out->push_back(std::move(ce));
   }
   std::fclose(f);
 }
 
-static bool cache_find(const std::vector<std::pair<std::string, int>>& c, const std::string& key, int* v) {
+static const std::vector<int>* cache_find(const std::vector<CacheEntry>& c, const std::string& key) {
   for (auto it = c.rbegin(); it != c.rend(); ++it)
-    if (it->first == key) {
-      *v = it->second;
-      return true;
-    }
-  return false;
+    if (it->key == key) return &it->v;
+  return nullptr;
 }
 
 // Milliseconds per call of fn (one warm-up call, then `reps` timed calls).
@@ -1630,133 +1662,215 @@ static float time_ms(F&& fn, int reps) {
   return ms;
 }
 
+static std::string tile_str(const pencil_tile& t) {
+  char b[96];
+  std::snprintf(b, sizeof b, "%d,%d,%d,%d,%d,%d,%d", t.m, t.r, t.k, t.oh, t.ow, t.kh, t.kw);
+  return b;
+}
+
+static std::string times_str(const std::vector<float>& ms) {
+  std::string out;
+  for (float x : ms) out += (out.empty() ? "" : ", ") + std::to_string(x);
+  return out;
+}
+
+static pencil_tile& plan_tile_mut(pencil_plan* P, int op) { return op == 0 ? P->fwd : op == 1 ? P->dx : P->dw; }
+
+// The autotuner.  It measures, on this GPU and with synthetic inputs, the
+// choices that leave the decrypted results unchanged: the NTT's residues per
+// thread (per context), each product's partition among the planner's
+// best-ranked ones (the caller's tile included), and each product's
+// multiply-accumulate schedule (all nine).  A partition changes the
+// ciphertext layout, so tune before encrypting with the plan.
 extern "C" pencil_status pencil_autotune(pencil_ctx* ctx, const pencil_layer* L, pencil_plan* P,
                                          const char* cache_path) {
   if (!ctx || !P) return PENCIL_EINVAL;
-  Geo G[3];
-  for (int op = 0; op < 3; ++op) TRY(get_geo(ctx, L, P, op, &G[op]));
-  std::vector<std::pair<std::string, int>> cache;
+  pencil_status lst = PENCIL_OK;
+  if (!layer_ok(ctx, L, &lst)) return lst;
+  for (int op = 0; op < 3; ++op) {
+    Geo G;
+    TRY(get_geo(ctx, L, P, op, &G));
+  }
+  std::vector<CacheEntry> cache;
   cache_read(cache_path, &cache);
   std::vector<std::string> fresh;
   const std::string arch = arch_name(ctx->device);
   Consts& C = ctx->C;
-  char buf[512];
-  const size_t n = (size_t)C.n, Lm = (size_t)C.L;
-  // 1) NTT residues per thread for this ring degree
-  std::snprintf(buf, sizeof buf, "%s N=%d L=%d ntt_loge", arch.c_str(), C.n, C.L);
-  int v = 0;
-  if (cache_find(cache, buf, &v)) {
-    C.ntt_loge = v;
+  char key[512];
+  auto layer_key = [&](const char* what, int op) {
+    std::snprintf(key, sizeof key, "%s N=%d L=%d layer=%d,%d,%d,%d,%d,%d,%d,%d op=%d %s", arch.c_str(), C.n, C.L,
+                  L->kind, L->batch, L->c_in, L->c_out, L->h, L->w, L->k, L->pad, op, what);
+    return std::string(key);
+  };
+  // candidate partitions per product: the caller's, then the planner's best
+  constexpr size_t kPartitions = 3;
+  std::vector<pencil_tile> cand[3];
+  for (int op = 0; op < 3; ++op) {
+    cand[op].push_back(plan_tile(P, op));
+    std::vector<pencil_tile> ranked;
+    pencil_tile best;
+    plan_op(L, op, C.log2n, &best, &ranked, kPartitions);
+    for (const pencil_tile& t : ranked) {
+      bool dup = false;
+      for (const pencil_tile& u : cand[op]) dup |= std::memcmp(&t, &u, sizeof t) == 0;
+      if (!dup && cand[op].size() < kPartitions) cand[op].push_back(t);
+    }
+  }
+  // scratch for the largest candidate of every product
+  const int64_t xs = (int64_t)L->batch * L->c_in * L->h * L->w;
+  const int64_t ys = (int64_t)L->batch * L->c_out * ho_of(L) * wo_of(L);
+  const int64_t wsz = (int64_t)L->c_out * L->c_in * kh_of(L) * kw_of(L);
+  const int64_t tmax = std::max(xs, std::max(ys, wsz));
+  uint64_t nin = 0, nout = 0, wsb = 0;
+  const uint64_t ctb = 2ull * C.L * C.n * 8;
+  for (int op = 0; op < 3; ++op)
+    for (const pencil_tile& t : cand[op]) {
+      pencil_plan Q = *P;
+      plan_tile_mut(&Q, op) = t;
+      pencil_sizes sz;
+      TRY(pencil_layout(ctx, L, &Q, &sz));
+      nin = std::max(nin, op == 0 ? sz.n_ct[0] : op == 1 ? sz.n_ct[1] : std::max(sz.n_ct[2], sz.n_ct[3]));
+      nout = std::max(nout, sz.n_out[op]);
+      wsb = std::max(wsb, op == 0 ? sz.ws_fwd_bytes : sz.ws_bwd_bytes);
+    }
+  uint8_t *cin = nullptr, *cin2 = nullptr, *cout = nullptr, *ws = nullptr;
+  int64_t *t0 = nullptr, *t1 = nullptr, *tout = nullptr;
+  auto release = [&] {
+    hipFree(cin);
+    hipFree(cin2);
+    hipFree(cout);
+    hipFree(ws);
+    hipFree(t0);
+    hipFree(t1);
+    hipFree(tout);
+  };
+  if (hipMalloc(&cin, nin * ctb) != hipSuccess || hipMalloc(&cin2, nin * ctb) != hipSuccess ||
+      hipMalloc(&cout, nout * ctb) != hipSuccess || hipMalloc(&ws, wsb) != hipSuccess ||
+      hipMalloc(&t0, tmax * 8) != hipSuccess || hipMalloc(&t1, tmax * 8) != hipSuccess ||
+      hipMalloc(&tout, tmax * 8) != hipSuccess) {
+    release();
+    return fail(ctx, PENCIL_ENOMEM, "autotune scratch");
+  }
+  // residues 1 and 2^16 + 1 (split form: 1 + 2^32): valid operands for every limb
+  hipMemsetD32((hipDeviceptr_t)cin, 0x00000001, nin * ctb / 4);
+  hipMemsetD32((hipDeviceptr_t)cin2, 0x00000001, nin * ctb / 4);
+  hipMemsetD32((hipDeviceptr_t)t0, 0x00000001, tmax * 2);  // 2^32 + 1 < t: valid Z_t entries
+  hipMemsetD32((hipDeviceptr_t)t1, 0x00000001, tmax * 2);
+  auto run = [&](int op, const pencil_plan* Q) -> pencil_status {
+    if (op == 0)
+      return pencil_linear_fwd(ctx, L, Q, (const uint64_t*)cin, t0, t1, nullptr, (uint64_t*)cout, tout, ws, 1,
+                               nullptr);
+    if (op == 1)
+      return pencil_linear_bwd(ctx, L, Q, (const uint64_t*)cin, nullptr, nullptr, t0, nullptr, t1, (uint64_t*)cout,
+                               tout, nullptr, nullptr, ws, 1, nullptr);
+    return pencil_linear_bwd(ctx, L, Q, nullptr, (const uint64_t*)cin, (const uint64_t*)cin2, t0, t1, nullptr,
+                             nullptr, nullptr, (uint64_t*)cout, tout, ws, 1, nullptr);
+  };
+  // the forward product and both backward ones, the way a training step runs them
+  auto step_ms = [&](const pencil_plan* Q) {
+    float total = 0;
+    for (int op = 0; op < 3; ++op) {
+      const float ms = time_ms([&] { return run(op, Q); }, 3);
+      if (ms < 0) return -1.0f;
+      total += ms;
+    }
+    return total;
+  };
+  pencil_status st = PENCIL_OK;
+  // 1) NTT residues per thread (context-wide), timed on this layer's products
+  std::snprintf(key, sizeof key, "%s N=%d L=%d ntt_loge", arch.c_str(), C.n, C.L);
+  if (const std::vector<int>* hit = cache_find(cache, key)) {
+    if (hit->size() == 1 && (*hit)[0] >= 4 && (*hit)[0] <= 5 && (C.log2n >= 12 || (*hit)[0] == 4))
+      C.ntt_loge = (*hit)[0];
   } else {
-    std::vector<int> cands;
-    if (C.log2n >= 14) cands = {5};
-    else if (C.log2n >= 12) cands = {4, 5};
-    else cands = {4};
-    uint64_t* polys = nullptr;
-    const int64_t count = 64;
-    if (hipMalloc(&polys, count * Lm * n * 8) != hipSuccess) return fail(ctx, PENCIL_ENOMEM, "autotune scratch");
-    hipMemsetD32((hipDeviceptr_t)polys, 0x00010001, count * Lm * n * 2);
-    float best = -1;
+    std::vector<int> cands = C.log2n >= 12 ? std::vector<int>{4, 5} : std::vector<int>{4};
+    std::vector<float> times;
     int bestv = C.ntt_loge;
-    std::string times;
+    float best = -1;
     for (int c : cands) {
       C.ntt_loge = c;
-      float ms = time_ms([&] { return pencil_ntt_forward(ctx, polys, count, nullptr); }, 5);
-      times += (times.empty() ? "" : ", ") + std::to_string(ms);
+      const float ms = step_ms(P);
+      times.push_back(ms);
       if (ms > 0 && (best < 0 || ms < best)) {
         best = ms;
         bestv = c;
       }
     }
-    hipFree(polys);
     C.ntt_loge = bestv;
-    fresh.push_back(std::string("{\"key\": \"") + buf + "\", \"choice\": " + std::to_string(bestv) +
-                    ", \"ms\": [" + times + "]}");
+    fresh.push_back(std::string("{\"key\": \"") + key + "\", \"choice\": " + std::to_string(bestv) +
+                    ", \"candidates\": [4, 5], \"ms\": [" + times_str(times) + "]}");
   }
-  // 2) multiply-accumulate chunk shape per product
-  const int64_t xs = (int64_t)L->batch * L->c_in * L->h * L->w;
-  const int64_t ho = ho_of(L), wo = wo_of(L);
-  const int64_t ys = (int64_t)L->batch * L->c_out * ho * wo, wsz = (int64_t)L->c_out * L->c_in * kh_of(L) * kw_of(L);
-  pencil_sizes sz;
-  TRY(pencil_layout(ctx, L, P, &sz));
-  const uint64_t ctb = sz.ct_bytes;
-  const uint64_t nin = std::max(sz.n_ct[0], std::max(sz.n_ct[1], sz.n_ct[2] + sz.n_ct[3]));
-  const uint64_t nout = std::max(sz.n_out[0], std::max(sz.n_out[1], sz.n_out[2]));
-  const uint64_t ws_b = std::max(sz.ws_fwd_bytes, sz.ws_bwd_bytes);
-  const int64_t tmax = std::max(xs, std::max(ys, wsz));
-  uint8_t *cin = nullptr, *cout = nullptr, *ws = nullptr;
-  int64_t *t0 = nullptr, *t1 = nullptr, *t2 = nullptr, *tout = nullptr;
-  auto release = [&] {
-    hipFree(cin);
-    hipFree(cout);
-    hipFree(ws);
-    hipFree(t0);
-    hipFree(t1);
-    hipFree(t2);
-    hipFree(tout);
-  };
-  for (int op = 0; op < 3; ++op) {
-    std::snprintf(buf, sizeof buf, "%s N=%d L=%d layer=%d,%d,%d,%d,%d,%d,%d,%d tile=%d,%d,%d,%d,%d,%d,%d op=%d",
-                  arch.c_str(), C.n, C.L, L->kind, L->batch, L->c_in, L->c_out, L->h, L->w, L->k, L->pad,
-                  plan_tile(P, op).m, plan_tile(P, op).r, plan_tile(P, op).k, plan_tile(P, op).oh, plan_tile(P, op).ow,
-                  plan_tile(P, op).kh, plan_tile(P, op).kw, op);
-    if (cache_find(cache, buf, &v) && v >= 0 && v < kMacVariants) {
-      P->sched[op] = v;
+  // 2) partition, then 3) multiply-accumulate schedule, per product
+  for (int op = 0; op < 3 && st == PENCIL_OK; ++op) {
+    const std::string pkey = layer_key("partition", op);
+    const std::vector<int>* hit = cache_find(cache, pkey);
+    bool applied = false;
+    if (hit && hit->size() == 7) {
+      pencil_tile t{(*hit)[0], (*hit)[1], (*hit)[2], (*hit)[3], (*hit)[4], (*hit)[5], (*hit)[6]};
+      pencil_plan Q = *P;
+      plan_tile_mut(&Q, op) = t;
+      Geo G;
+      if (get_geo(ctx, L, &Q, op, &G) == PENCIL_OK) {
+        plan_tile_mut(P, op) = t;
+        applied = true;
+      }
+    }
+    if (!applied && cand[op].size() > 1) {
+      std::vector<float> times;
+      std::string tiles;
+      size_t besti = 0;
+      float best = -1;
+      for (size_t i = 0; i < cand[op].size(); ++i) {
+        pencil_plan Q = *P;
+        plan_tile_mut(&Q, op) = cand[op][i];
+        Q.sched[op] = default_sched(L, op, cand[op][i], C.n);
+        const float ms = time_ms([&] { return run(op, &Q); }, 3);
+        times.push_back(ms);
+        tiles += (tiles.empty() ? "[" : ", [") + tile_str(cand[op][i]) + "]";
+        if (ms > 0 && (best < 0 || ms < best)) {
+          best = ms;
+          besti = i;
+        }
+      }
+      if (besti != 0) {
+        plan_tile_mut(P, op) = cand[op][besti];
+        P->sched[op] = default_sched(L, op, cand[op][besti], C.n);
+      }
+      fresh.push_back(std::string("{\"key\": \"") + pkey + "\", \"choice\": [" + tile_str(plan_tile(P, op)) +
+                      "], \"candidates\": [" + tiles + "], \"ms\": [" + times_str(times) + "]}");
+    }
+    const std::string skey = layer_key(("sched tile=" + tile_str(plan_tile(P, op))).c_str(), op);
+    hit = cache_find(cache, skey);
+    if (hit && hit->size() == 1 && (*hit)[0] >= 0 && (*hit)[0] < kMacVariants) {
+      P->sched[op] = (*hit)[0];
       continue;
     }
-    if (!cin) {
-      if (hipMalloc(&cin, nin * ctb) != hipSuccess || hipMalloc(&cout, nout * ctb) != hipSuccess ||
-          hipMalloc(&ws, ws_b) != hipSuccess || hipMalloc(&t0, tmax * 8) != hipSuccess ||
-          hipMalloc(&t1, tmax * 8) != hipSuccess || hipMalloc(&t2, tmax * 8) != hipSuccess ||
-          hipMalloc(&tout, tmax * 8) != hipSuccess) {
-        release();
-        return fail(ctx, PENCIL_ENOMEM, "autotune scratch");
-      }
-      hipMemsetD32((hipDeviceptr_t)cin, 0x00010001, nin * ctb / 4);
-      hipMemsetD32((hipDeviceptr_t)t0, 0x00010001, tmax * 2);
-      hipMemsetD32((hipDeviceptr_t)t1, 0x00010001, tmax * 2);
-      hipMemsetD32((hipDeviceptr_t)t2, 0x00010001, tmax * 2);
-    }
-    const uint64_t* cin2 = (const uint64_t*)(cin + sz.n_ct[2] * ctb);
-    float best = -1;
+    std::vector<float> times;
     int bestv = P->sched[op];
-    std::string times;
-    // Candidates: the direct-load chunk shapes.  The LDS-staged and
-    // one-component schedules stay selectable through pencil_plan.sched; they
-    // measured slower on every workload shape, and a batched step launches each
-    // schedule kind separately, so mixing kinds in one step costs a launch.
-    for (int cand = 3; cand < 6; ++cand) {
-      P->sched[op] = cand;
-      auto run = [&]() -> pencil_status {
-        if (op == 0)
-          return pencil_linear_fwd(ctx, L, P, (const uint64_t*)cin, t0, t1, nullptr, (uint64_t*)cout, tout, ws, 1,
-                                   nullptr);
-        if (op == 1)
-          return pencil_linear_bwd(ctx, L, P, (const uint64_t*)cin, nullptr, nullptr, t0, nullptr, t1,
-                                   (uint64_t*)cout, tout, nullptr, nullptr, ws, 1, nullptr);
-        return pencil_linear_bwd(ctx, L, P, nullptr, (const uint64_t*)cin, cin2, t0, t1, nullptr, nullptr, nullptr,
-                                 (uint64_t*)cout, tout, ws, 1, nullptr);
-      };
-      const float ms = time_ms(run, 3);
-      times += (times.empty() ? "" : ", ") + std::to_string(ms);
+    float best = -1;
+    for (int cand_s = 0; cand_s < kMacVariants; ++cand_s) {
+      pencil_plan Q = *P;
+      Q.sched[op] = cand_s;
+      const float ms = time_ms([&] { return run(op, &Q); }, 3);
+      times.push_back(ms);
       if (ms > 0 && (best < 0 || ms < best)) {
         best = ms;
-        bestv = cand;
+        bestv = cand_s;
       }
     }
     P->sched[op] = bestv;
-    fresh.push_back(std::string("{\"key\": \"") + buf + "\", \"choice\": " + std::to_string(bestv) +
-                    ", \"ms\": [" + times + "]}");
+    fresh.push_back(std::string("{\"key\": \"") + skey + "\", \"choice\": " + std::to_string(bestv) +
+                    ", \"ms\": [" + times_str(times) + "]}");
   }
   release();
-  if (cache_path && !fresh.empty()) {
+  if (st == PENCIL_OK && cache_path && !fresh.empty()) {
     FILE* f = std::fopen(cache_path, "a");
     if (f) {
       for (auto& l : fresh) std::fprintf(f, "%s\n", l.c_str());
       std::fclose(f);
     }
   }
-  return PENCIL_OK;
+  return st;
 }
 
 // ------------------------------------------------------------ profiling

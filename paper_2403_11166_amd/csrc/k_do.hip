@@ -9,7 +9,7 @@ namespace pencil {
 // multiply-accumulate's split form; the product path consumes ciphertexts in
 // this form.  Grid: n_ct * 2 * L, u_ntt is [n][L][N].
 template <int LOGN, int LOGE>
-__global__ void __launch_bounds__(512, (LOGE >= 5 ? 2 : 4)) k_encrypt(const uint64_t* u_ntt, const int64_t* share, uint64_t* ct, int side,
+__global__ void PENCIL_NTT_BOUNDS(LOGN, LOGE) k_encrypt(const uint64_t* u_ntt, const int64_t* share, uint64_t* ct, int side,
                                                   Geo G, View V, const uint64_t* pk_ntt, const uint64_t* pk_sh,
                                                   uint64_t nonce, uint64_t obj_base, Consts C, Tables T) {
   extern __shared__ uint64_t lds[];
@@ -50,7 +50,7 @@ __global__ void __launch_bounds__(512, (LOGE >= 5 ? 2 : 4)) k_encrypt(const uint
 
 // Decryption phase per limb: x = c0 + INTT(NTT(c1) * s).  Grid: n * L, x is [n][L][N].
 template <int LOGN, int LOGE>
-__global__ void __launch_bounds__(512) k_phase(const uint64_t* ct, uint64_t* x, const uint64_t* s_ntt,
+__global__ void PENCIL_NTT_BOUNDS(LOGN, LOGE) k_phase(const uint64_t* ct, uint64_t* x, const uint64_t* s_ntt,
                                                 const uint64_t* s_sh, Consts C, Tables T) {
   extern __shared__ uint64_t lds[];
   constexpr int n = 1 << LOGN;
@@ -174,7 +174,7 @@ __global__ void __launch_bounds__(256) k_decode(const uint64_t* x, int64_t* shar
 // pk = (-(a s + e), a), kept in both coefficient and NTT form.  One LDS buffer;
 // every thread re-reads only the global entries it wrote itself.
 template <int LOGN, int LOGE>
-__global__ void __launch_bounds__(512) k_keygen(uint64_t* s_ntt, int64_t* s_coeff, uint64_t* pk_coeff,
+__global__ void PENCIL_NTT_BOUNDS(LOGN, LOGE) k_keygen(uint64_t* s_ntt, int64_t* s_coeff, uint64_t* pk_coeff,
                                                  uint64_t* pk_ntt, Consts C, Tables T) {
   extern __shared__ uint64_t lds[];
   constexpr int n = 1 << LOGN;
@@ -280,6 +280,7 @@ hipError_t configure_lds_do() {
   }
   PENCIL_RAISE(13, 4)
   PENCIL_RAISE(13, 5)
+  PENCIL_RAISE(14, 4)
   PENCIL_RAISE(14, 5)
 #undef PENCIL_RAISE
   return e;

@@ -230,21 +230,15 @@ __device__ __forceinline__ void do_mac_t(uint64_t* smem, const MacArgs& A, const
     for (int b = 0; b < TR; ++b)
 #pragma unroll
       for (int c = 0; c < NC; ++c) acc[a][b][c] = Acc{0, 0, 0, 0, 0};
+  // term 0 has the ciphertext on the A side; a second term (the weight
+  // gradient's) has it on the K side
   if constexpr (DIRECT) {
     if (!B.active) return;
-    for (int tt = 0; tt < A.n_terms; ++tt) {
-      if (A.term[tt].a_is_ct)
-        mac_term_direct<TM, TR, NC, true>(A.term[tt], A, G, C, lc, B, acc);
-      else
-        mac_term_direct<TM, TR, NC, false>(A.term[tt], A, G, C, lc, B, acc);
-    }
+    mac_term_direct<TM, TR, NC, true>(A.term[0], A, G, C, lc, B, acc);
+    if (A.n_terms > 1) mac_term_direct<TM, TR, NC, false>(A.term[1], A, G, C, lc, B, acc);
   } else {
-    for (int tt = 0; tt < A.n_terms; ++tt) {
-      if (A.term[tt].a_is_ct)
-        mac_term<ROWS, COLS, true>(smem, A.term[tt], A, G, C, lc, B, acc);
-      else
-        mac_term<ROWS, COLS, false>(smem, A.term[tt], A, G, C, lc, B, acc);
-    }
+    mac_term<ROWS, COLS, true>(smem, A.term[0], A, G, C, lc, B, acc);
+    if (A.n_terms > 1) mac_term<ROWS, COLS, false>(smem, A.term[1], A, G, C, lc, B, acc);
   }
   if (!B.active) return;
   // re-randomisation term pk_c * u'_o, reduction and store
@@ -367,8 +361,226 @@ __device__ __forceinline__ void mac_term_direct(const MacTerm& T, const MacArgs&
   }
 }
 
-// Kind 0: LDS-staged 2 x 2 wave blocks, both components; 1: direct, the same;
-// 2: direct 2 x 2 wave blocks of one component each.
+// ------------------------------------------------------------------ kind 1
+// Direct loads, each wave a 2 x 2 block of (A row, K row) outputs for both
+// ciphertext components, with the 128-bit totals kept in LDS: each lane owns
+// its 16-byte words in a region private to its wave, so no barrier is needed,
+// and a wave holds only the three 64-bit partial sums per output in
+// registers (48 VGPRs for its 8 outputs instead of 80).
+struct Part {
+  uint64_t s0, s1, s2;  // partial sums of a0 b0, a0 b1 + a1 b0, a1 b1
+};
+
+__device__ __forceinline__ void part_mac(Part& x, uint64_t a, uint64_t b) {
+  const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32), b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
+  x.s0 += (uint64_t)a0 * b0;
+  x.s1 += (uint64_t)a0 * b1;
+  asm volatile("" : "+v"(x.s1));
+  x.s1 += (uint64_t)a1 * b0;
+  x.s2 += (uint64_t)a1 * b1;
+}
+
+// (lo, hi) += s0 + s1 2^30 + s2 2^60; the partial sums restart at zero.
+__device__ __forceinline__ void part_fold(Part& x, uint64_t& lo, uint64_t& hi) {
+  const uint64_t t1 = x.s1 << 30, t2 = x.s2 << 60;
+  uint64_t l = lo + x.s0;
+  uint64_t c = l < x.s0 ? 1 : 0;
+  l += t1;
+  c += l < t1 ? 1 : 0;
+  l += t2;
+  c += l < t2 ? 1 : 0;
+  hi += c + (x.s1 >> 34) + (x.s2 >> 4);
+  lo = l;
+  x.s0 = x.s1 = x.s2 = 0;
+}
+
+// Fold all 8 partial sums into their LDS totals; at fold f of each period of
+// mac_chunk folds, total f (if any) is also Barrett-reduced.
+__device__ __forceinline__ void fold_lds(Part (&acc)[8], u64x2* tot, uint32_t& nfold, uint32_t reduce_every,
+                                         const LimbConst& lc) {
+  const uint32_t f = nfold;
+  nfold = f + 1 == reduce_every ? 0 : f + 1;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    u64x2 t = tot[i * kMacSlots];
+    uint64_t lo = t[0], hi = t[1];
+    part_fold(acc[i], lo, hi);
+    if (f == (uint32_t)i) {
+      lo = reduce128(hi, lo, lc.q, lc.mu_lo, lc.mu_hi);
+      hi = 0;
+    }
+    tot[i * kMacSlots] = u64x2{lo, hi};
+  }
+}
+
+// A wave-uniform 64-bit pointer, kept in scalar registers.
+__device__ __forceinline__ const char* uni(const char* p) {
+  const uint64_t v = (uint64_t)p;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v), hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (const char*)(((uint64_t)hi << 32) | lo);
+}
+
+// Load at uniform base + per-lane byte offset (a scalar base and a 32-bit vector offset).
+__device__ __forceinline__ uint64_t ld(const char* base, uint32_t off) {
+  return *(const PENCIL_GLOBAL uint64_t*)((const PENCIL_GLOBAL char*)base + off);
+}
+
+// One term of a block's products: A rows and K columns advance through the
+// contraction; the ciphertext side supplies both components (component 1 at
+// c1 elements), the plaintext side one value for both.  Row and column
+// pointers are wave-uniform (scalar registers); each lane adds its slot.
+template <bool A_CT>
+__device__ __forceinline__ void mac_term_v2(const MacTerm& T, const MacArgs& A, const Geo& G, const Consts& C,
+                                            const LimbConst& lc, MacBlock& B, Part (&acc)[8], u64x2* tot) {
+  const int sp = G.nOY * G.nOX, kspan = G.nKY * G.nKX;
+  const int ksteps = G.nK * kspan;
+  const int64_t sa_str = (A_CT ? B.ct_stride : B.pt_stride) * 8, sk_str = (A_CT ? B.pt_stride : B.ct_stride) * 8;
+  const int64_t c1 = T.c1 * 8;
+  const uint32_t lane = (uint32_t)B.s * 8;
+  const char* pa[2];
+  const char* pk[2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    int row = B.row0 + B.rg + a;
+    if (row >= A.m_rows) row = B.row0 + B.rg;  // a padding row reads row 0 (never stored)
+    const int mi = row / sp, rsp = row % sp;
+    pa[a] = uni((const char*)(T.a + B.ln) + (((int64_t)mi * G.nK * sp + rsp) * kspan) * sa_str);
+  }
+#pragma unroll
+  for (int c2 = 0; c2 < 2; ++c2) {
+    int col = B.col0 + B.cg + c2;
+    if (col >= G.nR) col = B.col0 + B.cg;
+    pk[c2] = uni((const char*)(T.k + B.ln) + (int64_t)col * ksteps * sk_str);
+  }
+  const int64_t a_wrap = ((int64_t)(sp - 1) * kspan + 1) * sa_str;
+  const uint32_t fold_every = C.mac_fold, reduce_every = C.mac_chunk;
+  int kk = 0, left = ksteps;
+  struct Ops {
+    uint64_t ct[2][2], pt[2];
+  };
+  auto load = [&](Ops& o) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      if (A_CT) {
+        o.ct[i][0] = ld(pa[i], lane);
+        o.ct[i][1] = ld(pa[i] + c1, lane);
+        o.pt[i] = ld(pk[i], lane);
+      } else {
+        o.pt[i] = ld(pa[i], lane);
+        o.ct[i][0] = ld(pk[i], lane);
+        o.ct[i][1] = ld(pk[i] + c1, lane);
+      }
+    }
+    const bool adv = --left > 0;
+    const int64_t da = !adv ? 0 : (kk + 1 == kspan) ? a_wrap : sa_str;
+    const int64_t dk = adv ? sk_str : 0;
+    kk = (kk + 1 == kspan) ? 0 : kk + 1;
+    pa[0] = uni(pa[0] + da);
+    pa[1] = uni(pa[1] + da);
+    pk[0] = uni(pk[0] + dk);
+    pk[1] = uni(pk[1] + dk);
+  };
+  auto step = [&](const Ops& o) {
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int c2 = 0; c2 < 2; ++c2)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const uint64_t av = A_CT ? o.ct[a][c] : o.pt[a];
+          const uint64_t kv = A_CT ? o.pt[c2] : o.ct[c2][c];
+          part_mac(acc[(a * 2 + c2) * 2 + c], av, kv);
+        }
+    if (++B.nmac == fold_every) {
+      B.nmac = 0;
+      fold_lds(acc, tot, B.nfold, reduce_every, lc);
+    }
+  };
+  Ops x, y, z;
+  load(x);
+  load(y);
+  for (int k = 0; k < ksteps; k += 3) {
+    load(z);
+    step(x);
+    if (k + 1 >= ksteps) break;
+    load(x);
+    step(y);
+    if (k + 2 >= ksteps) break;
+    load(y);
+    step(z);
+  }
+}
+
+template <int ROWS, int COLS>
+__device__ __forceinline__ void do_mac_v2(u64x2* lds, const MacArgs& A, const Geo& G, const Consts& C,
+                                          int slot_block, int chunk) {
+  constexpr int WC = COLS / 2;
+  static_assert((ROWS / 2) * WC == 8, "8 waves per block");
+  const int n = C.n, L = C.L;
+  const int per_limb = n / kMacSlots;
+  const int l = slot_block / per_limb;
+  const LimbConst& lc = C.limb[l];
+  const int cchunks = (G.nR + COLS - 1) / COLS;
+  MacBlock B;
+  B.row0 = (chunk / cchunks) * ROWS;
+  B.col0 = (chunk % cchunks) * COLS;
+  B.s = threadIdx.x & (kMacSlots - 1);
+  B.grp = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  B.comp = 0;
+  B.rg = (B.grp / WC) * 2;
+  B.cg = (B.grp % WC) * 2;
+  B.ln = (int64_t)l * n + (int64_t)(slot_block % per_limb) * kMacSlots;
+  B.ct_stride = 2 * (int64_t)L * n;
+  B.pt_stride = (int64_t)L * n;
+  B.active = B.row0 + B.rg < A.m_rows && B.col0 + B.cg < G.nR;
+  B.nmac = B.nfold = 0;
+  if (!B.active) return;
+  u64x2* tot = lds + B.grp * 8 * kMacSlots + B.s;  // this lane's 8 totals, stride kMacSlots
+#pragma unroll
+  for (int i = 0; i < 8; ++i) tot[i * kMacSlots] = u64x2{0, 0};
+  Part acc[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) acc[i] = Part{0, 0, 0};
+  // term 0 has the ciphertext on the A side (forward, input gradient, the
+  // weight gradient's term A); the weight gradient's term B has it on the K side
+  mac_term_v2<true>(A.term[0], A, G, C, lc, B, acc, tot);
+  if (A.n_terms > 1) mac_term_v2<false>(A.term[1], A, G, C, lc, B, acc, tot);
+  // re-randomisation term pk_c * u'_o, reduction and store
+  const int64_t ln = B.ln, pt_stride = B.pt_stride, ct_stride = B.ct_stride;
+  const int s = B.s, sp = G.nOY * G.nOX;
+  const PENCIL_GLOBAL uint64_t* gpk = gview(A.pk);
+  const PENCIL_GLOBAL uint64_t* gu = gview(A.u);
+  PENCIL_GLOBAL uint64_t* gout = gview(A.out);
+  const uint64_t pk0 = gpk[ln + s], pk1 = gpk[pt_stride + ln + s];
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    const int row = B.row0 + B.rg + a;
+    if (row >= A.m_rows) continue;
+    const int mi = row / sp, oyi = (row % sp) / G.nOX, oxi = row % G.nOX;
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int col = B.col0 + B.cg + b;
+      if (col >= G.nR) continue;
+      const int64_t o = (((int64_t)mi * G.nR + col) * G.nOY + oyi) * G.nOX + oxi;
+      const uint64_t u = gu[o * pt_stride + ln + s];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const int i = (a * 2 + b) * 2 + c;
+        Part& x = acc[i];
+        part_mac(x, c ? pk1 : pk0, u);  // one more step: the partial sums hold fewer than mac_fold
+        const u64x2 t = tot[i * kMacSlots];
+        uint64_t lo = t[0], hi = t[1];
+        part_fold(x, lo, hi);
+        gout[o * ct_stride + (int64_t)c * pt_stride + ln + s] = reduce128(hi, lo, lc.q, lc.mu_lo, lc.mu_hi);
+      }
+    }
+  }
+}
+
+constexpr int kMacV2Lds = 8 * 8 * kMacSlots;  // u64x2 words: 8 waves x 8 totals x 64 lanes (64 KiB)
+
+// Kind 0: LDS-staged 2 x 2 wave blocks, both components; 2: direct 2 x 2
+// wave blocks of one component each (kind 1 is do_mac_kind1).
 template <int KIND>
 __device__ __forceinline__ void do_mac(uint64_t* smem, const MacArgs& A, const Geo& G, const Consts& C,
                                        int slot_block, int chunk) {
@@ -391,9 +603,20 @@ __global__ void __launch_bounds__(512) k_mac_lds(MacArgs A, Geo G, Consts C, int
   do_mac<0>(smem, A, G, C, w / chunks, w % chunks);
 }
 
+// Kind 1 through do_mac_v2: 2 x 2 wave blocks, both components, totals in LDS.
+__device__ __forceinline__ void do_mac_kind1(u64x2* tot, const MacArgs& A, const Geo& G, const Consts& C, int w,
+                                             int chunks) {
+  switch (A.variant % 3) {
+    case 1: do_mac_v2<2, 16>(tot, A, G, C, w / chunks, w % chunks); break;
+    case 2: do_mac_v2<8, 4>(tot, A, G, C, w / chunks, w % chunks); break;
+    default: do_mac_v2<4, 8>(tot, A, G, C, w / chunks, w % chunks); break;
+  }
+}
+
 __global__ void __launch_bounds__(512) k_mac_direct(MacArgs A, Geo G, Consts C, int chunks, int64_t total) {
+  __shared__ u64x2 tot[kMacV2Lds];
   const int w = (int)xcd_work(blockIdx.x, total);
-  do_mac<1>(nullptr, A, G, C, w / chunks, w % chunks);
+  do_mac_kind1(tot, A, G, C, w, chunks);
 }
 
 __global__ void __launch_bounds__(512) k_mac_direct_small(MacArgs A, Geo G, Consts C, int chunks, int64_t total) {
@@ -422,7 +645,16 @@ __global__ void __launch_bounds__(512) k_step_mac(STEP_ARGS) {
   step_mac<0>(segs, nseg, consts, smem);
 }
 
-__global__ void __launch_bounds__(512) k_step_mac_direct(STEP_ARGS) { step_mac<1>(segs, nseg, consts, nullptr); }
+__global__ void __launch_bounds__(512) k_step_mac_direct(STEP_ARGS) {
+  __shared__ u64x2 tot[kMacV2Lds];
+  const StepSeg& S = segs[find_seg(segs, nseg, blockIdx.x)];
+  const int64_t local = (int64_t)blockIdx.x - S.block_begin;
+  const int chunks = mac_chunks(S.mac.variant, S.mac.m_rows, S.G.nR);
+  const int64_t work = S.slot_blocks * chunks, padded = (work + 7) & ~(int64_t)7;
+  const int w = (int)xcd_work(local, padded);  // work items per launch stay below 2^31
+  if (w >= work) return;
+  do_mac_kind1(tot, S.mac, S.G, consts[S.ctx], w, chunks);
+}
 
 __global__ void __launch_bounds__(512) k_step_mac_direct_small(STEP_ARGS) {
   step_mac<2>(segs, nseg, consts, nullptr);
@@ -431,6 +663,10 @@ __global__ void __launch_bounds__(512) k_step_mac_direct_small(STEP_ARGS) {
 
 hipError_t launch_mac(const MacArgs& A, int64_t n_out, const Geo& G, const Consts& C, hipStream_t s) {
   if (n_out <= 0) return hipSuccess;
+  // the kernels take term 0 with the ciphertext on the A side and an optional
+  // term 1 with it on the K side
+  if (A.n_terms < 1 || A.n_terms > 2 || !A.term[0].a_is_ct || (A.n_terms == 2 && A.term[1].a_is_ct))
+    return hipErrorInvalidValue;
   const int64_t slot_blocks = (int64_t)C.n * C.L / kMacSlots;
   const int chunks = mac_chunks(A.variant, A.m_rows, G.nR);
   const int64_t total = slot_blocks * chunks;

@@ -5,27 +5,27 @@
 namespace pencil {
 
 template <int LOGN, int LOGE>
-__global__ void __launch_bounds__(512, (LOGE >= 5 ? 2 : 4)) k_ntt_plain(uint64_t* data, int inverse, Consts C, Tables T) {
+__global__ void PENCIL_NTT_BOUNDS(LOGN, LOGE) k_ntt_plain(uint64_t* data, int inverse, Consts C, Tables T) {
   extern __shared__ uint64_t lds[];
   do_ntt_plain<LOGN, LOGE>(lds, data, inverse, C, T, blockIdx.x);
 }
 
 template <int LOGN, int LOGE>
-__global__ void __launch_bounds__(512, (LOGE >= 5 ? 2 : 4)) k_ntt_ct(const uint64_t* src, uint64_t* dst, const int64_t* share, Geo G,
+__global__ void PENCIL_NTT_BOUNDS(LOGN, LOGE) k_ntt_ct(const uint64_t* src, uint64_t* dst, const int64_t* share, Geo G,
                                                  View V, Consts C, Tables T) {
   extern __shared__ uint64_t lds[];
   do_ntt_ct<LOGN, LOGE>(lds, src, dst, share, G, V, C, T, blockIdx.x);
 }
 
 template <int LOGN, int LOGE>
-__global__ void __launch_bounds__(512, (LOGE >= 5 ? 2 : 4)) k_ntt_pt(const int64_t* tensor, uint64_t* dst, int side, Geo G, View V,
+__global__ void PENCIL_NTT_BOUNDS(LOGN, LOGE) k_ntt_pt(const int64_t* tensor, uint64_t* dst, int side, Geo G, View V,
                                                  Consts C, Tables T) {
   extern __shared__ uint64_t lds[];
   do_ntt_pt<LOGN, LOGE>(lds, tensor, dst, side, G, V, C, T, blockIdx.x);
 }
 
 template <int LOGN, int LOGE>
-__global__ void __launch_bounds__(512, (LOGE >= 5 ? 2 : 4)) k_ntt_ternary(uint64_t* dst, uint64_t nonce, uint64_t obj_base,
+__global__ void PENCIL_NTT_BOUNDS(LOGN, LOGE) k_ntt_ternary(uint64_t* dst, uint64_t nonce, uint64_t obj_base,
                                                       uint32_t purpose, int split, Consts C, Tables T) {
   extern __shared__ uint64_t lds[];
   do_ntt_ternary<LOGN, LOGE>(lds, dst, nonce, obj_base, purpose, split, C, T, blockIdx.x);
@@ -70,6 +70,7 @@ hipError_t configure_lds_ntt() {
   }
   PENCIL_RAISE(13, 4)
   PENCIL_RAISE(13, 5)
+  PENCIL_RAISE(14, 4)
   PENCIL_RAISE(14, 5)
 #undef PENCIL_RAISE
   return e;

@@ -8,7 +8,7 @@ namespace pencil {
 // inputs (k_step_ntt: ciphertexts, plaintexts, re-randomisation masks) or the
 // inverse transforms of the outputs (k_step_intt).
 template <int LOGN, int LOGE>
-__global__ void __launch_bounds__(512, (LOGE >= 5 ? 2 : 4))
+__global__ void PENCIL_NTT_BOUNDS(LOGN, LOGE)
     k_step_ntt(const StepSeg* __restrict__ segs, int nseg, const Consts* __restrict__ consts,
                const Tables* __restrict__ tabs, const uint64_t* __restrict__ nonce) {
   extern __shared__ uint64_t lds[];
@@ -25,7 +25,7 @@ __global__ void __launch_bounds__(512, (LOGE >= 5 ? 2 : 4))
 }
 
 template <int LOGN, int LOGE>
-__global__ void __launch_bounds__(512, (LOGE >= 5 ? 2 : 4))
+__global__ void PENCIL_NTT_BOUNDS(LOGN, LOGE)
     k_step_intt(const StepSeg* __restrict__ segs, int nseg, const Consts* __restrict__ consts,
                 const Tables* __restrict__ tabs) {
   extern __shared__ uint64_t lds[];
@@ -58,6 +58,7 @@ hipError_t configure_lds_step() {
   }
   PENCIL_RAISE(13, 4)
   PENCIL_RAISE(13, 5)
+  PENCIL_RAISE(14, 4)
   PENCIL_RAISE(14, 5)
 #undef PENCIL_RAISE
   return e;

@@ -25,22 +25,31 @@ struct NttShape {
   static constexpr int start(int i) { return i == 0 ? 0 : start(i - 1) + size(i - 1); }
 };
 
-// Butterfly constants of one modulus q < 2^60: 4q, 2^64 - 4q, 4q + 1, and
-// 2q, 2^64 - 2q, 2^64 - q for the final reduction.  They are hidden from the
-// optimiser so that x - 4q stays the single 64-bit addition x + (2^64 - 4q)
-// instead of a borrow chain.
+// Launch bounds of a kernel that transforms one polynomial per workgroup:
+// N / E threads (1024 only for E = 16 at N = 16384, one workgroup per CU by
+// LDS) and the waves per SIMD the registers must allow (4 with 16 residues per
+// thread, 2 with 32).
+constexpr int ntt_threads(int logn, int loge) { return (1 << logn) >> loge; }
+constexpr int ntt_min_waves(int logn, int loge) { return ntt_threads(logn, loge) > 512 || loge < 5 ? 4 : 2; }
+#define PENCIL_NTT_BOUNDS(LOGN, LOGE) __launch_bounds__(ntt_threads(LOGN, LOGE), ntt_min_waves(LOGN, LOGE))
+
+// Butterfly constants of one modulus q < 2^60: 8q, 4q (and 2^64 minus each),
+// 4q + 1, and 2q, 2^64 - 2q, 2^64 - q for the final reduction.  They are
+// hidden from the optimiser so that x - 4q stays the single 64-bit addition
+// x + (2^64 - 4q) instead of a borrow chain.
 struct BflyK {
-  uint64_t q4, nq4, q4p1, q2, nq2, nq;
+  uint64_t q8, nq8, q4, nq4, q4p1, q2, nq2, nq;
 };
 
 __device__ __forceinline__ BflyK bfly_consts(uint64_t q) {
-  BflyK k{4 * q, 0 - 4 * q, 4 * q + 1, 2 * q, 0 - 2 * q, 0 - q};
-  asm volatile("" : "+s"(k.q4), "+s"(k.nq4), "+s"(k.q4p1), "+s"(k.q2), "+s"(k.nq2), "+s"(k.nq));
+  BflyK k{8 * q, 0 - 8 * q, 4 * q, 0 - 4 * q, 4 * q + 1, 2 * q, 0 - 2 * q, 0 - q};
+  asm volatile("" : "+s"(k.q8), "+s"(k.nq8), "+s"(k.q4), "+s"(k.nq4), "+s"(k.q4p1), "+s"(k.q2), "+s"(k.nq2),
+               "+s"(k.nq));
   return k;
 }
 
-// x - c if x >= c, else x, for x < 2^63 and c < 2^62 (nc = 2^64 - c): the sign
-// of x - c decides.
+// x - c if x >= c, else x, for x < 2c and c <= 2^63 (nc = 2^64 - c): x - c
+// taken as a signed 64-bit value is negative exactly when x < c.
 __device__ __forceinline__ uint64_t csub(uint64_t x, uint64_t c, uint64_t nc) {
   const uint64_t d = x + nc;
   const uint32_t m = (uint32_t)((int32_t)(uint32_t)(d >> 32) >> 31);
@@ -62,9 +71,12 @@ __device__ __forceinline__ uint64_t shoup_lazy(uint64_t y, const TW w, const Bfl
   return y * w.w + est * k.nq;
 }
 
-// Lazy Cooley-Tukey butterfly: x, y in [0, 8q) -> [0, 8q) (8q < 2^63).
-__device__ __forceinline__ void ct_bfly(uint64_t& x, uint64_t& y, const TW w, const BflyK& k) {
-  const uint64_t a = csub(x, k.q4, k.nq4);
+// Lazy Cooley-Tukey butterfly, reducing x on every other stage (`reduce` is
+// a compile-time constant after unrolling).  With reduce, x and y in [0, 16q) give a = x mod 8q in [0, 8q) and outputs in
+// [0, 12q); without, inputs in [0, 12q) give outputs in [0, 16q).  The Shoup
+// product t is below 4q for any y, and 16q < 2^64 for q < 2^60.
+__device__ __forceinline__ void ct_bfly(uint64_t& x, uint64_t& y, const TW w, const BflyK& k, const bool reduce) {
+  const uint64_t a = reduce ? csub(x, k.q8, k.nq8) : x;
   const uint64_t t = shoup_lazy(y, w, k);
   x = a + t;
   y = (a + k.q4p1) + ~t;  // a - t + 4q
@@ -108,7 +120,7 @@ __device__ __forceinline__ void fwd_pass(uint64_t* a, const PENCIL_GLOBAL TW* tw
 #pragma unroll
         for (int k = j << (S - s); k < ((j + 1) << (S - s)); ++k) {
           if (k & h) continue;
-          ct_bfly(v[r * K + k], v[r * K + k + h], w, bk);
+          ct_bfly(v[r * K + k], v[r * K + k + h], w, bk, ((S0 + s) & 1) == 0);
         }
       }
     }
@@ -120,7 +132,8 @@ __device__ __forceinline__ void fwd_pass(uint64_t* a, const PENCIL_GLOBAL TW* tw
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       uint64_t x = v[r * K + k];
-      if (LAST) {
+      if (LAST) {  // [0, 16q) -> [0, q)
+        x = csub(x, bk.q8, bk.nq8);
         x = csub(x, bk.q4, bk.nq4);
         x = csub(x, bk.q2, bk.nq2);
         x = csub(x, q, bk.nq);

@@ -23,12 +23,13 @@ def context(layer, seed):
     return _ctx[key]
 
 
-def build(layers, tensors, seed):
-    """Contexts, plans, encrypted inputs and output buffers for every layer."""
+def build(layers, tensors, seed, plans=None):
+    """Contexts, plans (the planner's unless given), encrypted inputs and output
+    buffers for every layer."""
     ents = []
     for li, (layer, ts) in enumerate(zip(layers, tensors)):
         ctx = context(layer, seed)
-        plan = ctx.plan_auto(layer)
+        plan = ctx.plan_auto(layer) if plans is None else plans[li]
         sz = ctx.layout(layer, plan)
         d = {k: dev(v) for k, v in ts.items()}
         io = dict(ct_x1=ctx.encrypt(layer, plan, "x_fwd", d["x1"], 500 + li),
@@ -133,12 +134,21 @@ def test_step_equals_per_layer_calls_config4():
 
 
 def test_every_schedule_variant_is_bit_identical_and_autotune_picks_one(tmp_path):
-    """The multiply-accumulate chunk shapes and the NTT widths are schedules only:
-    outputs are identical for every candidate, and the autotuner's choice is one of them."""
+    """The multiply-accumulate schedules are schedules only: under one plan the
+    outputs are identical for every candidate, and the autotuner's choice is one
+    of them.  The autotuner may also pick another partition (a different
+    ciphertext layout, so the inputs are encrypted with the tuned plan): the
+    decrypted products are the same as under the planner's partition."""
+    from paper_2403_11166_amd.api import plan_dict
     layer = MIXED[1]
     ts = layer_tensors(layer, 77)
-    ents = build([layer], [ts], 8)
-    ctx, _, plan, io = ents[0]
+    ctx = context(layer, 8)
+    cache = str(tmp_path / "tune.txt")
+    tuned = ctx.autotune(layer, ctx.plan_auto(layer), cache)
+    assert all(0 <= v < 9 for v in tuned.sched)
+    ents = build([layer], [ts], 8, plans=[tuned])
+    _, _, plan, io = ents[0]
+    chosen = list(plan.sched)
     results = []
     for v in range(9):
         for op in range(3):
@@ -146,15 +156,31 @@ def test_every_schedule_variant_is_bit_identical_and_autotune_picks_one(tmp_path
         results.append(per_layer(ents, 4000))
     for r in results[1:]:
         assert_same(r, results[0])
-    cache = str(tmp_path / "tune.txt")
-    tuned = ctx.autotune(layer, plan, cache)
-    assert all(0 <= v < 9 for v in tuned.sched)
-    ents[0] = (ctx, layer, tuned, io)
+    for op in range(3):
+        plan.sched[op] = chosen[op]
     assert_same(per_layer(ents, 4000), results[0])
+    # the same products under the planner's own partition decrypt to the same shares' sums
+    base = build([layer], [ts], 8)
+    per_layer(base, 4000)
+    t = ctx.t
+    for ents_, name in ((ents, "tuned"), (base, "planner")):
+        c, L_, p, o = ents_[0]
+        y1 = c.decrypt(L_, p, "fwd", o["ct_y"])
+        dx1 = c.decrypt(L_, p, "dx", o["ct_dx"])
+        dw1 = c.decrypt(L_, p, "dw", o["ct_dw"])
+        torch.cuda.synchronize()
+        recon = [(host_i64(o["y0"]) + host_i64(y1)) % t, (host_i64(o["dx0"]) + host_i64(dx1)) % t,
+                 (host_i64(o["dw_mask"]) + host_i64(dw1)) % t]
+        if name == "tuned":
+            first = recon
+        else:
+            for a, b in zip(first, recon):
+                assert np.array_equal(a, b)
     text = open(cache).read()
-    assert "ntt_loge" in text and "op=2" in text
-    again = ctx.autotune(layer, plan, cache)  # cache hit: same choice, no new lines
+    assert "ntt_loge" in text and "op=2" in text and "sched" in text
+    again = ctx.autotune(layer, ctx.plan_auto(layer), cache)  # cache hits: same choices, no new lines
     assert tuple(again.sched) == tuple(tuned.sched)
+    assert plan_dict(again) == plan_dict(tuned)
     assert open(cache).read() == text
 
 
