@@ -205,6 +205,21 @@ pencil_status pencil_linear_fwd(pencil_ctx* ctx, const pencil_layer* layer, cons
                                 const uint64_t* ct_x1, const int64_t* x0, const int64_t* w, const int64_t* bias,
                                 uint64_t* ct_y, int64_t* y0, void* ws, uint64_t nonce, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the forward
+ * product of pencil_linear_fwd without the ws argument.  Its staging lives in
+ * a scratch array inside the library's code object, 128 MiB per GPU, held from
+ * the first context created on that GPU until the process ends; layers whose
+ * ws_fwd_bytes exceed 128 MiB are refused with PENCIL_EUNSUPPORTED.  Nothing is
+ * allocated, no event is recorded (kernel timing does not cover it), and the
+ * results equal pencil_linear_fwd's bit for bit.  Every call on one GPU shares
+ * that GPU's array: calls that overlap on one GPU (several streams, threads or
+ * contexts) race and must be serialised by the caller. */
+pencil_status pencil_linear_fwd_noalloc(pencil_ctx* ctx, const pencil_layer* layer, const pencil_plan* plan,
+                                        const uint64_t* ct_x1, const int64_t* x0, const int64_t* w,
+                                        const int64_t* bias, uint64_t* ct_y, int64_t* y0, uint64_t nonce,
+                                        void* stream);
+
 /* MO: backward products.  Input gradient (Sec. III.B.2): ct_dy_dx holds <dY>_1
  * in DY_DX layout, dy0 is the MO's share; writes ct_dx (for the DO) and dx0.
  * Weight-gradient cross terms (Alg. 2): ct_x_dw (<X>_1, X_DW layout) and

@@ -76,6 +76,8 @@ SIGNATURES = {
                                       ctypes.c_void_p]),
     "pencil_linear_fwd": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Layer), ctypes.POINTER(Plan)]
                           + [ctypes.c_void_p] * 7 + [ctypes.c_uint64, ctypes.c_void_p]),
+    "pencil_linear_fwd_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Layer), ctypes.POINTER(Plan)]
+                                  + [ctypes.c_void_p] * 6 + [ctypes.c_uint64, ctypes.c_void_p]),
     "pencil_linear_bwd": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Layer), ctypes.POINTER(Plan)]
                           + [ctypes.c_void_p] * 11 + [ctypes.c_uint64, ctypes.c_void_p]),
     "pencil_decrypt": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Layer), ctypes.POINTER(Plan), ctypes.c_int,

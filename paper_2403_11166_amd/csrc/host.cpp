@@ -34,6 +34,7 @@ struct pencil_ctx {
   uint64_t* d_pk_coeff = nullptr;
   int64_t* d_s_coeff = nullptr;
   uint64_t* d_noise = nullptr;   // one word: the checked decryption's largest noise fraction
+  void* d_scratch = nullptr;     // this device's copy of the allocation-free entry points' scratch array
   std::string err;
   // kernel timing with HIP events on the launch stream (pencil_profile_*)
   bool prof_on = false;
@@ -366,6 +367,8 @@ extern "C" pencil_status pencil_ctx_create(const pencil_params* params, pencil_c
   };
   if (hipGetDevice(&ctx->device) != hipSuccess) return cleanup(fail(nullptr, PENCIL_EHIP, "no HIP device"));
   if (configure_lds_limits() != hipSuccess) return cleanup(fail(nullptr, PENCIL_EHIP, "cannot raise LDS limit"));
+  if (scratch_address(ctx->device, &ctx->d_scratch) != hipSuccess)
+    return cleanup(fail(nullptr, PENCIL_EHIP, "no device address for the scratch array"));
   const size_t ln = L * n * sizeof(uint64_t);
   if (hipMalloc(&ctx->d_tables, 2 * L * n * sizeof(TW)) != hipSuccess || hipMalloc(&ctx->d_s_ntt, ln) != hipSuccess ||
       hipMalloc(&ctx->d_s_sh, ln) != hipSuccess || hipMalloc(&ctx->d_pk_ntt, 2 * ln) != hipSuccess ||
@@ -869,8 +872,13 @@ struct TermIn {
 
 static pencil_status run_product(pencil_ctx* ctx, const pencil_layer* L, int op, const Geo& G, const TermIn* terms,
                                  int n_terms, const int64_t* add_share, const int64_t* bias, uint64_t* ct_out,
-                                 int64_t* share_out, uint8_t* ws, uint64_t nonce, int sched, hipStream_t s) {
+                                 int64_t* share_out, uint8_t* ws, uint64_t nonce, int sched, hipStream_t s,
+                                 bool allow_events = true) {
   if (sched < 0 || sched >= kMacVariants) return fail(ctx, PENCIL_EINVAL, "schedule variant %d invalid", sched);
+  // kernel timing records events only where the caller allows it
+  auto timed = [&](pencil_ctx* c, int kid, hipStream_t st, auto&& launch) -> hipError_t {
+    return allow_events ? ::timed(c, kid, st, launch) : launch();
+  };
   const Consts& C = ctx->C;
   const int64_t poly = (int64_t)C.L * C.n, ctw = 2 * poly;
   const int64_t na = n_a_tiles(G), nk = n_k_tiles(G), no = n_out_tiles(G);
@@ -946,6 +954,31 @@ extern "C" pencil_status pencil_linear_fwd(pencil_ctx* ctx, const pencil_layer* 
   TermIn t{ct_x1, w, 1};
   return run_product(ctx, L, PENCIL_OP_FWD, G, &t, 1, x0, bias, ct_y, y0, (uint8_t*)ws, nonce, P->sched[0],
                      (hipStream_t)stream);
+}
+
+extern "C" pencil_status pencil_linear_fwd_noalloc(pencil_ctx* ctx, const pencil_layer* L, const pencil_plan* P,
+                                                   const uint64_t* ct_x1, const int64_t* x0, const int64_t* w,
+                                                   const int64_t* bias, uint64_t* ct_y, int64_t* y0, uint64_t nonce,
+                                                   void* stream) {
+  if (!ctx) return PENCIL_EINVAL;
+  TRY(check_buf(ctx, ct_x1, "ct_x1"));
+  TRY(check_ptr(ctx, x0, "x0"));
+  TRY(check_ptr(ctx, w, "w"));
+  TRY(check_buf(ctx, ct_y, "ct_y"));
+  TRY(check_ptr(ctx, y0, "y0"));
+  if (!ctx->d_scratch) return fail(ctx, PENCIL_EHIP, "the library's scratch array has no device address");
+  Geo G;
+  TRY(get_geo(ctx, L, P, PENCIL_OP_FWD, &G));
+  if (!mac_grid_ok(G)) return fail(ctx, PENCIL_EUNSUPPORTED, "too many output tiles for one launch");
+  pencil_sizes sz;
+  TRY(pencil_layout(ctx, L, P, &sz));
+  if (sz.ws_fwd_bytes > kScratchBytes)
+    return fail(ctx, PENCIL_EUNSUPPORTED,
+                "the forward product needs %llu bytes of workspace; the allocation-free entry point has %llu",
+                (unsigned long long)sz.ws_fwd_bytes, (unsigned long long)kScratchBytes);
+  TermIn t{ct_x1, w, 1};
+  return run_product(ctx, L, PENCIL_OP_FWD, G, &t, 1, x0, bias, ct_y, y0, (uint8_t*)ctx->d_scratch, nonce,
+                     P->sched[0], (hipStream_t)stream, false);
 }
 
 extern "C" pencil_status pencil_linear_bwd(pencil_ctx* ctx, const pencil_layer* L, const pencil_plan* P,

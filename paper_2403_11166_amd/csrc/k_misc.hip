@@ -1,6 +1,8 @@
 // Flood and mask of the products' outputs, the Z_t kernels (local terms,
 // Pencil+ online correlations and combinations), the bias gradient, the DP
 // perturbation, stride relayouts and the step's nonce counter.
+#include <mutex>
+
 #include "device_common.h"
 
 namespace pencil {
@@ -740,6 +742,31 @@ hipError_t launch_step_flood(int words, const StepPhase& P, int64_t blocks, hipS
 hipError_t launch_set_u64(uint64_t* p, uint64_t v, int add, hipStream_t s) {
   hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(64), 0, s, p, v, add);
   return hipGetLastError();
+}
+
+// ------------------------------------------------ allocation-free scratch
+// The scratch memory of the allocation-free entry points: a file-scope device
+// array, so each GPU the library runs on holds its own copy from the moment
+// the code object is loaded until the process ends.  In host code the array's
+// name is a host-side stand-in, not a device address: only the address
+// hipGetSymbolAddress returns (per device, with that device current) is ever
+// passed to a kernel.
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+hipError_t scratch_address(int device, void** out) {
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    addr[device] = p;
+  }
+  *out = addr[device];
+  return hipSuccess;
 }
 
 hipError_t configure_lds_limits() {

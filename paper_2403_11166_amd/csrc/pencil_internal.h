@@ -208,6 +208,14 @@ hipError_t launch_set_u64(uint64_t* p, uint64_t v, int add, hipStream_t s);
 hipError_t launch_keygen(uint64_t* s_ntt, int64_t* s_coeff, uint64_t* pk_coeff, uint64_t* pk_ntt,
                          const Consts& C, const Tables& T, hipStream_t s);
 
+// Scratch array of the allocation-free entry points (one per GPU, in the
+// library's code object): kScratchBytes, 256-byte aligned.  scratch_address
+// returns its device address on `device`, which must be the current device;
+// the address is looked up once per device and kept.
+constexpr size_t kScratchBytes = size_t(128) << 20;
+constexpr int kMaxDevices = 64;
+hipError_t scratch_address(int device, void** out);
+
 // Kernels that stage more than 64 KiB of LDS opt in once per process; one
 // function per translation unit, all called by configure_lds_limits().
 hipError_t configure_lds_ntt();

@@ -43,6 +43,7 @@ hipError_t launch_keygen(uint64_t*, int64_t*, uint64_t*, uint64_t*, const Consts
   NODEV;
 }
 hipError_t configure_lds_limits() { return hipSuccess; }
+hipError_t scratch_address(int, void**) { NODEV; }
 #undef NODEV
 }  // namespace pencil
 
