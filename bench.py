@@ -29,9 +29,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# 32-bit integer multiply peak: 256 CUs x 64 lanes x 2.4 GHz, at half the VALU
-# issue rate (v_mad_u64_u32 / v_mul_lo_u32 / v_mul_hi_u32 on gfx950).
-MUL32_PEAK_TOPS = 256 * 64 * 2.4e9 / 2 / 1e12
+# 32-bit integer multiply peak: 256 CUs x 64 lanes x 2.4 GHz, the full VALU
+# issue rate.  On gfx950 the multiply forms the kernels use (v_mad_u64_u32,
+# v_mul_lo_u32, v_mul_hi_u32) issue at close to that rate: the library's probe
+# (pencil_probe_mul32, `--mul-probe`) measures 30-34 T/s.
+MUL32_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # 32-bit multiplies the algorithm needs per unit of work with 60-bit residues:
 # a Shoup butterfly (3 for the quotient estimate y1 ws1 + hi(y0 ws1) +
 # hi(y1 ws0), 3 + 3 for the low halves of y w and est q) and a
@@ -68,6 +70,8 @@ def parse():
                     help="use the planner's default schedules instead of timing the candidates first")
     ap.add_argument("--tune-cache", default=DEFAULT_TUNE_CACHE,
                     help="autotuner cache file (earlier choices are reused, new ones appended); '' = none")
+    ap.add_argument("--mul-probe", action="store_true",
+                    help="only measure the issue rate of the 32-bit multiply forms (the integer peak) and print it")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (the reference kernel that scales "
                          "HBM counters into bytes) and print its size and time")
@@ -77,14 +81,17 @@ def parse():
 # ------------------------------------------------------------- hbm traffic
 
 def kernel_source_hash():
-    """sha256 over the kernel sources (host.cpp included: the planner); a
+    """sha256 over the device sources (the .hip and .h files) and the committed
+    autotuning cache, which fixes the plans and schedules the benchmark runs; a
     traffic record holds for this hash only."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2403_11166_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        with open(os.path.join(ROOT, "paper_2403_11166_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+    files = [os.path.join(csrc, n) for n in sorted(os.listdir(csrc)) if n.endswith((".hip", ".h"))]
+    for path in files + [DEFAULT_TUNE_CACHE]:
+        if os.path.exists(path):
+            with open(path, "rb") as f:
+                h.update(f.read())
     return h.hexdigest()
 
 
@@ -397,6 +404,20 @@ def main():
     if args.copy_probe:
         copy_probe(args.copy_probe)
         return
+    if args.mul_probe:
+        import ctypes
+        import torch
+        from paper_2403_11166_amd import _abi as A
+        torch.cuda.init()
+        lib = A.load()
+        rates = {}
+        for kind, name in enumerate(("v_mad_u64_u32", "v_mul_lo_u32", "v_mul_hi_u32")):
+            r = ctypes.c_double()
+            A.check(lib.pencil_probe_mul32(kind, ctypes.byref(r)))
+            rates[name] = round(r.value / 1e12, 3)
+        print(json.dumps({"mul32_probe_T_per_s": rates, "assumed_peak_T_per_s": round(MUL32_PEAK_TOPS, 3),
+                          "cus": torch.cuda.get_device_properties(0).multi_processor_count}), flush=True)
+        return
     import torch
     from paper_2403_11166_amd import Context
     from paper_2403_11166_amd import _abi as A
@@ -691,6 +712,13 @@ def main():
     if m_plus > 0:
         plus = pencil_plus_bench(layers[0], m_plus, compare["step"] if "step" in compare else ms_step, torch)
 
+    # the integer peak's evidence: issue rates of the multiply forms on this GPU
+    probe = {}
+    for kind, name in enumerate(("v_mad_u64_u32", "v_mul_lo_u32", "v_mul_hi_u32")):
+        r = ctypes.c_double()
+        A.check(A.load().pencil_probe_mul32(kind, ctypes.byref(r)))
+        probe[name] = round(r.value / 1e12, 3)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(layers[0]["layer"], args.cpu_seconds)
@@ -728,6 +756,7 @@ def main():
         "launch_paths_ms_per_step": compare,
         "batched_speedup_vs_unbatched": round(compare["layer"] / min(compare["step"], compare["graph"]), 3),
         "roofline": roof,
+        "mul32_probe_T_per_s": probe,
         "kernels": breakdown,
         "cpu_baseline": cpu,
         "ntt": ntt_rec,

@@ -271,11 +271,37 @@ pencil_status pencil_zt_linear(pencil_ctx* ctx, const pencil_layer* layer, int o
  * u~ = u - sum k_i u'_i, v~ = v - sum l_j v'_j and the share combinations of the
  * online phase of the preprocessed products (Sec. IV.C, Alg. 3).
  * terms: host array of n_terms device pointers (n_terms >= 0; any number, the
- * library chains launches of 64 terms); coeffs: host array of n_terms values in
- * [0, t) (use t - c for -c); base: device pointer or NULL (zero); out: device,
- * may alias base but no term.  Enqueued on `stream`. */
+ * library chains launches of 64 terms); coeffs: host array of n_terms signed
+ * integers, taken mod t; base: device pointer or NULL (zero); out: device, may
+ * alias base but no term.  Enqueued on `stream`. */
 pencil_status pencil_zt_combine(pencil_ctx* ctx, int64_t count, int n_terms, const int64_t* const* terms,
-                                const uint64_t* coeffs, const int64_t* base, int64_t* out, void* stream);
+                                const int64_t* coeffs, const int64_t* base, int64_t* out, void* stream);
+
+/* The two-level sum of Alg. 3's online phase: out = base + sum_{i,j} ci[i] cj[j]
+ * terms[i * n_j + j] (mod t), i < n_i, j < n_j (the parties' preprocessed
+ * shares <u'_i o v'_j> weighted by the public coefficients k_i l_j).  ci, cj:
+ * host arrays of signed integers, taken mod t; the products ci[i] cj[j] mod t
+ * are formed here.  Otherwise as pencil_zt_combine. */
+pencil_status pencil_zt_combine_outer(pencil_ctx* ctx, int64_t count, int n_i, int n_j, const int64_t* const* terms,
+                                      const int64_t* ci, const int64_t* cj, const int64_t* base, int64_t* out,
+                                      void* stream);
+
+/* Fixed-point encoding (Sec. II.C) of values already scaled by 2^f and carried
+ * in float64 (integers, |x| < 2^53): out[i] = round(x[i]) mod t (nearest, ties
+ * to even), int64 in [0, t).  pencil_zt_decode is the inverse view: the
+ * centred representative of v[i] in (-t/2, t/2) as float64.  Device arrays of
+ * count entries; enqueued on `stream`. */
+pencil_status pencil_zt_encode(pencil_ctx* ctx, int64_t count, const double* x, int64_t* out, void* stream);
+pencil_status pencil_zt_decode(pencil_ctx* ctx, int64_t count, const int64_t* v, double* out, void* stream);
+
+/* Additive secret sharing over Z_t (Sec. II.C): s0 uniform, s1 = v - s0 mod
+ * t.  s0[i] is the 128-bit integer formed by words 2i and 2i+1 of the Philox
+ * stream (nonce, object, purpose 49) of the context's seed, reduced mod t.
+ * Use a distinct (nonce, object) per tensor.  v, s0, s1: device int64, count
+ * entries, v in [0, t); s0 and s1 must not alias each other (either may alias
+ * v).  Enqueued on `stream`. */
+pencil_status pencil_zt_share(pencil_ctx* ctx, int64_t count, const int64_t* v, uint64_t nonce, uint64_t object,
+                              int64_t* s0, int64_t* s1, void* stream);
 
 /* Bias-gradient share (Sec. III.B.2): db[o] = sum of dy over the batch and,
  * for a convolution, over the output rows and columns, mod t.  Each party runs
@@ -379,6 +405,32 @@ pencil_status pencil_step_graph_capture(pencil_step* step);
 /* The next replay uses base nonce `nonce`. */
 pencil_status pencil_step_set_nonce(pencil_step* step, uint64_t nonce, void* stream);
 pencil_status pencil_step_graph_launch(pencil_step* step, void* stream);
+
+/* Worst-case noise of one product's output before decryption (Sec. II.B:
+ * decryption is correct while it stays below q / (2t) ~ Delta / 2), from the
+ * parameters and the partition alone (host only, no GPU): every input
+ * coefficient's fresh noise is at most 42 N + 23 (CBD errors of magnitude
+ * <= 21 times ternary u and s, plus the roundings of round(q m / t)); a
+ * product sums `terms` contraction tiles of plaintext polynomials with at most
+ * `nnz` nonzero coefficients of magnitude at most 2^(plaintext_bits - 1)
+ * (centred; 41 for uniform shares of Z_t, about 13 for fixed-point weights
+ * with f = 12); re-randomisation adds 42 N + 21 and the flood at most
+ * 2^flood_bits.  All values are log2.  Returns PENCIL_ENOISE when
+ * product + flood reaches Delta / 2 (decryption may fail), PENCIL_OK
+ * otherwise; smudge_bits = flood_bits - product_bits is how far the flood
+ * exceeds the product noise it hides. */
+typedef struct {
+    double product_bits, flood_bits, budget_bits, margin_bits, smudge_bits;
+} pencil_noise;
+pencil_status pencil_noise_bound(const pencil_params* params, const pencil_layer* layer, const pencil_plan* plan,
+                                 int op, uint32_t plaintext_bits, pencil_noise* out /* host */);
+
+/* Measurement aid for the integer roofline: the rate, per second over the
+ * whole current GPU, of one 32-bit multiply instruction form -- kind 0
+ * v_mad_u64_u32 (the multiply-accumulate's), 1 v_mul_lo_u32, 2 v_mul_hi_u32
+ * (both in the NTT's Shoup products) -- from 8 waves per SIMD each running 8
+ * independent chains.  Synchronous; allocates and frees a small buffer. */
+pencil_status pencil_probe_mul32(int kind, double* per_s /* host */);
 
 /* Kernel timing: while enabled, every kernel this context launches is bracketed
  * by HIP events recorded on its launch stream.  enable() clears the totals.

@@ -13,7 +13,9 @@ bit for bit):
 * flood: words i*W .. i*W+W-1 (W = ceil((fb+1)/64), little-endian) form an
   integer V, keep its low fb+1 bits, and the flood is V - 2^fb, uniform in
   [-2^fb, 2^fb);
-* model owner's mask: words 2i and 2i+1 form a 128-bit integer, reduced mod t.
+* model owner's mask: words 2i and 2i+1 form a 128-bit integer, reduced mod t;
+* additive share (Sec. II.C): the same construction on its own stream
+  (purpose P_SHARE): s0 = that value, s1 = v - s0 mod t.
 
 Stream names: key = (seed, nonce); counter words (block, object, purpose,
 limb).  Key generation uses nonce 2^64 - 1.
@@ -36,6 +38,7 @@ P_RR_E0 = 33
 P_RR_E1 = 34
 P_FLOOD = 35
 P_MASK = 36
+P_SHARE = 49
 
 
 def ternary(seed, nonce, obj, purpose, n):
@@ -113,3 +116,13 @@ def cbd21_at(seed, nonce, obj, purpose, idx):
         w = int(stream_words(seed, nonce, obj, purpose, 0, i, 1)[0])
         out.append(bin(w & m).count("1") - bin((w >> 21) & m).count("1"))
     return out
+
+
+def shares_mod_t(seed, nonce, obj, v, t):
+    """Additive shares (s0, s1) of the integer array v over Z_t: s0[i] is the
+    128-bit integer of stream words 2i, 2i+1 (purpose P_SHARE) mod t, and
+    s1 = v - s0 mod t."""
+    v = np.asarray(v, dtype=np.int64).ravel()
+    w = stream_words(seed, nonce, obj, P_SHARE, 0, 0, 2 * v.size)
+    s0 = np.array([(int(w[2 * i]) + (int(w[2 * i + 1]) << 64)) % t for i in range(v.size)], dtype=np.int64)
+    return s0, np.mod(v - s0, t).astype(np.int64)

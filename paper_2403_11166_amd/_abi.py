@@ -52,6 +52,11 @@ class Info(ctypes.Structure):
                 ("t", ctypes.c_uint64), ("seed", ctypes.c_uint64)]
 
 
+class Noise(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("product_bits", "flood_bits", "budget_bits", "margin_bits",
+                                               "smudge_bits")]
+
+
 class StepIO(ctypes.Structure):
     _fields_ = [(n, ctypes.c_void_p) for n in ("ct_x1", "ct_dy_dx", "ct_x_dw", "ct_dy_dw", "x0", "dy0", "w", "bias",
                                                 "ct_y", "ct_dx", "ct_dw", "y0", "dx0", "dw_mask")]
@@ -86,14 +91,27 @@ SIGNATURES = {
                                               ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                               ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
     "pencil_plan_auto_n": (ctypes.c_int, [ctypes.c_uint32, ctypes.POINTER(Layer), ctypes.POINTER(Plan)]),
+    "pencil_probe_mul32": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_double)]),
+    "pencil_noise_bound": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.POINTER(Layer), ctypes.POINTER(Plan),
+                                          ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(Noise)]),
     "pencil_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "pencil_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(KernelStat), ctypes.c_int,
                                            ctypes.POINTER(ctypes.c_int)]),
     "pencil_zt_linear": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Layer), ctypes.c_int, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "pencil_zt_combine": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
-                                         ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_uint64),
+                                         ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_int64),
                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "pencil_zt_combine_outer": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
+                                               ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_int64),
+                                               ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p, ctypes.c_void_p,
+                                               ctypes.c_void_p]),
+    "pencil_zt_encode": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p]),
+    "pencil_zt_decode": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p]),
+    "pencil_zt_share": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_uint64,
+                                       ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "pencil_bias_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Layer), ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p]),
     "pencil_dp_noise": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64,

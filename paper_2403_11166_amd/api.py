@@ -67,9 +67,9 @@ def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def _need(t, name):
-    if t.device.type != "cuda" or not t.is_contiguous() or t.dtype != torch.int64:
-        raise ValueError(f"{name} must be a contiguous int64 CUDA tensor")
+def _need(t, name, dtype=torch.int64):
+    if t.device.type != "cuda" or not t.is_contiguous() or t.dtype != dtype:
+        raise ValueError(f"{name} must be a contiguous {str(dtype).split('.')[-1]} CUDA tensor")
 
 
 # Every random value is drawn from Philox keyed by (seed, nonce): two calls that
@@ -277,7 +277,7 @@ class Context:
 
     def zt_combine(self, terms, coeffs, base=None, out=None):
         """out = base + sum_i coeffs[i] * terms[i] mod t, element-wise (int64 tensors in [0, t));
-        coefficients may be negative integers (taken mod t)."""
+        coefficients are signed integers (the library takes them mod t)."""
         terms = list(terms)
         like = base if base is not None else terms[0]
         for x in terms + ([base] if base is not None else []):
@@ -287,8 +287,25 @@ class Context:
         out = torch.empty_like(like) if out is None else out
         n = len(terms)
         ptrs = (ctypes.c_void_p * max(n, 1))(*[x.data_ptr() for x in terms])
-        cs = (ctypes.c_uint64 * max(n, 1))(*[int(c) % self.t for c in coeffs])
+        cs = (ctypes.c_int64 * max(n, 1))(*[int(c) for c in coeffs])
         self._check(self.lib.pencil_zt_combine(self.h, like.numel(), n, ptrs, cs, _ptr(base), _ptr(out), _stream()))
+        return out
+
+    def zt_combine_outer(self, terms, ci, cj, base=None, out=None):
+        """out = base + sum_ij ci[i] cj[j] terms[i][j] mod t (terms: nested lists, n_i x n_j)."""
+        flat = [x for row in terms for x in row]
+        like = base if base is not None else flat[0]
+        for x in flat + ([base] if base is not None else []):
+            _need(x, "term")
+            if x.shape != like.shape:
+                raise ValueError("zt_combine_outer: shape mismatch")
+        out = torch.empty_like(like) if out is None else out
+        ni, nj = len(terms), len(terms[0]) if terms else 0
+        ptrs = (ctypes.c_void_p * max(ni * nj, 1))(*[x.data_ptr() for x in flat])
+        a = (ctypes.c_int64 * max(ni, 1))(*[int(c) for c in ci])
+        b = (ctypes.c_int64 * max(nj, 1))(*[int(c) for c in cj])
+        self._check(self.lib.pencil_zt_combine_outer(self.h, like.numel(), ni, nj, ptrs, a, b, _ptr(base), _ptr(out),
+                                                     _stream()))
         return out
 
     def bias_grad(self, layer, dy):
@@ -300,6 +317,32 @@ class Context:
         self._check(self.lib.pencil_bias_grad(self.h, ctypes.byref(layer_struct(layer)), _ptr(dy), _ptr(out),
                                               _stream()))
         return out
+
+    def zt_encode(self, x):
+        """float64 fixed-point integers -> int64 in [0, t) (round to nearest, mod t)."""
+        x = x.detach().contiguous()
+        _need(x, "x", torch.float64)
+        out = torch.empty(x.shape, dtype=torch.int64, device=x.device)
+        self._check(self.lib.pencil_zt_encode(self.h, x.numel(), _ptr(x), _ptr(out), _stream()))
+        return out
+
+    def zt_decode(self, v):
+        """int64 in [0, t) -> centred float64 representatives."""
+        v = v.contiguous()
+        _need(v, "v")
+        out = torch.empty(v.shape, dtype=torch.float64, device=v.device)
+        self._check(self.lib.pencil_zt_decode(self.h, v.numel(), _ptr(v), _ptr(out), _stream()))
+        return out
+
+    def zt_share(self, v, nonce, obj=0):
+        """Additive shares (s0 uniform over Z_t from the stream (nonce, obj), s1 = v - s0)."""
+        v = v.contiguous()
+        _need(v, "v")
+        s0 = torch.empty_like(v)
+        s1 = torch.empty_like(v)
+        self._check(self.lib.pencil_zt_share(self.h, v.numel(), _ptr(v), int(nonce) & ((1 << 64) - 1),
+                                             int(obj) & ((1 << 64) - 1), _ptr(s0), _ptr(s1), _stream()))
+        return s0, s1
 
     def dp_noise_(self, x, sd, nonce, obj):
         """In place: x + floor(sd * z) mod t with z standard normal draws of the stream (nonce, obj)."""

@@ -10,22 +10,14 @@ as the two encrypted cross terms of Alg. 2 plus the two parties' local terms,
 the bias gradient, and optionally the data owner's DP perturbation.
 
 Tensors carry fixed-point integers in float64 (autograd rejects integer
-dtypes; t < 2^53 keeps them exact) in centred form, (-t/2, t/2).  Every Z_t
-product runs in libpencil's HIP kernels; this module converts dtypes and
-draws the share and nonce randomness.
+dtypes; t < 2^53 keeps them exact) in centred form, (-t/2, t/2).  Every step
+runs in libpencil's HIP kernels -- the Z_t encoding and its centred view, the
+secret sharing, the products; this module sequences the calls and reserves
+the nonces.
 """
 import torch
 
-from .api import Context, _get, fresh_seed, stride_map
-
-
-def _to_zt(x, t):
-    v = torch.round(x).to(torch.int64)
-    return torch.remainder(v, t).contiguous()
-
-
-def _centred(v, t):
-    return torch.where(v > (t - 1) // 2, v - t, v).to(torch.float64)
+from .api import Context, _get, stride_map
 
 
 class EncryptedLinearEngine:
@@ -37,14 +29,12 @@ class EncryptedLinearEngine:
     owner's perturbation of its weight- and bias-gradient shares (Sec. III.B.2;
     0 = none)."""
 
-    def __init__(self, layer, ctx: Context, plan=None, seed=None, dp_sd_w=0.0, dp_sd_b=0.0):
+    def __init__(self, layer, ctx: Context, plan=None, dp_sd_w=0.0, dp_sd_b=0.0):
         self.layer = layer
         self.strided = int(_get(layer, "stride", 1)) > 1
         self.eq = stride_map(layer) if self.strided else layer
         self.ctx = ctx
         self.plan = ctx.plan_auto(self.eq) if plan is None else plan
-        self.gen = torch.Generator(device=ctx.device)
-        self.gen.manual_seed(fresh_seed() & ((1 << 63) - 1) if seed is None else seed)
         self.nonce = None  # the last nonce drawn
         self.dp_sd_w, self.dp_sd_b = float(dp_sd_w), float(dp_sd_b)
 
@@ -54,9 +44,8 @@ class EncryptedLinearEngine:
         return self.nonce
 
     def shares(self, v):
-        t = self.ctx.t
-        s0 = torch.randint(0, t, v.shape, generator=self.gen, device=v.device, dtype=torch.int64)
-        return s0, torch.remainder(v - s0, t)
+        """Additive shares of v over Z_t, from a fresh nonce of the context's seed."""
+        return self.ctx.zt_share(v, self.next_nonce())
 
     def to_eq(self, which, v):
         return self.ctx.stride_relayout(self.layer, which, v) if self.strided else v
@@ -68,9 +57,9 @@ class EncryptedLinearEngine:
 class EncryptedLinearFunction(torch.autograd.Function):
     @staticmethod
     def forward(fctx, x, w, b, engine):
-        c, L, t = engine.ctx, engine.eq, engine.ctx.t
-        X, W = _to_zt(x, t), _to_zt(w, t)
-        bz = _to_zt(b, t) if b is not None else None
+        c, L = engine.ctx, engine.eq
+        X, W = c.zt_encode(x), c.zt_encode(w)
+        bz = c.zt_encode(b) if b is not None else None
         x0, x1 = engine.shares(X)
         x0, x1, W = engine.to_eq("x", x0), engine.to_eq("x", x1), engine.to_eq("w", W)
         ct_x = c.encrypt(L, engine.plan, "x_fwd", x1, engine.next_nonce())
@@ -79,14 +68,14 @@ class EncryptedLinearFunction(torch.autograd.Function):
         fctx.engine = engine
         fctx.has_bias = b is not None
         fctx.save_for_backward(x0, x1, W)
-        return _centred(c.zt_combine([y0, y1], [1, 1]), t)
+        return c.zt_decode(c.zt_combine([y0, y1], [1, 1]))
 
     @staticmethod
     def backward(fctx, grad_y):
         engine = fctx.engine
-        c, L, t = engine.ctx, engine.eq, engine.ctx.t
+        c, L = engine.ctx, engine.eq
         x0, x1, W = fctx.saved_tensors
-        dY = _to_zt(grad_y, t)
+        dY = c.zt_encode(grad_y)
         dy0, dy1 = engine.shares(dY)
         n = engine.next_nonce()
         ct_dy_dx = c.encrypt(L, engine.plan, "dy_dx", dy1, n)
@@ -109,8 +98,8 @@ class EncryptedLinearFunction(torch.autograd.Function):
             db_do = c.bias_grad(L, dy1)
             if engine.dp_sd_b > 0:
                 c.dp_noise_(db_do, engine.dp_sd_b, dp_nonce, 1)
-            db = _centred(c.zt_combine([c.bias_grad(L, dy0)], [1], base=db_do), t)
-        return _centred(dX, t), _centred(dW, t), db, None
+            db = c.zt_decode(c.zt_combine([c.bias_grad(L, dy0)], [1], base=db_do))
+        return c.zt_decode(dX), c.zt_decode(dW), db, None
 
 
 def encrypted_linear(x, w, engine, b=None):

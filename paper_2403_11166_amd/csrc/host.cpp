@@ -634,9 +634,10 @@ static pencil_status get_geo(pencil_ctx* ctx, const pencil_layer* L, const penci
 // An NTT of one limb-polynomial costs (N/2) log2 N butterflies of ~1.4 units
 // each, a product 2 components per limb; both weights are calibrated on
 // MI355X step-kernel times (N = 8192: ~88 ns per limb transform, ~19 ns per
-// limb product).  Input ciphertexts arrive in the NTT domain: the MO
-// transforms only its share (component 0 of fwd and dx operands) and splits
-// and copies the rest, a copy of a polynomial costing ~0.36 of its transform.
+// limb product).  Input ciphertexts arrive in the NTT domain, split, and are
+// read in place: the MO transforms only its share for the fwd and dx operands
+// and stages component 0 with it added (the copy costing ~0.36 of a
+// transform).
 struct Cost {
   double ntt_polys, products;
 };
@@ -1108,15 +1109,46 @@ extern "C" pencil_status pencil_zt_linear(pencil_ctx* ctx, const pencil_layer* L
   return PENCIL_OK;
 }
 
+// A signed coefficient as a residue mod t.
+static uint64_t coeff_mod_t(int64_t c, uint64_t t) {
+  const int64_t r = c % (int64_t)t;
+  return (uint64_t)(r < 0 ? r + (int64_t)t : r);
+}
+
+static pencil_status zt_combine_reduced(pencil_ctx* ctx, int64_t count, int n_terms, const int64_t* const* terms,
+                                        const uint64_t* coeffs, const int64_t* base, int64_t* out, void* stream);
+
 extern "C" pencil_status pencil_zt_combine(pencil_ctx* ctx, int64_t count, int n_terms, const int64_t* const* terms,
-                                           const uint64_t* coeffs, const int64_t* base, int64_t* out, void* stream) {
+                                           const int64_t* coeffs, const int64_t* base, int64_t* out, void* stream) {
   if (!ctx) return PENCIL_EINVAL;
   if (count < 0 || n_terms < 0) return fail(ctx, PENCIL_EINVAL, "negative count or term count");
   if (n_terms > 0 && (!terms || !coeffs)) return fail(ctx, PENCIL_EINVAL, "terms or coeffs is NULL");
+  std::vector<uint64_t> c(n_terms);
+  for (int i = 0; i < n_terms; ++i) c[i] = coeff_mod_t(coeffs[i], ctx->C.t);
+  return zt_combine_reduced(ctx, count, n_terms, terms, c.data(), base, out, stream);
+}
+
+extern "C" pencil_status pencil_zt_combine_outer(pencil_ctx* ctx, int64_t count, int n_i, int n_j,
+                                                 const int64_t* const* terms, const int64_t* ci, const int64_t* cj,
+                                                 const int64_t* base, int64_t* out, void* stream) {
+  if (!ctx) return PENCIL_EINVAL;
+  if (count < 0 || n_i < 0 || n_j < 0 || (int64_t)n_i * n_j > (1 << 20))
+    return fail(ctx, PENCIL_EINVAL, "bad term counts");
+  const int n = n_i * n_j;
+  if (n > 0 && (!terms || !ci || !cj)) return fail(ctx, PENCIL_EINVAL, "terms or coefficients NULL");
+  const uint64_t t = ctx->C.t;
+  std::vector<uint64_t> c(n);
+  for (int i = 0; i < n_i; ++i)
+    for (int j = 0; j < n_j; ++j)
+      c[i * n_j + j] = (uint64_t)((u128)coeff_mod_t(ci[i], t) * coeff_mod_t(cj[j], t) % t);
+  return zt_combine_reduced(ctx, count, n, terms, c.data(), base, out, stream);
+}
+
+static pencil_status zt_combine_reduced(pencil_ctx* ctx, int64_t count, int n_terms, const int64_t* const* terms,
+                                        const uint64_t* coeffs, const int64_t* base, int64_t* out, void* stream) {
   TRY(check_ptr(ctx, out, "out"));
   for (int i = 0; i < n_terms; ++i) {
     TRY(check_ptr(ctx, terms[i], "terms[i]"));
-    if (coeffs[i] >= ctx->C.t) return fail(ctx, PENCIL_EINVAL, "coeffs[%d] not below t", i);
     if (terms[i] == out) return fail(ctx, PENCIL_EINVAL, "terms[%d] aliases out", i);
   }
   // chunks of kZtTerms terms; each later chunk adds onto the previous result
@@ -1134,6 +1166,47 @@ extern "C" pencil_status pencil_zt_combine(pencil_ctx* ctx, int64_t count, int n
     b = out;
     i += T.n;
   } while (i < n_terms);
+  return PENCIL_OK;
+}
+
+extern "C" pencil_status pencil_zt_encode(pencil_ctx* ctx, int64_t count, const double* x, int64_t* out,
+                                          void* stream) {
+  if (!ctx) return PENCIL_EINVAL;
+  if (count < 0) return fail(ctx, PENCIL_EINVAL, "count < 0");
+  if (count > 0) {
+    TRY(check_ptr(ctx, x, "x"));
+    TRY(check_ptr(ctx, out, "out"));
+  }
+  const hipError_t e = launch_zt_encode(x, out, count, ctx->C, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(ctx, PENCIL_EHIP, "encode launch: %s", hipGetErrorString(e));
+  return PENCIL_OK;
+}
+
+extern "C" pencil_status pencil_zt_decode(pencil_ctx* ctx, int64_t count, const int64_t* v, double* out,
+                                          void* stream) {
+  if (!ctx) return PENCIL_EINVAL;
+  if (count < 0) return fail(ctx, PENCIL_EINVAL, "count < 0");
+  if (count > 0) {
+    TRY(check_ptr(ctx, v, "v"));
+    TRY(check_ptr(ctx, out, "out"));
+  }
+  const hipError_t e = launch_zt_decode(v, out, count, ctx->C, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(ctx, PENCIL_EHIP, "decode launch: %s", hipGetErrorString(e));
+  return PENCIL_OK;
+}
+
+extern "C" pencil_status pencil_zt_share(pencil_ctx* ctx, int64_t count, const int64_t* v, uint64_t nonce,
+                                         uint64_t object, int64_t* s0, int64_t* s1, void* stream) {
+  if (!ctx) return PENCIL_EINVAL;
+  if (count < 0) return fail(ctx, PENCIL_EINVAL, "count < 0");
+  if (count > 0) {
+    TRY(check_ptr(ctx, v, "v"));
+    TRY(check_ptr(ctx, s0, "s0"));
+    TRY(check_ptr(ctx, s1, "s1"));
+    if (s0 == s1) return fail(ctx, PENCIL_EINVAL, "s0 and s1 alias");
+  }
+  const hipError_t e = launch_zt_share(v, s0, s1, count, nonce, object, ctx->C, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(ctx, PENCIL_EHIP, "share launch: %s", hipGetErrorString(e));
   return PENCIL_OK;
 }
 
@@ -1904,6 +1977,81 @@ extern "C" pencil_status pencil_autotune(pencil_ctx* ctx, const pencil_layer* L,
     }
   }
   return st;
+}
+
+// ------------------------------------------------------------ noise bound
+
+extern "C" pencil_status pencil_noise_bound(const pencil_params* params, const pencil_layer* L, const pencil_plan* P,
+                                            int op, uint32_t plaintext_bits, pencil_noise* out) {
+  if (!out || op < 0 || op > 2) return fail(nullptr, PENCIL_EINVAL, "bad noise-bound request");
+  if (plaintext_bits < 1 || plaintext_bits > 62) return fail(nullptr, PENCIL_EINVAL, "plaintext_bits outside [1, 62]");
+  pencil_ctx tmp;  // host-only: parameters and geometry, no device state
+  pencil_status st = resolve_params(params, &tmp);
+  if (st != PENCIL_OK) return st;
+  Geo G;
+  st = get_geo(&tmp, L, P, op, &G);
+  if (st != PENCIL_OK) {
+    g_create_err = tmp.err;
+    return st;
+  }
+  const double n = (double)tmp.C.n;
+  // nonzero coefficients of a plaintext polynomial: K tiles (weights, or dY for
+  // the weight gradient's term A) and, for the weight gradient's term B, A tiles
+  const double nnz_k = (double)G.rt * G.kt * G.kh * G.kw;
+  const double nnz_a = (double)G.mt * G.kt * G.ha * G.wa;
+  const double nnz = std::min(n, op == PENCIL_OP_DW ? std::max(nnz_k, nnz_a) : nnz_k);
+  const double terms = (double)G.nK * G.nKY * G.nKX * (op == PENCIL_OP_DW ? 2 : 1);
+  const double p = std::ldexp(1.0, (int)plaintext_bits - 1);
+  // input noise: CBD errors (|e| <= 21) times ternary u and s, plus e0, plus
+  // the two roundings of round(q m / t) (encryption, share add)
+  const double fresh = 42 * n + 23;
+  const double product = terms * nnz * p * fresh + (42 * n + 21);  // + re-randomisation
+  const double flood = std::ldexp(1.0, (int)tmp.C.flood_bits);
+  Big q{1};
+  for (int l = 0; l < tmp.C.L; ++l) q = big_mul_small(q, tmp.C.limb[l].q);
+  const Big delta = big_div_small(q, tmp.C.t);
+  double dd = 0;
+  for (size_t w = delta.size(); w-- > 0;) dd = dd * 18446744073709551616.0 + (double)delta[w];
+  out->product_bits = std::log2(product);
+  out->flood_bits = (double)tmp.C.flood_bits;
+  out->budget_bits = std::log2(dd / 2);
+  out->margin_bits = out->budget_bits - std::log2(product + flood);
+  out->smudge_bits = out->flood_bits - out->product_bits;
+  if (product + flood >= dd / 2)
+    return fail(nullptr, PENCIL_ENOISE,
+                "op %d: worst-case noise 2^%.1f (product 2^%.1f + flood 2^%.1f) reaches Delta/2 = 2^%.1f", op,
+                std::log2(product + flood), out->product_bits, out->flood_bits, out->budget_bits);
+  return PENCIL_OK;
+}
+
+// ------------------------------------------------------------ multiply probe
+
+extern "C" pencil_status pencil_probe_mul32(int kind, double* per_s) {
+  if (kind < 0 || kind > 2 || !per_s) return fail(nullptr, PENCIL_EINVAL, "probe kind %d invalid", kind);
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                              hipSuccess)
+    return fail(nullptr, PENCIL_EHIP, "no HIP device");
+  const int64_t threads = (int64_t)cus * 8 * 256;  // 8 waves per SIMD
+  const int iters = 4096;
+  uint64_t* out = nullptr;
+  if (hipMalloc(&out, threads * sizeof(uint64_t)) != hipSuccess) return fail(nullptr, PENCIL_ENOMEM, "probe buffer");
+  hipEvent_t a = nullptr, b = nullptr;
+  float ms = 0;
+  hipError_t e = hipEventCreate(&a);
+  if (e == hipSuccess) e = hipEventCreate(&b);
+  if (e == hipSuccess) e = launch_probe_mul(kind, out, threads, iters, nullptr);  // warm-up
+  if (e == hipSuccess) e = hipEventRecord(a, nullptr);
+  for (int r = 0; r < 5 && e == hipSuccess; ++r) e = launch_probe_mul(kind, out, threads, iters, nullptr);
+  if (e == hipSuccess) e = hipEventRecord(b, nullptr);
+  if (e == hipSuccess) e = hipEventSynchronize(b);
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+  if (a) hipEventDestroy(a);
+  if (b) hipEventDestroy(b);
+  hipFree(out);
+  if (e != hipSuccess || ms <= 0) return fail(nullptr, PENCIL_EHIP, "probe: %s", hipGetErrorString(e));
+  *per_s = 5.0 * (double)threads * iters * 8 / (ms * 1e-3);
+  return PENCIL_OK;
 }
 
 // ------------------------------------------------------------ profiling

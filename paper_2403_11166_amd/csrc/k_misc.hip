@@ -744,6 +744,110 @@ hipError_t launch_set_u64(uint64_t* p, uint64_t v, int add, hipStream_t s) {
   return hipGetLastError();
 }
 
+// ------------------------------------------------ fixed point and sharing
+// Fixed-point values carried in float64 (integers, |x| < 2^53) to Z_t: round to
+// nearest (ties to even), then reduce mod t.
+__global__ void __launch_bounds__(256) k_zt_encode(const double* __restrict__ x, int64_t* __restrict__ out,
+                                                   int64_t count, int64_t t) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  int64_t v = __double2ll_rn(gview(x)[i]) % t;
+  gview(out)[i] = v < 0 ? v + t : v;
+}
+
+// Z_t to the centred representative in float64: v - t above (t - 1) / 2.
+__global__ void __launch_bounds__(256) k_zt_decode(const int64_t* __restrict__ v, double* __restrict__ out,
+                                                   int64_t count, int64_t t) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const int64_t a = gview(v)[i];
+  gview(out)[i] = (double)(a > (t - 1) / 2 ? a - t : a);
+}
+
+// Additive shares over Z_t: s0 uniform (entry i from stream words 2i, 2i+1 of
+// (nonce, object, P_SHARE), a 128-bit integer reduced mod t), s1 = v - s0.
+// Each thread draws one Philox block, two entries.
+__global__ void __launch_bounds__(256) k_zt_share(const int64_t* __restrict__ v, int64_t* __restrict__ s0,
+                                                  int64_t* __restrict__ s1, int64_t count, uint64_t nonce,
+                                                  uint64_t obj, Consts C) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (2 * b >= count) return;
+  const U64x4 w = philox((uint64_t)b, obj, P_SHARE, 0, C.seed, nonce);
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int64_t i = 2 * b + h;
+    if (i >= count) break;
+    const uint64_t hi = reduce64(w.v[2 * h + 1], C.one_sh_t, C.t);
+    uint64_t r = mul_shoup(hi, C.r64t, C.r64t_sh, C.t) + reduce64(w.v[2 * h], C.one_sh_t, C.t);
+    if (r >= C.t) r -= C.t;
+    const uint64_t x = (uint64_t)gview(v)[i];
+    gview(s0)[i] = (int64_t)r;
+    gview(s1)[i] = (int64_t)(x >= r ? x - r : x + C.t - r);
+  }
+}
+
+hipError_t launch_zt_encode(const double* x, int64_t* out, int64_t count, const Consts& C, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zt_encode, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, x, out, count,
+                     (int64_t)C.t);
+  return hipGetLastError();
+}
+
+hipError_t launch_zt_decode(const int64_t* v, double* out, int64_t count, const Consts& C, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zt_decode, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, v, out, count,
+                     (int64_t)C.t);
+  return hipGetLastError();
+}
+
+hipError_t launch_zt_share(const int64_t* v, int64_t* s0, int64_t* s1, int64_t count, uint64_t nonce, uint64_t obj,
+                           const Consts& C, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  const int64_t pairs = (count + 1) / 2;
+  hipLaunchKernelGGL(k_zt_share, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, s, v, s0, s1, count, nonce,
+                     obj, C);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------ integer multiply probe
+// Issue rate of one 32-bit multiply form (the integer roofline's peak): each
+// thread runs 8 independent dependent chains of `iters` instructions.  Kind 0:
+// v_mad_u64_u32 (acc = lo32(acc) * a + acc), 1: v_mul_lo_u32, 2: v_mul_hi_u32.
+template <int KIND>
+__global__ void __launch_bounds__(256) k_probe_mul(uint64_t* out, uint32_t seed, int iters) {
+  const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t a[8];
+  uint64_t x[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    a[i] = (seed ^ (g * 8u + (uint32_t)i)) | 0x80000001u;
+    x[i] = a[i] * 0x9E3779B9u + (uint64_t)i;
+  }
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      if (KIND == 0) x[i] = (uint64_t)(uint32_t)x[i] * a[i] + x[i];
+      if (KIND == 1) x[i] = (uint32_t)x[i] * a[i];
+      if (KIND == 2) x[i] = __umulhi((uint32_t)x[i], a[i]);
+    }
+  }
+  uint64_t sum = 0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) sum ^= x[i];
+  out[g] = sum;
+}
+
+hipError_t launch_probe_mul(int kind, uint64_t* out, int64_t threads, int iters, hipStream_t s) {
+  const dim3 grid((unsigned)(threads / 256)), block(256);
+  switch (kind) {
+    case 0: hipLaunchKernelGGL(k_probe_mul<0>, grid, block, 0, s, out, 12345u, iters); break;
+    case 1: hipLaunchKernelGGL(k_probe_mul<1>, grid, block, 0, s, out, 12345u, iters); break;
+    case 2: hipLaunchKernelGGL(k_probe_mul<2>, grid, block, 0, s, out, 12345u, iters); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 // ------------------------------------------------ allocation-free scratch
 // The scratch memory of the allocation-free entry points: a file-scope device
 // array, so each GPU the library runs on holds its own copy from the moment

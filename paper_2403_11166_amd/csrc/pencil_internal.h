@@ -78,7 +78,7 @@ enum Purpose : uint32_t {
   P_SK = 1, P_PK_A = 2, P_PK_E = 3,
   P_ENC_U = 16, P_ENC_E0 = 17, P_ENC_E1 = 18,
   P_RR_U = 32, P_RR_E0 = 33, P_RR_E1 = 34, P_FLOOD = 35, P_MASK = 36,
-  P_DP = 48,
+  P_DP = 48, P_SHARE = 49,
 };
 constexpr uint64_t kKeygenNonce = ~0ull;
 
@@ -207,6 +207,17 @@ hipError_t launch_step_flood(int words, const StepPhase& P, int64_t blocks, hipS
 hipError_t launch_set_u64(uint64_t* p, uint64_t v, int add, hipStream_t s);
 hipError_t launch_keygen(uint64_t* s_ntt, int64_t* s_coeff, uint64_t* pk_coeff, uint64_t* pk_ntt,
                          const Consts& C, const Tables& T, hipStream_t s);
+
+// Fixed point (float64 integers <-> Z_t, centred) and additive sharing.
+hipError_t launch_zt_encode(const double* x, int64_t* out, int64_t count, const Consts& C, hipStream_t s);
+hipError_t launch_zt_decode(const int64_t* v, double* out, int64_t count, const Consts& C, hipStream_t s);
+hipError_t launch_zt_share(const int64_t* v, int64_t* s0, int64_t* s1, int64_t count, uint64_t nonce, uint64_t obj,
+                           const Consts& C, hipStream_t s);
+
+// Multiply probe: `threads` (a multiple of 256) threads, 8 chains of `iters`
+// instructions of kind 0 (v_mad_u64_u32), 1 (v_mul_lo_u32) or 2
+// (v_mul_hi_u32) each; out receives one word per thread.
+hipError_t launch_probe_mul(int kind, uint64_t* out, int64_t threads, int iters, hipStream_t s);
 
 // Scratch array of the allocation-free entry points (one per GPU, in the
 // library's code object): kScratchBytes, 256-byte aligned.  scratch_address

@@ -92,16 +92,12 @@ def online(ctx, layer, kind, u, v, u_masks, v_masks, share0, share1, k, l):
     correlation per operator instead of m + 1; the outputs are the same
     integers mod t, and the messages (u~, v~) and what each party uses are
     unchanged (both parties know k and l)."""
-    m = len(u_masks)
-    t = ctx.t
-    u_t = ctx.zt_combine(u_masks, [-int(c) for c in k], base=u)                  # MO -> DO
-    v_t = ctx.zt_combine(v_masks, [-int(c) for c in l], base=v)                  # DO -> MO
-    kl = [int(k[i]) * int(l[j]) % t for i in range(m) for j in range(m)]
+    neg_k, neg_l = [-int(c) for c in k], [-int(c) for c in l]
+    u_t = ctx.zt_combine(u_masks, neg_k, base=u)                                 # MO -> DO
+    v_t = ctx.zt_combine(v_masks, neg_l, base=v)                                 # DO -> MO
     # DO: sum_j l_j <u o v'_j>_1 = u~ o (sum_j l_j v'_j) + sum_ij k_i l_j <u'_i o v'_j>_1
-    v_l = ctx.zt_combine(v_masks, [int(c) for c in l])
-    out1 = ctx.zt_combine([share1[i][j] for i in range(m) for j in range(m)], kl,
-                          base=apply(ctx, layer, kind, u_t, v_l))
+    v_l = ctx.zt_combine(v_masks, l)
+    out1 = ctx.zt_combine_outer(share1, k, l, base=apply(ctx, layer, kind, u_t, v_l))
     # MO: u o v~ + sum_ij k_i l_j <u'_i o v'_j>_0
-    out0 = ctx.zt_combine([share0[i][j] for i in range(m) for j in range(m)], kl,
-                          base=apply(ctx, layer, kind, u, v_t))
+    out0 = ctx.zt_combine_outer(share0, k, l, base=apply(ctx, layer, kind, u, v_t))
     return out0, out1, u_t, v_t

@@ -44,6 +44,12 @@ hipError_t launch_keygen(uint64_t*, int64_t*, uint64_t*, uint64_t*, const Consts
 }
 hipError_t configure_lds_limits() { return hipSuccess; }
 hipError_t scratch_address(int, void**) { NODEV; }
+hipError_t launch_probe_mul(int, uint64_t*, int64_t, int, hipStream_t) { NODEV; }
+hipError_t launch_zt_encode(const double*, int64_t*, int64_t, const Consts&, hipStream_t) { NODEV; }
+hipError_t launch_zt_decode(const int64_t*, double*, int64_t, const Consts&, hipStream_t) { NODEV; }
+hipError_t launch_zt_share(const int64_t*, int64_t*, int64_t*, int64_t, uint64_t, uint64_t, const Consts&, hipStream_t) {
+  NODEV;
+}
 #undef NODEV
 }  // namespace pencil
 

@@ -25,7 +25,7 @@ def _engine(layer, seed):
     from paper_2403_11166_amd import Context
     from paper_2403_11166_amd.autograd import EncryptedLinearEngine
     ctx = Context(layer.log2_n, layer.num_limbs, layer.prime_bits, seed)
-    return EncryptedLinearEngine(layer, ctx, seed=seed)
+    return EncryptedLinearEngine(layer, ctx)
 
 
 LAYERS = [conv(4, 3, 5, 8, k=3, pad=1, log2_n=12, num_limbs=2, prime_bits=50),
@@ -164,7 +164,7 @@ def test_dp_noise_lands_on_weight_and_bias_gradients():
     layer = LAYERS[1]
     ctx = Context(layer.log2_n, layer.num_limbs, layer.prime_bits, 77)
     sd_w, sd_b = 2.0 ** 24 * 0.01, 2.0 ** 12 * 0.01
-    eng = EncryptedLinearEngine(layer, ctx, seed=77, dp_sd_w=sd_w, dp_sd_b=sd_b)
+    eng = EncryptedLinearEngine(layer, ctx, dp_sd_w=sd_w, dp_sd_b=sd_b)
     ts = layer_tensors(layer, 78)
     x = torch.tensor(centred_np(ts["X"]), dtype=torch.float64, device="cuda", requires_grad=True)
     w = torch.tensor(centred_np(ts["W"]), dtype=torch.float64, device="cuda", requires_grad=True)
@@ -205,7 +205,7 @@ def test_two_engines_on_one_context_draw_disjoint_randomness():
     ts = layer_tensors(layer, 92)
     outs = []
     for _ in range(2):
-        eng = EncryptedLinearEngine(layer, ctx, seed=5)   # equal share draws in both engines
+        eng = EncryptedLinearEngine(layer, ctx)
         x = torch.tensor(centred_np(ts["X"]), dtype=torch.float64, device="cuda")
         w = torch.tensor(centred_np(ts["W"]), dtype=torch.float64, device="cuda")
         outs.append(encrypted_linear(x, w, eng))

@@ -141,3 +141,19 @@ def test_uniform_flood_mask():
     m = S.mask_mod_t(2, 3, 4, 400, t)
     assert all(0 <= x < t for x in m)
     assert S.mask_mod_t(2, 3, 4, 400, t, [1, 399]) == [m[1], m[399]]
+
+
+def test_additive_shares():
+    """Shares of Sec. II.C: s0 from raw stream words (purpose P_SHARE), s0 + s1 = v
+    mod t, s0 spread over Z_t, and a different object gives a different draw."""
+    t = PR.T
+    rng = np.random.default_rng(3)
+    v = rng.integers(0, t, 5000, dtype=np.int64)
+    s0, s1 = S.shares_mod_t(7, 8, 9, v, t)
+    assert ((s0 >= 0) & (s0 < t) & (s1 >= 0) & (s1 < t)).all()
+    assert (np.mod(s0 + s1, t) == v).all()
+    w = PH.stream_words(7, 8, 9, S.P_SHARE, 0, 2 * 4321, 2)
+    assert int(s0[4321]) == (int(w[0]) + (int(w[1]) << 64)) % t
+    assert abs(s0.astype(np.float64).mean() / t - 0.5) < 0.02
+    other, _ = S.shares_mod_t(7, 8, 10, v, t)
+    assert not (other == s0).any()
