@@ -309,19 +309,24 @@ static pencil_status resolve_params(const pencil_params* p, pencil_ctx* ctx) {
   }
   // Multiply-accumulate headroom.  Operands are split into 30-bit halves
   // a = a0 + a1 2^30 with a1 <= amax = (q - 1) >> 30; one step adds at most
-  // 2 (2^30 - 1) amax to the cross-term partial sum, so mac_fold steps keep all
-  // three 64-bit partial sums in range.  A fold adds at most
-  // F = mac_fold * (q - 1)^2 to the 128-bit total, which holds mac_chunk folds
-  // on top of a reduced residue.
+  // 2 (2^30 - 1) amax to a cross-term partial sum holding both cross products,
+  // so mac_fold steps keep all three 64-bit partial sums in range; with the
+  // cross products in two sums, a step adds at most max((2^30 - 1)^2,
+  // (2^30 - 1) amax, amax^2) to each and mac_fold4 steps fit.  A fold adds at
+  // most F = max(mac_fold, mac_fold4) * (q - 1)^2 to the 128-bit total, which
+  // holds mac_chunk folds on top of a reduced residue.
   {
     uint64_t qmax = 0;
     for (int l = 0; l < C.L; ++l) qmax = std::max(qmax, C.limb[l].q);
     const u128 lo30 = (1u << 30) - 1, amax = (qmax - 1) >> 30;
     const u128 step_max = std::max(std::max(lo30 * lo30, 2 * lo30 * amax), amax * amax);
-    u128 fold = ((u128)~0ull) / step_max;
+    const u128 step_max4 = std::max(std::max(lo30 * lo30, lo30 * amax), amax * amax);
+    u128 fold = ((u128)~0ull) / step_max, fold4 = ((u128)~0ull) / step_max4;
     if (fold > 64) fold = 64;
+    if (fold4 > 64) fold4 = 64;
     C.mac_fold = (uint32_t)fold;
-    const u128 per_fold = fold * (u128)(qmax - 1) * (qmax - 1);
+    C.mac_fold4 = (uint32_t)fold4;
+    const u128 per_fold = std::max(fold, fold4) * (u128)(qmax - 1) * (qmax - 1);
     const u128 room = (~(u128)0) - qmax;
     u128 chunk = room / per_fold;
     if (chunk > 1024) chunk = 1024;

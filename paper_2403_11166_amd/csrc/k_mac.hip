@@ -365,38 +365,76 @@ __device__ __forceinline__ void mac_term_direct(const MacTerm& T, const MacArgs&
 // Direct loads, each wave a 2 x 2 block of (A row, K row) outputs for both
 // ciphertext components, with the 128-bit totals kept in LDS: each lane owns
 // its 16-byte words in a region private to its wave, so no barrier is needed,
-// and a wave holds only the three 64-bit partial sums per output in
-// registers (48 VGPRs for its 8 outputs instead of 80).
+// and a wave holds only the 64-bit partial sums of its 8 outputs in
+// registers.  With SPLIT the two cross products a0 b1 and a1 b0 go to
+// separate partial sums, so every partial sum gains one product below 2^60 per
+// step and a fold is due every mac_fold4 steps (16 for 60-bit primes) instead
+// of every mac_fold (8): fewer folds for 16 more registers, which the batched
+// step's kernel can spend and the per-call kernel (whose by-value arguments
+// hold more scalar registers) cannot without losing occupancy.
+template <bool SPLIT>
 struct Part {
-  uint64_t s0, s1, s2;  // partial sums of a0 b0, a0 b1 + a1 b0, a1 b1
+  uint64_t s0, s1, s1b, s2;  // partial sums of a0 b0, a0 b1 (+ a1 b0 unless SPLIT), a1 b0, a1 b1
+};
+template <>
+struct Part<false> {
+  uint64_t s0, s1, s2;
 };
 
-__device__ __forceinline__ void part_mac(Part& x, uint64_t a, uint64_t b) {
+template <bool SPLIT>
+__device__ __forceinline__ void part_mac(Part<SPLIT>& x, uint64_t a, uint64_t b) {
   const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32), b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
   x.s0 += (uint64_t)a0 * b0;
   x.s1 += (uint64_t)a0 * b1;
-  asm volatile("" : "+v"(x.s1));
-  x.s1 += (uint64_t)a1 * b0;
+  if constexpr (SPLIT) {
+    x.s1b += (uint64_t)a1 * b0;
+  } else {
+    // two multiply-adds into s1 (summing the products first would cost a 64-bit add)
+    asm volatile("" : "+v"(x.s1));
+    x.s1 += (uint64_t)a1 * b0;
+  }
   x.s2 += (uint64_t)a1 * b1;
 }
 
-// (lo, hi) += s0 + s1 2^30 + s2 2^60; the partial sums restart at zero.
-__device__ __forceinline__ void part_fold(Part& x, uint64_t& lo, uint64_t& hi) {
-  const uint64_t t1 = x.s1 << 30, t2 = x.s2 << 60;
-  uint64_t l = lo + x.s0;
-  uint64_t c = l < x.s0 ? 1 : 0;
-  l += t1;
-  c += l < t1 ? 1 : 0;
-  l += t2;
-  c += l < t2 ? 1 : 0;
-  hi += c + (x.s1 >> 34) + (x.s2 >> 4);
-  lo = l;
+// (w0, w1, w2, w3) += (a0, a1, a2, a3) as 128-bit integers of 32-bit words
+// (a carry chain; the total never wraps).
+__device__ __forceinline__ void add128w(uint32_t& w0, uint32_t& w1, uint32_t& w2, uint32_t& w3, uint32_t a0,
+                                        uint32_t a1, uint32_t a2, uint32_t a3) {
+  unsigned c;
+  w0 = __builtin_addc(w0, a0, 0u, &c);
+  w1 = __builtin_addc(w1, a1, c, &c);
+  w2 = __builtin_addc(w2, a2, c, &c);
+  w3 = w3 + a3 + c;
+}
+
+// (lo, hi) += s0 + (s1 [+ s1b]) 2^30 + s2 2^60; the partial sums restart at
+// zero.  s1 2^30 is (s1 << 30) below 2^64 and s1 >> 34 above; s2 2^60 is
+// (s2 mod 16) << 60 below and s2 >> 4 above.
+template <bool SPLIT>
+__device__ __forceinline__ void part_fold(Part<SPLIT>& x, uint64_t& lo, uint64_t& hi) {
+  uint32_t w0 = (uint32_t)lo, w1 = (uint32_t)(lo >> 32), w2 = (uint32_t)hi, w3 = (uint32_t)(hi >> 32);
+  add128w(w0, w1, w2, w3, (uint32_t)x.s0, (uint32_t)(x.s0 >> 32), 0, 0);
+  const uint64_t t1 = x.s1 << 30;
+  add128w(w0, w1, w2, w3, (uint32_t)t1, (uint32_t)(t1 >> 32), (uint32_t)(x.s1 >> 34), 0);
+  if constexpr (SPLIT) {
+    const uint64_t t1b = x.s1b << 30;
+    add128w(w0, w1, w2, w3, (uint32_t)t1b, (uint32_t)(t1b >> 32), (uint32_t)(x.s1b >> 34), 0);
+    x.s1b = 0;
+  }
+  const uint64_t u2 = x.s2 >> 4;
+  unsigned c;
+  w1 = __builtin_addc(w1, (uint32_t)x.s2 << 28, 0u, &c);
+  w2 = __builtin_addc(w2, (uint32_t)u2, c, &c);
+  w3 = w3 + (uint32_t)(u2 >> 32) + c;
+  lo = ((uint64_t)w1 << 32) | w0;
+  hi = ((uint64_t)w3 << 32) | w2;
   x.s0 = x.s1 = x.s2 = 0;
 }
 
 // Fold all 8 partial sums into their LDS totals; at fold f of each period of
 // mac_chunk folds, total f (if any) is also Barrett-reduced.
-__device__ __forceinline__ void fold_lds(Part (&acc)[8], u64x2* tot, uint32_t& nfold, uint32_t reduce_every,
+template <bool SPLIT>
+__device__ __forceinline__ void fold_lds(Part<SPLIT> (&acc)[8], u64x2* tot, uint32_t& nfold, uint32_t reduce_every,
                                          const LimbConst& lc) {
   const uint32_t f = nfold;
   nfold = f + 1 == reduce_every ? 0 : f + 1;
@@ -429,9 +467,9 @@ __device__ __forceinline__ uint64_t ld(const char* base, uint32_t off) {
 // contraction; the ciphertext side supplies both components (component 1 at
 // c1 elements), the plaintext side one value for both.  Row and column
 // pointers are wave-uniform (scalar registers); each lane adds its slot.
-template <bool A_CT>
+template <bool A_CT, bool SPLIT>
 __device__ __forceinline__ void mac_term_v2(const MacTerm& T, const MacArgs& A, const Geo& G, const Consts& C,
-                                            const LimbConst& lc, MacBlock& B, Part (&acc)[8], u64x2* tot) {
+                                            const LimbConst& lc, MacBlock& B, Part<SPLIT> (&acc)[8], u64x2* tot) {
   const int sp = G.nOY * G.nOX, kspan = G.nKY * G.nKX;
   const int ksteps = G.nK * kspan;
   const int64_t sa_str = (A_CT ? B.ct_stride : B.pt_stride) * 8, sk_str = (A_CT ? B.pt_stride : B.ct_stride) * 8;
@@ -453,22 +491,27 @@ __device__ __forceinline__ void mac_term_v2(const MacTerm& T, const MacArgs& A, 
     pk[c2] = uni((const char*)(T.k + B.ln) + (int64_t)col * ksteps * sk_str);
   }
   const int64_t a_wrap = ((int64_t)(sp - 1) * kspan + 1) * sa_str;
-  const uint32_t fold_every = C.mac_fold, reduce_every = C.mac_chunk;
+  const uint32_t fold_every = SPLIT ? C.mac_fold4 : C.mac_fold, reduce_every = C.mac_chunk;
   int kk = 0, left = ksteps;
   struct Ops {
     uint64_t ct[2][2], pt[2];
   };
   auto load = [&](Ops& o) {
+    // a copy of the lane offset made in this step, so that the loads below see
+    // its zero-extension and take the scalar-base form (one register move
+    // instead of a 64-bit address add per load)
+    uint32_t off = lane;
+    asm volatile("" : "+v"(off));
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       if (A_CT) {
-        o.ct[i][0] = ld(pa[i], lane);
-        o.ct[i][1] = ld(pa[i] + c1, lane);
-        o.pt[i] = ld(pk[i], lane);
+        o.ct[i][0] = ld(pa[i], off);
+        o.ct[i][1] = ld(pa[i] + c1, off);
+        o.pt[i] = ld(pk[i], off);
       } else {
-        o.pt[i] = ld(pa[i], lane);
-        o.ct[i][0] = ld(pk[i], lane);
-        o.ct[i][1] = ld(pk[i] + c1, lane);
+        o.pt[i] = ld(pa[i], off);
+        o.ct[i][0] = ld(pk[i], off);
+        o.ct[i][1] = ld(pk[i] + c1, off);
       }
     }
     const bool adv = --left > 0;
@@ -511,7 +554,7 @@ __device__ __forceinline__ void mac_term_v2(const MacTerm& T, const MacArgs& A, 
   }
 }
 
-template <int ROWS, int COLS>
+template <int ROWS, int COLS, bool SPLIT>
 __device__ __forceinline__ void do_mac_v2(u64x2* lds, const MacArgs& A, const Geo& G, const Consts& C,
                                           int slot_block, int chunk) {
   constexpr int WC = COLS / 2;
@@ -538,13 +581,13 @@ __device__ __forceinline__ void do_mac_v2(u64x2* lds, const MacArgs& A, const Ge
   u64x2* tot = lds + B.grp * 8 * kMacSlots + B.s;  // this lane's 8 totals, stride kMacSlots
 #pragma unroll
   for (int i = 0; i < 8; ++i) tot[i * kMacSlots] = u64x2{0, 0};
-  Part acc[8];
+  Part<SPLIT> acc[8];
 #pragma unroll
-  for (int i = 0; i < 8; ++i) acc[i] = Part{0, 0, 0};
+  for (int i = 0; i < 8; ++i) acc[i] = Part<SPLIT>{};
   // term 0 has the ciphertext on the A side (forward, input gradient, the
   // weight gradient's term A); the weight gradient's term B has it on the K side
-  mac_term_v2<true>(A.term[0], A, G, C, lc, B, acc, tot);
-  if (A.n_terms > 1) mac_term_v2<false>(A.term[1], A, G, C, lc, B, acc, tot);
+  mac_term_v2<true, SPLIT>(A.term[0], A, G, C, lc, B, acc, tot);
+  if (A.n_terms > 1) mac_term_v2<false, SPLIT>(A.term[1], A, G, C, lc, B, acc, tot);
   // re-randomisation term pk_c * u'_o, reduction and store
   const int64_t ln = B.ln, pt_stride = B.pt_stride, ct_stride = B.ct_stride;
   const int s = B.s, sp = G.nOY * G.nOX;
@@ -566,8 +609,8 @@ __device__ __forceinline__ void do_mac_v2(u64x2* lds, const MacArgs& A, const Ge
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
         const int i = (a * 2 + b) * 2 + c;
-        Part& x = acc[i];
-        part_mac(x, c ? pk1 : pk0, u);  // one more step: the partial sums hold fewer than mac_fold
+        Part<SPLIT>& x = acc[i];
+        part_mac(x, c ? pk1 : pk0, u);  // one more step: the partial sums hold fewer than a fold's steps
         const u64x2 t = tot[i * kMacSlots];
         uint64_t lo = t[0], hi = t[1];
         part_fold(x, lo, hi);
@@ -604,19 +647,20 @@ __global__ void __launch_bounds__(512) k_mac_lds(MacArgs A, Geo G, Consts C, int
 }
 
 // Kind 1 through do_mac_v2: 2 x 2 wave blocks, both components, totals in LDS.
+template <bool SPLIT>
 __device__ __forceinline__ void do_mac_kind1(u64x2* tot, const MacArgs& A, const Geo& G, const Consts& C, int w,
                                              int chunks) {
   switch (A.variant % 3) {
-    case 1: do_mac_v2<2, 16>(tot, A, G, C, w / chunks, w % chunks); break;
-    case 2: do_mac_v2<8, 4>(tot, A, G, C, w / chunks, w % chunks); break;
-    default: do_mac_v2<4, 8>(tot, A, G, C, w / chunks, w % chunks); break;
+    case 1: do_mac_v2<2, 16, SPLIT>(tot, A, G, C, w / chunks, w % chunks); break;
+    case 2: do_mac_v2<8, 4, SPLIT>(tot, A, G, C, w / chunks, w % chunks); break;
+    default: do_mac_v2<4, 8, SPLIT>(tot, A, G, C, w / chunks, w % chunks); break;
   }
 }
 
 __global__ void __launch_bounds__(512) k_mac_direct(MacArgs A, Geo G, Consts C, int chunks, int64_t total) {
   __shared__ u64x2 tot[kMacV2Lds];
   const int w = (int)xcd_work(blockIdx.x, total);
-  do_mac_kind1(tot, A, G, C, w, chunks);
+  do_mac_kind1<false>(tot, A, G, C, w, chunks);
 }
 
 __global__ void __launch_bounds__(512) k_mac_direct_small(MacArgs A, Geo G, Consts C, int chunks, int64_t total) {
@@ -645,7 +689,7 @@ __global__ void __launch_bounds__(512) k_step_mac(STEP_ARGS) {
   step_mac<0>(segs, nseg, consts, smem);
 }
 
-__global__ void __launch_bounds__(512) k_step_mac_direct(STEP_ARGS) {
+__global__ void __launch_bounds__(512, 4) k_step_mac_direct(STEP_ARGS) {
   __shared__ u64x2 tot[kMacV2Lds];
   const StepSeg& S = segs[find_seg(segs, nseg, blockIdx.x)];
   const int64_t local = (int64_t)blockIdx.x - S.block_begin;
@@ -653,7 +697,7 @@ __global__ void __launch_bounds__(512) k_step_mac_direct(STEP_ARGS) {
   const int64_t work = S.slot_blocks * chunks, padded = (work + 7) & ~(int64_t)7;
   const int w = (int)xcd_work(local, padded);  // work items per launch stay below 2^31
   if (w >= work) return;
-  do_mac_kind1(tot, S.mac, S.G, consts[S.ctx], w, chunks);
+  do_mac_kind1<true>(tot, S.mac, S.G, consts[S.ctx], w, chunks);
 }
 
 __global__ void __launch_bounds__(512) k_step_mac_direct_small(STEP_ARGS) {

@@ -27,7 +27,7 @@ struct Consts {
   int32_t log2n, n, L, flood_words;
   uint32_t flood_bits, mac_chunk, qwords;
   int32_t ntt_loge;              // log2 of the residues each NTT thread keeps (4 or 5)
-  uint32_t mac_fold, pad1;       // MAC steps per fold of the 64-bit partial sums
+  uint32_t mac_fold, mac_fold4;  // MAC steps per fold of the 64-bit partial sums (three, four sums)
   uint64_t t, t_half;            // t and (t - 1) / 2
   uint64_t rho, rho_sh;          // q mod t, floor(rho * 2^64 / t)
   uint64_t r64t, r64t_sh;        // 2^64 mod t and floor(r64t * 2^64 / t)
