@@ -279,6 +279,17 @@ static pencil_status resolve_params(const pencil_params* p, pencil_ctx* ctx) {
   C.seed = p->seed;
   for (int l = 0; l < C.L; ++l) {
     const uint64_t ql = I.primes[l];
+    {
+      // the forward transform's final reduction folds the bits above the
+      // modulus' bit length B with delta = 2^B - q (one conditional
+      // subtraction left), which needs delta < 2^32 and 2^B + 15 delta < 2q
+      int b = 0;
+      while (b < 64 && (ql >> b) != 0) ++b;
+      const u128 top = (u128)1 << b, delta = top - ql;
+      if (delta >> 32 || top + 15 * delta >= 2 * (u128)ql)
+        return fail(nullptr, PENCIL_EUNSUPPORTED, "modulus %llu too far below a power of two",
+                    (unsigned long long)ql);
+    }
     LimbConst& lc = C.limb[l];
     lc.q = ql;
     lc.r64 = (uint64_t)(((u128)1 << 64) % ql);

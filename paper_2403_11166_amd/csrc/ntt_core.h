@@ -33,18 +33,20 @@ constexpr int ntt_threads(int logn, int loge) { return (1 << logn) >> loge; }
 constexpr int ntt_min_waves(int logn, int loge) { return ntt_threads(logn, loge) > 512 || loge < 5 ? 4 : 2; }
 #define PENCIL_NTT_BOUNDS(LOGN, LOGE) __launch_bounds__(ntt_threads(LOGN, LOGE), ntt_min_waves(LOGN, LOGE))
 
-// Butterfly constants of one modulus q < 2^60: 8q, 4q (and 2^64 minus each),
-// 4q + 1, and 2q, 2^64 - 2q, 2^64 - q for the final reduction.  They are
-// hidden from the optimiser so that x - 4q stays the single 64-bit addition
-// x + (2^64 - 4q) instead of a borrow chain.
+// Butterfly constants of one modulus q < 2^60: 8q, 4q and 2^64 minus each,
+// 2^64 - q, and for the final reduction the bit length B of q (q < 2^B), 2^B - 1
+// and delta = 2^B - q.  They are hidden from the optimiser so that x - 4q stays
+// the single 64-bit addition x + (2^64 - 4q) instead of a borrow chain.
 struct BflyK {
-  uint64_t q8, nq8, q4, nq4, q4p1, q2, nq2, nq;
+  uint64_t q8, nq8, q4, nq4, nq, top_mask;
+  uint32_t top_bits, top_delta;
 };
 
 __device__ __forceinline__ BflyK bfly_consts(uint64_t q) {
-  BflyK k{8 * q, 0 - 8 * q, 4 * q, 0 - 4 * q, 4 * q + 1, 2 * q, 0 - 2 * q, 0 - q};
-  asm volatile("" : "+s"(k.q8), "+s"(k.nq8), "+s"(k.q4), "+s"(k.nq4), "+s"(k.q4p1), "+s"(k.q2), "+s"(k.nq2),
-               "+s"(k.nq));
+  const uint32_t b = 64 - (uint32_t)__builtin_clzll(q);
+  BflyK k{8 * q, 0 - 8 * q, 4 * q, 0 - 4 * q, 0 - q, (1ull << b) - 1, b, (uint32_t)((1ull << b) - q)};
+  asm volatile("" : "+s"(k.q8), "+s"(k.nq8), "+s"(k.q4), "+s"(k.nq4), "+s"(k.nq), "+s"(k.top_mask),
+               "+s"(k.top_bits), "+s"(k.top_delta));
   return k;
 }
 
@@ -72,22 +74,32 @@ __device__ __forceinline__ uint64_t shoup_lazy(uint64_t y, const TW w, const Bfl
 }
 
 // Lazy Cooley-Tukey butterfly, reducing x on every other stage (`reduce` is
-// a compile-time constant after unrolling).  With reduce, x and y in [0, 16q) give a = x mod 8q in [0, 8q) and outputs in
-// [0, 12q); without, inputs in [0, 12q) give outputs in [0, 16q).  The Shoup
-// product t is below 4q for any y, and 16q < 2^64 for q < 2^60.
+// a compile-time constant after unrolling).  With reduce, x and y in [0, 16q)
+// give a = x mod 8q in [0, 8q) and outputs in [0, 12q); without, inputs in
+// [0, 12q) give outputs in [0, 16q).  The Shoup product t is below 4q for any
+// y, and 16q < 2^64 for q < 2^60.
 __device__ __forceinline__ void ct_bfly(uint64_t& x, uint64_t& y, const TW w, const BflyK& k, const bool reduce) {
   const uint64_t a = reduce ? csub(x, k.q8, k.nq8) : x;
   const uint64_t t = shoup_lazy(y, w, k);
   x = a + t;
-  y = (a + k.q4p1) + ~t;  // a - t + 4q
+  y = (a + k.q4) - t;
 }
 
 // Lazy Gentleman-Sande butterfly: u, v in [0, 4q) -> [0, 4q).
 __device__ __forceinline__ void gs_bfly(uint64_t& u, uint64_t& v, const TW w, const BflyK& k) {
   const uint64_t s = csub(u + v, k.q4, k.nq4);
-  const uint64_t d = (u + k.q4p1) + ~v;  // u - v + 4q
+  const uint64_t d = (u + k.q4) - v;
   v = shoup_lazy(d, w, k);
   u = s;
+}
+
+// x in [0, 16q) -> x mod q.  With x = h 2^B + r (r < 2^B, h < 16),
+// x = r + h delta (mod q), and r + h delta < 2^B + 15 delta < 2q because the
+// moduli lie within 2^B / 17 of 2^B (checked when the context is made).
+__device__ __forceinline__ uint64_t reduce_16q(uint64_t x, uint64_t q, const BflyK& k) {
+  const uint32_t h = (uint32_t)(x >> k.top_bits);
+  const uint64_t y = (uint64_t)h * k.top_delta + (x & k.top_mask);
+  return csub(y, q, k.nq);
 }
 
 // Forward (merged negacyclic Cooley-Tukey, psi^rev twiddles; natural order in,
@@ -132,12 +144,7 @@ __device__ __forceinline__ void fwd_pass(uint64_t* a, const PENCIL_GLOBAL TW* tw
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       uint64_t x = v[r * K + k];
-      if (LAST) {  // [0, 16q) -> [0, q)
-        x = csub(x, bk.q8, bk.nq8);
-        x = csub(x, bk.q4, bk.nq4);
-        x = csub(x, bk.q2, bk.nq2);
-        x = csub(x, q, bk.nq);
-      }
+      if (LAST) x = reduce_16q(x, q, bk);
       a[lpad(base + (k << LT))] = x;
     }
   }

@@ -115,3 +115,23 @@ def test_bound_dominates_the_oracles_measured_noise():
         for slot, (mm, rr, yy, xx) in E.out_slots(g, tile, mi, ri, oyi, oxi):
             E.to_virtual_out(layer, "fwd", y1)[mm, rr, yy, xx] = dec[slot]
     assert ((y0 + y1) % t == LN.layer_op(layer, "fwd", X, W, t)).all()
+
+
+def test_every_parameter_set_admits_the_short_final_reduction():
+    """The forward transform's final reduction takes x in [0, 16q) to x mod q by
+    folding the bits above the modulus' bit length B (delta = 2^B - q), which
+    needs delta < 2^32 and 2^B + 15 delta < 2q; every parameter set the library
+    accepts meets it (a context refuses moduli that do not)."""
+    A, lib = _lib()
+    layer = fc(8, 4, 2, log2_n=10, num_limbs=1, prime_bits=60)
+    plan = _plan(A, lib, layer)
+    checked = 0
+    for bits in range(40, 61):
+        for log2_n in range(10, 15):
+            for limbs in (1, 2, 3, 4):
+                st, _ = _bound(A, lib, _params(A, log2_n, limbs, bits), layer, plan, 0, 8)
+                # other refusals (q below t, no noise budget) are about t, not the moduli
+                msg = lib.pencil_last_error(None) or b""
+                assert st in (A.PENCIL_OK, A.PENCIL_ENOISE) or b"power of two" not in msg, (bits, log2_n, limbs)
+                checked += st in (A.PENCIL_OK, A.PENCIL_ENOISE)
+    assert checked >= 50
