@@ -119,6 +119,29 @@ __device__ __forceinline__ int64_t k_slot_at(const Geo& G, const View& V, const 
   return r * V.s0 + k * V.s1 + a * V.sy + b * V.sx;
 }
 
+// Entry e of a reverse-encoded K tile, e = ((rr kt + kk) kh + dy) kw + dx over
+// rr < rt, kk < kt, dy < kh, dx < kw (every K-tile slot that k_slot_at maps
+// to the tensor is one such entry, and each entry has one slot): its slot
+// O + rr S - (kk ha wa + dy wa + dx) and the tensor offset of its value, or
+// -1 for an entry past the tensor (a ragged tile).
+__device__ __forceinline__ int64_t k_entry_at(const Geo& G, const View& V, const TileOrigin& T, int e, int& slot) {
+  const int thw = G.kt * G.kh * G.kw, hw = G.kh * G.kw;
+  const int rr = fdiv(e, G.dv_kthw);
+  const int rem = e - rr * thw;
+  const int kk = fdiv(rem, G.dv_khw);
+  const int rem2 = rem - kk * hw;
+  const int dy = fdiv(rem2, G.dv_kw), dx = rem2 - dy * G.kw;
+  slot = G.O + rr * G.S - (kk * G.ha * G.wa + dy * G.wa + dx);
+  const int r = T.i0 + rr, k = T.i1 + kk;
+  int a = T.y + dy, b = T.x + dx;
+  if (r >= G.R || k >= G.K || a >= G.KH || b >= G.KW) return -1;
+  if (V.flip) {
+    a = V.KH - 1 - a;
+    b = V.KW - 1 - b;
+  }
+  return r * V.s0 + k * V.s1 + a * V.sy + b * V.sx;
+}
+
 __device__ __forceinline__ int64_t slot_at(int side, const Geo& G, const View& V, const TileOrigin& T, int slot) {
   return side == 0 ? a_slot_at(G, V, T, slot) : k_slot_at(G, V, T, slot);
 }

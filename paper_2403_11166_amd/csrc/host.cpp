@@ -573,6 +573,9 @@ static bool make_geo(const OpGeom& g, const pencil_tile& t, int n, Geo* G) {
   o.dv_hw = recip((int64_t)o.ha * o.wa);
   o.dv_wa = recip(o.wa);
   o.dv_s = recip(o.S);
+  o.dv_kw = recip(o.kw);
+  o.dv_khw = recip((int64_t)o.kh * o.kw);
+  o.dv_kthw = recip((int64_t)o.kt * o.kh * o.kw);
   return true;
 }
 

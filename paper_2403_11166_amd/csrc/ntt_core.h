@@ -106,8 +106,11 @@ __device__ __forceinline__ uint64_t reduce_16q(uint64_t x, uint64_t q, const Bfl
 // bit-reversed out) stages S0 .. S0+S-1.  At stage l (t = N >> (l+1)) the pair
 // (i0, i0 + t) of group i = i0 >> (log2 N - l) uses tw[2^l + i].  A thread takes
 // E / 2^S groups of 2^S residues {base + k * 2^LT}, LT = log2 N - S0 - S.
-template <int LOGN, int LOGE, int S0, int S, bool LAST>
-__device__ __forceinline__ void fwd_pass(uint64_t* a, const PENCIL_GLOBAL TW* tw, uint64_t q, const BflyK& bk) {
+// `in(i)` supplies input residue i: the LDS polynomial, or for the first pass
+// values the caller computes (an encoding), which then skip the LDS.
+template <int LOGN, int LOGE, int S0, int S, bool LAST, typename In>
+__device__ __forceinline__ void fwd_pass(uint64_t* a, In in, const PENCIL_GLOBAL TW* tw, uint64_t q,
+                                         const BflyK& bk) {
   using Sh = NttShape<LOGN, LOGE>;
   constexpr int T = Sh::T, G = Sh::E >> S, K = 1 << S, LT = LOGN - S0 - S;
   const int tid = threadIdx.x;
@@ -117,7 +120,7 @@ __device__ __forceinline__ void fwd_pass(uint64_t* a, const PENCIL_GLOBAL TW* tw
     const int g = r * T + tid;
     const int base = ((g >> LT) << (LOGN - S0)) + (g & ((1 << LT) - 1));
 #pragma unroll
-    for (int k = 0; k < K; ++k) v[r * K + k] = a[lpad(base + (k << LT))];
+    for (int k = 0; k < K; ++k) v[r * K + k] = in(base + (k << LT));
   }
 #pragma unroll
   for (int s = 0; s < S; ++s) {
@@ -194,27 +197,37 @@ __device__ __forceinline__ void inv_pass(uint64_t* a, const PENCIL_GLOBAL TW* tw
   }
 }
 
+// Forward transform into the LDS polynomial `a` (outputs in [0, q)) of the
+// inputs in [0, q) that `in(i)` supplies to the first pass; the transform's
+// first LDS access is the first pass' store, so `a` must not be in use.
+// Callers synchronise after (outputs read).
+template <int LOGN, int LOGE, typename In>
+__device__ __forceinline__ void ntt_fwd_in(uint64_t* a, In in, const TW* tw_generic, uint64_t q) {
+  using Sh = NttShape<LOGN, LOGE>;
+  const BflyK bk = bfly_consts(q);
+  const PENCIL_GLOBAL TW* tw = gview(tw_generic);
+  auto lds = [a](int i) { return a[lpad(i)]; };
+  fwd_pass<LOGN, LOGE, Sh::start(0), Sh::size(0), Sh::NP == 1>(a, in, tw, q, bk);
+  __syncthreads();
+  if constexpr (Sh::NP > 1) {
+    fwd_pass<LOGN, LOGE, Sh::start(1), Sh::size(1), Sh::NP == 2>(a, lds, tw, q, bk);
+    __syncthreads();
+  }
+  if constexpr (Sh::NP > 2) {
+    fwd_pass<LOGN, LOGE, Sh::start(2), Sh::size(2), Sh::NP == 3>(a, lds, tw, q, bk);
+    __syncthreads();
+  }
+  if constexpr (Sh::NP > 3) {
+    fwd_pass<LOGN, LOGE, Sh::start(3), Sh::size(3), true>(a, lds, tw, q, bk);
+    __syncthreads();
+  }
+}
+
 // Forward transform of the LDS polynomial (inputs in [0, q), outputs in [0, q)).
 // Callers synchronise before (inputs written) and after (outputs read).
 template <int LOGN, int LOGE>
 __device__ __forceinline__ void ntt_fwd(uint64_t* a, const TW* tw_generic, uint64_t q) {
-  using Sh = NttShape<LOGN, LOGE>;
-  const BflyK bk = bfly_consts(q);
-  const PENCIL_GLOBAL TW* tw = gview(tw_generic);
-  fwd_pass<LOGN, LOGE, Sh::start(0), Sh::size(0), Sh::NP == 1>(a, tw, q, bk);
-  __syncthreads();
-  if constexpr (Sh::NP > 1) {
-    fwd_pass<LOGN, LOGE, Sh::start(1), Sh::size(1), Sh::NP == 2>(a, tw, q, bk);
-    __syncthreads();
-  }
-  if constexpr (Sh::NP > 2) {
-    fwd_pass<LOGN, LOGE, Sh::start(2), Sh::size(2), Sh::NP == 3>(a, tw, q, bk);
-    __syncthreads();
-  }
-  if constexpr (Sh::NP > 3) {
-    fwd_pass<LOGN, LOGE, Sh::start(3), Sh::size(3), true>(a, tw, q, bk);
-    __syncthreads();
-  }
+  ntt_fwd_in<LOGN, LOGE>(a, [a](int i) { return a[lpad(i)]; }, tw_generic, q);
 }
 
 // Inverse transform without the N^-1 factor (inputs in [0, 4q), outputs in [0, 4q)).
@@ -285,17 +298,16 @@ __device__ __forceinline__ void do_ntt_ct(uint64_t* lds, const uint64_t* src, ui
   const LimbConst& lc = C.limb[l];
   const PENCIL_GLOBAL int64_t* gshare = gview(share);
   const TileOrigin to = a_tile_origin(G, j);
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+  auto enc = [&](int i) {
     uint64_t v = 0;
     const int64_t off = a_slot_at(G, V, to, i);
     if (off >= 0) {
       const uint64_t m = (uint64_t)gshare[off];
       v = delta_scale(m, round_rho(m, C), lc);
     }
-    lds[lpad(i)] = v;
-  }
-  __syncthreads();
-  ntt_fwd<LOGN, LOGE>(lds, T.fw + (int64_t)l * n, lc.q);
+    return v;
+  };
+  ntt_fwd_in<LOGN, LOGE>(lds, enc, T.fw + (int64_t)l * n, lc.q);
   // 16-byte accesses: a polynomial is 16-byte aligned
   const PENCIL_GLOBAL u64x2* g2 = (const PENCIL_GLOBAL u64x2*)gview(src + at);
   PENCIL_GLOBAL u64x2* o2 = (PENCIL_GLOBAL u64x2*)gview(dst + at);
@@ -318,17 +330,31 @@ __device__ __forceinline__ void do_ntt_pt(uint64_t* lds, const int64_t* tensor, 
   const LimbConst& lc = C.limb[l];
   const PENCIL_GLOBAL int64_t* gt = gview(tensor);
   const TileOrigin to = tile_origin(side, G, j);
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    uint64_t v = 0;
-    const int64_t off = slot_at(side, G, V, to, i);
-    if (off >= 0) {
-      uint64_t w = (uint64_t)gt[off];
-      v = w <= C.t_half ? w : lc.q - (C.t - w);
+  auto lift = [&](int64_t off) {
+    const uint64_t w = (uint64_t)gt[off];
+    return w <= C.t_half ? w : lc.q - (C.t - w);
+  };
+  if (side == 0) {
+    // A tiles are dense: each slot gathers its value in the first pass
+    auto enc = [&](int i) {
+      const int64_t off = a_slot_at(G, V, to, i);
+      return off >= 0 ? lift(off) : (uint64_t)0;
+    };
+    ntt_fwd_in<LOGN, LOGE>(lds, enc, T.fw + (int64_t)l * n, lc.q);
+  } else {
+    // K tiles hold rt kt kh kw entries, often far fewer than N (a kernel
+    // window per channel pair): zero the polynomial, then scatter the entries
+    for (int i = threadIdx.x; i < n; i += blockDim.x) lds[lpad(i)] = 0;
+    __syncthreads();
+    const int nnz = G.rt * G.kt * G.kh * G.kw;
+    for (int e = threadIdx.x; e < nnz; e += blockDim.x) {
+      int slot;
+      const int64_t off = k_entry_at(G, V, to, e, slot);
+      if (off >= 0 && slot >= 0 && slot < n) lds[lpad(slot)] = lift(off);
     }
-    lds[lpad(i)] = v;
+    __syncthreads();
+    ntt_fwd<LOGN, LOGE>(lds, T.fw + (int64_t)l * n, lc.q);
   }
-  __syncthreads();
-  ntt_fwd<LOGN, LOGE>(lds, T.fw + (int64_t)l * n, lc.q);
   PENCIL_GLOBAL uint64_t* o = gview(dst + p * n);
   PENCIL_GLOBAL u64x2* o2 = (PENCIL_GLOBAL u64x2*)o;
   for (int i = threadIdx.x; i < n / 2; i += blockDim.x)

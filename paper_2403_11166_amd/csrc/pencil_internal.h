@@ -59,9 +59,11 @@ struct Geo {
   int32_t RS;                                   // rt * S: stride of m inside a tile
   int32_t O;                                    // reverse-encoding offset
   int32_t pad1;
-  // Reciprocals ceil(2^32 / d) of the in-tile divisors d = RS, ha*wa, wa and S
-  // (0 for d = 1): floor(n / d) = umulhi(n, m) for n, d < 2^16.
+  // Reciprocals ceil(2^32 / d) of the in-tile divisors d = RS, ha*wa, wa and S,
+  // and of kw, kh*kw, kt*kh*kw for enumerating a K tile's entries (0 for
+  // d = 1): floor(n / d) = umulhi(n, m) for n, d < 2^16.
   uint32_t dv_rs, dv_hw, dv_wa, dv_s;
+  uint32_t dv_kw, dv_khw, dv_kthw, pad2;
 };
 
 // Maps virtual coordinates (i0, i1, y, x) of an operand to an element offset of
