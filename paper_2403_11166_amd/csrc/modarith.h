@@ -16,13 +16,17 @@ __device__ __forceinline__ uint64_t sub_mod(uint64_t a, uint64_t b, uint64_t q) 
   return a >= b ? a - b : a + q - b;
 }
 
-// (hi, lo) of the 128-bit product a * b, from four 32 x 32 -> 64 products.
+// (hi, lo) of the 128-bit product a * b from four 32 x 32 + 64 -> 64
+// multiply-adds (each sum stays below 2^64: (2^32 - 1)^2 + 2 (2^32 - 1) =
+// 2^64 - 1): t = a0 b1 + hi32(a0 b0), u = a1 b0 + lo32(t), so that
+// a b = lo32(a0 b0) + 2^32 lo32(u) + 2^64 (a1 b1 + hi32(t) + hi32(u)).
 __device__ __forceinline__ void mul_wide(uint64_t a, uint64_t b, uint64_t& hi, uint64_t& lo) {
-  uint64_t a0 = (uint32_t)a, a1 = a >> 32, b0 = (uint32_t)b, b1 = b >> 32;
-  uint64_t p00 = a0 * b0, p01 = a0 * b1, p10 = a1 * b0, p11 = a1 * b1;
-  uint64_t mid = (p00 >> 32) + (uint32_t)p01 + (uint32_t)p10;
-  lo = (mid << 32) | (uint32_t)p00;
-  hi = p11 + (p01 >> 32) + (p10 >> 32) + (mid >> 32);
+  const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32), b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
+  const uint64_t p00 = (uint64_t)a0 * b0;
+  const uint64_t t = (uint64_t)a0 * b1 + (p00 >> 32);
+  const uint64_t u = (uint64_t)a1 * b0 + (uint32_t)t;
+  lo = (u << 32) | (uint32_t)p00;
+  hi = (uint64_t)a1 * b1 + (t >> 32) + (u >> 32);
 }
 
 // Shoup's multiplication by a fixed w < q with companion ws = floor(w 2^64 / q):
