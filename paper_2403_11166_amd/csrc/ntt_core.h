@@ -122,6 +122,17 @@ __device__ __forceinline__ void fwd_pass(uint64_t* a, In in, const PENCIL_GLOBAL
 #pragma unroll
     for (int k = 0; k < K; ++k) v[r * K + k] = in(base + (k << LT));
   }
+  // A wave whose first-pass inputs are all zero (most waves of a sparse K
+  // tile) skips the butterflies: its outputs are zero, a representative of
+  // the same residues the lazy butterflies would give.
+  bool work = true;
+  if constexpr (S0 == 0) {
+    uint64_t any = 0;
+#pragma unroll
+    for (int i = 0; i < Sh::E; ++i) any |= v[i];
+    work = __builtin_amdgcn_ballot_w64(any != 0) != 0;
+  }
+  if (work) {
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     const int h = 1 << (S - 1 - s);
@@ -139,6 +150,7 @@ __device__ __forceinline__ void fwd_pass(uint64_t* a, In in, const PENCIL_GLOBAL
         }
       }
     }
+  }
   }
 #pragma unroll
   for (int r = 0; r < G; ++r) {
