@@ -657,10 +657,27 @@ def main():
 
         enc_ms = timed_calls(lambda r: c.encrypt(L_, plan, "x_fwd", e["d"]["x1"], 9000 + r, out=out_ct, ws=enc_ws))
         dec_ms = timed_calls(lambda r: c.decrypt(L_, plan, "fwd", e["out_f"][0], ws=dec_ws))
+        # rooflines of the two ends: encryption transforms u, e0 + round(q m / t)
+        # and e1 (3 L limb-transforms per ciphertext) and writes both components;
+        # decryption transforms c1 forward and the phase back (2 L) and reads both
+        # components.  Both are bound by the transforms' 32-bit multiplies.
+        n_, lg_ = c.n, c.n.bit_length() - 1
+        bfly_ = MUL32_PER_BUTTERFLY * (n_ // 2) * lg_
+        ct_bytes = 2 * c.L * n_ * 8
+
+        def ends_roof(count, ms, transforms):
+            mul = count * transforms * c.L * bfly_
+            return {"bound": "alu", "mul32_Tps": round(mul / (ms / 1e3) / 1e12, 3),
+                    "frac": round(mul / (ms / 1e3) / 1e12 / MUL32_PEAK_TOPS, 4),
+                    "GBps": round(count * ct_bytes / (ms / 1e3) / 1e9, 1),
+                    "hbm_frac": round(count * ct_bytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+
         do_side = {"encrypt": {"ciphertexts": int(sz.n_ct[0]), "ms": round(enc_ms, 4),
-                               "ciphertexts_per_s": round(sz.n_ct[0] / (enc_ms / 1e3), 1)},
+                               "ciphertexts_per_s": round(sz.n_ct[0] / (enc_ms / 1e3), 1),
+                               "roofline": ends_roof(int(sz.n_ct[0]), enc_ms, 3)},
                    "decrypt": {"ciphertexts": int(sz.n_out[0]), "ms": round(dec_ms, 4),
-                               "ciphertexts_per_s": round(sz.n_out[0] / (dec_ms / 1e3), 1)},
+                               "ciphertexts_per_s": round(sz.n_out[0] / (dec_ms / 1e3), 1),
+                               "roofline": ends_roof(int(sz.n_out[0]), dec_ms, 2)},
                    "layer": f"{L_.kind} {L_.c_in}->{L_.c_out} {L_.h}x{L_.w} b{L_.batch}"}
 
     # ------------------------------------------- bias gradient and DP noise
