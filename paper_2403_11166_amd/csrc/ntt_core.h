@@ -54,9 +54,7 @@ __device__ __forceinline__ BflyK bfly_consts(uint64_t q) {
 // taken as a signed 64-bit value is negative exactly when x < c.
 __device__ __forceinline__ uint64_t csub(uint64_t x, uint64_t c, uint64_t nc) {
   const uint64_t d = x + nc;
-  const uint32_t m = (uint32_t)((int32_t)(uint32_t)(d >> 32) >> 31);
-  const uint64_t back = ((uint64_t)((uint32_t)(c >> 32) & m) << 32) | ((uint32_t)c & m);
-  return d + back;
+  return (int64_t)d < 0 ? x : d;
 }
 
 // Lazy Shoup product y w mod q in [0, 4q) for any y < 2^64, w < q, with
