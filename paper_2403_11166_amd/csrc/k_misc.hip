@@ -16,10 +16,10 @@ __device__ __forceinline__ void do_flood(uint64_t* ct, int64_t n_out, int64_t* s
                                          const Geo& G, const View& OV, uint64_t nonce, uint64_t obj_base,
                                          const Consts& C, int64_t g) {
   const int n = C.n, L = C.L;
-  const int per = n / 4;
-  if (g >= n_out * per) return;
-  const int64_t o = g / per;
-  const int n0 = (int)(g % per) * 4;
+  const int per_log = C.log2n - 2;  // a thread takes 4 of the N coefficients of one output
+  if (g >= (n_out << per_log)) return;
+  const int64_t o = g >> per_log;
+  const int n0 = (int)(g & ((1 << per_log) - 1)) * 4;
   const uint64_t obj = obj_base + (uint64_t)o;
   const uint64_t blk4 = (uint64_t)(n0 / 4);
   U64x4 e0 = philox(blk4, obj, P_RR_E0, 0, C.seed, nonce);
@@ -36,14 +36,15 @@ __device__ __forceinline__ void do_flood(uint64_t* ct, int64_t n_out, int64_t* s
   const int64_t ct_stride = 2 * (int64_t)L * n;
   PENCIL_GLOBAL uint64_t* c0p = gview(ct) + o * ct_stride;
   PENCIL_GLOBAL uint64_t* c1p = c0p + (int64_t)L * n;
-  // output-tile coordinates of o = ((mi*nR + ri)*nOY + oyi)*nOX + oxi
-  int64_t ti = o;
-  const int oxi = (int)(ti % G.nOX);
-  ti /= G.nOX;
-  const int oyi = (int)(ti % G.nOY);
-  ti /= G.nOY;
-  const int ri = (int)(ti % G.nR);
-  const int mi = (int)(ti / G.nR);
+  // output-tile coordinates of o = ((mi*nR + ri)*nOY + oyi)*nOX + oxi, in
+  // 32-bit arithmetic (a step's outputs number far fewer than 2^32)
+  uint32_t ti = (uint32_t)o;
+  const int oxi = (int)(ti % (uint32_t)G.nOX);
+  ti /= (uint32_t)G.nOX;
+  const int oyi = (int)(ti % (uint32_t)G.nOY);
+  ti /= (uint32_t)G.nOY;
+  const int ri = (int)(ti % (uint32_t)G.nR);
+  const int mi = (int)(ti / (uint32_t)G.nR);
   // per-coefficient draws: re-randomisation errors, the mask s = (wlo + 2^64 whi) mod t
   int64_t ev0[4], ev1[4];
   uint64_t sv[4], rrv[4];

@@ -166,8 +166,9 @@ __device__ __forceinline__ void fwd_pass(uint64_t* a, In in, const PENCIL_GLOBAL
 // Inverse (Gentleman-Sande, psi^-rev twiddles; bit-reversed in, natural out)
 // stages with t = 2^L0 .. 2^(L0+S-1): pair (i0, i0 + t), i = i0 >> (l + 1),
 // twiddle itw[(N >> (l + 1)) + i].  Groups are {base + k * 2^L0}.
-template <int LOGN, int LOGE, int L0, int S>
-__device__ __forceinline__ void inv_pass(uint64_t* a, const PENCIL_GLOBAL TW* tw, uint64_t q, const BflyK& bk) {
+template <int LOGN, int LOGE, int L0, int S, typename In>
+__device__ __forceinline__ void inv_pass(uint64_t* a, In in, const PENCIL_GLOBAL TW* tw, uint64_t q,
+                                         const BflyK& bk) {
   using Sh = NttShape<LOGN, LOGE>;
   constexpr int T = Sh::T, G = Sh::E >> S, K = 1 << S;
   const int tid = threadIdx.x;
@@ -177,7 +178,7 @@ __device__ __forceinline__ void inv_pass(uint64_t* a, const PENCIL_GLOBAL TW* tw
     const int g = r * T + tid;
     const int base = ((g >> L0) << (L0 + S)) + (g & ((1 << L0) - 1));
 #pragma unroll
-    for (int k = 0; k < K; ++k) v[r * K + k] = a[lpad(base + (k << L0))];
+    for (int k = 0; k < K; ++k) v[r * K + k] = in(base + (k << L0));
   }
 #pragma unroll
   for (int s = 0; s < S; ++s) {
@@ -240,26 +241,35 @@ __device__ __forceinline__ void ntt_fwd(uint64_t* a, const TW* tw_generic, uint6
   ntt_fwd_in<LOGN, LOGE>(a, [a](int i) { return a[lpad(i)]; }, tw_generic, q);
 }
 
-// Inverse transform without the N^-1 factor (inputs in [0, 4q), outputs in [0, 4q)).
-template <int LOGN, int LOGE>
-__device__ __forceinline__ void ntt_inv(uint64_t* a, const TW* tw_generic, uint64_t q) {
+// Inverse transform without the N^-1 factor (inputs in [0, 4q), outputs in
+// [0, 4q)) into the LDS polynomial `a`, of the inputs `in(i)` supplies to the
+// first pass (as for ntt_fwd_in, `a` must not be in use).
+template <int LOGN, int LOGE, typename In>
+__device__ __forceinline__ void ntt_inv_in(uint64_t* a, In in, const TW* tw_generic, uint64_t q) {
   using Sh = NttShape<LOGN, LOGE>;
   const BflyK bk = bfly_consts(q);
   const PENCIL_GLOBAL TW* tw = gview(tw_generic);
-  inv_pass<LOGN, LOGE, Sh::start(0), Sh::size(0)>(a, tw, q, bk);
+  auto lds = [a](int i) { return a[lpad(i)]; };
+  inv_pass<LOGN, LOGE, Sh::start(0), Sh::size(0)>(a, in, tw, q, bk);
   __syncthreads();
   if constexpr (Sh::NP > 1) {
-    inv_pass<LOGN, LOGE, Sh::start(1), Sh::size(1)>(a, tw, q, bk);
+    inv_pass<LOGN, LOGE, Sh::start(1), Sh::size(1)>(a, lds, tw, q, bk);
     __syncthreads();
   }
   if constexpr (Sh::NP > 2) {
-    inv_pass<LOGN, LOGE, Sh::start(2), Sh::size(2)>(a, tw, q, bk);
+    inv_pass<LOGN, LOGE, Sh::start(2), Sh::size(2)>(a, lds, tw, q, bk);
     __syncthreads();
   }
   if constexpr (Sh::NP > 3) {
-    inv_pass<LOGN, LOGE, Sh::start(3), Sh::size(3)>(a, tw, q, bk);
+    inv_pass<LOGN, LOGE, Sh::start(3), Sh::size(3)>(a, lds, tw, q, bk);
     __syncthreads();
   }
+}
+
+// Inverse transform of the LDS polynomial; callers synchronise before and after.
+template <int LOGN, int LOGE>
+__device__ __forceinline__ void ntt_inv(uint64_t* a, const TW* tw_generic, uint64_t q) {
+  ntt_inv_in<LOGN, LOGE>(a, [a](int i) { return a[lpad(i)]; }, tw_generic, q);
 }
 
 // ------------------------------------------------------------------ kernels
@@ -272,19 +282,16 @@ __device__ __forceinline__ void do_ntt_plain(uint64_t* lds, uint64_t* data, int 
   const int L = C.L;
   const int l = (int)(p % L);
   const LimbConst& lc = C.limb[l];
-  // residues move in 16-byte pairs; a pair never straddles an LDS pad word
+  // the first butterfly pass reads its residues straight from memory; results
+  // leave the LDS in 16-byte pairs (a pair never straddles an LDS pad word)
   PENCIL_GLOBAL u64x2* g = (PENCIL_GLOBAL u64x2*)gview(data + p * n);
-  for (int i = threadIdx.x; i < n / 2; i += blockDim.x) {
-    const u64x2 v = g[i];
-    lds[lpad(2 * i)] = v[0];
-    lds[lpad(2 * i) + 1] = v[1];
-  }
-  __syncthreads();
+  const PENCIL_GLOBAL uint64_t* g1 = gview(data + p * n);
+  auto src = [g1](int i) { return g1[i]; };
   if (!inverse) {
-    ntt_fwd<LOGN, LOGE>(lds, T.fw + (int64_t)l * n, lc.q);
+    ntt_fwd_in<LOGN, LOGE>(lds, src, T.fw + (int64_t)l * n, lc.q);
     for (int i = threadIdx.x; i < n / 2; i += blockDim.x) g[i] = u64x2{lds[lpad(2 * i)], lds[lpad(2 * i) + 1]};
   } else {
-    ntt_inv<LOGN, LOGE>(lds, T.iw + (int64_t)l * n, lc.q);
+    ntt_inv_in<LOGN, LOGE>(lds, src, T.iw + (int64_t)l * n, lc.q);
     for (int i = threadIdx.x; i < n / 2; i += blockDim.x)
       g[i] = u64x2{mul_shoup(lds[lpad(2 * i)], lc.ninv, lc.ninv_sh, lc.q),
                    mul_shoup(lds[lpad(2 * i) + 1], lc.ninv, lc.ninv_sh, lc.q)};

@@ -150,7 +150,7 @@ def test_every_schedule_variant_is_bit_identical_and_autotune_picks_one(tmp_path
     _, _, plan, io = ents[0]
     chosen = list(plan.sched)
     results = []
-    for v in range(9):
+    for v in range(12):
         for op in range(3):
             plan.sched[op] = v
         results.append(per_layer(ents, 4000))
@@ -206,3 +206,34 @@ def test_failed_rebind_leaves_the_step_unbound():
     step.bind([io for _, _, _, io in ents], ws)
     step.run(5000)
     torch.cuda.synchronize()
+
+
+def test_restart_at_step_k_reproduces_the_continuous_run():
+    """The state a training run carries from step to step is the key seed and
+    the nonce counter: a run restarted at step k from fresh contexts (key
+    generation again from the same seed), a fresh step and a fresh graph, with
+    the base nonce of step k, reproduces step k of the continuous run bit for
+    bit, as a graph replay and as an eager run."""
+    tensors = [layer_tensors(l, 120 + i) for i, l in enumerate(MIXED)]
+    n, base, k = len(MIXED), 7000, 2
+    ents = build(MIXED, tensors, 17)
+    step, _ws = make_step(ents)
+    step.capture()
+    step.set_nonce(base)
+    outs = []
+    for _ in range(k + 1):
+        step.replay()
+        outs.append(snapshot(ents))
+    assert not np.array_equal(outs[0][0]["ct_y"], outs[k][0]["ct_y"])
+    step.close()
+    del ents, step, _ws
+    _ctx.clear()
+    ents2 = build(MIXED, tensors, 17)
+    step2, _ws2 = make_step(ents2)
+    step2.capture()
+    step2.set_nonce(base + 2 * n * k)
+    step2.replay()
+    assert_same(snapshot(ents2), outs[k])
+    clear(ents2)
+    step2.run(base + 2 * n * k)
+    assert_same(snapshot(ents2), outs[k])
