@@ -103,16 +103,14 @@ typedef struct {
 
 typedef struct {
     pencil_tile fwd, dx, dw;
-    /* Schedule of each product's multiply-accumulate, 0..11.  Each wave of a
-     * workgroup accumulates a 2 x 2 block of (input row, weight row) outputs
-     * for 64 NTT slots.  v / 3 is the kind: 0 stages operands in LDS, 1 loads
-     * them directly (both ciphertext components per wave), 2 loads them
-     * directly for one component per wave (all 512-lane workgroups), 3 is
-     * kind 1 with 1024-lane workgroups.  v mod 3 is the workgroup's chunk:
-     * 4 x 8, 2 x 16 or 8 x 4 rows (kinds 0 and 1), 4 x 4, 2 x 8 or 8 x 2
-     * (kind 2), 4 x 16, 2 x 32 or 8 x 8 (kind 3).  Results do not depend on
-     * it; pencil_plan_auto picks a kind-1 chunk by a cost model,
-     * pencil_autotune by measurement. */
+    /* Schedule of each product's multiply-accumulate, 0..8.  Each wave of a
+     * 512-lane workgroup accumulates a 2 x 2 block of (input row, weight row)
+     * outputs for 64 NTT slots.  v / 3 is the kind: 0 stages operands in LDS,
+     * 1 loads them directly (both ciphertext components per wave), 2 loads
+     * them directly for one component per wave.  v mod 3 is the workgroup's
+     * chunk: 4 x 8, 2 x 16 or 8 x 4 rows (kinds 0 and 1), 4 x 4, 2 x 8 or 8 x 2
+     * (kind 2).  Results do not depend on it; pencil_plan_auto picks a kind-1
+     * chunk by a cost model, pencil_autotune by measurement. */
     int32_t sched[3];
 } pencil_plan;
 
@@ -351,7 +349,7 @@ pencil_status pencil_stride_relayout(pencil_ctx* ctx, const pencil_layer* stride
  * each product's partition among the caller's tile and the planner's best-
  * ranked ones (App. A leaves the split of large operands open; the choice is
  * written into the plan's tiles), and each product's multiply-accumulate
- * schedule among all twelve (written into plan->sched).  A partition fixes the
+ * schedule among all nine (written into plan->sched).  A partition fixes the
  * ciphertext layout: tune before the DO encrypts with the plan, and give both
  * parties the tuned plan.  Output ciphertexts and shares under one plan are
  * bit-identical for every schedule and NTT width.  cache_path (may be NULL) is

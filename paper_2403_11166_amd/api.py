@@ -167,7 +167,7 @@ class Context:
         return p
 
     def autotune(self, layer, plan, cache_path=None):
-        """Measure the NTT width, the planner's best partitions and the twelve multiply-accumulate
+        """Measure the NTT width, the planner's best partitions and the nine multiply-accumulate
         schedules on this GPU and return the tuned plan (tune before encrypting with it)."""
         p = plan_struct(plan)
         q = A.Plan()

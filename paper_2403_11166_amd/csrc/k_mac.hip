@@ -1,6 +1,4 @@
 // Pointwise multiply-accumulate of the product path (per call and batched).
-#include <utility>
-
 #include "device_common.h"
 
 namespace pencil {
@@ -560,7 +558,7 @@ template <int ROWS, int COLS, bool SPLIT>
 __device__ __forceinline__ void do_mac_v2(u64x2* lds, const MacArgs& A, const Geo& G, const Consts& C,
                                           int slot_block, int chunk) {
   constexpr int WC = COLS / 2;
-  static_assert((ROWS / 2) * WC == 8 || (ROWS / 2) * WC == 16, "8 or 16 waves per block");
+  static_assert((ROWS / 2) * WC == 8, "8 waves per block");
   const int n = C.n, L = C.L;
   const int per_limb = n / kMacSlots;
   const int l = slot_block / per_limb;
@@ -623,7 +621,6 @@ __device__ __forceinline__ void do_mac_v2(u64x2* lds, const MacArgs& A, const Ge
 }
 
 constexpr int kMacV2Lds = 8 * 8 * kMacSlots;  // u64x2 words: 8 waves x 8 totals x 64 lanes (64 KiB)
-constexpr int kMacV2Lds16 = 2 * kMacV2Lds;    // 16-wave blocks (128 KiB, dynamic)
 
 // Kind 0: LDS-staged 2 x 2 wave blocks, both components; 2: direct 2 x 2
 // wave blocks of one component each (kind 1 is do_mac_kind1).
@@ -666,24 +663,6 @@ __global__ void __launch_bounds__(512) k_mac_direct(MacArgs A, Geo G, Consts C, 
   do_mac_kind1<false>(tot, A, G, C, w, chunks);
 }
 
-// Kind 3: kind 1 with 16-wave blocks, twice the outputs per chunk, so that
-// fewer chunks of one slot range re-read its operand rows.
-template <bool SPLIT>
-__device__ __forceinline__ void do_mac_kind3(u64x2* tot, const MacArgs& A, const Geo& G, const Consts& C, int w,
-                                             int chunks) {
-  switch (A.variant % 3) {
-    case 1: do_mac_v2<2, 32, SPLIT>(tot, A, G, C, w / chunks, w % chunks); break;
-    case 2: do_mac_v2<8, 8, SPLIT>(tot, A, G, C, w / chunks, w % chunks); break;
-    default: do_mac_v2<4, 16, SPLIT>(tot, A, G, C, w / chunks, w % chunks); break;
-  }
-}
-
-__global__ void __launch_bounds__(1024) k_mac_direct16(MacArgs A, Geo G, Consts C, int chunks, int64_t total) {
-  extern __shared__ u64x2 tot16[];
-  const int w = (int)xcd_work(blockIdx.x, total);
-  do_mac_kind3<false>(tot16, A, G, C, w, chunks);
-}
-
 __global__ void __launch_bounds__(512) k_mac_direct_small(MacArgs A, Geo G, Consts C, int chunks, int64_t total) {
   const int w = (int)xcd_work(blockIdx.x, total);
   do_mac<2>(nullptr, A, G, C, w / chunks, w % chunks);
@@ -721,17 +700,6 @@ __global__ void __launch_bounds__(512, 4) k_step_mac_direct(STEP_ARGS) {
   do_mac_kind1<true>(tot, S.mac, S.G, consts[S.ctx], w, chunks);
 }
 
-__global__ void __launch_bounds__(1024) k_step_mac_direct16(STEP_ARGS) {
-  extern __shared__ u64x2 tot16[];
-  const StepSeg& S = segs[find_seg(segs, nseg, blockIdx.x)];
-  const int64_t local = (int64_t)blockIdx.x - S.block_begin;
-  const int chunks = mac_chunks(S.mac.variant, S.mac.m_rows, S.G.nR);
-  const int64_t work = S.slot_blocks * chunks, padded = (work + 7) & ~(int64_t)7;
-  const int w = (int)xcd_work(local, padded);  // work items per launch stay below 2^31
-  if (w >= work) return;
-  do_mac_kind3<true>(tot16, S.mac, S.G, consts[S.ctx], w, chunks);
-}
-
 __global__ void __launch_bounds__(512) k_step_mac_direct_small(STEP_ARGS) {
   step_mac<2>(segs, nseg, consts, nullptr);
 }
@@ -747,10 +715,7 @@ hipError_t launch_mac(const MacArgs& A, int64_t n_out, const Geo& G, const Const
   const int chunks = mac_chunks(A.variant, A.m_rows, G.nR);
   const int64_t total = slot_blocks * chunks;
   if (total >= (1ll << 31)) return hipErrorInvalidConfiguration;  // work items are int
-  if (A.variant >= 9)
-    hipLaunchKernelGGL(k_mac_direct16, dim3((unsigned)total), dim3(1024), kMacV2Lds16 * sizeof(u64x2), s, A, G, C,
-                       chunks, total);
-  else if (A.variant >= 6)
+  if (A.variant >= 6)
     hipLaunchKernelGGL(k_mac_direct_small, dim3((unsigned)total), dim3(512), 0, s, A, G, C, chunks, total);
   else if (A.variant >= 3)
     hipLaunchKernelGGL(k_mac_direct, dim3((unsigned)total), dim3(512), 0, s, A, G, C, chunks, total);
@@ -762,10 +727,7 @@ hipError_t launch_mac(const MacArgs& A, int64_t n_out, const Geo& G, const Const
 
 hipError_t launch_step_mac(const StepPhase& P, int64_t blocks, int kind, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
-  if (kind == 3)
-    hipLaunchKernelGGL(k_step_mac_direct16, dim3((unsigned)blocks), dim3(1024), kMacV2Lds16 * sizeof(u64x2), s,
-                       P.segs, P.nseg, P.consts);
-  else if (kind == 2)
+  if (kind == 2)
     hipLaunchKernelGGL(k_step_mac_direct_small, dim3((unsigned)blocks), dim3(512), 0, s, P.segs, P.nseg, P.consts);
   else if (kind == 1)
     hipLaunchKernelGGL(k_step_mac_direct, dim3((unsigned)blocks), dim3(512), 0, s, P.segs, P.nseg, P.consts);
@@ -775,15 +737,10 @@ hipError_t launch_step_mac(const StepPhase& P, int64_t blocks, int kind, hipStre
 }
 
 hipError_t configure_lds_mac() {
-  const int mac_lds = kMacSmemWords * sizeof(uint64_t), lds16 = kMacV2Lds16 * sizeof(u64x2);
-  hipError_t e = hipSuccess;
-  for (const auto& fl : {std::make_pair((const void*)k_mac_lds, mac_lds), std::make_pair((const void*)k_step_mac, mac_lds),
-                         std::make_pair((const void*)k_mac_direct16, lds16),
-                         std::make_pair((const void*)k_step_mac_direct16, lds16)}) {
-    const hipError_t r = hipFuncSetAttribute(fl.first, hipFuncAttributeMaxDynamicSharedMemorySize, fl.second);
-    if (r != hipSuccess) e = r;
-  }
-  return e;
+  const int mac_lds = kMacSmemWords * sizeof(uint64_t);
+  hipError_t m1 = hipFuncSetAttribute((const void*)k_mac_lds, hipFuncAttributeMaxDynamicSharedMemorySize, mac_lds);
+  hipError_t m2 = hipFuncSetAttribute((const void*)k_step_mac, hipFuncAttributeMaxDynamicSharedMemorySize, mac_lds);
+  return m1 != hipSuccess ? m1 : m2;
 }
 
 }  // namespace pencil

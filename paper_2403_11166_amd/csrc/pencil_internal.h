@@ -144,15 +144,14 @@ struct StepPhase {
 // Variant v = 3 kind + shape.  Every wave accumulates a 2 x 2 block of
 // (A row, K row) outputs.  Kind 0 stages operands in LDS, kind 1 loads them
 // directly, both for the two ciphertext components; kind 2 loads directly for
-// one component (the block's waves alternate components); kind 3 is kind 1
-// with 16-wave (1024-lane) blocks.  The shape picks the chunk (A rows x K rows)
-// of the block's waves: 4 x 8, 2 x 16, 8 x 4 (kinds 0, 1), 4 x 4, 2 x 8, 8 x 2
-// (kind 2) or 4 x 16, 2 x 32, 8 x 8 (kind 3).
-constexpr int kMacVariants = 12;
+// one component (the block's waves alternate components).  The shape picks the
+// chunk (A rows x K rows) of the block's 8 waves: 4 x 8, 2 x 16, 8 x 4
+// (kinds 0, 1) or 4 x 4, 2 x 8, 8 x 2 (kind 2).
+constexpr int kMacVariants = 9;
 __host__ __device__ inline int mac_rows(int variant) { return variant % 3 == 1 ? 2 : variant % 3 == 2 ? 8 : 4; }
 __host__ __device__ inline int mac_cols(int variant) {
   const int c = variant % 3 == 1 ? 16 : variant % 3 == 2 ? 4 : 8;
-  return variant >= 9 ? 2 * c : variant >= 6 ? c / 2 : c;
+  return variant >= 6 ? c / 2 : c;
 }
 __host__ __device__ inline int mac_chunks(int variant, int m_rows, int n_r) {
   return ((m_rows + mac_rows(variant) - 1) / mac_rows(variant)) * ((n_r + mac_cols(variant) - 1) / mac_cols(variant));
