@@ -403,20 +403,55 @@ __global__ void __launch_bounds__(1024) k_zt_mfma(const int64_t* a, const int64_
   }
 }
 
-// Z_t linear combination out = base + sum_i c_i x_i (mod t), one thread per
-// element: the masked operands and share combinations of the preprocessed
-// products (Pencil+, online phase).  Operands and coefficients are below
-// t < 2^48, so each product fits 96 bits and 64 of them plus base fit 128.
-__global__ void __launch_bounds__(256) k_zt_combine(ZtTerms T, const int64_t* base, int64_t* out, int64_t count,
-                                                    Consts C) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= count) return;
-  uint64_t hi = 0, lo = base ? (uint64_t)gview(base)[g] : 0;
-  for (int i = 0; i < T.n; ++i) {
-    uint64_t ph, pl;
-    mul_wide((uint64_t)gview(T.x[i])[g], T.c[i], ph, pl);
+// Z_t linear combination out = base + sum_i c_i x_i (mod t): the masked
+// operands and share combinations of the preprocessed products (Pencil+,
+// online phase).  Operands and coefficients are below t < 2^48, so each
+// product fits 96 bits and 64 of them plus base fit 128.  The sum is a pure
+// stream of loads, so a block holds 64 consecutive elements and kCombWaves
+// waves: wave w takes the terms w, w + kCombWaves, ..., issues up to kCombUnroll
+// of their loads before the first multiply, and the waves' 128-bit partial
+// sums meet in LDS, where the first wave adds base and reduces mod t.
+constexpr int kCombWaves = 8, kCombUnroll = 8;
+
+__global__ void __launch_bounds__(64 * kCombWaves) k_zt_combine(ZtTerms T, const int64_t* base, int64_t* out,
+                                                               int64_t count, Consts C) {
+  __shared__ uint64_t part_lo[kCombWaves][64], part_hi[kCombWaves][64];
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t g = (int64_t)blockIdx.x * 64 + lane;
+  const bool live = g < count;
+  uint64_t hi = 0, lo = 0;
+  if (live) {
+    for (int i0 = w; i0 < T.n; i0 += kCombWaves * kCombUnroll) {
+      uint64_t x[kCombUnroll];
+#pragma unroll
+      for (int u = 0; u < kCombUnroll; ++u) {
+        const int i = i0 + u * kCombWaves;
+        x[u] = i < T.n ? (uint64_t)gview(T.x[i])[g] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < kCombUnroll; ++u) {
+        const int i = i0 + u * kCombWaves;
+        if (i < T.n) {
+          uint64_t ph, pl;
+          mul_wide(x[u], T.c[i], ph, pl);
+          lo += pl;
+          hi += ph + (lo < pl ? 1 : 0);
+        }
+      }
+    }
+  }
+  part_lo[w][lane] = lo;
+  part_hi[w][lane] = hi;
+  __syncthreads();
+  if (w != 0 || !live) return;
+  lo = base ? (uint64_t)gview(base)[g] : 0;
+  hi = 0;
+#pragma unroll
+  for (int k = 0; k < kCombWaves; ++k) {
+    const uint64_t pl = part_lo[k][lane];
     lo += pl;
-    hi += ph + (lo < pl ? 1 : 0);
+    hi += part_hi[k][lane] + (lo < pl ? 1 : 0);
   }
   const uint64_t v = add_mod(mul_shoup(reduce64(hi, C.one_sh_t, C.t), C.r64t, C.r64t_sh, C.t),
                              reduce64(lo, C.one_sh_t, C.t), C.t);
@@ -648,7 +683,8 @@ hipError_t launch_flood_mask(uint64_t* ct, int64_t n_out, int64_t* share0, const
 hipError_t launch_zt_combine(const ZtTerms& T, const int64_t* base, int64_t* out, int64_t count, const Consts& C,
                              hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_zt_combine, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, T, base, out, count, C);
+  hipLaunchKernelGGL(k_zt_combine, dim3((unsigned)((count + 63) / 64)), dim3(64 * kCombWaves), 0, s, T, base, out,
+                     count, C);
   return hipGetLastError();
 }
 

@@ -42,7 +42,7 @@ def instance(layer, kind, m, seed):
     return u, v, um, vm, s, k, l
 
 
-@pytest.mark.parametrize("n_terms", [0, 1, 3, 16, 21])
+@pytest.mark.parametrize("n_terms", [0, 1, 3, 9, 16, 21, 64, 65, 130])
 def test_zt_combine_matches_oracle(n_terms):
     ctx = context(SMALL[0])
     rng = np.random.default_rng(n_terms)
