@@ -340,6 +340,16 @@ __global__ void __launch_bounds__(1024) k_zt_mfma(const int64_t* a, const int64_
   zt_v4d acc[5];
 #pragma unroll
   for (int s = 0; s < 5; ++s) acc[s] = zt_v4d{0, 0, 0, 0};
+  // this lane's contraction index c = 4 step + lc as (k, dy, dx), divided out
+  // once and then advanced by 4 per step
+  int k = 0, dy = 0, dx = 0;
+  {
+    const int64_t c = s_begin * 4 + lc;
+    k = (int)(c / kk);
+    const int rem = (int)(c - (int64_t)k * kk);
+    dy = rem / G.KW;
+    dx = rem - dy * G.KW;
+  }
   constexpr int U = 4;  // contraction steps whose loads are issued together
   for (int64_t st0 = s_begin; st0 < s_end; st0 += U) {
     uint64_t av[U], bv[U];
@@ -347,20 +357,23 @@ __global__ void __launch_bounds__(1024) k_zt_mfma(const int64_t* a, const int64_
     for (int u = 0; u < U; ++u) {
       const int64_t c = (st0 + u) * 4 + lc;
       const bool live = st0 + u < s_end && c < ctot;
-      int k = 0, dy = 0, dx = 0;
-      if (kk == 1) {
-        k = (int)c;
-      } else {
-        k = (int)(c / kk);
-        const int rem = (int)(c - (int64_t)k * kk);
-        dy = rem / G.KW;
-        dx = rem - dy * G.KW;
-      }
       const int ky = KV.flip ? KV.KH - 1 - dy : dy, kx = KV.flip ? KV.KW - 1 - dx : dx;
       bv[u] = live && cv ? (uint64_t)gk[kbase + (int64_t)k * KV.s1 + (int64_t)ky * KV.sy + (int64_t)kx * KV.sx] : 0;
       const int ys = ay + dy, xs = ax + dx;
       const bool in = live && rv && ys >= 0 && ys < AV.H && xs >= 0 && xs < AV.W;
       av[u] = in ? (uint64_t)ga[abase + (int64_t)k * AV.s1 + (int64_t)ys * AV.sy + (int64_t)xs * AV.sx] : 0;
+      if (kk == 1) {
+        k += 4;
+      } else {
+        dx += 4;
+        while (dx >= G.KW) {
+          dx -= G.KW;
+          if (++dy == G.KH) {
+            dy = 0;
+            ++k;
+          }
+        }
+      }
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -401,6 +414,88 @@ __global__ void __launch_bounds__(1024) k_zt_mfma(const int64_t* a, const int64_
       gview(out)[(int64_t)m * OV.s0 + (int64_t)ocol * OV.s1 + (int64_t)y * OV.sy + (int64_t)x * OV.sx] = (int64_t)v;
     }
   }
+}
+
+// The correlation of a fully connected layer (1 x 1 kernel, 1 x 1 output) with
+// a long contraction and few outputs.  Each wave owns a 2 x 2 block of (row,
+// column) outputs and its 64 lanes split the contraction (lane l takes the
+// indices l, l + 64, ...), so an operand stored contiguously along the
+// contraction is read with coalesced loads, and the waves spread over every CU
+// even where the grid of 16 x 16 output tiles is small.  Products use the
+// 21-bit halves of the vector kernel; each lane's three partial sums per
+// output, added across the wave by shuffles, hold the whole contraction (the
+// launcher bounds its length), and lanes 0-3 then reduce one output each.
+__global__ void __launch_bounds__(256) k_zt_dot(const int64_t* a, const int64_t* kt, int64_t* out, Geo G, View AV,
+                                                View KV, View OV, Consts C) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int P = G.M, R = G.R, K = G.K;
+  const int cb = (R + 1) / 2;
+  if (wave >= (int64_t)((P + 1) / 2) * cb) return;  // the whole wave leaves; no barrier follows
+  const int row0 = (int)(wave / cb) * 2, col0 = (int)(wave % cb) * 2;
+  const bool row1 = row0 + 1 < P, col1 = col0 + 1 < R;
+  const PENCIL_GLOBAL int64_t* ga[2] = {gview(a) + (int64_t)row0 * AV.s0,
+                                        gview(a) + (int64_t)(row1 ? row0 + 1 : row0) * AV.s0};
+  const PENCIL_GLOBAL int64_t* gk[2] = {gview(kt) + (int64_t)col0 * KV.s0,
+                                        gview(kt) + (int64_t)(col1 ? col0 + 1 : col0) * KV.s0};
+  constexpr uint64_t kLo = (1ull << 21) - 1;
+  uint64_t s0[4] = {}, s1[4] = {}, s2[4] = {};
+  constexpr int U = 4;  // contraction indices per lane whose loads are issued together
+  for (int k0 = lane; k0 < K; k0 += 64 * U) {
+    uint64_t av[U][2], bv[U][2];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = k0 + 64 * u;
+      const bool live = k < K;
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        av[u][i] = live ? (uint64_t)ga[i][(int64_t)k * AV.s1] : 0;
+        bv[u][i] = live ? (uint64_t)gk[i][(int64_t)k * KV.s1] : 0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const uint32_t a0 = (uint32_t)(av[u][i] & kLo), a1 = (uint32_t)(av[u][i] >> 21);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const uint32_t b0 = (uint32_t)(bv[u][j] & kLo), b1 = (uint32_t)(bv[u][j] >> 21);
+          s0[i * 2 + j] += (uint64_t)a0 * b0;
+          s1[i * 2 + j] += (uint64_t)a0 * b1;
+          s1[i * 2 + j] += (uint64_t)a1 * b0;
+          s2[i * 2 + j] += (uint64_t)a1 * b1;
+        }
+      }
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1)
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {
+      s0[o] += __shfl_xor(s0[o], d);
+      s1[o] += __shfl_xor(s1[o], d);
+      s2[o] += __shfl_xor(s2[o], d);
+    }
+  if (lane >= 4) return;
+  uint64_t x0 = s0[0], x1 = s1[0], x2 = s2[0];
+#pragma unroll
+  for (int o = 1; o < 4; ++o)
+    if (lane == o) {
+      x0 = s0[o];
+      x1 = s1[o];
+      x2 = s2[o];
+    }
+  const int row = row0 + (lane >> 1), col = col0 + (lane & 1);
+  if (row >= P || col >= R) return;
+  // x0 + x1 2^21 + x2 2^42 as a 128-bit value, then mod t
+  const uint64_t t1 = x1 << 21, t2 = x2 << 42;
+  uint64_t lo = x0 + t1;
+  uint64_t hi = (lo < t1 ? 1 : 0) + (x1 >> 43) + (x2 >> 22);
+  lo += t2;
+  hi += lo < t2 ? 1 : 0;
+  gview(out)[(int64_t)row * OV.s0 + (int64_t)col * OV.s1] =
+      (int64_t)add_mod(mul_shoup(reduce64(hi, C.one_sh_t, C.t), C.r64t, C.r64t_sh, C.t), reduce64(lo, C.one_sh_t, C.t),
+                       C.t);
 }
 
 // Z_t linear combination out = base + sum_i c_i x_i (mod t): the masked
@@ -715,6 +810,8 @@ hipError_t launch_stride_relayout(const Relayout& R, const int64_t* in, int64_t*
   return hipGetLastError();
 }
 
+constexpr int64_t kDotMinK = 256, kDotMaxTiles = 64, kMfmaMinTiles = 256, kMfmaMinWaves = 512;
+
 hipError_t launch_zt_corr(const int64_t* a, const int64_t* k, int64_t* out, const Geo& G, const View& AV,
                           const View& KV, const View& OV, const Consts& C, hipStream_t s) {
   const int64_t total = (int64_t)G.M * G.R * G.OH * G.OW;
@@ -728,27 +825,42 @@ hipError_t launch_zt_corr(const int64_t* a, const int64_t* k, int64_t* out, cons
   const int tb = 64 - __builtin_clzll(C.t), hb = tb > 21 ? tb - 21 : 0;
   const int mb = std::max(42, std::max(22 + hb, 2 * hb));
   const int64_t per_wave_max = mb >= 63 ? 1 : (int64_t)1 << (64 - mb);
-  // Matrix-core kernel when there are at least 256 output tiles of 16 x 16
-  // (with fewer, the vector kernel's smaller tiles spread the work wider and
-  // measured faster): four contraction indices per step, about eight steps per
-  // wave, at most 16 waves; a diagonal sum takes per-term values below 2^30
-  // (t < 2^43; 2^(2 bitlen(t) - 58) above), so a wave may run
-  // 2^53 / (4 * that) steps.
-  if (((rows + 15) / 16) * ((G.R + 15) / 16) >= 256) {
+  const int64_t tiles = ((rows + 15) / 16) * ((G.R + 15) / 16);
+  // Fully connected shapes (1 x 1 kernel and output) whose contraction is long
+  // and whose outputs fill few 16 x 16 tiles: one 2 x 2 output block per wave,
+  // the lanes splitting the contraction, whose whole length one partial sum
+  // then holds.
+  const bool fc = G.KH == 1 && G.KW == 1 && G.OH == 1 && G.OW == 1 && AV.H == 1 && AV.W == 1 && AV.pad == 0 &&
+                  AV.pady == 0;
+  if (fc && ctot >= kDotMinK && tiles < kDotMaxTiles && ctot <= per_wave_max) {
+    const int64_t waves = (int64_t)((G.M + 1) / 2) * ((G.R + 1) / 2);
+    if ((waves + 3) / 4 < (1ll << 31)) {
+      hipLaunchKernelGGL(k_zt_dot, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, a, k, out, G, AV, KV, OV, C);
+      return hipGetLastError();
+    }
+  }
+  // Matrix-core kernel, one 16 x 16 output tile per workgroup: four
+  // contraction indices per step, about eight steps per wave, at most 16
+  // waves; a diagonal sum takes per-term values below 2^30 (t < 2^43;
+  // 2^(2 bitlen(t) - 58) above), so a wave may run 2^53 / (4 * that) steps.
+  // Taken when its grid has at least kMfmaMinTiles tiles or kMfmaMinWaves
+  // waves; smaller grids measured faster on the vector kernel, whose 8 x 8
+  // tiles spread the work over more waves.
+  {
     const int d2b = tb > 29 ? tb - 29 : 0;  // bits of the top digit
     const int termb = std::max(30, std::max(tb - 13, 2 * d2b));
     const int64_t steps = (ctot + 3) / 4;
     const int64_t max_steps = termb >= 51 ? 0 : (int64_t)1 << (51 - termb);
     int nwm = (int)std::min<int64_t>(kZtWaves, std::max<int64_t>(1, steps / 8));
     const int64_t gx = (rows + 15) / 16, gy = ((int64_t)G.R + 15) / 16;
-    if ((steps + nwm - 1) / nwm <= max_steps && gx < (1ll << 31) && gy < 65536) {
+    if ((tiles >= kMfmaMinTiles || tiles * nwm >= kMfmaMinWaves) && (steps + nwm - 1) / nwm <= max_steps &&
+        gx < (1ll << 31) && gy < 65536) {
       hipLaunchKernelGGL(k_zt_mfma, dim3((unsigned)gx, (unsigned)gy), dim3(64 * nwm), 0, s, a, k, out, G, AV, KV, OV,
                          C);
       return hipGetLastError();
     }
   }
-  const int64_t blocks2 = ((rows + 15) / 16) * ((G.R + 15) / 16);
-  const int ti = blocks2 >= 512 ? 2 : 1;
+  const int ti = tiles >= 512 ? 2 : 1;
   const int64_t steps16 = ctot / 16;
   const int nw = steps16 < 1 ? 1 : steps16 > kZtWaves ? kZtWaves : (int)steps16;
   const int64_t gx = (rows + 8 * ti - 1) / (8 * ti), gy = ((int64_t)G.R + 8 * ti - 1) / (8 * ti);

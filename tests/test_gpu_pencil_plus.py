@@ -153,3 +153,32 @@ def test_zt_linear_matrix_core_path_with_a_47_bit_t():
         got = host_i64(ctx.zt_linear(layer, op, dev(a), dev(b)))
         want = LN.layer_op(layer, op, a, b, t47, tdot=LN.tensordot_mod_t_object)
         assert np.array_equal(got, want), (layer, op)
+
+
+@pytest.mark.parametrize("t_plain", [T, 140737488355213])
+def test_zt_linear_lane_split_contraction(t_plain):
+    """Fully connected correlations with a long contraction and few outputs run
+    with the lanes of a wave splitting the contraction (a 2 x 2 output block per
+    wave): odd row and column counts, operands strided along the contraction
+    (input and weight gradients), and with a 47-bit t the longest contraction
+    one partial sum may hold, on all-maximal operands (checked in Python
+    integers)."""
+    from oracle import linear as LN
+    from paper_2403_11166_amd import Context
+    ctx = Context(12, 2, 50, 7, t=t_plain)
+    assert ctx.t == t_plain
+    rng = np.random.default_rng(t_plain % 1000)
+    kw = dict(log2_n=12, num_limbs=2, prime_bits=50)
+    cases = [(fc(5, 300, 3, **kw), "fwd", False), (fc(3, 7, 257, **kw), "dx", False),
+             (fc(301, 5, 3, **kw), "dw", False), (fc(2, 4096, 3, **kw), "fwd", True),
+             (fc(2, 4097, 3, **kw), "fwd", True), (fc(8, 1000, 16, **kw), "fwd", False)]
+    for layer, op, top in cases:
+        def draw(shape):
+            if top:
+                return np.full(shape, t_plain - 1, dtype=np.int64)
+            return rng.integers(0, t_plain, shape, dtype=np.int64)
+        x, w, dy = draw(layer.x_shape()), draw(layer.w_shape()), draw(layer.y_shape())
+        a, b = {"fwd": (x, w), "dx": (dy, w), "dw": (x, dy)}[op]
+        got = host_i64(ctx.zt_linear(layer, op, dev(a), dev(b)))
+        want = LN.layer_op(layer, op, a, b, t_plain, tdot=LN.tensordot_mod_t_object)
+        assert np.array_equal(got, want), (layer, op)
