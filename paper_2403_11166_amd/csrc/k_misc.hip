@@ -286,24 +286,30 @@ __global__ void __launch_bounds__(1024) k_zt_gemm(const int64_t* a, const int64_
 }
 
 // The same correlation on the fp64 matrix cores.  Each operand, centred into
-// (-t/2, t/2), is split into signed 14-bit digits v = d0 + d1 2^14 + d2 2^28
-// (d0, d1 in [0, 2^14), d2 the signed rest); the nine digit products of a pair
-// land on five diagonals T_s = sum d_i e_j (i + j = s), each a 16 x 16 x 4
-// fp64 multiply-accumulate.  Every digit product and running sum is an
-// integer below 2^53 (the launcher bounds the terms per wave), so the fp64
-// arithmetic is exact; at the end each T_s is reduced mod t and the five are
-// recombined with 2^14s mod t.  A workgroup owns a 16 x 16 output tile and
-// splits the contraction over its waves, four contraction indices per step.
-// Lane l holds A[row l % 16][c + l / 16] and B[c + l / 16][col l % 16], and
-// register r of its accumulator holds output (l / 16 + 4 r, l % 16).
+// (-t/2, t/2), is split into DIG signed digits of B = 21 (DIG = 2) or 14
+// (DIG = 3) bits, v = d0 + d1 2^B [+ d2 2^2B] (all but the top digit in
+// [0, 2^B), the top one the signed rest); the DIG^2 digit products of a pair
+// land on 2 DIG - 1 diagonals T_s = sum d_i e_j (i + j = s), each a
+// 16 x 16 x 4 fp64 multiply-accumulate.  Every digit product and running sum
+// is an integer below 2^53 (the launcher bounds the terms per wave, and takes
+// two digits only while t < 2^42), so the fp64 arithmetic is exact; at the end
+// each T_s is reduced mod t and the diagonals are recombined with 2^(B s) mod
+// t.  A workgroup owns a 16 x 16 output tile and splits the contraction over
+// its waves, four contraction indices per step.  Lane l holds
+// A[row l % 16][c + l / 16] and B[c + l / 16][col l % 16], and register r of
+// its accumulator holds output (l / 16 + 4 r, l % 16).
 typedef double zt_v4d __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ void zt_digits(uint64_t v, const Consts& C, double (&d)[3]) {
-  const int64_t c = v > C.t_half ? (int64_t)v - (int64_t)C.t : (int64_t)v;
-  const int64_t d0 = c & 0x3FFF, r1 = c >> 14, d1 = r1 & 0x3FFF, d2 = r1 >> 14;
-  d[0] = (double)d0;
-  d[1] = (double)d1;
-  d[2] = (double)d2;
+template <int DIG>
+__device__ __forceinline__ void zt_digits(uint64_t v, const Consts& C, double (&d)[DIG]) {
+  constexpr int B = DIG == 2 ? 21 : 14;
+  int64_t c = v > C.t_half ? (int64_t)v - (int64_t)C.t : (int64_t)v;
+#pragma unroll
+  for (int i = 0; i < DIG - 1; ++i) {
+    d[i] = (double)(c & ((1ll << B) - 1));
+    c >>= B;
+  }
+  d[DIG - 1] = (double)c;
 }
 
 __device__ __forceinline__ uint64_t zt_mod_signed(int64_t x, const Consts& C) {
@@ -312,6 +318,7 @@ __device__ __forceinline__ uint64_t zt_mod_signed(int64_t x, const Consts& C) {
   return x < 0 && r ? C.t - r : r;
 }
 
+template <int DIG>
 __global__ void __launch_bounds__(1024) k_zt_mfma(const int64_t* a, const int64_t* kt, int64_t* out, Geo G, View AV,
                                                   View KV, View OV, Consts C) {
   __shared__ uint64_t red[kZtWaves][256];
@@ -337,9 +344,10 @@ __global__ void __launch_bounds__(1024) k_zt_mfma(const int64_t* a, const int64_
   const int64_t ctot = (int64_t)G.K * kk;
   const int64_t steps = (ctot + 3) / 4, per = (steps + nw - 1) / nw;
   const int64_t s_begin = wv * per, s_end = s_begin + per < steps ? s_begin + per : steps;
-  zt_v4d acc[5];
+  constexpr int ND = 2 * DIG - 1, B = DIG == 2 ? 21 : 14;
+  zt_v4d acc[ND];
 #pragma unroll
-  for (int s = 0; s < 5; ++s) acc[s] = zt_v4d{0, 0, 0, 0};
+  for (int s = 0; s < ND; ++s) acc[s] = zt_v4d{0, 0, 0, 0};
   // this lane's contraction index c = 4 step + lc as (k, dy, dx), divided out
   // once and then advanced by 4 per step
   int k = 0, dy = 0, dx = 0;
@@ -377,25 +385,26 @@ __global__ void __launch_bounds__(1024) k_zt_mfma(const int64_t* a, const int64_
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      double da[3], db[3];
-      zt_digits(av[u], C, da);
-      zt_digits(bv[u], C, db);
+      double da[DIG], db[DIG];
+      zt_digits<DIG>(av[u], C, da);
+      zt_digits<DIG>(bv[u], C, db);
 #pragma unroll
-      for (int i = 0; i < 3; ++i)
+      for (int i = 0; i < DIG; ++i)
 #pragma unroll
-        for (int j = 0; j < 3; ++j) acc[i + j] = __builtin_amdgcn_mfma_f64_16x16x4f64(da[i], db[j], acc[i + j], 0, 0, 0);
+        for (int j = 0; j < DIG; ++j)
+          acc[i + j] = __builtin_amdgcn_mfma_f64_16x16x4f64(da[i], db[j], acc[i + j], 0, 0, 0);
     }
   }
-  // 2^(14 s) mod t
-  uint64_t pw[5];
+  // 2^(B s) mod t
+  uint64_t pw[ND];
   pw[0] = 1;
 #pragma unroll
-  for (int s = 1; s < 5; ++s) pw[s] = reduce64((uint64_t)1 << (14 * s), C.one_sh_t, C.t);
+  for (int s = 1; s < ND; ++s) pw[s] = reduce64((uint64_t)1 << (B * s), C.one_sh_t, C.t);
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     uint64_t hi = 0, lo = 0;
 #pragma unroll
-    for (int s = 0; s < 5; ++s) {
+    for (int s = 0; s < ND; ++s) {
       uint64_t ph, pl;
       mul_wide(zt_mod_signed((int64_t)acc[s][r], C), pw[s], ph, pl);
       lo += pl;
@@ -841,23 +850,31 @@ hipError_t launch_zt_corr(const int64_t* a, const int64_t* k, int64_t* out, cons
   }
   // Matrix-core kernel, one 16 x 16 output tile per workgroup: four
   // contraction indices per step, about eight steps per wave, at most 16
-  // waves; a diagonal sum takes per-term values below 2^30 (t < 2^43;
-  // 2^(2 bitlen(t) - 58) above), so a wave may run 2^53 / (4 * that) steps.
-  // Taken when its grid has at least kMfmaMinTiles tiles or kMfmaMinWaves
-  // waves; smaller grids measured faster on the vector kernel, whose 8 x 8
-  // tiles spread the work over more waves.
+  // waves.  A wave may run 2^53 / (4 * 2^termb) steps, termb bounding a
+  // diagonal's per-index term: with two 21-bit digits (t < 2^42; top digit
+  // below 2^(bitlen(t) - 22)) 2^42; with three 14-bit digits 2^30 (t < 2^43;
+  // 2^(2 bitlen(t) - 58) above).  Taken when its grid has at least
+  // kMfmaMinTiles tiles or kMfmaMinWaves waves; smaller grids measured faster
+  // on the vector kernel, whose 8 x 8 tiles spread the work over more waves.
   {
-    const int d2b = tb > 29 ? tb - 29 : 0;  // bits of the top digit
-    const int termb = std::max(30, std::max(tb - 13, 2 * d2b));
     const int64_t steps = (ctot + 3) / 4;
-    const int64_t max_steps = termb >= 51 ? 0 : (int64_t)1 << (51 - termb);
-    int nwm = (int)std::min<int64_t>(kZtWaves, std::max<int64_t>(1, steps / 8));
+    const int nwm = (int)std::min<int64_t>(kZtWaves, std::max<int64_t>(1, steps / 8));
+    const int64_t per = (steps + nwm - 1) / nwm;
     const int64_t gx = (rows + 15) / 16, gy = ((int64_t)G.R + 15) / 16;
-    if ((tiles >= kMfmaMinTiles || tiles * nwm >= kMfmaMinWaves) && (steps + nwm - 1) / nwm <= max_steps &&
-        gx < (1ll << 31) && gy < 65536) {
-      hipLaunchKernelGGL(k_zt_mfma, dim3((unsigned)gx, (unsigned)gy), dim3(64 * nwm), 0, s, a, k, out, G, AV, KV, OV,
-                         C);
-      return hipGetLastError();
+    const int d2b = tb > 29 ? tb - 29 : 0;  // bits of the top 14-bit-split digit
+    const int termb3 = std::max(30, std::max(tb - 13, 2 * d2b));
+    const int64_t max3 = termb3 >= 51 ? 0 : (int64_t)1 << (51 - termb3);
+    const int64_t max2 = tb <= 42 ? (int64_t)1 << (51 - 42) : 0;
+    if ((tiles >= kMfmaMinTiles || tiles * nwm >= kMfmaMinWaves) && gx < (1ll << 31) && gy < 65536) {
+      const dim3 grid((unsigned)gx, (unsigned)gy), block(64 * nwm);
+      if (per <= max2) {
+        hipLaunchKernelGGL(k_zt_mfma<2>, grid, block, 0, s, a, k, out, G, AV, KV, OV, C);
+        return hipGetLastError();
+      }
+      if (per <= max3) {
+        hipLaunchKernelGGL(k_zt_mfma<3>, grid, block, 0, s, a, k, out, G, AV, KV, OV, C);
+        return hipGetLastError();
+      }
     }
   }
   const int ti = tiles >= 512 ? 2 : 1;

@@ -182,3 +182,23 @@ def test_zt_linear_lane_split_contraction(t_plain):
         got = host_i64(ctx.zt_linear(layer, op, dev(a), dev(b)))
         want = LN.layer_op(layer, op, a, b, t_plain, tdot=LN.tensordot_mod_t_object)
         assert np.array_equal(got, want), (layer, op)
+
+
+@pytest.mark.parametrize("batch", [32768, 32769])
+def test_zt_linear_matrix_core_at_its_digit_bound(batch):
+    """With t < 2^42 the matrix-core correlation splits operands into two 21-bit
+    digits while one wave sums at most 2^11 contraction indices (2^9 steps of
+    four); a weight gradient over a batch of 32768 with 16 waves per tile sits
+    exactly at that bound, and one index more takes the three-digit form.
+    Operands of the largest centred magnitude, (t - 1) / 2, make every digit
+    product and diagonal sum as large as it can be; the exact result of each
+    entry is batch ((t - 1) / 2)^2 mod t."""
+    from paper_2403_11166_amd import Context
+    ctx = Context(12, 2, 50, 9)
+    layer = fc(batch, 128, 128, log2_n=12, num_limbs=2, prime_bits=50)  # 64 output tiles of 16 x 16
+    h = (T - 1) // 2
+    x = dev(np.full(layer.x_shape(), h, dtype=np.int64))
+    dy = dev(np.full(layer.y_shape(), h, dtype=np.int64))
+    got = host_i64(ctx.zt_linear(layer, "dw", x, dy))
+    assert got.size == 128 * 128
+    assert (got == (batch * h * h) % T).all()
