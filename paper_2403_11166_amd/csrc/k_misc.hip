@@ -425,42 +425,97 @@ __global__ void __launch_bounds__(1024) k_zt_mfma(const int64_t* a, const int64_
   }
 }
 
-// The correlation of a fully connected layer (1 x 1 kernel, 1 x 1 output) with
-// a long contraction and few outputs.  Each wave owns a 2 x 2 block of (row,
-// column) outputs and its 64 lanes split the contraction (lane l takes the
-// indices l, l + 64, ...), so an operand stored contiguously along the
-// contraction is read with coalesced loads, and the waves spread over every CU
-// even where the grid of 16 x 16 output tiles is small.  Products use the
-// 21-bit halves of the vector kernel; each lane's three partial sums per
-// output, added across the wave by shuffles, hold the whole contraction (the
-// launcher bounds its length), and lanes 0-3 then reduce one output each.
+// The correlation for output grids too small to fill the GPU with tiles but
+// with a long contraction (fully connected forward products, weight gradients
+// of layers with few channels).  A wave owns a 2 x 2 block of (row, column)
+// outputs and its 64 lanes split the contraction (lane l takes the flattened
+// indices c = (k, dy, dx) with c = l mod 64 NWB); with NWB = 4 the four waves
+// of a workgroup share one block and split it four ways, else a workgroup
+// holds four blocks.  An operand stored contiguously along the contraction is
+// read with coalesced loads.  Products use the 21-bit halves of the vector
+// kernel; the partial sums of all lanes (and waves) of a block, which hold the
+// whole contraction (the launcher bounds its length), are added by shuffles
+// (and through LDS), and four lanes then reduce one output each.  A lane
+// advances its index by the mixed-radix digits (D.dk, D.ddy, D.ddx) of the
+// stride 64 NWB.  WIN = false is the fully connected form (1 x 1 kernel and
+// output, no padding): the contraction index is the channel alone.
+struct DotStep {
+  int32_t dk, ddy, ddx, pad;
+};
+
+template <int NWB, bool WIN>
 __global__ void __launch_bounds__(256) k_zt_dot(const int64_t* a, const int64_t* kt, int64_t* out, Geo G, View AV,
-                                                View KV, View OV, Consts C) {
-  const int lane = threadIdx.x & 63;
-  const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int P = G.M, R = G.R, K = G.K;
+                                                View KV, View OV, Consts C, DotStep D) {
+  __shared__ uint64_t red[4][4][3];  // NWB = 4: [wave][output][partial sum]
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t blk = NWB == 1 ? (int64_t)blockIdx.x * 4 + wv : (int64_t)blockIdx.x;
+  const int ohw = G.OH * G.OW, P = G.M * ohw, R = G.R, kk = G.KH * G.KW;
   const int cb = (R + 1) / 2;
-  if (wave >= (int64_t)((P + 1) / 2) * cb) return;  // the whole wave leaves; no barrier follows
-  const int row0 = (int)(wave / cb) * 2, col0 = (int)(wave % cb) * 2;
-  const bool row1 = row0 + 1 < P, col1 = col0 + 1 < R;
-  const PENCIL_GLOBAL int64_t* ga[2] = {gview(a) + (int64_t)row0 * AV.s0,
-                                        gview(a) + (int64_t)(row1 ? row0 + 1 : row0) * AV.s0};
-  const PENCIL_GLOBAL int64_t* gk[2] = {gview(kt) + (int64_t)col0 * KV.s0,
-                                        gview(kt) + (int64_t)(col1 ? col0 + 1 : col0) * KV.s0};
+  // the whole wave (NWB = 1) or workgroup (NWB = 4) leaves together
+  if (blk >= (int64_t)((P + 1) / 2) * cb) return;
+  const int row0 = (int)(blk / cb) * 2, col0 = (int)(blk % cb) * 2;
+  const PENCIL_GLOBAL int64_t* ga = gview(a);
+  const PENCIL_GLOBAL int64_t* gk = gview(kt);
+  int64_t abase[2], kbase[2];
+  int ay[2], ax[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int row = row0 + i < P ? row0 + i : row0;  // a padding row repeats row0 (never stored)
+    const int m = WIN ? row / ohw : row, rem = row - m * ohw, y = WIN ? rem / G.OW : 0, x = rem - y * G.OW;
+    abase[i] = (int64_t)m * AV.s0;
+    ay[i] = y - AV.pady;
+    ax[i] = x - AV.pad;
+    const int col = col0 + i < R ? col0 + i : col0;
+    kbase[i] = (int64_t)col * KV.s0;
+  }
+  const int ctot = G.K * kk;  // at most 2^22 (the launcher's bound)
+  const int stride = 64 * NWB;
+  int c = lane + 64 * (NWB == 1 ? 0 : wv);
+  int k = c, dy = 0, dx = 0;
+  if constexpr (WIN) {
+    k = c / kk;
+    const int rem = c - k * kk;
+    dy = rem / G.KW;
+    dx = rem - dy * G.KW;
+  }
   constexpr uint64_t kLo = (1ull << 21) - 1;
   uint64_t s0[4] = {}, s1[4] = {}, s2[4] = {};
   constexpr int U = 4;  // contraction indices per lane whose loads are issued together
-  for (int k0 = lane; k0 < K; k0 += 64 * U) {
+  for (; c < ctot; c += stride * U) {
     uint64_t av[U][2], bv[U][2];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int k = k0 + 64 * u;
-      const bool live = k < K;
+      const bool live = c + stride * u < ctot;
+      if constexpr (!WIN) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          av[u][i] = live ? (uint64_t)ga[abase[i] + (int64_t)k * AV.s1] : 0;
+          bv[u][i] = live ? (uint64_t)gk[kbase[i] + (int64_t)k * KV.s1] : 0;
+        }
+        k += stride;
+        continue;
+      }
+      const int ky = KV.flip ? KV.KH - 1 - dy : dy, kx = KV.flip ? KV.KW - 1 - dx : dx;
+      const int64_t koff = (int64_t)k * KV.s1 + (int64_t)ky * KV.sy + (int64_t)kx * KV.sx;
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
-        av[u][i] = live ? (uint64_t)ga[i][(int64_t)k * AV.s1] : 0;
-        bv[u][i] = live ? (uint64_t)gk[i][(int64_t)k * KV.s1] : 0;
+        const int ys = ay[i] + dy, xs = ax[i] + dx;
+        const bool in = live && ys >= 0 && ys < AV.H && xs >= 0 && xs < AV.W;
+        av[u][i] = in ? (uint64_t)ga[abase[i] + (int64_t)k * AV.s1 + (int64_t)ys * AV.sy + (int64_t)xs * AV.sx] : 0;
+        bv[u][i] = live ? (uint64_t)gk[kbase[i] + koff] : 0;
       }
+      // advance (k, dy, dx) by the stride: each digit carries at most once
+      dx += D.ddx;
+      if (dx >= G.KW) {
+        dx -= G.KW;
+        ++dy;
+      }
+      dy += D.ddy;
+      if (dy >= G.KH) {
+        dy -= G.KH;
+        ++k;
+      }
+      k += D.dk;
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)
@@ -485,7 +540,7 @@ __global__ void __launch_bounds__(256) k_zt_dot(const int64_t* a, const int64_t*
       s1[o] += __shfl_xor(s1[o], d);
       s2[o] += __shfl_xor(s2[o], d);
     }
-  if (lane >= 4) return;
+  // lane o < 4 takes output o = (row0 + o / 2, col0 + o % 2)
   uint64_t x0 = s0[0], x1 = s1[0], x2 = s2[0];
 #pragma unroll
   for (int o = 1; o < 4; ++o)
@@ -494,15 +549,34 @@ __global__ void __launch_bounds__(256) k_zt_dot(const int64_t* a, const int64_t*
       x1 = s1[o];
       x2 = s2[o];
     }
+  if constexpr (NWB == 4) {
+    if (lane < 4) {
+      red[wv][lane][0] = x0;
+      red[wv][lane][1] = x1;
+      red[wv][lane][2] = x2;
+    }
+    __syncthreads();
+    if (wv != 0) return;
+    if (lane < 4) {
+#pragma unroll
+      for (int w = 1; w < 4; ++w) {
+        x0 += red[w][lane][0];
+        x1 += red[w][lane][1];
+        x2 += red[w][lane][2];
+      }
+    }
+  }
+  if (lane >= 4) return;
   const int row = row0 + (lane >> 1), col = col0 + (lane & 1);
   if (row >= P || col >= R) return;
+  const int m = WIN ? row / ohw : row, rem = row - m * ohw, y = WIN ? rem / G.OW : 0, x = rem - y * G.OW;
   // x0 + x1 2^21 + x2 2^42 as a 128-bit value, then mod t
   const uint64_t t1 = x1 << 21, t2 = x2 << 42;
   uint64_t lo = x0 + t1;
   uint64_t hi = (lo < t1 ? 1 : 0) + (x1 >> 43) + (x2 >> 22);
   lo += t2;
   hi += lo < t2 ? 1 : 0;
-  gview(out)[(int64_t)row * OV.s0 + (int64_t)col * OV.s1] =
+  gview(out)[(int64_t)m * OV.s0 + (int64_t)col * OV.s1 + (int64_t)y * OV.sy + (int64_t)x * OV.sx] =
       (int64_t)add_mod(mul_shoup(reduce64(hi, C.one_sh_t, C.t), C.r64t, C.r64t_sh, C.t), reduce64(lo, C.one_sh_t, C.t),
                        C.t);
 }
@@ -819,7 +893,7 @@ hipError_t launch_stride_relayout(const Relayout& R, const int64_t* in, int64_t*
   return hipGetLastError();
 }
 
-constexpr int64_t kDotMinK = 256, kDotMaxTiles = 64, kMfmaMinTiles = 256, kMfmaMinWaves = 512;
+constexpr int64_t kDotMinK = 256, kDotWideK = 8192, kDotMaxTiles = 64, kMfmaMinTiles = 256, kMfmaMinWaves = 512;
 
 hipError_t launch_zt_corr(const int64_t* a, const int64_t* k, int64_t* out, const Geo& G, const View& AV,
                           const View& KV, const View& OV, const Consts& C, hipStream_t s) {
@@ -835,16 +909,26 @@ hipError_t launch_zt_corr(const int64_t* a, const int64_t* k, int64_t* out, cons
   const int mb = std::max(42, std::max(22 + hb, 2 * hb));
   const int64_t per_wave_max = mb >= 63 ? 1 : (int64_t)1 << (64 - mb);
   const int64_t tiles = ((rows + 15) / 16) * ((G.R + 15) / 16);
-  // Fully connected shapes (1 x 1 kernel and output) whose contraction is long
-  // and whose outputs fill few 16 x 16 tiles: one 2 x 2 output block per wave,
-  // the lanes splitting the contraction, whose whole length one partial sum
-  // then holds.
-  const bool fc = G.KH == 1 && G.KW == 1 && G.OH == 1 && G.OW == 1 && AV.H == 1 && AV.W == 1 && AV.pad == 0 &&
-                  AV.pady == 0;
-  if (fc && ctot >= kDotMinK && tiles < kDotMaxTiles && ctot <= per_wave_max) {
-    const int64_t waves = (int64_t)((G.M + 1) / 2) * ((G.R + 1) / 2);
-    if ((waves + 3) / 4 < (1ll << 31)) {
-      hipLaunchKernelGGL(k_zt_dot, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, a, k, out, G, AV, KV, OV, C);
+  // Long contractions whose outputs fill few 16 x 16 tiles: 2 x 2 output
+  // blocks, the lanes of one wave (or, from kDotWideK indices, of four waves)
+  // splitting the contraction, whose whole length one partial sum then holds.
+  if (ctot >= kDotMinK && tiles < kDotMaxTiles && ctot <= per_wave_max) {
+    const int64_t blocks = (int64_t)((rows + 1) / 2) * ((G.R + 1) / 2);
+    const int nwb = ctot >= kDotWideK ? 4 : 1;
+    const int kk = G.KH * G.KW, st = 64 * nwb;
+    const DotStep D{st / kk, (st % kk) / G.KW, (st % kk) % G.KW, 0};
+    const int64_t grid = nwb == 4 ? blocks : (blocks + 3) / 4;
+    const bool win = !(kk == 1 && G.OH == 1 && G.OW == 1 && AV.H == 1 && AV.W == 1 && AV.pad == 0 && AV.pady == 0);
+    if (grid < (1ll << 31)) {
+      const dim3 g((unsigned)grid), b(256);
+      if (nwb == 4 && win)
+        hipLaunchKernelGGL((k_zt_dot<4, true>), g, b, 0, s, a, k, out, G, AV, KV, OV, C, D);
+      else if (nwb == 4)
+        hipLaunchKernelGGL((k_zt_dot<4, false>), g, b, 0, s, a, k, out, G, AV, KV, OV, C, D);
+      else if (win)
+        hipLaunchKernelGGL((k_zt_dot<1, true>), g, b, 0, s, a, k, out, G, AV, KV, OV, C, D);
+      else
+        hipLaunchKernelGGL((k_zt_dot<1, false>), g, b, 0, s, a, k, out, G, AV, KV, OV, C, D);
       return hipGetLastError();
     }
   }

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from oracle import pencil_plus as PP
-from workloads import CONFIGS, T_PLAIN, conv, fc
+from workloads import CONFIGS, T_PLAIN, conv, conv1d, fc
 
 from gpu_common import dev, host_i64
 
@@ -157,11 +157,12 @@ def test_zt_linear_matrix_core_path_with_a_47_bit_t():
 
 @pytest.mark.parametrize("t_plain", [T, 140737488355213])
 def test_zt_linear_lane_split_contraction(t_plain):
-    """Fully connected correlations with a long contraction and few outputs run
-    with the lanes of a wave splitting the contraction (a 2 x 2 output block per
-    wave): odd row and column counts, operands strided along the contraction
-    (input and weight gradients), and with a 47-bit t the longest contraction
-    one partial sum may hold, on all-maximal operands (checked in Python
+    """Correlations with a long contraction and few outputs run with the lanes
+    of a wave (or of four waves) splitting the contraction, a 2 x 2 output block
+    per wave: odd row and column counts, operands strided along the
+    contraction (input and weight gradients), convolution windows with padding
+    and a flipped kernel, and with a 47-bit t the longest contraction one
+    partial sum may hold, on all-maximal operands (checked in Python
     integers)."""
     from oracle import linear as LN
     from paper_2403_11166_amd import Context
@@ -171,7 +172,11 @@ def test_zt_linear_lane_split_contraction(t_plain):
     kw = dict(log2_n=12, num_limbs=2, prime_bits=50)
     cases = [(fc(5, 300, 3, **kw), "fwd", False), (fc(3, 7, 257, **kw), "dx", False),
              (fc(301, 5, 3, **kw), "dw", False), (fc(2, 4096, 3, **kw), "fwd", True),
-             (fc(2, 4097, 3, **kw), "fwd", True), (fc(8, 1000, 16, **kw), "fwd", False)]
+             (fc(2, 4097, 3, **kw), "fwd", True), (fc(8, 1000, 16, **kw), "fwd", False),
+             # convolutions: padded windows, a flipped kernel, a one-row Conv1d, and a
+             # weight gradient long enough for four waves per output block
+             (conv(2, 64, 3, 4, k=3, pad=1, **kw), "fwd", False), (conv(2, 3, 64, 4, k=3, pad=1, **kw), "dx", False),
+             (conv1d(8, 4, 3, 300, k=5, pad=2, **kw), "dw", False), (conv(64, 3, 8, 16, k=3, pad=1, **kw), "dw", False)]
     for layer, op, top in cases:
         def draw(shape):
             if top:
