@@ -894,6 +894,7 @@ hipError_t launch_stride_relayout(const Relayout& R, const int64_t* in, int64_t*
 }
 
 constexpr int64_t kDotMinK = 256, kDotWideK = 8192, kDotMaxTiles = 64, kMfmaMinTiles = 256, kMfmaMinWaves = 512;
+constexpr int kDotMaxSkinny = 4;
 
 hipError_t launch_zt_corr(const int64_t* a, const int64_t* k, int64_t* out, const Geo& G, const View& AV,
                           const View& KV, const View& OV, const Consts& C, hipStream_t s) {
@@ -909,10 +910,12 @@ hipError_t launch_zt_corr(const int64_t* a, const int64_t* k, int64_t* out, cons
   const int mb = std::max(42, std::max(22 + hb, 2 * hb));
   const int64_t per_wave_max = mb >= 63 ? 1 : (int64_t)1 << (64 - mb);
   const int64_t tiles = ((rows + 15) / 16) * ((G.R + 15) / 16);
-  // Long contractions whose outputs fill few 16 x 16 tiles: 2 x 2 output
-  // blocks, the lanes of one wave (or, from kDotWideK indices, of four waves)
-  // splitting the contraction, whose whole length one partial sum then holds.
-  if (ctot >= kDotMinK && tiles < kDotMaxTiles && ctot <= per_wave_max) {
+  // Long contractions whose outputs fill few 16 x 16 tiles, or only a few
+  // columns of each (at most kDotMaxSkinny, where the other kernels' tiles
+  // would compute mostly padding): 2 x 2 output blocks, the lanes of one wave
+  // (or, from kDotWideK indices, of four waves) splitting the contraction,
+  // whose whole length one partial sum then holds.
+  if (ctot >= kDotMinK && (tiles < kDotMaxTiles || G.R <= kDotMaxSkinny) && ctot <= per_wave_max) {
     const int64_t blocks = (int64_t)((rows + 1) / 2) * ((G.R + 1) / 2);
     const int nwb = ctot >= kDotWideK ? 4 : 1;
     const int kk = G.KH * G.KW, st = 64 * nwb;

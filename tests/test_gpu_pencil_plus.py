@@ -176,7 +176,9 @@ def test_zt_linear_lane_split_contraction(t_plain):
              # convolutions: padded windows, a flipped kernel, a one-row Conv1d, and a
              # weight gradient long enough for four waves per output block
              (conv(2, 64, 3, 4, k=3, pad=1, **kw), "fwd", False), (conv(2, 3, 64, 4, k=3, pad=1, **kw), "dx", False),
-             (conv1d(8, 4, 3, 300, k=5, pad=2, **kw), "dw", False), (conv(64, 3, 8, 16, k=3, pad=1, **kw), "dw", False)]
+             (conv1d(8, 4, 3, 300, k=5, pad=2, **kw), "dw", False), (conv(64, 3, 8, 16, k=3, pad=1, **kw), "dw", False),
+             # many output tiles but three columns: the input gradient of a three-channel layer
+             (conv(16, 3, 32, 16, k=3, pad=1, **kw), "dx", False)]
     for layer, op, top in cases:
         def draw(shape):
             if top:
