@@ -396,38 +396,26 @@ __device__ __forceinline__ void part_mac(Part<SPLIT>& x, uint64_t a, uint64_t b)
   x.s2 += (uint64_t)a1 * b1;
 }
 
-// (w0, w1, w2, w3) += (a0, a1, a2, a3) as 128-bit integers of 32-bit words
-// (a carry chain; the total never wraps).
-__device__ __forceinline__ void add128w(uint32_t& w0, uint32_t& w1, uint32_t& w2, uint32_t& w3, uint32_t a0,
-                                        uint32_t a1, uint32_t a2, uint32_t a3) {
-  unsigned c;
-  w0 = __builtin_addc(w0, a0, 0u, &c);
-  w1 = __builtin_addc(w1, a1, c, &c);
-  w2 = __builtin_addc(w2, a2, c, &c);
-  w3 = w3 + a3 + c;
-}
-
 // (lo, hi) += s0 + (s1 [+ s1b]) 2^30 + s2 2^60; the partial sums restart at
-// zero.  s1 2^30 is (s1 << 30) below 2^64 and s1 >> 34 above; s2 2^60 is
-// (s2 mod 16) << 60 below and s2 >> 4 above.
+// zero.  The fold is formed as a 128-bit value (flo, fhi) in 64-bit pieces:
+// with a = s1 + s1b = a' + ca 2^64, a 2^30 is (a' << 30) below 2^64 and
+// (a' >> 34) + ca 2^30 above; s2 2^60 is (s2 << 60) below and s2 >> 4 above.
+// The total never wraps.
 template <bool SPLIT>
 __device__ __forceinline__ void part_fold(Part<SPLIT>& x, uint64_t& lo, uint64_t& hi) {
-  uint32_t w0 = (uint32_t)lo, w1 = (uint32_t)(lo >> 32), w2 = (uint32_t)hi, w3 = (uint32_t)(hi >> 32);
-  add128w(w0, w1, w2, w3, (uint32_t)x.s0, (uint32_t)(x.s0 >> 32), 0, 0);
-  const uint64_t t1 = x.s1 << 30;
-  add128w(w0, w1, w2, w3, (uint32_t)t1, (uint32_t)(t1 >> 32), (uint32_t)(x.s1 >> 34), 0);
+  uint64_t a = x.s1, ca = 0;
   if constexpr (SPLIT) {
-    const uint64_t t1b = x.s1b << 30;
-    add128w(w0, w1, w2, w3, (uint32_t)t1b, (uint32_t)(t1b >> 32), (uint32_t)(x.s1b >> 34), 0);
+    a += x.s1b;
+    ca = a < x.s1b ? 1 : 0;
     x.s1b = 0;
   }
-  const uint64_t u2 = x.s2 >> 4;
-  unsigned c;
-  w1 = __builtin_addc(w1, (uint32_t)x.s2 << 28, 0u, &c);
-  w2 = __builtin_addc(w2, (uint32_t)u2, c, &c);
-  w3 = w3 + (uint32_t)(u2 >> 32) + c;
-  lo = ((uint64_t)w1 << 32) | w0;
-  hi = ((uint64_t)w3 << 32) | w2;
+  const uint64_t t1 = a << 30, t2 = x.s2 << 60;
+  uint64_t flo = x.s0 + t1;
+  uint64_t fhi = (a >> 34) + (x.s2 >> 4) + (ca << 30) + (flo < t1 ? 1 : 0);
+  flo += t2;
+  fhi += flo < t2 ? 1 : 0;
+  lo += flo;
+  hi += fhi + (lo < flo ? 1 : 0);
   x.s0 = x.s1 = x.s2 = 0;
 }
 
