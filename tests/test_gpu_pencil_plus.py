@@ -209,3 +209,24 @@ def test_zt_linear_matrix_core_at_its_digit_bound(batch):
     got = host_i64(ctx.zt_linear(layer, "dw", x, dy))
     assert got.size == 128 * 128
     assert (got == (batch * h * h) % T).all()
+
+
+@pytest.mark.parametrize("case", range(6))
+def test_zt_linear_at_the_kernel_selection_boundaries(case):
+    """Shapes on either side of each point where the correlation changes
+    kernel: 8191 / 8192 contraction indices (one or four waves per lane-split
+    block), four / five output columns (lane-split or matrix-core kernel for a
+    grid of many tiles), 63 / 64 output tiles (lane-split or matrix-core
+    kernel for a long contraction)."""
+    from oracle import linear as LN
+    from paper_2403_11166_amd import Context
+    kw = dict(log2_n=12, num_limbs=2, prime_bits=50)
+    layer, op = [(fc(8191, 5, 3, **kw), "dw"), (fc(8192, 5, 3, **kw), "dw"),
+                 (conv(16, 4, 32, 16, k=3, pad=1, **kw), "dx"), (conv(16, 5, 32, 16, k=3, pad=1, **kw), "dx"),
+                 (fc(112, 300, 144, **kw), "fwd"), (fc(128, 300, 128, **kw), "fwd")][case]
+    ctx = context(SMALL[0])
+    rng = np.random.default_rng(60 + case)
+    x, w, dy = (rng.integers(0, T, s, dtype=np.int64) for s in (layer.x_shape(), layer.w_shape(), layer.y_shape()))
+    a, b = {"fwd": (x, w), "dx": (dy, w), "dw": (x, dy)}[op]
+    got = host_i64(ctx.zt_linear(layer, op, dev(a), dev(b)))
+    assert np.array_equal(got, LN.layer_op(layer, op, a, b, T)), (layer, op)
